@@ -1,0 +1,230 @@
+"""ctypes binding of ``libmlmc.so`` (declared in include/mlmc.h).
+
+Argument marshalling only: every numerical step runs in the HIP library.
+PyTorch provides device memory (tensors passed by ``data_ptr()``) and the
+current HIP stream.  The library must have been built
+(``python -m paper_1907_10271_amd.build``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import math
+import os
+from typing import Optional, Sequence, Union
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libmlmc.so")
+
+MLMC_OK, MLMC_EINVAL, MLMC_ENOMEM, MLMC_EHIP, MLMC_ESTATE = 0, -1, -2, -3, -4
+FP64, MIXED = 0, 1
+S_OK, S_NOCONV, S_NAN, S_BREAKDOWN, S_SKIPPED = 0, 1, 2, 3, 4
+
+EXPORTS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_level_info", "mlmc_num_levels",
+           "mlmc_footprint", "mlmc_sample_field", "mlmc_strip_apply", "mlmc_strip_rhs_diag",
+           "mlmc_strip_solve_theta", "mlmc_solve_batch", "mlmc_buckle_batch", "mlmc_level_stats"]
+
+
+class Request(C.Structure):
+    _fields_ = [("sample", C.c_int64), ("level", C.c_int32), ("coupled", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("iters_f", C.c_int32), ("iters_c", C.c_int32), ("relres_f", C.c_double),
+                ("relres_c", C.c_double), ("status_f", C.c_int32), ("status_c", C.c_int32)]
+
+
+class LevelAcc(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_plus", C.c_int64), ("n_minus", C.c_int64),
+                ("sum_y", C.c_double), ("sum_y2", C.c_double), ("sum_qf", C.c_double),
+                ("sum_qc", C.c_double), ("sum_cost", C.c_double), ("comp_y", C.c_double),
+                ("comp_y2", C.c_double), ("comp_qf", C.c_double), ("comp_qc", C.c_double)]
+
+    def total(self, name: str) -> float:
+        comp = {"sum_y": "comp_y", "sum_y2": "comp_y2", "sum_qf": "comp_qf", "sum_qc": "comp_qc"}[name]
+        return getattr(self, name) + getattr(self, comp)
+
+
+INFO_DTYPE = np.dtype([("iters_f", "<i4"), ("iters_c", "<i4"), ("relres_f", "<f8"), ("relres_c", "<f8"),
+                       ("status_f", "<i4"), ("status_c", "<i4")])
+assert INFO_DTYPE.itemsize == C.sizeof(Info) == 32
+
+_lib = None
+
+
+class MLMCError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mlmc error {code}: {msg}")
+        self.code = code
+
+
+def load() -> C.CDLL:
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library missing: {LIB_PATH} (run python -m paper_1907_10271_amd.build)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i, d, sz = C.c_void_p, C.c_int, C.c_double, C.c_size_t
+    lib.mlmc_create.argtypes = [C.c_char_p, sz, C.POINTER(vp)]
+    lib.mlmc_destroy.argtypes = [vp]
+    lib.mlmc_destroy.restype = None
+    lib.mlmc_last_error.argtypes = [vp]
+    lib.mlmc_last_error.restype = C.c_char_p
+    lib.mlmc_level_info.argtypes = [vp, i] + [C.POINTER(C.c_int64)] * 4
+    lib.mlmc_num_levels.argtypes = [vp]
+    lib.mlmc_footprint.argtypes = [vp, i, i, i, C.POINTER(sz)]
+    lib.mlmc_sample_field.argtypes = [vp, i, i, vp, i, vp, i, vp]
+    lib.mlmc_strip_apply.argtypes = [vp, i, i, vp, vp, vp, i, vp]
+    lib.mlmc_strip_rhs_diag.argtypes = [vp, i, i, vp, vp, vp, vp]
+    lib.mlmc_strip_solve_theta.argtypes = [vp, i, i, vp, vp, vp, vp, i, d, vp]
+    lib.mlmc_solve_batch.argtypes = [vp, i, C.POINTER(Request), vp, C.c_int64, i, vp, vp, vp, i, d, vp]
+    lib.mlmc_buckle_batch.argtypes = [vp, i, C.POINTER(Request), vp, C.c_int64, vp, vp, vp, i, d, vp]
+    lib.mlmc_level_stats.argtypes = [vp, i, i, vp, vp, d, d, C.POINTER(LevelAcc), vp]
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def info_to_numpy(buf) -> np.ndarray:
+    """Device ``uint8`` buffer of ``mlmc_info`` records -> numpy structured array."""
+    host = buf.cpu().numpy()
+    return host.view(INFO_DTYPE)
+
+
+class Context:
+    """Owns one ``mlmc_ctx`` (a workload definition on the current HIP device)."""
+
+    def __init__(self, config: Union[str, dict], mem_budget_bytes: int = 0):
+        self.lib = load()
+        if isinstance(config, dict):
+            self.cfg = config
+            text = json.dumps(config)
+        else:
+            text = config
+            self.cfg = json.loads(config)
+        h = C.c_void_p()
+        rc = self.lib.mlmc_create(text.encode(), mem_budget_bytes, C.byref(h))
+        if rc != MLMC_OK:
+            raise MLMCError(rc, self.lib.mlmc_last_error(None).decode())
+        self.h = h
+        self.n_levels = self.lib.mlmc_num_levels(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mlmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != MLMC_OK:
+            raise MLMCError(rc, self.lib.mlmc_last_error(self.h).decode())
+
+    # ------------------------------------------------------------ queries
+    def level_info(self, level: int):
+        v = [C.c_int64() for _ in range(4)]
+        self._check(self.lib.mlmc_level_info(self.h, level, *[C.byref(x) for x in v]))
+        return {"n_nodes": v[0].value, "n_dofs": v[1].value, "n_elem": v[2].value, "n_gp": v[3].value}
+
+    def footprint(self, kind: int, level: int, precision: int = FP64) -> int:
+        b = C.c_size_t()
+        self._check(self.lib.mlmc_footprint(self.h, kind, level, precision, C.byref(b)))
+        return b.value
+
+    # ------------------------------------------------------------ strip
+    def sample_field(self, level: int, xi, dtype: int = 0, stream=None):
+        torch = _torch()
+        n = xi.shape[0]
+        ngp = self.level_info(level)["n_gp"]
+        out = torch.empty((n, ngp), dtype=torch.float64 if dtype == 0 else torch.int16, device=xi.device)
+        self._check(self.lib.mlmc_sample_field(self.h, level, n, _ptr(xi), xi.shape[1], _ptr(out), dtype,
+                                               _stream(stream)))
+        return out
+
+    def strip_apply(self, level: int, theta, x, raw: bool = False, stream=None):
+        torch = _torch()
+        y = torch.empty_like(x)
+        self._check(self.lib.mlmc_strip_apply(self.h, level, x.shape[0], _ptr(theta), _ptr(x), _ptr(y), int(raw),
+                                              _stream(stream)))
+        return y
+
+    def strip_rhs_diag(self, level: int, theta, stream=None):
+        torch = _torch()
+        n = theta.shape[0]
+        nd = self.level_info(level)["n_dofs"]
+        b = torch.empty((n, nd), dtype=torch.float64, device=theta.device)
+        dinv = torch.empty_like(b)
+        self._check(self.lib.mlmc_strip_rhs_diag(self.h, level, n, _ptr(theta), _ptr(b), _ptr(dinv),
+                                                 _stream(stream)))
+        return b, dinv
+
+    def strip_solve_theta(self, level: int, theta, precision: int = FP64, rtol: float = 0.0,
+                          want_d: bool = False, stream=None):
+        torch = _torch()
+        n = theta.shape[0]
+        q = torch.empty(n, dtype=torch.float64, device=theta.device)
+        info = torch.zeros(n * 32, dtype=torch.uint8, device=theta.device)
+        d = None
+        if want_d:
+            d = torch.empty((n, self.level_info(level)["n_dofs"]), dtype=torch.float64, device=theta.device)
+        self._check(self.lib.mlmc_strip_solve_theta(self.h, level, n, _ptr(theta), _ptr(q), _ptr(d), _ptr(info),
+                                                    precision, rtol, _stream(stream)))
+        return q, d, info_to_numpy(info)
+
+    def solve_batch(self, requests: Sequence, xi, precision: int = FP64, rtol: float = 0.0, stream=None):
+        """``requests``: sequence of ``(sample_row, level, coupled)``."""
+        torch = _torch()
+        n = len(requests)
+        arr = (Request * max(n, 1))()
+        for k, (s, l, c) in enumerate(requests):
+            arr[k].sample, arr[k].level, arr[k].coupled = int(s), int(l), int(bool(c))
+        qf = torch.empty(n, dtype=torch.float64, device=xi.device)
+        qc = torch.empty(n, dtype=torch.float64, device=xi.device)
+        info = torch.zeros(max(n, 1) * 32, dtype=torch.uint8, device=xi.device)
+        self._check(self.lib.mlmc_solve_batch(self.h, n, arr, _ptr(xi), xi.shape[0], xi.shape[1], _ptr(qf), _ptr(qc),
+                                              _ptr(info), precision, rtol, _stream(stream)))
+        return qf, qc, info_to_numpy(info)[:n]
+
+    # ------------------------------------------------------------ plate
+    def buckle_batch(self, requests: Sequence, offsets, precision: int = FP64, tol: float = 0.0, stream=None):
+        torch = _torch()
+        n = len(requests)
+        arr = (Request * max(n, 1))()
+        for k, (s, l, c) in enumerate(requests):
+            arr[k].sample, arr[k].level, arr[k].coupled = int(s), int(l), int(bool(c))
+        lf = torch.empty(n, dtype=torch.float64, device=offsets.device)
+        lc = torch.empty(n, dtype=torch.float64, device=offsets.device)
+        info = torch.zeros(max(n, 1) * 32, dtype=torch.uint8, device=offsets.device)
+        self._check(self.lib.mlmc_buckle_batch(self.h, n, arr, _ptr(offsets), offsets.shape[0], _ptr(lf), _ptr(lc), _ptr(info),
+                                               precision, tol, _stream(stream)))
+        return lf, lc, info_to_numpy(info)[:n]
+
+    # ------------------------------------------------------------ sums
+    def level_stats(self, level: int, q_fine, q_coarse=None, cost_per_sample: float = 0.0,
+                    lambda_star: float = math.nan, acc: Optional[LevelAcc] = None, stream=None) -> LevelAcc:
+        acc = LevelAcc() if acc is None else acc
+        self._check(self.lib.mlmc_level_stats(self.h, level, q_fine.shape[0], _ptr(q_fine), _ptr(q_coarse),
+                                              cost_per_sample, lambda_star, C.byref(acc), _stream(stream)))
+        return acc

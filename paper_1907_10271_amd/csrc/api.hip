@@ -1,0 +1,580 @@
+// C ABI of the MLMC sample-solve library: context, level hierarchy, device
+// pools and the host loop around the HIP kernels.  The declarations and their
+// contracts are in include/mlmc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "json.hpp"
+#include "kl_setup.hpp"
+#include "mlmc.h"
+#include "plate.hpp"
+#include "strip_kernels.hpp"
+
+using namespace mlmc;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct StripPool {
+  int cap = 0;
+  double *x = nullptr, *r = nullptr, *p = nullptr, *Ap = nullptr, *dinv = nullptr, *theta = nullptr;
+  double *part_pap = nullptr, *part_rz = nullptr, *part_rr = nullptr, *rzs = nullptr;
+  double *tol2 = nullptr, *bb = nullptr, *relres = nullptr, *qpart = nullptr;
+  int *it_a = nullptr, *it_b = nullptr, *status = nullptr, *active = nullptr, *outidx = nullptr;
+  int64_t *rows = nullptr;
+  size_t bytes = 0;
+};
+
+struct StripLevel {
+  StripGeom g{};
+  double *modes = nullptr;  // dev [4 nelem][K], sqrt(mu) folded in
+  StripPool pool;
+};
+
+}  // namespace
+
+struct mlmc_ctx {
+  std::string err;
+  Json cfg;
+  int kind = 0;  // 0 strip, 1 plate
+  int nlev = 0;
+  int K = 0;
+  StripMat mat{};
+  double rtol = 1e-10;
+  int max_iter = 100000;
+  std::vector<StripLevel> lv;
+  size_t budget = 0, used = 0;
+  int *h_active = nullptr;
+  int h_active_cap = 0;
+  double *d_stats = nullptr, *h_stats = nullptr;
+  PlateCtx *plate = nullptr;
+  int device = 0;
+};
+
+namespace {
+
+int fail(mlmc_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                        \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess)                                                                        \
+      return fail(ctx, MLMC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+StripGeom make_geom(const Json &cfg, int level) {
+  StripGeom g{};
+  g.nx = (int)cfg.number("nx0") << level;
+  g.ny = (int)cfg.number("ny0") << level;
+  g.nnx = g.nx + 1;
+  g.nny = g.ny + 1;
+  g.nnode = g.nnx * g.nny;
+  g.nelem = g.nx * g.ny;
+  g.tiles_x = (g.nnx + TILE_X - 1) / TILE_X;
+  g.tiles_y = (g.nny + TILE_Y - 1) / TILE_Y;
+  g.ntiles = g.tiles_x * g.tiles_y;
+  g.Lx = cfg.number("Lx");
+  g.Ly = cfg.number("Ly");
+  g.hx = g.Lx / g.nx;
+  g.hy = g.Ly / g.ny;
+  g.ihx = 1.0 / g.hx;
+  g.ihy = 1.0 / g.hy;
+  g.wdet = 0.25 * g.hx * g.hy;
+  g.delta = cfg.number("delta");
+  std::vector<double> reg = cfg.numbers("qoi_region");
+  if (reg.size() != 4) throw std::runtime_error("qoi_region needs 4 numbers");
+  // elements whose centroid (e + 1/2) h lies in [lo, hi]
+  g.qx0 = std::max(0, (int)std::ceil(reg[0] / g.hx - 0.5));
+  g.qx1 = std::min(g.nx, (int)std::floor(reg[1] / g.hx - 0.5) + 1);
+  g.qy0 = std::max(0, (int)std::ceil(reg[2] / g.hy - 0.5));
+  g.qy1 = std::min(g.ny, (int)std::floor(reg[3] / g.hy - 0.5) + 1);
+  if (g.qx1 <= g.qx0 || g.qy1 <= g.qy0) throw std::runtime_error("qoi_region holds no element centroid");
+  return g;
+}
+
+StripMat make_material(const Json &cfg) {
+  const Json &m = cfg.at("material");
+  const double E1 = m.number("E11"), E2 = m.number("E22"), G = m.number("G12"), nu12 = m.number("nu12");
+  const double nu21 = nu12 * E2 / E1, den = 1.0 - nu12 * nu21;
+  StripMat s{};
+  s.Q11 = E1 / den;
+  s.Q22 = E2 / den;
+  s.Q12 = nu12 * E2 / den;
+  s.Q66 = G;
+  s.U1 = (3 * s.Q11 + 3 * s.Q22 + 2 * s.Q12 + 4 * s.Q66) / 8;
+  s.U2 = (s.Q11 - s.Q22) / 2;
+  s.U3 = (s.Q11 + s.Q22 - 2 * s.Q12 - 4 * s.Q66) / 8;
+  s.U4 = (s.Q11 + s.Q22 + 6 * s.Q12 - 4 * s.Q66) / 8;
+  s.U5 = (s.Q11 + s.Q22 - 2 * s.Q12 + 4 * s.Q66) / 8;
+  return s;
+}
+
+size_t strip_slot_bytes(const StripGeom &g) {
+  const size_t vec = (size_t)2 * g.nnode * sizeof(double);
+  return 6 * vec                                      // x, r, p (2 buffers), Ap, dinv
+         + (size_t)4 * g.nelem * sizeof(double)       // theta
+         + (size_t)5 * g.ntiles * sizeof(double)      // partials
+         + (size_t)qoi_parts(g) * sizeof(double)      // QoI partial maxima
+         + 8 * sizeof(double) + 8 * sizeof(int) + sizeof(int64_t);
+}
+
+void free_pool(mlmc_ctx *c, StripPool &p) {
+  void *bufs[] = {p.x, p.r, p.p, p.Ap, p.dinv, p.theta, p.part_pap, p.part_rz, p.part_rr, p.rzs, p.tol2, p.bb,
+                  p.relres, p.qpart, p.it_a, p.it_b, p.status, p.active, p.outidx, p.rows};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  c->used -= p.bytes;
+  p = StripPool{};
+}
+
+template <class T>
+hipError_t dalloc(T **p, size_t n) {
+  return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+// make sure the pool of `level` holds at least n slots (n <= max fitting)
+int ensure_pool(mlmc_ctx *c, int level, int n) {
+  StripLevel &L = c->lv[level];
+  if (L.pool.cap >= n) return MLMC_OK;
+  free_pool(c, L.pool);
+  const StripGeom &g = L.g;
+  const size_t need = strip_slot_bytes(g) * (size_t)n;
+  if (c->used + need > c->budget)
+    return fail(c, MLMC_ENOMEM, "level " + std::to_string(level) + ": " + std::to_string(n) +
+                                     " slots exceed the memory budget");
+  StripPool &p = L.pool;
+  const size_t vec = (size_t)2 * g.nnode * n;
+  HIPCHK(c, dalloc(&p.x, vec));
+  HIPCHK(c, dalloc(&p.r, vec));
+  HIPCHK(c, dalloc(&p.p, 2 * vec));
+  HIPCHK(c, dalloc(&p.Ap, vec));
+  HIPCHK(c, dalloc(&p.dinv, vec));
+  HIPCHK(c, dalloc(&p.theta, (size_t)4 * g.nelem * n));
+  HIPCHK(c, dalloc(&p.part_pap, (size_t)g.ntiles * n));
+  HIPCHK(c, dalloc(&p.part_rz, (size_t)2 * g.ntiles * n));
+  HIPCHK(c, dalloc(&p.part_rr, (size_t)2 * g.ntiles * n));
+  HIPCHK(c, dalloc(&p.rzs, (size_t)2 * n));
+  HIPCHK(c, dalloc(&p.tol2, (size_t)n));
+  HIPCHK(c, dalloc(&p.bb, (size_t)n));
+  HIPCHK(c, dalloc(&p.relres, (size_t)n));
+  HIPCHK(c, dalloc(&p.qpart, (size_t)qoi_parts(g) * n));
+  HIPCHK(c, dalloc(&p.it_a, (size_t)n));
+  HIPCHK(c, dalloc(&p.it_b, (size_t)n));
+  HIPCHK(c, dalloc(&p.status, (size_t)n));
+  HIPCHK(c, dalloc(&p.active, (size_t)n));
+  HIPCHK(c, dalloc(&p.outidx, (size_t)n));
+  HIPCHK(c, dalloc(&p.rows, (size_t)n));
+  HIPCHK(c, hipMemset(p.active, 0, sizeof(int) * n));
+  p.cap = n;
+  p.bytes = need;
+  c->used += need;
+  if (c->h_active_cap < n) {
+    if (c->h_active) (void)hipHostFree(c->h_active);
+    HIPCHK(c, hipHostMalloc((void **)&c->h_active, sizeof(int) * n));
+    c->h_active_cap = n;
+  }
+  return MLMC_OK;
+}
+
+PcgSlots slots_of(mlmc_ctx *c, int level, const double *theta, double rtol) {
+  StripPool &p = c->lv[level].pool;
+  PcgSlots S{};
+  S.x = p.x;
+  S.r = p.r;
+  S.p = p.p;
+  S.Ap = p.Ap;
+  S.dinv = p.dinv;
+  S.theta = theta;
+  S.part_pap = p.part_pap;
+  S.part_rz = p.part_rz;
+  S.part_rr = p.part_rr;
+  S.rzs = p.rzs;
+  S.tol2 = p.tol2;
+  S.bb = p.bb;
+  S.relres = p.relres;
+  S.it_a = p.it_a;
+  S.it_b = p.it_b;
+  S.status = p.status;
+  S.active = p.active;
+  S.S = p.cap;
+  S.max_iter = c->max_iter;
+  S.rtol2 = rtol * rtol;
+  return S;
+}
+
+// largest batch of `level` that fits next to the other pools
+int max_slots(mlmc_ctx *c, int level) {
+  const size_t per = strip_slot_bytes(c->lv[level].g);
+  const size_t other = c->used - c->lv[level].pool.bytes;
+  if (c->budget <= other) return 0;
+  return (int)std::min<size_t>((c->budget - other) / per, 8192);
+}
+
+// run set-up + PCG to completion for n slots whose theta is ready
+int run_pcg(mlmc_ctx *c, int level, const PcgSlots &S, int n, hipStream_t st) {
+  const StripGeom &g = c->lv[level].g;
+  launch_setup(g, c->mat, S, n, nullptr, nullptr, st);
+  HIPCHK(c, hipGetLastError());
+  const int block = 32;
+  for (long it = 0;; it += block) {
+    for (int b = 0; b < block; ++b) launch_pcg_iteration(g, c->mat, S, n, st);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->h_active, S.active, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    bool any = false;
+    for (int k = 0; k < n; ++k) any |= c->h_active[k] != 0;
+    if (!any) break;
+    if (it > (long)c->max_iter + 4 * block) return fail(c, MLMC_EHIP, "PCG loop did not terminate");
+  }
+  return MLMC_OK;
+}
+
+int build_strip(mlmc_ctx *c) {
+  const Json &cfg = c->cfg;
+  c->nlev = (int)cfg.number("n_levels");
+  if (c->nlev < 1 || c->nlev > 12) throw std::runtime_error("n_levels out of range");
+  c->mat = make_material(cfg);
+  c->rtol = cfg.number_or("rtol", 1e-10);
+  c->max_iter = (int)cfg.number_or("max_iter", 100000);
+  const Json &kl = cfg.at("kl");
+  c->K = (int)kl.number("n_modes");
+  if (c->K < 1 || c->K > 32) throw std::runtime_error("n_modes must be in 1..32");
+  const double s = kl.number("sigma_deg") * M_PI / 180.0, var = s * s;
+  const std::string type = kl.string_or("type", "");
+  c->lv.resize(c->nlev);
+  for (int l = 0; l < c->nlev; ++l) c->lv[l].g = make_geom(cfg, l);
+  const int K = c->K;
+  if (type == "exp_separable") {
+    SeparableKL sk = separable_kl(cfg.number("Lx"), cfg.number("Ly"), var, kl.number("corr_x"),
+                                  kl.number("corr_y"), K);
+    for (int l = 0; l < c->nlev; ++l) {
+      StripGeom &g = c->lv[l].g;
+      const size_t ngp = (size_t)4 * g.nelem;
+      std::vector<double> tab(ngp * K);
+      for (size_t gp = 0; gp < ngp; ++gp) {
+        const size_t e = gp / 4;
+        const int q = (int)(gp % 4);
+        const double x = g.hx * ((double)(e % g.nx) + ((q & 1) ? GP_P : GP_M));
+        const double y = g.hy * ((double)(e / g.nx) + ((q & 2) ? GP_P : GP_M));
+        for (int k = 0; k < K; ++k)
+          tab[gp * K + k] = std::sqrt(sk.mu[k]) * sk.x.mode(sk.ix[k], x - sk.x.a) * sk.y.mode(sk.iy[k], y - sk.y.a);
+      }
+      HIPCHK(c, dalloc(&c->lv[l].modes, tab.size()));
+      HIPCHK(c, hipMemcpy(c->lv[l].modes, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+      c->used += tab.size() * sizeof(double);
+    }
+  } else if (type == "matern32") {
+    std::vector<double> nq = kl.numbers("nystrom");
+    if (nq.size() != 2) throw std::runtime_error("nystrom needs [nqx, nqy]");
+    const double len = kl.number("length");
+    MaternKL mk = matern_kl(cfg.number("Lx"), cfg.number("Ly"), var, len, (int)nq[0], (int)nq[1], K);
+    if (!(mk.max_residual < 1e-10)) throw std::runtime_error("Nystrom eigen-solve did not converge");
+    std::vector<double> coef((size_t)mk.n * K);
+    for (int j = 0; j < mk.n; ++j)
+      for (int k = 0; k < K; ++k) coef[(size_t)j * K + k] = mk.wq[j] * mk.phi[(size_t)j * K + k] / std::sqrt(mk.mu[k]);
+    double *dgx, *dgy, *dcoef;
+    HIPCHK(c, dalloc(&dgx, mk.n));
+    HIPCHK(c, dalloc(&dgy, mk.n));
+    HIPCHK(c, dalloc(&dcoef, coef.size()));
+    HIPCHK(c, hipMemcpy(dgx, mk.px.data(), mk.n * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(dgy, mk.py.data(), mk.n * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(dcoef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice));
+    for (int l = 0; l < c->nlev; ++l) {
+      StripGeom &g = c->lv[l].g;
+      const size_t ngp = (size_t)4 * g.nelem;
+      HIPCHK(c, dalloc(&c->lv[l].modes, ngp * K));
+      c->used += ngp * K * sizeof(double);
+      launch_modes_nystrom(dgx, dgy, dcoef, mk.n, K, var, std::sqrt(3.0) / len, g, c->lv[l].modes, nullptr);
+      HIPCHK(c, hipGetLastError());
+    }
+    HIPCHK(c, hipDeviceSynchronize());
+    (void)hipFree(dgx);
+    (void)hipFree(dgy);
+    (void)hipFree(dcoef);
+  } else {
+    throw std::runtime_error("unknown kl.type '" + type + "'");
+  }
+  return MLMC_OK;
+}
+
+bool bad_level(const mlmc_ctx *c, int level) { return level < 0 || level >= c->nlev; }
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int mlmc_create(const char *config_json, size_t mem_budget_bytes, mlmc_ctx **out) {
+  if (!out) { g_create_error = "out is NULL"; return MLMC_EINVAL; }
+  *out = nullptr;
+  if (!config_json) { g_create_error = "config_json is NULL"; return MLMC_EINVAL; }
+  mlmc_ctx *c = new mlmc_ctx();
+  int rc = MLMC_OK;
+  try {
+    c->cfg = parse_json(config_json);
+    const std::string kind = c->cfg.string_or("kind", "");
+    if (hipGetDevice(&c->device) != hipSuccess) throw std::runtime_error("no HIP device");
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) throw std::runtime_error("hipMemGetInfo failed");
+    c->budget = mem_budget_bytes ? mem_budget_bytes : (size_t)(0.9 * (double)fr);
+    if (hipMalloc((void **)&c->d_stats, 16 * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_stats, 16 * sizeof(double)) != hipSuccess)
+      throw std::runtime_error("allocation of the stats buffers failed");
+    if (kind == "strip") {
+      c->kind = 0;
+      rc = build_strip(c);
+    } else if (kind == "plate") {
+      c->kind = 1;
+      c->plate = plate_create(c->cfg, c->err);
+      if (!c->plate) rc = MLMC_EINVAL;
+      else c->nlev = plate_num_levels(c->plate);
+    } else {
+      throw std::runtime_error("config 'kind' must be \"strip\" or \"plate\"");
+    }
+  } catch (const std::exception &e) {
+    c->err = e.what();
+    rc = MLMC_EINVAL;
+  }
+  if (rc != MLMC_OK) {
+    g_create_error = c->err;
+    mlmc_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return MLMC_OK;
+}
+
+void mlmc_destroy(mlmc_ctx *c) {
+  if (!c) return;
+  for (auto &L : c->lv) {
+    free_pool(c, L.pool);
+    if (L.modes) (void)hipFree(L.modes);
+  }
+  if (c->h_active) (void)hipHostFree(c->h_active);
+  if (c->d_stats) (void)hipFree(c->d_stats);
+  if (c->h_stats) (void)hipHostFree(c->h_stats);
+  if (c->plate) plate_destroy(c->plate);
+  delete c;
+}
+
+const char *mlmc_last_error(const mlmc_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int mlmc_num_levels(const mlmc_ctx *c) { return c ? c->nlev : MLMC_EINVAL; }
+
+int mlmc_level_info(const mlmc_ctx *c, int level, int64_t *n_nodes, int64_t *n_dofs, int64_t *n_elem,
+                    int64_t *n_gp) {
+  if (!c) return MLMC_EINVAL;
+  if (bad_level(c, level)) return fail(const_cast<mlmc_ctx *>(c), MLMC_EINVAL, "level out of range");
+  int64_t nn, nd, ne, ng;
+  if (c->kind == 0) {
+    const StripGeom &g = c->lv[level].g;
+    nn = g.nnode;
+    nd = 2 * (int64_t)g.nnode;
+    ne = g.nelem;
+    ng = 4 * (int64_t)g.nelem;
+  } else {
+    plate_level_sizes(c->plate, level, &nn, &nd, &ne);
+    ng = 4 * ne;
+  }
+  if (n_nodes) *n_nodes = nn;
+  if (n_dofs) *n_dofs = nd;
+  if (n_elem) *n_elem = ne;
+  if (n_gp) *n_gp = ng;
+  return MLMC_OK;
+}
+
+int mlmc_footprint(const mlmc_ctx *c, int kind, int level, int precision, size_t *bytes) {
+  if (!c || !bytes) return MLMC_EINVAL;
+  mlmc_ctx *m = const_cast<mlmc_ctx *>(c);
+  if (kind != c->kind) return fail(m, MLMC_ESTATE, "kind does not match the context's model");
+  if (bad_level(c, level)) return fail(m, MLMC_EINVAL, "level out of range");
+  if (precision != MLMC_FP64 && precision != MLMC_MIXED) return fail(m, MLMC_EINVAL, "bad precision");
+  *bytes = (kind == 0) ? strip_slot_bytes(c->lv[level].g) : plate_slot_bytes(c->plate, level, precision);
+  return MLMC_OK;
+}
+
+int mlmc_sample_field(mlmc_ctx *c, int level, int n, const double *xi, int ld_xi, void *theta, int dtype,
+                      void *stream) {
+  if (!c) return MLMC_EINVAL;
+  if (c->kind != 0) return fail(c, MLMC_ESTATE, "sample_field needs a strip context");
+  if (bad_level(c, level)) return fail(c, MLMC_EINVAL, "level out of range");
+  if (n < 0 || ld_xi < c->K + 3) return fail(c, MLMC_EINVAL, "n < 0 or ld_xi < n_modes + 3");
+  if (dtype != 0 && dtype != 1) return fail(c, MLMC_EINVAL, "dtype must be 0 (FP64) or 1 (BF16)");
+  if (n == 0) return MLMC_OK;
+  if (!xi || !theta) return fail(c, MLMC_EINVAL, "null pointer");
+  const StripGeom &g = c->lv[level].g;
+  launch_kl_synth(c->lv[level].modes, c->K, g, xi, ld_xi, nullptr, n, dtype == 0 ? (double *)theta : nullptr,
+                  dtype == 1 ? (uint16_t *)theta : nullptr, 4 * g.nelem, (hipStream_t)stream);
+  HIPCHK(c, hipGetLastError());
+  return MLMC_OK;
+}
+
+int mlmc_strip_apply(mlmc_ctx *c, int level, int n, const double *theta, const double *x, double *y, int raw,
+                     void *stream) {
+  if (!c) return MLMC_EINVAL;
+  if (c->kind != 0) return fail(c, MLMC_ESTATE, "strip_apply needs a strip context");
+  if (bad_level(c, level) || n < 0) return fail(c, MLMC_EINVAL, "level out of range or n < 0");
+  if (n == 0) return MLMC_OK;
+  if (!theta || !x || !y) return fail(c, MLMC_EINVAL, "null pointer");
+  if (n > 65535) return fail(c, MLMC_EINVAL, "n > 65535");
+  launch_apply(c->lv[level].g, c->mat, theta, x, y, raw, n, (hipStream_t)stream);
+  HIPCHK(c, hipGetLastError());
+  return MLMC_OK;
+}
+
+int mlmc_strip_rhs_diag(mlmc_ctx *c, int level, int n, const double *theta, double *b, double *dinv,
+                        void *stream) {
+  if (!c) return MLMC_EINVAL;
+  if (c->kind != 0) return fail(c, MLMC_ESTATE, "needs a strip context");
+  if (bad_level(c, level) || n < 0) return fail(c, MLMC_EINVAL, "level out of range or n < 0");
+  if (n == 0) return MLMC_OK;
+  if (!theta || !b || !dinv) return fail(c, MLMC_EINVAL, "null pointer");
+  if (n > max_slots(c, level)) return fail(c, MLMC_ENOMEM, "batch exceeds the memory budget");
+  int rc = ensure_pool(c, level, n);
+  if (rc) return rc;
+  PcgSlots S = slots_of(c, level, theta, c->rtol);
+  launch_setup(c->lv[level].g, c->mat, S, n, b, dinv, (hipStream_t)stream);
+  HIPCHK(c, hipGetLastError());
+  return MLMC_OK;
+}
+
+int mlmc_strip_solve_theta(mlmc_ctx *c, int level, int n, const double *theta, double *q, double *d,
+                           mlmc_info *info, int precision, double rtol, void *stream) {
+  if (!c) return MLMC_EINVAL;
+  if (c->kind != 0) return fail(c, MLMC_ESTATE, "needs a strip context");
+  if (bad_level(c, level) || n < 0) return fail(c, MLMC_EINVAL, "level out of range or n < 0");
+  if (precision != MLMC_FP64 && precision != MLMC_MIXED) return fail(c, MLMC_EINVAL, "bad precision");
+  if (n == 0) return MLMC_OK;
+  if (!theta || !q) return fail(c, MLMC_EINVAL, "null pointer");
+  if (precision == MLMC_MIXED) return fail(c, MLMC_EINVAL, "mixed precision is not built for strip_solve_theta");
+  const int cap = max_slots(c, level);
+  if (n > cap) return fail(c, MLMC_ENOMEM, "batch exceeds the memory budget");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = ensure_pool(c, level, n);
+  if (rc) return rc;
+  if (info) launch_info_init(info, nullptr, n, st);
+  PcgSlots S = slots_of(c, level, theta, rtol > 0 ? rtol : c->rtol);
+  rc = run_pcg(c, level, S, n, st);
+  if (rc) return rc;
+  launch_qoi(c->lv[level].g, c->mat, S, n, c->lv[level].pool.qpart, nullptr, q, info, 0, st);
+  if (d) launch_total_disp(c->lv[level].g, S.x, d, n, st);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(st));
+  return MLMC_OK;
+}
+
+int mlmc_solve_batch(mlmc_ctx *c, int n_req, const mlmc_request *req, const double *xi, int64_t n_rows, int ld_xi,
+                     double *q_fine, double *q_coarse, mlmc_info *info, int precision, double rtol, void *stream) {
+  if (!c) return MLMC_EINVAL;
+  if (c->kind != 0) return fail(c, MLMC_ESTATE, "solve_batch needs a strip context");
+  if (n_req < 0) return fail(c, MLMC_EINVAL, "n_req < 0");
+  if (n_req == 0) return MLMC_OK;
+  if (!req || !xi || !q_fine || !q_coarse || !info) return fail(c, MLMC_EINVAL, "null pointer");
+  if (ld_xi < c->K + 3) return fail(c, MLMC_EINVAL, "ld_xi < n_modes + 3");
+  if (precision != MLMC_FP64 && precision != MLMC_MIXED) return fail(c, MLMC_EINVAL, "bad precision");
+  if (precision == MLMC_MIXED) return fail(c, MLMC_EINVAL, "mixed precision is not built yet");
+  for (int i = 0; i < n_req; ++i) {
+    if (bad_level(c, req[i].level)) return fail(c, MLMC_EINVAL, "request " + std::to_string(i) + ": bad level");
+    if (req[i].sample < 0 || req[i].sample >= n_rows)
+      return fail(c, MLMC_EINVAL, "request " + std::to_string(i) + ": sample row outside [0, n_rows)");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const double rt = rtol > 0 ? rtol : c->rtol;
+  launch_info_init(info, q_coarse, n_req, st);
+  HIPCHK(c, hipGetLastError());
+  // jobs per level: (row, output index) for fine (coarse = 0) and coarse (1) solves
+  std::vector<std::vector<int64_t>> rows(c->nlev * 2);
+  std::vector<std::vector<int>> outs(c->nlev * 2);
+  for (int i = 0; i < n_req; ++i) {
+    const int l = req[i].level;
+    rows[2 * l].push_back(req[i].sample);
+    outs[2 * l].push_back(i);
+    if (req[i].coupled && l > 0) {
+      rows[2 * (l - 1) + 1].push_back(req[i].sample);
+      outs[2 * (l - 1) + 1].push_back(i);
+    }
+  }
+  for (int l = 0; l < c->nlev; ++l) {
+    for (int coarse = 0; coarse < 2; ++coarse) {
+      const auto &R = rows[2 * l + coarse];
+      const auto &O = outs[2 * l + coarse];
+      const int total = (int)R.size();
+      if (!total) continue;
+      const int cap = std::min(max_slots(c, l), total);
+      if (cap < 1) return fail(c, MLMC_ENOMEM, "level " + std::to_string(l) + ": no slot fits the budget");
+      int rc = ensure_pool(c, l, cap);
+      if (rc) return rc;
+      StripLevel &L = c->lv[l];
+      for (int off = 0; off < total; off += cap) {
+        const int n = std::min(cap, total - off);
+        HIPCHK(c, hipMemcpyAsync(L.pool.rows, R.data() + off, sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(L.pool.outidx, O.data() + off, sizeof(int) * n, hipMemcpyHostToDevice, st));
+        launch_kl_synth(L.modes, c->K, L.g, xi, ld_xi, L.pool.rows, n, L.pool.theta, nullptr, 4 * L.g.nelem, st);
+        PcgSlots S = slots_of(c, l, L.pool.theta, rt);
+        rc = run_pcg(c, l, S, n, st);
+        if (rc) return rc;
+        launch_qoi(L.g, c->mat, S, n, L.pool.qpart, L.pool.outidx, coarse ? q_coarse : q_fine, info, coarse, st);
+        HIPCHK(c, hipGetLastError());
+        // the row/index buffers are reused by the next chunk
+        HIPCHK(c, hipStreamSynchronize(st));
+      }
+    }
+  }
+  HIPCHK(c, hipStreamSynchronize(st));
+  return MLMC_OK;
+}
+
+int mlmc_buckle_batch(mlmc_ctx *c, int n_req, const mlmc_request *req, const double *ply_offsets, int64_t n_rows,
+                      double *lam_fine, double *lam_coarse, mlmc_info *info, int precision, double tol,
+                      void *stream) {
+  if (!c) return MLMC_EINVAL;
+  if (c->kind != 1) return fail(c, MLMC_ESTATE, "buckle_batch needs a plate context");
+  return plate_buckle_batch(c->plate, c->err, n_req, req, ply_offsets, n_rows, lam_fine, lam_coarse, info,
+                            precision, tol, (hipStream_t)stream);
+}
+
+int mlmc_level_stats(mlmc_ctx *c, int level, int n, const double *q_fine, const double *q_coarse,
+                     double cost_per_sample, double lambda_star, mlmc_level_acc *acc, void *stream) {
+  if (!c) return MLMC_EINVAL;
+  if (bad_level(c, level) || n < 0) return fail(c, MLMC_EINVAL, "level out of range or n < 0");
+  if (!acc) return fail(c, MLMC_EINVAL, "acc is NULL");
+  if (n == 0) return MLMC_OK;
+  if (!q_fine) return fail(c, MLMC_EINVAL, "q_fine is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  const int ind = std::isnan(lambda_star) ? 0 : 1;
+  launch_level_stats(q_fine, q_coarse, n, lambda_star, ind, c->d_stats, st);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(c->h_stats, c->d_stats, 10 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  const double *o = c->h_stats;
+  auto add = [](double &s, double &cp, double v, double vc) {
+    const double t = s + v;
+    if (std::fabs(s) >= std::fabs(v)) cp += (s - t) + v;
+    else cp += (v - t) + s;
+    s = t;
+    cp += vc;
+  };
+  add(acc->sum_y, acc->comp_y, o[0], o[1]);
+  add(acc->sum_y2, acc->comp_y2, o[2], o[3]);
+  add(acc->sum_qf, acc->comp_qf, o[4], o[5]);
+  add(acc->sum_qc, acc->comp_qc, o[6], o[7]);
+  acc->n += n;
+  acc->n_plus += (int64_t)o[8];
+  acc->n_minus += (int64_t)o[9];
+  acc->sum_cost += cost_per_sample * n;
+  return MLMC_OK;
+}
+
+}  // extern "C"

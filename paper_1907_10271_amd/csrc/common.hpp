@@ -1,0 +1,61 @@
+// Shared host/device definitions of the MLMC library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mlmc {
+
+// node tile of the strip operator: owned nodes per work-group
+constexpr int TILE_X = 32;
+constexpr int TILE_Y = 8;
+constexpr int TILE_THREADS = TILE_X * TILE_Y;  // one owned node per thread
+constexpr int HALO_X = TILE_X + 2;             // nodes incl. one-node halo
+constexpr int HALO_Y = TILE_Y + 2;
+constexpr int ELEM_X = TILE_X + 1;             // elements touching the owned nodes
+constexpr int ELEM_Y = TILE_Y + 1;
+constexpr int TILE_NODES_H = HALO_X * HALO_Y;
+constexpr int TILE_ELEMS = ELEM_X * ELEM_Y;
+
+// 2x2 Gauss rule: the bilinear interpolation weights at +-1/sqrt(3) are
+// (1 + 1/sqrt3)/2 and (1 - 1/sqrt3)/2
+constexpr double GP_P = 0.78867513459481288225;
+constexpr double GP_M = 0.21132486540518711775;
+
+// geometry of one strip level (uniform rectangles hx x hy)
+struct StripGeom {
+  int nx, ny;        // elements per row / column
+  int nnx, nny;      // nodes per row / column
+  int nnode, nelem;
+  int tiles_x, tiles_y, ntiles;
+  int qx0, qx1, qy0, qy1;  // QoI element index ranges [q*0, q*1)
+  double hx, hy, ihx, ihy, wdet;  // wdet = Gauss weight x det J = hx hy / 4
+  double delta;                   // u = -delta on x = Lx
+  double Lx, Ly;
+};
+
+// rotation invariants of the ply stiffness: Qbar(theta) is linear in
+// cos 2theta, sin 2theta, cos 4theta, sin 4theta with these coefficients
+struct StripMat {
+  double U1, U2, U3, U4, U5;
+  double Q11, Q22, Q12, Q66;
+};
+
+// per-slot PCG state of a level pool (device pointers)
+struct PcgSlots {
+  double *x, *r, *p, *Ap, *dinv;   // [S][2 nnode]
+  const double *theta;             // [S][4 nelem]
+  double *part_pap;                // [S][ntiles]
+  double *part_rz, *part_rr;       // [2][S][ntiles]
+  double *rzs;                     // [2][S]
+  double *tol2, *bb, *relres;      // [S]
+  int *it_a, *it_b, *status, *active;  // [S]
+  int S;
+  int max_iter;
+  double rtol2;
+};
+
+enum SampleStatus { S_OK = 0, S_NOCONV = 1, S_NAN = 2, S_BREAKDOWN = 3, S_SKIPPED = 4 };
+
+}  // namespace mlmc

@@ -1,0 +1,154 @@
+// Device building blocks of the strip model (Section 3.1 of the paper):
+// rotated ply stiffness at a Gauss point and the bilinear element operator
+// with 2x2 Gauss quadrature, written for uniform rectangles.
+#pragma once
+
+#include "common.hpp"
+
+namespace mlmc {
+
+// rotated plane-stress stiffness at one Gauss point (global axes, engineering shear)
+struct Qb {
+  double q11, q22, q12, q66, q16, q26;
+};
+
+// Qbar(theta) from the rotation invariants: the fibre axes are turned by +theta
+// from x; entries are linear in cos 2theta, sin 2theta, cos 4theta, sin 4theta.
+__device__ __forceinline__ Qb qbar_of(const StripMat &m, double th) {
+  double s2, c2;
+  sincos(2.0 * th, &s2, &c2);
+  const double c4 = 2.0 * c2 * c2 - 1.0;
+  const double s4 = 2.0 * s2 * c2;
+  Qb q;
+  q.q11 = m.U1 + m.U2 * c2 + m.U3 * c4;
+  q.q22 = m.U1 - m.U2 * c2 + m.U3 * c4;
+  q.q12 = m.U4 - m.U3 * c4;
+  q.q66 = m.U5 - m.U3 * c4;
+  const double h = 0.5 * m.U2 * s2;
+  q.q16 = h + m.U3 * s4;
+  q.q26 = h - m.U3 * s4;
+  return q;
+}
+
+// Element forces f = sum_q w_q detJ B_q^T Qbar_q B_q d_e for one bilinear
+// rectangle.  Nodes are numbered counter-clockwise from the lower-left
+// corner; Gauss point q has xi index (q & 1) and eta index (q >> 1), low = -1/sqrt3.
+//
+// With edge differences du_b = u1 - u0, du_t = u2 - u3, du_l = u3 - u0,
+// du_r = u2 - u1 the derivatives at the Gauss points are
+//   du/dx = (P du_b + M du_t)/hx at eta = -g,  (M du_b + P du_t)/hx at eta = +g,
+//   du/dy = (P du_l + M du_r)/hy at xi  = -g,  (M du_l + P du_r)/hy at xi  = +g,
+// (P, M the interpolation weights of the Gauss abscissae), so every
+// derivative is shared by two Gauss points; the transposed operator uses the
+// same pairs.
+__device__ __forceinline__ void elem_forces(const StripGeom &g, const Qb q[4], const double u[4],
+                                            const double v[4], double fu[4], double fv[4]) {
+  const double P = GP_P, M = GP_M;
+  const double dub = u[1] - u[0], dut = u[2] - u[3], dul = u[3] - u[0], dur = u[2] - u[1];
+  const double dvb = v[1] - v[0], dvt = v[2] - v[3], dvl = v[3] - v[0], dvr = v[2] - v[1];
+  const double uxL = (P * dub + M * dut) * g.ihx, uxH = (M * dub + P * dut) * g.ihx;
+  const double vxL = (P * dvb + M * dvt) * g.ihx, vxH = (M * dvb + P * dvt) * g.ihx;
+  const double uyL = (P * dul + M * dur) * g.ihy, uyH = (M * dul + P * dur) * g.ihy;
+  const double vyL = (P * dvl + M * dvr) * g.ihy, vyH = (M * dvl + P * dvr) * g.ihy;
+  double sxx[4], syy[4], txy[4];
+#define MLMC_GP_STRESS(Q, UX, VX, UY, VY)                                   \
+  {                                                                         \
+    const double ex = UX, ey = VY, gm = UY + VX;                            \
+    sxx[Q] = q[Q].q11 * ex + q[Q].q12 * ey + q[Q].q16 * gm;                 \
+    syy[Q] = q[Q].q12 * ex + q[Q].q22 * ey + q[Q].q26 * gm;                 \
+    txy[Q] = q[Q].q16 * ex + q[Q].q26 * ey + q[Q].q66 * gm;                 \
+  }
+  MLMC_GP_STRESS(0, uxL, vxL, uyL, vyL)
+  MLMC_GP_STRESS(1, uxL, vxL, uyH, vyH)
+  MLMC_GP_STRESS(2, uxH, vxH, uyL, vyL)
+  MLMC_GP_STRESS(3, uxH, vxH, uyH, vyH)
+#undef MLMC_GP_STRESS
+  const double w = g.wdet;
+  const double axL = (sxx[0] + sxx[1]) * w, axH = (sxx[2] + sxx[3]) * w;
+  const double atyL = (txy[0] + txy[2]) * w, atyH = (txy[1] + txy[3]) * w;
+  const double ayL = (syy[0] + syy[2]) * w, ayH = (syy[1] + syy[3]) * w;
+  const double atxL = (txy[0] + txy[1]) * w, atxH = (txy[2] + txy[3]) * w;
+  const double gub = (P * axL + M * axH) * g.ihx, gut = (M * axL + P * axH) * g.ihx;
+  const double gul = (P * atyL + M * atyH) * g.ihy, gur = (M * atyL + P * atyH) * g.ihy;
+  const double gvl = (P * ayL + M * ayH) * g.ihy, gvr = (M * ayL + P * ayH) * g.ihy;
+  const double gvb = (P * atxL + M * atxH) * g.ihx, gvt = (M * atxL + P * atxH) * g.ihx;
+  fu[0] = -gub - gul;
+  fu[1] = gub - gur;
+  fu[2] = gut + gur;
+  fu[3] = -gut + gul;
+  fv[0] = -gvb - gvl;
+  fv[1] = gvb - gvr;
+  fv[2] = gvt + gvr;
+  fv[3] = -gvt + gvl;
+}
+
+// largest compressive stress along the fibres at the four Gauss points:
+// sigma_11 = cos^2 sxx + sin^2 syy + 2 sin cos txy, written with cos 2theta, sin 2theta
+__device__ __forceinline__ double elem_max_fibre_compression(const StripGeom &g, const StripMat &m,
+                                                             const double th[4], const double u[4],
+                                                             const double v[4]) {
+  const double P = GP_P, M = GP_M;
+  const double dub = u[1] - u[0], dut = u[2] - u[3], dul = u[3] - u[0], dur = u[2] - u[1];
+  const double dvb = v[1] - v[0], dvt = v[2] - v[3], dvl = v[3] - v[0], dvr = v[2] - v[1];
+  const double ux[2] = {(P * dub + M * dut) * g.ihx, (M * dub + P * dut) * g.ihx};
+  const double vx[2] = {(P * dvb + M * dvt) * g.ihx, (M * dvb + P * dvt) * g.ihx};
+  const double uy[2] = {(P * dul + M * dur) * g.ihy, (M * dul + P * dur) * g.ihy};
+  const double vy[2] = {(P * dvl + M * dvr) * g.ihy, (M * dvl + P * dvr) * g.ihy};
+  double best = -1.0 / 0.0;
+  for (int q = 0; q < 4; ++q) {
+    const int a = q & 1, b = q >> 1;
+    double s2, c2;
+    sincos(2.0 * th[q], &s2, &c2);
+    const double c4 = 2.0 * c2 * c2 - 1.0, s4 = 2.0 * s2 * c2;
+    const double q11 = m.U1 + m.U2 * c2 + m.U3 * c4, q22 = m.U1 - m.U2 * c2 + m.U3 * c4;
+    const double q12 = m.U4 - m.U3 * c4, q66 = m.U5 - m.U3 * c4;
+    const double q16 = 0.5 * m.U2 * s2 + m.U3 * s4, q26 = 0.5 * m.U2 * s2 - m.U3 * s4;
+    const double ex = ux[b], ey = vy[a], gm = uy[a] + vx[b];
+    const double sxx = q11 * ex + q12 * ey + q16 * gm;
+    const double syy = q12 * ex + q22 * ey + q26 * gm;
+    const double txy = q16 * ex + q26 * ey + q66 * gm;
+    const double s11 = 0.5 * ((1.0 + c2) * sxx + (1.0 - c2) * syy) + s2 * txy;
+    best = fmax(best, -s11);
+  }
+  return best;
+}
+
+// ---------------------------------------------------------------- reductions
+// Fixed-order work-group sum (256 threads): butterfly within each wave of 64,
+// then the four wave sums in order.  Every thread returns the total.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double *red4) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red4[wid] = v;
+  __syncthreads();
+  return ((red4[0] + red4[1]) + red4[2]) + red4[3];
+}
+
+// sum of n values in fixed order: thread t adds entries t, t+256, ... then block_sum
+__device__ __forceinline__ double block_sum_strided(const double *a, int n, double *red4) {
+  double s = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) s += a[k];
+  return block_sum(s, red4);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ double block_max(double v, double *red4) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red4[wid] = v;
+  __syncthreads();
+  return fmax(fmax(red4[0], red4[1]), fmax(red4[2], red4[3]));
+}
+
+}  // namespace mlmc

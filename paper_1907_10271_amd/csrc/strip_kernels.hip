@@ -1,0 +1,600 @@
+// HIP kernels of the strip sample solve (Section 3.1 of the paper):
+// KL synthesis of the angle field, Dirichlet lifting and Jacobi diagonal,
+// the two fused passes of batched Jacobi-PCG, the fibre-stress QoI and the
+// FP64 level sums (Section 2.3).
+//
+// Work decomposition: a work-group owns a TILE_X x TILE_Y block of nodes of
+// one sample (blockIdx.x = tile, blockIdx.y = slot).  It recomputes the
+// elements touching its nodes (one-element halo), stages their nodal forces
+// in LDS and gathers each owned node's four element contributions in a fixed
+// order, so every result is independent of the batch it runs in and
+// bit-reproducible.  Dot products use fixed-order wave butterflies and a
+// fixed-order sum over tiles.
+#include "strip_kernels.hpp"
+#include "strip_device.hpp"
+
+#include <cmath>
+
+namespace mlmc {
+
+namespace {
+
+struct TileCoord {
+  int i0, j0;
+};
+
+__device__ __forceinline__ TileCoord tile_of(const StripGeom &g, int t) {
+  return {(t % g.tiles_x) * TILE_X, (t / g.tiles_x) * TILE_Y};
+}
+
+__device__ __forceinline__ bool node_in(const StripGeom &g, int i, int j) {
+  return i >= 0 && i < g.nnx && j >= 0 && j < g.nny;
+}
+
+__device__ __forceinline__ bool elem_in(const StripGeom &g, int ex, int ey) {
+  return ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny;
+}
+
+// element phase shared by the operator kernels: nodal values are in LDS
+// (halo layout), element forces go to eo[8][TILE_ELEMS]
+__device__ __forceinline__ void tile_elements(const StripGeom &g, const StripMat &m, const double *theta_s,
+                                              TileCoord tc, const double *nu, const double *nv,
+                                              double (*eo)[TILE_ELEMS]) {
+  for (int k = threadIdx.x; k < TILE_ELEMS; k += TILE_THREADS) {
+    const int lex = k % ELEM_X, ley = k / ELEM_X;
+    const int ex = tc.i0 - 1 + lex, ey = tc.j0 - 1 + ley;
+    double fu[4] = {0.0, 0.0, 0.0, 0.0}, fv[4] = {0.0, 0.0, 0.0, 0.0};
+    if (elem_in(g, ex, ey)) {
+      const double *tp = theta_s + 4 * ((size_t)ey * g.nx + ex);
+      const double2 t01 = *reinterpret_cast<const double2 *>(tp);
+      const double2 t23 = *reinterpret_cast<const double2 *>(tp + 2);
+      Qb q[4] = {qbar_of(m, t01.x), qbar_of(m, t01.y), qbar_of(m, t23.x), qbar_of(m, t23.y)};
+      const int n0 = ley * HALO_X + lex;
+      const double u[4] = {nu[n0], nu[n0 + 1], nu[n0 + HALO_X + 1], nu[n0 + HALO_X]};
+      const double v[4] = {nv[n0], nv[n0 + 1], nv[n0 + HALO_X + 1], nv[n0 + HALO_X]};
+      elem_forces(g, q, u, v, fu, fv);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      eo[c][k] = fu[c];
+      eo[4 + c][k] = fv[c];
+    }
+  }
+}
+
+// sum of the four element contributions of owned node (li, lj), fixed order
+__device__ __forceinline__ void gather_node(const double (*eo)[TILE_ELEMS], int li, int lj, int cu,
+                                            double &yu, double &yv) {
+  const int e = lj * ELEM_X + li;
+  // element (i-1, j-1): node 2; (i, j-1): node 3; (i-1, j): node 1; (i, j): node 0
+  yu = ((eo[cu + 2][e] + eo[cu + 3][e + 1]) + eo[cu + 1][e + ELEM_X]) + eo[cu + 0][e + ELEM_X + 1];
+  yv = ((eo[cu + 6][e] + eo[cu + 7][e + 1]) + eo[cu + 5][e + ELEM_X]) + eo[cu + 4][e + ELEM_X + 1];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- KL synthesis
+// theta[s][gp] = sum_k modes[gp][k] xi[row_s][k] + A sech^2((x_gp - x0)/w)
+// (modes pre-multiplied by sqrt(mu_k)); one thread per Gauss point, a group of
+// SYN_SAMPLES samples per block so the mode row is read once per group.
+constexpr int SYN_SAMPLES = 8;
+constexpr int MAX_MODES = 32;
+
+__global__ __launch_bounds__(256) void k_kl_synth(const double *__restrict__ modes, int K, StripGeom g,
+                                                  const double *__restrict__ xi, int ld_xi,
+                                                  const int64_t *__restrict__ rows, int n,
+                                                  double *__restrict__ th64, uint16_t *__restrict__ th16,
+                                                  int ld_out) {
+  const int ngp = 4 * g.nelem;
+  const int gp = blockIdx.x * 256 + threadIdx.x;
+  if (gp >= ngp) return;
+  double mk[MAX_MODES];
+#pragma unroll
+  for (int k = 0; k < MAX_MODES; ++k) mk[k] = (k < K) ? modes[(size_t)gp * K + k] : 0.0;
+  const int e = gp >> 2, q = gp & 3;
+  const double x = g.hx * ((e % g.nx) + ((q & 1) ? GP_P : GP_M));
+  const int s0 = blockIdx.y * SYN_SAMPLES;
+  for (int si = 0; si < SYN_SAMPLES; ++si) {
+    const int s = s0 + si;
+    if (s >= n) break;
+    const int64_t row = rows ? rows[s] : s;
+    const double *xr = xi + (size_t)row * ld_xi;
+    double th = 0.0;
+#pragma unroll
+    for (int k = 0; k < MAX_MODES; ++k)
+      if (k < K) th = fma(mk[k], xr[k], th);
+    const double A = xr[K];
+    if (A != 0.0) {
+      const double c = cosh((x - xr[K + 1]) / xr[K + 2]);
+      th += A / (c * c);
+    }
+    if (th64) th64[(size_t)s * ld_out + gp] = th;
+    if (th16) {
+      // round to float, then to bfloat16 with round-to-nearest-even
+      const float f = (float)th;
+      uint32_t b = __float_as_uint(f);
+      b += 0x7FFFu + ((b >> 16) & 1u);
+      th16[(size_t)s * ld_out + gp] = (uint16_t)(b >> 16);
+    }
+  }
+}
+
+// Nystrom interpolation of the Matern eigenfunctions at every Gauss point:
+// modes[gp][k] = sum_j k(x_gp, x_j) coef[j][k], coef = w_j phi_k(x_j) / sqrt(mu_k)
+__global__ __launch_bounds__(256) void k_modes_nystrom(const double *__restrict__ gx, const double *__restrict__ gy,
+                                                       const double *__restrict__ coef, int ngrid, int K,
+                                                       double var, double kappa, StripGeom g,
+                                                       double *__restrict__ modes) {
+  const int ngp = 4 * g.nelem;
+  const int gp = blockIdx.x * 256 + threadIdx.x;
+  if (gp >= ngp) return;
+  const int e = gp >> 2, q = gp & 3;
+  const double x = g.hx * ((e % g.nx) + ((q & 1) ? GP_P : GP_M));
+  const double y = g.hy * ((e / g.nx) + ((q & 2) ? GP_P : GP_M));
+  double acc[MAX_MODES];
+#pragma unroll
+  for (int k = 0; k < MAX_MODES; ++k) acc[k] = 0.0;
+  for (int j = 0; j < ngrid; ++j) {
+    const double dx = x - gx[j], dy = y - gy[j];
+    const double z = kappa * sqrt(dx * dx + dy * dy);
+    const double kv = var * (1.0 + z) * exp(-z);
+    const double *c = coef + (size_t)j * K;
+#pragma unroll
+    for (int k = 0; k < MAX_MODES; ++k)
+      if (k < K) acc[k] = fma(kv, c[k], acc[k]);
+  }
+  for (int k = 0; k < K; ++k) modes[(size_t)gp * K + k] = acc[k];
+}
+
+// ---------------------------------------------------------------- operator
+// y = P K P x + (I - P) x  (or y = K x when raw): test/diagnostic entry point
+__global__ __launch_bounds__(TILE_THREADS) void k_apply(StripGeom g, StripMat m, const double *__restrict__ theta,
+                                                        const double *__restrict__ x, double *__restrict__ y,
+                                                        int raw) {
+  __shared__ double nu[TILE_NODES_H], nv[TILE_NODES_H];
+  __shared__ double eo[8][TILE_ELEMS];
+  const int s = blockIdx.y;
+  const TileCoord tc = tile_of(g, blockIdx.x);
+  const size_t vb = (size_t)s * 2 * g.nnode;
+  for (int k = threadIdx.x; k < TILE_NODES_H; k += TILE_THREADS) {
+    const int i = tc.i0 - 1 + k % HALO_X, j = tc.j0 - 1 + k / HALO_X;
+    double a = 0.0, b = 0.0;
+    if (node_in(g, i, j)) {
+      const double2 xv = *reinterpret_cast<const double2 *>(x + vb + 2 * ((size_t)j * g.nnx + i));
+      a = xv.x;
+      b = xv.y;
+      if (!raw) {
+        if (i == 0) { a = 0.0; b = 0.0; }
+        if (i == g.nx) a = 0.0;
+      }
+    }
+    nu[k] = a;
+    nv[k] = b;
+  }
+  __syncthreads();
+  tile_elements(g, m, theta + (size_t)s * 4 * g.nelem, tc, nu, nv, eo);
+  __syncthreads();
+  const int li = threadIdx.x % TILE_X, lj = threadIdx.x / TILE_X;
+  const int i = tc.i0 + li, j = tc.j0 + lj;
+  if (i < g.nnx && j < g.nny) {
+    double yu, yv;
+    gather_node(eo, li, lj, 0, yu, yv);
+    const size_t o = vb + 2 * ((size_t)j * g.nnx + i);
+    if (!raw) {
+      const double2 xv = *reinterpret_cast<const double2 *>(x + o);
+      if (i == 0) { yu = xv.x; yv = xv.y; }
+      if (i == g.nx) yu = xv.x;
+    }
+    *reinterpret_cast<double2 *>(y + o) = make_double2(yu, yv);
+  }
+}
+
+// ---------------------------------------------------------------- PCG set-up
+// b = -P K g and dinv = 1/diag(P K P + I - P); x = 0, r = b; partial sums of
+// r.z and r.r into parity buffer 0; slot marked active at iteration 0.
+__global__ __launch_bounds__(TILE_THREADS) void k_setup(StripGeom g, StripMat m, PcgSlots S,
+                                                        double *__restrict__ b_out, double *__restrict__ dinv_out) {
+  __shared__ double eo[16][TILE_ELEMS];
+  __shared__ double red4[4];
+  const int s = blockIdx.y, t = blockIdx.x;
+  const TileCoord tc = tile_of(g, t);
+  const double *theta_s = S.theta + (size_t)s * 4 * g.nelem;
+  for (int k = threadIdx.x; k < TILE_ELEMS; k += TILE_THREADS) {
+    const int lex = k % ELEM_X, ley = k / ELEM_X;
+    const int ex = tc.i0 - 1 + lex, ey = tc.j0 - 1 + ley;
+    double du[4] = {0, 0, 0, 0}, dv[4] = {0, 0, 0, 0}, gu[4] = {0, 0, 0, 0}, gv[4] = {0, 0, 0, 0};
+    if (elem_in(g, ex, ey)) {
+      const double *tp = theta_s + 4 * ((size_t)ey * g.nx + ex);
+      Qb q[4] = {qbar_of(m, tp[0]), qbar_of(m, tp[1]), qbar_of(m, tp[2]), qbar_of(m, tp[3])};
+      // diagonal entries: the element operator applied to unit vectors
+      for (int a = 0; a < 4; ++a) {
+        double u[4] = {0, 0, 0, 0}, v[4] = {0, 0, 0, 0}, fu[4], fv[4];
+        u[a] = 1.0;
+        elem_forces(g, q, u, v, fu, fv);
+        du[a] = fu[a];
+        u[a] = 0.0;
+        v[a] = 1.0;
+        elem_forces(g, q, u, v, fu, fv);
+        dv[a] = fv[a];
+      }
+      // K g on elements touching the loaded edge (nodes 1 and 2 at x = Lx)
+      if (ex == g.nx - 1) {
+        const double u[4] = {0.0, -g.delta, -g.delta, 0.0}, v[4] = {0, 0, 0, 0};
+        elem_forces(g, q, u, v, gu, gv);
+      }
+    }
+    for (int c = 0; c < 4; ++c) {
+      eo[c][k] = du[c];
+      eo[4 + c][k] = dv[c];
+      eo[8 + c][k] = gu[c];
+      eo[12 + c][k] = gv[c];
+    }
+  }
+  __syncthreads();
+  const int li = threadIdx.x % TILE_X, lj = threadIdx.x / TILE_X;
+  const int i = tc.i0 + li, j = tc.j0 + lj;
+  double prz = 0.0, prr = 0.0;
+  if (i < g.nnx && j < g.nny) {
+    double diu, div, kgu, kgv;
+    gather_node(eo, li, lj, 0, diu, div);
+    gather_node(eo, li, lj, 8, kgu, kgv);
+    double bu = -kgu, bv = -kgv, du = 1.0 / diu, dv = 1.0 / div;
+    if (i == 0) { bu = 0.0; bv = 0.0; du = 1.0; dv = 1.0; }
+    if (i == g.nx) { bu = 0.0; du = 1.0; }
+    const size_t o = (size_t)s * 2 * g.nnode + 2 * ((size_t)j * g.nnx + i);
+    *reinterpret_cast<double2 *>(S.dinv + o) = make_double2(du, dv);
+    *reinterpret_cast<double2 *>(S.r + o) = make_double2(bu, bv);
+    *reinterpret_cast<double2 *>(S.x + o) = make_double2(0.0, 0.0);
+    if (b_out) *reinterpret_cast<double2 *>(b_out + o) = make_double2(bu, bv);
+    if (dinv_out) *reinterpret_cast<double2 *>(dinv_out + o) = make_double2(du, dv);
+    prz = bu * (du * bu) + bv * (dv * bv);
+    prr = bu * bu + bv * bv;
+  }
+  prz = block_sum(prz, red4);
+  prr = block_sum(prr, red4);
+  if (threadIdx.x == 0) {
+    S.part_rz[(size_t)s * g.ntiles + t] = prz;
+    S.part_rr[(size_t)s * g.ntiles + t] = prr;
+    if (t == 0) {
+      S.it_a[s] = 0;
+      S.status[s] = S_OK;
+      S.active[s] = 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- PCG pass 1
+// Convergence test on the reduced r.r, beta = rz_k / rz_{k-1},
+// p_k = z_k + beta p_{k-1} on the tile and its halo, Ap = A p_k on the owned
+// nodes, partial p.Ap.  p is double-buffered by iteration parity because
+// neighbouring tiles read p_{k-1} in their halos while this one writes p_k.
+__global__ __launch_bounds__(TILE_THREADS) void k_pass1(StripGeom g, StripMat m, PcgSlots S) {
+  __shared__ double nu[TILE_NODES_H], nv[TILE_NODES_H];
+  __shared__ double eo[8][TILE_ELEMS];
+  __shared__ double red4[4];
+  __shared__ int flag;
+  const int s = blockIdx.y, t = blockIdx.x;
+  // one read of the slot flag per block: tile 0 of this launch may clear it concurrently
+  if (threadIdx.x == 0) flag = S.active[s];
+  __syncthreads();
+  if (!flag) return;
+  const int it = S.it_a[s], par = it & 1;
+  const size_t pb = ((size_t)par * S.S + s) * g.ntiles;
+  const double rz = block_sum_strided(S.part_rz + pb, g.ntiles, red4);
+  const double rr = block_sum_strided(S.part_rr + pb, g.ntiles, red4);
+  const double bb = (it == 0) ? rr : S.bb[s];
+  const double tol2 = S.rtol2 * bb;
+  int verdict = -1;
+  if (!isfinite(rr) || !isfinite(rz)) verdict = S_NAN;
+  else if (rr <= tol2) verdict = S_OK;
+  else if (it >= S.max_iter) verdict = S_NOCONV;
+  if (t == 0 && threadIdx.x == 0) {
+    if (it == 0) S.bb[s] = rr;
+    S.rzs[(size_t)par * S.S + s] = rz;
+    S.relres[s] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    S.it_b[s] = it;
+    if (verdict >= 0) {
+      S.status[s] = verdict;
+      S.active[s] = 0;
+    }
+  }
+  if (verdict >= 0) return;
+  const double beta = (it == 0) ? 0.0 : rz / S.rzs[(size_t)(par ^ 1) * S.S + s];
+  const TileCoord tc = tile_of(g, t);
+  const size_t vb = (size_t)s * 2 * g.nnode;
+  const double *p_old = S.p + (size_t)par * S.S * 2 * g.nnode + vb;
+  double *p_new = S.p + (size_t)(par ^ 1) * S.S * 2 * g.nnode + vb;
+  for (int k = threadIdx.x; k < TILE_NODES_H; k += TILE_THREADS) {
+    const int i = tc.i0 - 1 + k % HALO_X, j = tc.j0 - 1 + k / HALO_X;
+    double a = 0.0, b = 0.0;
+    if (node_in(g, i, j)) {
+      const size_t o = 2 * ((size_t)j * g.nnx + i);
+      const double2 rv = *reinterpret_cast<const double2 *>(S.r + vb + o);
+      const double2 dv = *reinterpret_cast<const double2 *>(S.dinv + vb + o);
+      a = dv.x * rv.x;
+      b = dv.y * rv.y;
+      if (it > 0) {
+        const double2 po = *reinterpret_cast<const double2 *>(p_old + o);
+        a = fma(beta, po.x, a);
+        b = fma(beta, po.y, b);
+      }
+    }
+    nu[k] = a;
+    nv[k] = b;
+  }
+  __syncthreads();
+  tile_elements(g, m, S.theta + (size_t)s * 4 * g.nelem, tc, nu, nv, eo);
+  __syncthreads();
+  const int li = threadIdx.x % TILE_X, lj = threadIdx.x / TILE_X;
+  const int i = tc.i0 + li, j = tc.j0 + lj;
+  double part = 0.0;
+  if (i < g.nnx && j < g.nny) {
+    double yu, yv;
+    gather_node(eo, li, lj, 0, yu, yv);
+    const int h = (lj + 1) * HALO_X + li + 1;
+    const double pu = nu[h], pv = nv[h];
+    if (i == 0) { yu = pu; yv = pv; }
+    if (i == g.nx) yu = pu;
+    const size_t o = 2 * ((size_t)j * g.nnx + i);
+    *reinterpret_cast<double2 *>(p_new + o) = make_double2(pu, pv);
+    *reinterpret_cast<double2 *>(S.Ap + vb + o) = make_double2(yu, yv);
+    part = pu * yu + pv * yv;
+  }
+  part = block_sum(part, red4);
+  if (threadIdx.x == 0) S.part_pap[(size_t)s * g.ntiles + t] = part;
+}
+
+// ---------------------------------------------------------------- PCG pass 2
+// alpha = rz / p.Ap; x += alpha p; r -= alpha Ap; partial r.z (z = dinv r) and r.r
+__global__ __launch_bounds__(TILE_THREADS) void k_pass2(StripGeom g, PcgSlots S) {
+  __shared__ double red4[4];
+  __shared__ int flag;
+  const int s = blockIdx.y, t = blockIdx.x;
+  if (threadIdx.x == 0) flag = S.active[s];
+  __syncthreads();
+  if (!flag) return;
+  const int it = S.it_b[s], par = it & 1;
+  const double pap = block_sum_strided(S.part_pap + (size_t)s * g.ntiles, g.ntiles, red4);
+  const double rz = S.rzs[(size_t)par * S.S + s];
+  if (!(pap > 0.0) || !isfinite(pap)) {
+    if (t == 0 && threadIdx.x == 0) {
+      S.status[s] = isfinite(pap) ? S_BREAKDOWN : S_NAN;
+      S.active[s] = 0;
+    }
+    return;
+  }
+  const double alpha = rz / pap;
+  const TileCoord tc = tile_of(g, t);
+  const size_t vb = (size_t)s * 2 * g.nnode;
+  const double *p_new = S.p + (size_t)(par ^ 1) * S.S * 2 * g.nnode + vb;
+  const int li = threadIdx.x % TILE_X, lj = threadIdx.x / TILE_X;
+  const int i = tc.i0 + li, j = tc.j0 + lj;
+  double prz = 0.0, prr = 0.0;
+  if (i < g.nnx && j < g.nny) {
+    const size_t o = 2 * ((size_t)j * g.nnx + i);
+    const double2 pv = *reinterpret_cast<const double2 *>(p_new + o);
+    const double2 av = *reinterpret_cast<const double2 *>(S.Ap + vb + o);
+    double2 xv = *reinterpret_cast<const double2 *>(S.x + vb + o);
+    double2 rv = *reinterpret_cast<const double2 *>(S.r + vb + o);
+    const double2 dv = *reinterpret_cast<const double2 *>(S.dinv + vb + o);
+    xv.x = fma(alpha, pv.x, xv.x);
+    xv.y = fma(alpha, pv.y, xv.y);
+    rv.x = fma(-alpha, av.x, rv.x);
+    rv.y = fma(-alpha, av.y, rv.y);
+    *reinterpret_cast<double2 *>(S.x + vb + o) = xv;
+    *reinterpret_cast<double2 *>(S.r + vb + o) = rv;
+    prz = rv.x * (dv.x * rv.x) + rv.y * (dv.y * rv.y);
+    prr = rv.x * rv.x + rv.y * rv.y;
+  }
+  prz = block_sum(prz, red4);
+  prr = block_sum(prr, red4);
+  if (threadIdx.x == 0) {
+    const size_t pb = ((size_t)(par ^ 1) * S.S + s) * g.ntiles + t;
+    S.part_rz[pb] = prz;
+    S.part_rr[pb] = prr;
+    if (t == 0) S.it_a[s] = it + 1;
+  }
+}
+
+// ---------------------------------------------------------------- QoI
+// partial max of -sigma_11 over the Gauss points of the QoI-region elements
+// (256 elements per block); final per-slot max written through an index map
+__global__ __launch_bounds__(256) void k_qoi_part(StripGeom g, StripMat m, const double *__restrict__ theta,
+                                                  const double *__restrict__ x, int nparts,
+                                                  double *__restrict__ part) {
+  __shared__ double red4[4];
+  const int s = blockIdx.y;
+  const int qw = g.qx1 - g.qx0, qh = g.qy1 - g.qy0;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  double best = -1.0 / 0.0;
+  if (k < qw * qh) {
+    const int ex = g.qx0 + k % qw, ey = g.qy0 + k / qw;
+    const double *xs = x + (size_t)s * 2 * g.nnode;
+    const int n0 = ey * g.nnx + ex;
+    const int nd[4] = {n0, n0 + 1, n0 + g.nnx + 1, n0 + g.nnx};
+    double u[4], v[4];
+    for (int a = 0; a < 4; ++a) {
+      const double2 d = *reinterpret_cast<const double2 *>(xs + 2 * (size_t)nd[a]);
+      u[a] = d.x;
+      v[a] = d.y;
+    }
+    // prescribed values are not stored in x: u = -delta on the loaded edge
+    if (ex + 1 == g.nx) { u[1] = -g.delta; u[2] = -g.delta; }
+    const double *tp = theta + (size_t)s * 4 * g.nelem + 4 * ((size_t)ey * g.nx + ex);
+    const double th[4] = {tp[0], tp[1], tp[2], tp[3]};
+    best = elem_max_fibre_compression(g, m, th, u, v);
+  }
+  best = block_max(best, red4);
+  if (threadIdx.x == 0) part[(size_t)s * nparts + blockIdx.x] = best;
+}
+
+__global__ void k_qoi_final(const double *__restrict__ part, int nparts, int n, const int *__restrict__ out_idx,
+                            double *__restrict__ q, PcgSlots S, mlmc_info_dev *__restrict__ info, int coarse,
+                            double *__restrict__ d_out, int nnode, double delta, int nnx) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  double best = -1.0 / 0.0;
+  for (int k = 0; k < nparts; ++k) best = fmax(best, part[(size_t)s * nparts + k]);
+  const int o = out_idx ? out_idx[s] : s;
+  if (q) q[o] = best;
+  if (info) {
+    if (coarse) {
+      info[o].iters_c = S.it_b[s];
+      info[o].relres_c = S.relres[s];
+      info[o].status_c = S.status[s];
+    } else {
+      info[o].iters_f = S.it_b[s];
+      info[o].relres_f = S.relres[s];
+      info[o].status_f = S.status[s];
+    }
+  }
+}
+
+// total displacement d = x + g (g = -delta on the loaded-edge u)
+__global__ void k_total_disp(StripGeom g, const double *__restrict__ x, double *__restrict__ d, int n) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t tot = (size_t)n * 2 * g.nnode;
+  if (k >= tot) return;
+  const size_t node = (k / 2) % g.nnode;
+  const int i = (int)(node % g.nnx);
+  double v = x[k];
+  if ((k & 1) == 0 && i == g.nx) v = -g.delta;
+  d[k] = v;
+}
+
+__global__ void k_info_init(mlmc_info_dev *info, double *q_coarse, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  info[k].iters_f = 0;
+  info[k].iters_c = 0;
+  info[k].relres_f = 0.0;
+  info[k].relres_c = 0.0;
+  info[k].status_f = S_SKIPPED;
+  info[k].status_c = S_SKIPPED;
+  if (q_coarse) q_coarse[k] = 0.0;
+}
+
+// ---------------------------------------------------------------- level sums
+// Neumaier-compensated FP64 sums in a fixed order: thread t takes entries
+// t, t+256, ...; the 256 (sum, compensation) pairs are combined by a fixed
+// tree with error-free additions.
+struct Comp {
+  double s, c;
+};
+__device__ __forceinline__ void neu_add(Comp &a, double v) {
+  const double t = a.s + v;
+  if (fabs(a.s) >= fabs(v)) a.c += (a.s - t) + v;
+  else a.c += (v - t) + a.s;
+  a.s = t;
+}
+__device__ __forceinline__ Comp comp_merge(Comp a, Comp b) {
+  Comp r = a;
+  neu_add(r, b.s);
+  r.c += b.c;
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_level_stats(const double *__restrict__ qf, const double *__restrict__ qc,
+                                                     int n, double lambda_star, int indicator,
+                                                     double *__restrict__ out) {
+  __shared__ Comp sh[4][256];
+  __shared__ long long cnt[2][256];
+  Comp a[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  long long np = 0, nm = 0;
+  for (int k = threadIdx.x; k < n; k += 256) {
+    double f = qf[k], c = qc ? qc[k] : 0.0;
+    if (indicator) {
+      f = (f < lambda_star) ? 1.0 : 0.0;
+      if (qc) c = (c < lambda_star) ? 1.0 : 0.0;
+    }
+    const double y = f - c;
+    neu_add(a[0], y);
+    neu_add(a[1], y * y);
+    neu_add(a[2], f);
+    neu_add(a[3], c);
+    np += (y > 0.5);
+    nm += (y < -0.5);
+  }
+  for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] = a[c];
+  cnt[0][threadIdx.x] = np;
+  cnt[1][threadIdx.x] = nm;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) {
+      for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] = comp_merge(sh[c][threadIdx.x], sh[c][threadIdx.x + w]);
+      cnt[0][threadIdx.x] += cnt[0][threadIdx.x + w];
+      cnt[1][threadIdx.x] += cnt[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < 4; ++c) {
+      out[2 * c] = sh[c][0].s;
+      out[2 * c + 1] = sh[c][0].c;
+    }
+    out[8] = (double)cnt[0][0];
+    out[9] = (double)cnt[1][0];
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+static inline dim3 tile_grid(const StripGeom &g, int n) { return dim3(g.ntiles, n); }
+
+void launch_kl_synth(const double *modes, int K, const StripGeom &g, const double *xi, int ld_xi,
+                     const int64_t *rows, int n, double *th64, uint16_t *th16, int ld_out, hipStream_t st) {
+  if (n <= 0) return;
+  dim3 grid((4 * g.nelem + 255) / 256, (n + SYN_SAMPLES - 1) / SYN_SAMPLES);
+  hipLaunchKernelGGL(k_kl_synth, grid, dim3(256), 0, st, modes, K, g, xi, ld_xi, rows, n, th64, th16, ld_out);
+}
+
+void launch_modes_nystrom(const double *gx, const double *gy, const double *coef, int ngrid, int K, double var,
+                          double kappa, const StripGeom &g, double *modes, hipStream_t st) {
+  dim3 grid((4 * g.nelem + 255) / 256);
+  hipLaunchKernelGGL(k_modes_nystrom, grid, dim3(256), 0, st, gx, gy, coef, ngrid, K, var, kappa, g, modes);
+}
+
+void launch_apply(const StripGeom &g, const StripMat &m, const double *theta, const double *x, double *y, int raw,
+                  int n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_apply, tile_grid(g, n), dim3(TILE_THREADS), 0, st, g, m, theta, x, y, raw);
+}
+
+void launch_setup(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n, double *b_out, double *dinv_out,
+                  hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_setup, tile_grid(g, n), dim3(TILE_THREADS), 0, st, g, m, S, b_out, dinv_out);
+}
+
+void launch_pcg_iteration(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_pass1, tile_grid(g, n), dim3(TILE_THREADS), 0, st, g, m, S);
+  hipLaunchKernelGGL(k_pass2, tile_grid(g, n), dim3(TILE_THREADS), 0, st, g, S);
+}
+
+int qoi_parts(const StripGeom &g) { return ((g.qx1 - g.qx0) * (g.qy1 - g.qy0) + 255) / 256; }
+
+void launch_qoi(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n, double *part, const int *out_idx,
+                double *q, mlmc_info_dev *info, int coarse, hipStream_t st) {
+  if (n <= 0) return;
+  const int np = qoi_parts(g);
+  hipLaunchKernelGGL(k_qoi_part, dim3(np, n), dim3(256), 0, st, g, m, S.theta, S.x, np, part);
+  hipLaunchKernelGGL(k_qoi_final, dim3((n + 127) / 128), dim3(128), 0, st, part, np, n, out_idx, q, S, info,
+                     coarse, nullptr, g.nnode, g.delta, g.nnx);
+}
+
+void launch_total_disp(const StripGeom &g, const double *x, double *d, int n, hipStream_t st) {
+  const size_t tot = (size_t)n * 2 * g.nnode;
+  if (!tot) return;
+  hipLaunchKernelGGL(k_total_disp, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, g, x, d, n);
+}
+
+void launch_info_init(mlmc_info_dev *info, double *q_coarse, int n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_info_init, dim3((n + 255) / 256), dim3(256), 0, st, info, q_coarse, n);
+}
+
+void launch_level_stats(const double *qf, const double *qc, int n, double lambda_star, int indicator, double *out,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_level_stats, dim3(1), dim3(256), 0, st, qf, qc, n, lambda_star, indicator, out);
+}
+
+}  // namespace mlmc

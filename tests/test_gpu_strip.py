@@ -1,0 +1,203 @@
+"""GPU parity of the strip path against the FP64 oracle, through the C ABI.
+
+Tolerances (FP64 mode):
+  * angle field: <= 1e-13 rad absolute (separable modes are closed form;
+    Matern modes come from two independent eigen-solvers whose eigenvector
+    error is ~eps / relative gap, gaps >= 1e-5);
+  * operator, lifting, diagonal: <= 1e-13 relative to the max-norm;
+  * QoI: both sides solve to a tight tolerance (GPU PCG at rtol 1e-13, the
+    oracle by sparse LU): <= 1e-10 relative;
+  * at the production rtol 1e-10 the GPU's true residual <= 1.01 rtol and the
+    PCG iteration counts agree with the oracle's PCG within 1%.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import mlmc_inputs as mi
+from tests.conftest import gpu_available
+from tests.gpu_util import context, dev, oracle_kl, oracle_strip
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _rows(name, level, n, start=0):
+    return mi.strip_xi(mi.load_config(name), level, start, n)
+
+
+@pytest.mark.parametrize("name,level", [("strip_c1", 0), ("strip_c1", 1), ("strip_c2", 0), ("strip_c2", 1)])
+def test_field_parity(name, level):
+    ctx = context(name)
+    xi = _rows(name, level, 5)
+    th = ctx.sample_field(level, dev(xi)).cpu().numpy()
+    om = oracle_strip(name, level)
+    for k in range(5):
+        ref = om.theta(xi[k]).ravel()
+        assert np.abs(th[k] - ref).max() <= 1e-13, (k, np.abs(th[k] - ref).max())
+
+
+def test_field_bf16_rounding():
+    ctx = context("strip_c2")
+    xi = _rows("strip_c2", 0, 3)
+    t16 = ctx.sample_field(0, dev(xi), dtype=1).cpu().numpy().astype(np.uint16).astype(np.uint32)
+    back = (t16 << 16).view(np.float32).astype(np.float64)
+    ref = np.stack([oracle_strip("strip_c2", 0).theta(r).ravel() for r in xi])
+    assert np.all(np.abs(back - ref) <= np.abs(ref) * 2.0 ** -8 + 1e-30)
+
+
+@pytest.mark.parametrize("name,level", [("strip_c1", 0), ("strip_c1", 1), ("strip_c2", 1)])
+def test_operator_parity(name, level):
+    from oracle.strip import assemble
+    ctx = context(name)
+    om = oracle_strip(name, level)
+    xi = _rows(name, level, 3)
+    rng = np.random.default_rng(11)
+    thetas = np.stack([om.theta(r).ravel() for r in xi])
+    x = rng.standard_normal((3, 2 * om.mesh.n_nodes))
+    y_raw = ctx.strip_apply(level, dev(thetas), dev(x), raw=True).cpu().numpy()
+    y_bc = ctx.strip_apply(level, dev(thetas), dev(x), raw=False).cpu().numpy()
+    con = om.bc.dofs
+    for k in range(3):
+        K = assemble(om.mesh, om.Q, thetas[k].reshape(-1, 4))
+        ref = K @ x[k]
+        assert np.abs(y_raw[k] - ref).max() <= 1e-13 * np.abs(ref).max()
+        xp = x[k].copy()
+        xp[con] = 0.0
+        ref2 = K @ xp
+        ref2[con] = x[k][con]
+        assert np.abs(y_bc[k] - ref2).max() <= 1e-13 * np.abs(ref2).max()
+
+
+@pytest.mark.parametrize("name,level", [("strip_c1", 0), ("strip_c2", 1)])
+def test_rhs_and_diagonal_parity(name, level):
+    from oracle.strip import assemble, reduce_system
+    ctx = context(name)
+    om = oracle_strip(name, level)
+    xi = _rows(name, level, 2)
+    thetas = np.stack([om.theta(r).ravel() for r in xi])
+    b, dinv = ctx.strip_rhs_diag(level, dev(thetas))
+    b, dinv = b.cpu().numpy(), dinv.cpu().numpy()
+    for k in range(2):
+        K = assemble(om.mesh, om.Q, thetas[k].reshape(-1, 4))
+        free, Kff, bf = reduce_system(K, om.bc)
+        assert np.abs(b[k][free] - bf).max() <= 1e-13 * np.abs(bf).max()
+        assert np.all(b[k][om.bc.dofs] == 0.0)
+        d = Kff.diagonal()
+        assert np.abs(1.0 / dinv[k][free] - d).max() <= 1e-13 * np.abs(d).max()
+        assert np.all(dinv[k][om.bc.dofs] == 1.0)
+
+
+@pytest.mark.parametrize("name,level", [("strip_c1", 0), ("strip_c1", 1), ("strip_c2", 0), ("strip_c2", 1)])
+def test_qoi_parity_tight(name, level):
+    ctx = context(name)
+    om = oracle_strip(name, level)
+    n = 6
+    xi = _rows(name, level, n)
+    qf, qc, info = ctx.solve_batch([(k, level, False) for k in range(n)], dev(xi), rtol=1e-13)
+    qf = qf.cpu().numpy()
+    for k in range(n):
+        assert info[k]["status_f"] == 0
+        ref = om.solve(xi[k], method="direct").q
+        assert abs(qf[k] - ref) <= 1e-10 * abs(ref), (k, qf[k], ref)
+
+
+@pytest.mark.parametrize("name,level", [("strip_c1", 1), ("strip_c2", 1)])
+def test_production_rtol_residual_and_iterations(name, level):
+    from oracle.strip import assemble, jacobi_pcg, reduce_system
+    ctx = context(name)
+    om = oracle_strip(name, level)
+    xi = _rows(name, level, 3)
+    thetas = np.stack([om.theta(r).ravel() for r in xi])
+    rtol = mi.load_config(name)["rtol"]
+    q, d, info = ctx.strip_solve_theta(level, dev(thetas), rtol=rtol, want_d=True)
+    d = d.cpu().numpy()
+    for k in range(3):
+        K = assemble(om.mesh, om.Q, thetas[k].reshape(-1, 4))
+        free, Kff, b = reduce_system(K, om.bc)
+        true_res = np.linalg.norm(b - Kff @ d[k][free]) / np.linalg.norm(b)
+        assert true_res <= 1.01 * rtol
+        assert np.all(d[k][om.bc.dofs] == om.bc.values)
+        ref = jacobi_pcg(Kff, b, rtol)
+        assert abs(int(info[k]["iters_f"]) - ref.iters) <= max(2, 0.01 * ref.iters)
+        assert info[k]["relres_f"] <= rtol
+
+
+def test_coupled_pairs_telescoping_bitwise():
+    name = "strip_c2"
+    ctx = context(name)
+    xi = _rows(name, 2, 4)
+    reqs = [(k, 2, True) for k in range(4)]
+    qf, qc, info = ctx.solve_batch(reqs, dev(xi))
+    qf1, _, _ = ctx.solve_batch([(k, 1, False) for k in range(4)], dev(xi))
+    q0, _, _ = ctx.solve_batch([(k, 0, False) for k in range(4)], dev(xi))
+    qc = qc.cpu().numpy()
+    assert np.array_equal(qc, qf1.cpu().numpy())       # coarse half == level-1 result
+    # telescoping for fixed samples: Q_0 + (Q_1 - Q_0) + (Q_2 - Q_1) = Q_2
+    tele = q0.cpu().numpy() + (qf1.cpu().numpy() - q0.cpu().numpy()) + (qf.cpu().numpy() - qc)
+    assert np.allclose(tele, qf.cpu().numpy(), rtol=1e-15, atol=0)
+    assert np.all(info["status_f"] == 0) and np.all(info["status_c"] == 0)
+
+
+def test_batch_composition_invariance_and_determinism():
+    name = "strip_c1"
+    ctx = context(name)
+    xi = _rows(name, 1, 12)
+    mix = [(k, k % 2, bool(k % 3)) for k in range(12)]
+    a_f, a_c, _ = ctx.solve_batch(mix, dev(xi))
+    b_f, b_c, _ = ctx.solve_batch(mix, dev(xi))
+    assert np.array_equal(a_f.cpu().numpy(), b_f.cpu().numpy())
+    assert np.array_equal(a_c.cpu().numpy(), b_c.cpu().numpy())
+    for k in (0, 5, 7):
+        s_f, s_c, _ = ctx.solve_batch([mix[k]], dev(xi))
+        assert s_f.cpu().numpy()[0] == a_f.cpu().numpy()[k]
+        assert s_c.cpu().numpy()[0] == a_c.cpu().numpy()[k]
+
+
+def test_level_stats_against_fsum():
+    ctx = context("strip_c1")
+    rng = np.random.default_rng(5)
+    qf = 66.0 + rng.standard_normal(5003)
+    qc = qf - 1e-3 * rng.standard_normal(5003)
+    acc = ctx.level_stats(1, dev(qf), dev(qc), cost_per_sample=2.0)
+    y = qf - qc
+    assert acc.n == 5003 and acc.sum_cost == 2.0 * 5003
+    assert abs(acc.total("sum_y") - math.fsum(y)) <= 1e-15 * math.fsum(np.abs(y))
+    assert abs(acc.total("sum_y2") - math.fsum(y * y)) <= 1e-15 * math.fsum(y * y)
+    assert abs(acc.total("sum_qf") - math.fsum(qf)) <= 1e-15 * math.fsum(qf)
+    # indicator mode: 1(lambda < lambda*)
+    lf = rng.uniform(0.8, 0.9, 1000)
+    lc = lf + rng.uniform(0, 0.01, 1000)
+    acc2 = ctx.level_stats(1, dev(lf), dev(lc), lambda_star=0.85)
+    yf = (lf < 0.85).astype(float) - (lc < 0.85).astype(float)
+    assert acc2.n_plus == int(np.sum(yf > 0)) and acc2.n_minus == int(np.sum(yf < 0))
+    assert acc2.total("sum_y") == yf.sum()
+
+
+def test_error_paths():
+    import paper_1907_10271_amd as pk
+    ctx = context("strip_c1")
+    xi = dev(_rows("strip_c1", 0, 2))
+    with pytest.raises(pk.MLMCError) as e:
+        ctx.solve_batch([(0, 5, False)], xi)
+    assert e.value.code == -1
+    with pytest.raises(pk.MLMCError):
+        ctx.solve_batch([(7, 0, False)], xi)          # row outside the parameter array
+    with pytest.raises(pk.MLMCError) as e:
+        ctx.buckle_batch([(0, 0, False)], xi)
+    assert e.value.code == -4
+    with pytest.raises(pk.MLMCError):
+        pk.Context('{"kind": "strip"}')
+
+
+def test_nan_and_iteration_limit_reported_per_sample():
+    ctx = context("strip_c1")
+    xi = _rows("strip_c1", 0, 3)
+    xi[1, 0] = np.nan
+    qf, _, info = ctx.solve_batch([(k, 0, False) for k in range(3)], dev(xi))
+    assert info[1]["status_f"] == 2 and info[0]["status_f"] == 0 and info[2]["status_f"] == 0
+    cfg = dict(mi.load_config("strip_c1"), max_iter=3)
+    import paper_1907_10271_amd as pk
+    c2 = pk.Context(cfg)
+    _, _, info2 = c2.solve_batch([(0, 0, False)], dev(_rows("strip_c1", 0, 1)))
+    assert info2[0]["status_f"] == 1 and info2[0]["iters_f"] == 3
