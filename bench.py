@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark of the MLMC sample-solve path on one MI355X.
+
+Workload: the four-level FP64 waviness strip (20 x 5 mm orthotropic strip,
+Q1 meshes 64x16, 128x32, 256x64, 512x128; Matern-3/2 KL field with 20 modes
+plus a sech^2 wrinkle; Jacobi-PCG to rtol 1e-10).  One step is one MLMC
+batch round: on every level a batch of coupled samples (Y_0 = Q_0 on level 0,
+fine/coarse pairs with shared parameters above) goes through KL synthesis,
+lifting, PCG, the QoI and the FP64 level sums.  The per-level batch sizes
+follow the shape of the optimal MLMC allocation (more samples on coarse
+levels).  Parameter rows are generated and copied to the GPU before the
+timed region.
+
+Printed: one JSON line with the whole-job rate (coupled samples/s), per-level
+rates, the roofline of the dominant kernel (the PCG operator pass, timed with
+HIP events on the solve stream) and the CPU oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import mlmc_inputs as mi  # noqa: E402
+
+WORKLOAD = "strip_c2"
+DEFAULT_MIX = [2048, 512, 128, 64]
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mix", type=str, default=",".join(map(str, DEFAULT_MIX)))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-samples", type=str, default="16,8,4,2",
+                    help="oracle samples per level for the CPU baseline")
+    ap.add_argument("--levels", type=str, default="",
+                    help="run only these levels (comma list; profiling runs, the line is then not the benchmark)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for hardware byte counters)")
+    return ap.parse_args()
+
+
+# ------------------------------------------------------------------ CPU oracle
+_ORACLE_MODELS = None
+
+
+def _oracle_job(job):
+    level, row_idx = job
+    models, rows = _ORACLE_MODELS
+    row = rows[level][row_idx]
+    t0 = time.perf_counter()
+    models[level].solve(row)
+    if level > 0:
+        models[level - 1].solve(row)
+    return level, time.perf_counter() - t0
+
+
+def cpu_baseline(cfg, mix, counts):
+    """The oracle (FP64 numpy/scipy, single-threaded BLAS per worker) on a bounded
+    sample of the same workload, one worker process per host core."""
+    global _ORACLE_MODELS
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import multiprocessing as mp
+
+    from oracle.kl import KL
+    from oracle.strip import StripModel
+    kl = KL(cfg)
+    nl = len(mix)
+    models = [StripModel(cfg, l, kl) for l in range(nl)]
+    for m in models:          # per-level mode tables (set-up, not timed, as on the GPU)
+        m.modes()
+    rows = [mi.strip_xi(cfg, l, 10 ** 6, counts[l]) for l in range(nl)]
+    _ORACLE_MODELS = (models, rows)
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    jobs = [(l, k) for l in reversed(range(nl)) for k in range(counts[l])]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_job, jobs, chunksize=1)
+    wall = time.perf_counter() - t0
+    per_level = [np.mean([t for l, t in res if l == lv]) for lv in range(nl)]
+    # throughput on the benchmark's mix: cores workers sharing the per-sample costs
+    step_cpu_s = sum(n * t for n, t in zip(mix, per_level))
+    value = sum(mix) / (step_cpu_s / cores)
+    sample = (f"{'+'.join(str(c) for c in counts)} coupled samples on levels 0..{nl - 1} "
+              f"({wall:.1f} s wall on {cores} worker processes); per-sample oracle seconds "
+              + ", ".join(f"L{l}={t:.3f}" for l, t in enumerate(per_level)))
+    return {"value": value, "unit": "coupled samples/s", "cores": cores, "kind": "oracle", "sample": sample,
+            "per_level_s_per_sample": per_level}
+
+
+# ------------------------------------------------------------------ GPU
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU: --gpus {args.gpus} is not supported (the path is "
+              f"data-parallel over samples; the multi-GPU design shards sample ranges and all-reduces "
+              f"the per-level sums, but it is not built)", file=sys.stderr)
+        sys.exit(2)
+    cfg = mi.load_config(WORKLOAD)
+    mix = [int(v) for v in args.mix.split(",")]
+    assert len(mix) == cfg["n_levels"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, mix, [int(v) for v in args.cpu_samples.split(",")])
+
+    import torch
+    import paper_1907_10271_amd as pk
+    dev = torch.device("cuda:0")
+    ctx = pk.Context(mi.config_text(WORKLOAD))
+    nsteps = args.warmup + args.steps
+    xi = []
+    for l, n in enumerate(mix):
+        rows = mi.strip_xi(cfg, l, 0, n * nsteps)
+        xi.append(torch.from_numpy(rows).to(dev))
+    torch.cuda.synchronize()
+    reqs = [[(k, l, l > 0) for k in range(n)] for l, n in enumerate(mix)]
+    levels = [int(v) for v in args.levels.split(",")] if args.levels else list(range(len(mix)))
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    stream = torch.cuda.current_stream()
+
+    def step(s, events=None):
+        accs = []
+        for l, n in enumerate(mix):
+            if l not in levels:
+                accs.append(None)
+                continue
+            x = xi[l][s * n:(s + 1) * n]
+            if events is not None:
+                events[l][0].record(stream)
+            qf, qc, info = ctx.solve_batch(reqs[l], x)
+            acc = ctx.level_stats(l, qf, qc if l > 0 else None)
+            if events is not None:
+                events[l][1].record(stream)
+            accs.append((acc, info))
+        return accs
+
+    for s in range(args.warmup):
+        step(s)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in mix]
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for s in range(args.steps):
+        results.append(step(args.warmup + s, ev[s]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    per_level = []
+    for l, n in enumerate(mix):
+        if l not in levels:
+            continue
+        ms = np.mean([ev[s][l][0].elapsed_time(ev[s][l][1]) for s in range(args.steps)])
+        its_f = np.concatenate([r[l][1]["iters_f"] for r in results])
+        ok = all(np.all(r[l][1]["status_f"] == 0) for r in results)
+        per_level.append({"level": l, "mesh": f"{cfg['nx0'] << l}x{cfg['ny0'] << l}", "samples": n,
+                          "coupled": l > 0, "ms": round(float(ms), 3),
+                          "samples_per_s": round(n / (ms / 1e3), 1),
+                          "pcg_iters_mean": round(float(its_f.mean()), 1), "all_converged": bool(ok)})
+    p1 = ctx.profile_read(0)
+    p2 = ctx.profile_read(1)
+    achieved = p1["bytes"] / (p1["ms"] / 1e3) / 1e9
+    total = sum(n for l, n in enumerate(mix) if l in levels)
+    out = {
+        "metric": "coupled-sample solves/s (4-level FP64 waviness strip, one MLMC batch round per step)",
+        "value": round(total / (ms_per_step / 1e3), 2),
+        "unit": "coupled samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded KL parameters and wrinkles)",
+        "config": {"workload": "waviness strip 20x5 mm, 4 levels 64x16..512x128, Matern-3/2 20 modes + wrinkle, "
+                               "Jacobi-PCG rtol 1e-10, FP64",
+                   "batch_per_level": mix, "parallelism": "single GPU, data-parallel over samples"},
+        "per_level": per_level,
+        "roofline": {"bound": "hbm", "kernel": "k_pass1 (PCG operator pass)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "launches": p1["launches"], "avg_launch_us": round(p1["ms"] * 1e3 / p1["launches"], 3),
+                     "alg_bytes_per_launch": round(p1["bytes"] / p1["launches"], 1)},
+        "vector_pass": {"kernel": "k_pass2", "achieved_GBs": round(p2["bytes"] / (p2["ms"] / 1e3) / 1e9, 1),
+                        "avg_launch_us": round(p2["ms"] * 1e3 / p2["launches"], 3)},
+        "cpu_baseline": None if cpu is None else {k: v for k, v in cpu.items() if k != "per_level_s_per_sample"},
+    }
+    if len(levels) != len(mix):
+        out["metric"] = "profiling run on levels " + args.levels + " only (not the benchmark)"
+    if cpu is not None:
+        out["cpu_baseline"]["value"] = round(cpu["value"], 3)
+        out["gpu_over_cpu"] = round(out["value"] / cpu["value"], 1)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -189,6 +189,21 @@ int mlmc_buckle_batch(mlmc_ctx *ctx, int n_req, const mlmc_request *req, const d
 int mlmc_level_stats(mlmc_ctx *ctx, int level, int n, const double *q_fine, const double *q_coarse,
                      double cost_per_sample, double lambda_star, mlmc_level_acc *acc, void *stream);
 
+/* ------------------------------------------------------------ diagnostics */
+
+/* Kernel timing for roofline measurement.  While enabled, every launch of the
+ * two PCG passes (kernel 0: operator pass, fused p-update + A p + p.Ap;
+ * kernel 1: vector pass, x/r update + r.z, r.r) is bracketed by HIP events on
+ * the stream of the solve.  mlmc_profile_read returns the summed event time
+ * (ms), the number of launches and the algorithmic HBM bytes of those
+ * launches (bytes each active sample must move per iteration times the
+ * iterations it ran: operator pass reads r, dinv, p and writes A p, 4 vectors
+ * of 16 B/node, plus 32 B/element of angles; vector pass reads x, r, p, A p,
+ * dinv and writes x, r, p, 8 vectors of 16 B/node).  Timing adds a small
+ * host-side cost per launch; results are unchanged. */
+int mlmc_profile_enable(mlmc_ctx *ctx, int on);
+int mlmc_profile_read(mlmc_ctx *ctx, int kernel, double *total_ms, int64_t *launches, double *alg_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,8 @@ S_OK, S_NOCONV, S_NAN, S_BREAKDOWN, S_SKIPPED = 0, 1, 2, 3, 4
 
 EXPORTS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_level_info", "mlmc_num_levels",
            "mlmc_footprint", "mlmc_sample_field", "mlmc_strip_apply", "mlmc_strip_rhs_diag",
-           "mlmc_strip_solve_theta", "mlmc_solve_batch", "mlmc_buckle_batch", "mlmc_level_stats"]
+           "mlmc_strip_solve_theta", "mlmc_solve_batch", "mlmc_buckle_batch", "mlmc_level_stats",
+           "mlmc_profile_enable", "mlmc_profile_read"]
 
 
 class Request(C.Structure):
@@ -84,6 +85,8 @@ def load() -> C.CDLL:
     lib.mlmc_solve_batch.argtypes = [vp, i, C.POINTER(Request), vp, C.c_int64, i, vp, vp, vp, i, d, vp]
     lib.mlmc_buckle_batch.argtypes = [vp, i, C.POINTER(Request), vp, C.c_int64, vp, vp, vp, i, d, vp]
     lib.mlmc_level_stats.argtypes = [vp, i, i, vp, vp, d, d, C.POINTER(LevelAcc), vp]
+    lib.mlmc_profile_enable.argtypes = [vp, i]
+    lib.mlmc_profile_read.argtypes = [vp, i, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     _lib = lib
     return lib
 
@@ -220,6 +223,15 @@ class Context:
         self._check(self.lib.mlmc_buckle_batch(self.h, n, arr, _ptr(offsets), offsets.shape[0], _ptr(lf), _ptr(lc), _ptr(info),
                                                precision, tol, _stream(stream)))
         return lf, lc, info_to_numpy(info)[:n]
+
+    # ------------------------------------------------------------ diagnostics
+    def profile(self, on: bool = True):
+        self._check(self.lib.mlmc_profile_enable(self.h, int(on)))
+
+    def profile_read(self, kernel: int):
+        ms, n, b = C.c_double(), C.c_int64(), C.c_double()
+        self._check(self.lib.mlmc_profile_read(self.h, kernel, C.byref(ms), C.byref(n), C.byref(b)))
+        return {"ms": ms.value, "launches": n.value, "bytes": b.value}
 
     # ------------------------------------------------------------ sums
     def level_stats(self, level: int, q_fine, q_coarse=None, cost_per_sample: float = 0.0,

@@ -58,6 +58,12 @@ struct mlmc_ctx {
   double *d_stats = nullptr, *h_stats = nullptr;
   PlateCtx *plate = nullptr;
   int device = 0;
+  // diagnostics: event timing of the PCG passes
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  double prof_ms[2] = {0, 0}, prof_bytes[2] = {0, 0};
+  int64_t prof_launches[2] = {0, 0};
+  std::vector<int> h_iters;
 };
 
 namespace {
@@ -85,6 +91,12 @@ StripGeom make_geom(const Json &cfg, int level) {
   g.tiles_x = (g.nnx + TILE_X - 1) / TILE_X;
   g.tiles_y = (g.nny + TILE_Y - 1) / TILE_Y;
   g.ntiles = g.tiles_x * g.tiles_y;
+  g.sw_ntx = (g.nnx + SWEEP_MAXW - 1) / SWEEP_MAXW;
+  g.sw_tw = (g.nnx + g.sw_ntx - 1) / g.sw_ntx;
+  g.sw_nty = (g.nny + SWEEP_MAXTY - 1) / SWEEP_MAXTY;
+  g.sw_ty = (g.nny + g.sw_nty - 1) / g.sw_nty;
+  g.sw_ntiles = g.sw_ntx * g.sw_nty;
+  g.nchunks = (g.nnode + CHUNK - 1) / CHUNK;
   g.Lx = cfg.number("Lx");
   g.Ly = cfg.number("Ly");
   g.hx = g.Lx / g.nx;
@@ -123,9 +135,9 @@ StripMat make_material(const Json &cfg) {
 
 size_t strip_slot_bytes(const StripGeom &g) {
   const size_t vec = (size_t)2 * g.nnode * sizeof(double);
-  return 6 * vec                                      // x, r, p (2 buffers), Ap, dinv
+  return 5 * vec                                      // x, r, p, Ap, dinv
          + (size_t)4 * g.nelem * sizeof(double)       // theta
-         + (size_t)5 * g.ntiles * sizeof(double)      // partials
+         + (size_t)(g.sw_ntiles + 4 * g.nchunks) * sizeof(double)  // partials
          + (size_t)qoi_parts(g) * sizeof(double)      // QoI partial maxima
          + 8 * sizeof(double) + 8 * sizeof(int) + sizeof(int64_t);
 }
@@ -158,13 +170,13 @@ int ensure_pool(mlmc_ctx *c, int level, int n) {
   const size_t vec = (size_t)2 * g.nnode * n;
   HIPCHK(c, dalloc(&p.x, vec));
   HIPCHK(c, dalloc(&p.r, vec));
-  HIPCHK(c, dalloc(&p.p, 2 * vec));
+  HIPCHK(c, dalloc(&p.p, vec));
   HIPCHK(c, dalloc(&p.Ap, vec));
   HIPCHK(c, dalloc(&p.dinv, vec));
   HIPCHK(c, dalloc(&p.theta, (size_t)4 * g.nelem * n));
-  HIPCHK(c, dalloc(&p.part_pap, (size_t)g.ntiles * n));
-  HIPCHK(c, dalloc(&p.part_rz, (size_t)2 * g.ntiles * n));
-  HIPCHK(c, dalloc(&p.part_rr, (size_t)2 * g.ntiles * n));
+  HIPCHK(c, dalloc(&p.part_pap, (size_t)g.sw_ntiles * n));
+  HIPCHK(c, dalloc(&p.part_rz, (size_t)2 * g.nchunks * n));
+  HIPCHK(c, dalloc(&p.part_rr, (size_t)2 * g.nchunks * n));
   HIPCHK(c, dalloc(&p.rzs, (size_t)2 * n));
   HIPCHK(c, dalloc(&p.tol2, (size_t)n));
   HIPCHK(c, dalloc(&p.bb, (size_t)n));
@@ -228,15 +240,49 @@ int run_pcg(mlmc_ctx *c, int level, const PcgSlots &S, int n, hipStream_t st) {
   launch_setup(g, c->mat, S, n, nullptr, nullptr, st);
   HIPCHK(c, hipGetLastError());
   const int block = 32;
+  if (c->prof && c->ev.size() < 3 * block) {
+    c->ev.resize(3 * block);
+    for (auto &e : c->ev) HIPCHK(c, hipEventCreate(&e));
+  }
   for (long it = 0;; it += block) {
-    for (int b = 0; b < block; ++b) launch_pcg_iteration(g, c->mat, S, n, st);
+    for (int b = 0; b < block; ++b) {
+      const int k = (int)(it + b);
+      if (c->prof) {
+        HIPCHK(c, hipEventRecord(c->ev[3 * b], st));
+        launch_pcg_pass1(g, c->mat, S, n, k, st);
+        HIPCHK(c, hipEventRecord(c->ev[3 * b + 1], st));
+        launch_pcg_pass2(g, S, n, k, st);
+        HIPCHK(c, hipEventRecord(c->ev[3 * b + 2], st));
+      } else {
+        launch_pcg_iteration(g, c->mat, S, n, k, st);
+      }
+    }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->h_active, S.active, sizeof(int) * n, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
+    if (c->prof) {
+      for (int b = 0; b < block; ++b) {
+        float t1 = 0, t2 = 0;
+        HIPCHK(c, hipEventElapsedTime(&t1, c->ev[3 * b], c->ev[3 * b + 1]));
+        HIPCHK(c, hipEventElapsedTime(&t2, c->ev[3 * b + 1], c->ev[3 * b + 2]));
+        c->prof_ms[0] += t1;
+        c->prof_ms[1] += t2;
+      }
+      c->prof_launches[0] += block;
+      c->prof_launches[1] += block;
+    }
     bool any = false;
     for (int k = 0; k < n; ++k) any |= c->h_active[k] != 0;
     if (!any) break;
     if (it > (long)c->max_iter + 4 * block) return fail(c, MLMC_EHIP, "PCG loop did not terminate");
+  }
+  if (c->prof) {
+    c->h_iters.resize(n);
+    HIPCHK(c, hipMemcpy(c->h_iters.data(), S.it_b, sizeof(int) * n, hipMemcpyDeviceToHost));
+    double its = 0;
+    for (int k = 0; k < n; ++k) its += c->h_iters[k];
+    c->prof_bytes[0] += its * (4.0 * 16.0 * g.nnode + 32.0 * g.nelem);
+    c->prof_bytes[1] += its * (8.0 * 16.0 * g.nnode);
   }
   return MLMC_OK;
 }
@@ -366,6 +412,7 @@ void mlmc_destroy(mlmc_ctx *c) {
   if (c->d_stats) (void)hipFree(c->d_stats);
   if (c->h_stats) (void)hipHostFree(c->h_stats);
   if (c->plate) plate_destroy(c->plate);
+  for (auto &e : c->ev) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -574,6 +621,26 @@ int mlmc_level_stats(mlmc_ctx *c, int level, int n, const double *q_fine, const 
   acc->n_plus += (int64_t)o[8];
   acc->n_minus += (int64_t)o[9];
   acc->sum_cost += cost_per_sample * n;
+  return MLMC_OK;
+}
+
+int mlmc_profile_enable(mlmc_ctx *c, int on) {
+  if (!c) return MLMC_EINVAL;
+  c->prof = on != 0;
+  for (int k = 0; k < 2; ++k) {
+    c->prof_ms[k] = 0;
+    c->prof_bytes[k] = 0;
+    c->prof_launches[k] = 0;
+  }
+  return MLMC_OK;
+}
+
+int mlmc_profile_read(mlmc_ctx *c, int kernel, double *total_ms, int64_t *launches, double *alg_bytes) {
+  if (!c) return MLMC_EINVAL;
+  if (kernel < 0 || kernel > 1) return fail(c, MLMC_EINVAL, "kernel must be 0 or 1");
+  if (total_ms) *total_ms = c->prof_ms[kernel];
+  if (launches) *launches = c->prof_launches[kernel];
+  if (alg_bytes) *alg_bytes = c->prof_bytes[kernel];
   return MLMC_OK;
 }
 

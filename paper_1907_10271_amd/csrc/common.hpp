@@ -10,13 +10,23 @@ namespace mlmc {
 // node tile of the strip operator: owned nodes per work-group
 constexpr int TILE_X = 32;
 constexpr int TILE_Y = 8;
-constexpr int TILE_THREADS = TILE_X * TILE_Y;  // one owned node per thread
+constexpr int TILE_NODES = TILE_X * TILE_Y;    // owned nodes per tile
+constexpr int TILE_THREADS = 320;              // >= halo elements: one element per thread
 constexpr int HALO_X = TILE_X + 2;             // nodes incl. one-node halo
 constexpr int HALO_Y = TILE_Y + 2;
 constexpr int ELEM_X = TILE_X + 1;             // elements touching the owned nodes
 constexpr int ELEM_Y = TILE_Y + 1;
 constexpr int TILE_NODES_H = HALO_X * HALO_Y;
 constexpr int TILE_ELEMS = ELEM_X * ELEM_Y;
+static_assert(TILE_ELEMS <= TILE_THREADS && TILE_NODES <= TILE_THREADS, "tile too large for the block");
+constexpr int TILE_WAVES = TILE_THREADS / 64;
+
+// column sweep: one wave owns up to SWEEP_MAXW node columns plus one halo
+// column on each side and walks up the element rows
+constexpr int SWEEP_MAXW = 62;
+constexpr int SWEEP_MAXTY = 16;
+// vector pass: CHUNK consecutive nodes per 256-thread block
+constexpr int CHUNK = 1024;
 
 // 2x2 Gauss rule: the bilinear interpolation weights at +-1/sqrt(3) are
 // (1 + 1/sqrt3)/2 and (1 - 1/sqrt3)/2
@@ -28,7 +38,9 @@ struct StripGeom {
   int nx, ny;        // elements per row / column
   int nnx, nny;      // nodes per row / column
   int nnode, nelem;
-  int tiles_x, tiles_y, ntiles;
+  int tiles_x, tiles_y, ntiles;    // 2-D LDS tiles (set-up and the stand-alone operator)
+  int sw_tw, sw_ty, sw_ntx, sw_nty, sw_ntiles;  // column-sweep tiles of the PCG operator pass
+  int nchunks;                     // contiguous node chunks of the PCG vector pass
   int qx0, qx1, qy0, qy1;  // QoI element index ranges [q*0, q*1)
   double hx, hy, ihx, ihy, wdet;  // wdet = Gauss weight x det J = hx hy / 4
   double delta;                   // u = -delta on x = Lx
@@ -44,10 +56,10 @@ struct StripMat {
 
 // per-slot PCG state of a level pool (device pointers)
 struct PcgSlots {
-  double *x, *r, *p, *Ap, *dinv;   // [S][2 nnode]
+  double *x, *r, *p, *Ap, *dinv;   // [S][2 nnode]; all slots iterate in lock-step
   const double *theta;             // [S][4 nelem]
-  double *part_pap;                // [S][ntiles]
-  double *part_rz, *part_rr;       // [2][S][ntiles]
+  double *part_pap;                // [S][sw_ntiles]
+  double *part_rz, *part_rr;       // [2][S][nchunks]
   double *rzs;                     // [2][S]
   double *tol2, *bb, *relres;      // [S]
   int *it_a, *it_b, *status, *active;  // [S]

@@ -12,11 +12,41 @@ struct Qb {
   double q11, q22, q12, q66, q16, q26;
 };
 
+// sin and cos of a small angle from their Taylor series (Horner in x^2): for
+// |x| <= 1 the first omitted terms are below x^19/19! < 1e-17 and x^20/20! <
+// 1e-18, so the result is within a few ulp; larger arguments use sincos().
+__device__ __forceinline__ void sincos_small(double x, double *s, double *c) {
+  if (fabs(x) > 1.0) {
+    sincos(x, s, c);
+    return;
+  }
+  const double z = x * x;
+  double ps = -1.0 / 355687428096000.0;  // -1/17!
+  ps = fma(ps, z, 1.0 / 1307674368000.0);
+  ps = fma(ps, z, -1.0 / 6227020800.0);
+  ps = fma(ps, z, 1.0 / 39916800.0);
+  ps = fma(ps, z, -1.0 / 362880.0);
+  ps = fma(ps, z, 1.0 / 5040.0);
+  ps = fma(ps, z, -1.0 / 120.0);
+  ps = fma(ps, z, 1.0 / 6.0);
+  *s = fma(-x * z, ps, x);               // x - x^3/3! + ...
+  double pc = 1.0 / 6402373705728000.0;  // 1/18!
+  pc = fma(pc, z, -1.0 / 20922789888000.0);
+  pc = fma(pc, z, 1.0 / 87178291200.0);
+  pc = fma(pc, z, -1.0 / 479001600.0);
+  pc = fma(pc, z, 1.0 / 3628800.0);
+  pc = fma(pc, z, -1.0 / 40320.0);
+  pc = fma(pc, z, 1.0 / 720.0);
+  pc = fma(pc, z, -1.0 / 24.0);
+  pc = fma(pc, z, 0.5);
+  *c = fma(-z, pc, 1.0);                 // 1 - x^2/2! + ...
+}
+
 // Qbar(theta) from the rotation invariants: the fibre axes are turned by +theta
 // from x; entries are linear in cos 2theta, sin 2theta, cos 4theta, sin 4theta.
 __device__ __forceinline__ Qb qbar_of(const StripMat &m, double th) {
   double s2, c2;
-  sincos(2.0 * th, &s2, &c2);
+  sincos_small(2.0 * th, &s2, &c2);
   const double c4 = 2.0 * c2 * c2 - 1.0;
   const double s4 = 2.0 * s2 * c2;
   Qb q;
@@ -40,34 +70,41 @@ __device__ __forceinline__ Qb qbar_of(const StripMat &m, double th) {
 //   du/dy = (P du_l + M du_r)/hy at xi  = -g,  (M du_l + P du_r)/hy at xi  = +g,
 // (P, M the interpolation weights of the Gauss abscissae), so every
 // derivative is shared by two Gauss points; the transposed operator uses the
-// same pairs.
-__device__ __forceinline__ void elem_forces(const StripGeom &g, const Qb q[4], const double u[4],
-                                            const double v[4], double fu[4], double fv[4]) {
+// same pairs.  Gauss points are processed one at a time so only one rotated
+// stiffness is live.  QB(q) must yield the Qb of Gauss point q.
+template <class QbAt>
+__device__ __forceinline__ void elem_forces_q(const StripGeom &g, QbAt QB, const double u[4], const double v[4],
+                                              double fu[4], double fv[4]) {
   const double P = GP_P, M = GP_M;
   const double dub = u[1] - u[0], dut = u[2] - u[3], dul = u[3] - u[0], dur = u[2] - u[1];
   const double dvb = v[1] - v[0], dvt = v[2] - v[3], dvl = v[3] - v[0], dvr = v[2] - v[1];
-  const double uxL = (P * dub + M * dut) * g.ihx, uxH = (M * dub + P * dut) * g.ihx;
-  const double vxL = (P * dvb + M * dvt) * g.ihx, vxH = (M * dvb + P * dvt) * g.ihx;
-  const double uyL = (P * dul + M * dur) * g.ihy, uyH = (M * dul + P * dur) * g.ihy;
-  const double vyL = (P * dvl + M * dvr) * g.ihy, vyH = (M * dvl + P * dvr) * g.ihy;
-  double sxx[4], syy[4], txy[4];
-#define MLMC_GP_STRESS(Q, UX, VX, UY, VY)                                   \
-  {                                                                         \
-    const double ex = UX, ey = VY, gm = UY + VX;                            \
-    sxx[Q] = q[Q].q11 * ex + q[Q].q12 * ey + q[Q].q16 * gm;                 \
-    syy[Q] = q[Q].q12 * ex + q[Q].q22 * ey + q[Q].q26 * gm;                 \
-    txy[Q] = q[Q].q16 * ex + q[Q].q26 * ey + q[Q].q66 * gm;                 \
+  const double ux[2] = {(P * dub + M * dut) * g.ihx, (M * dub + P * dut) * g.ihx};
+  const double vx[2] = {(P * dvb + M * dvt) * g.ihx, (M * dvb + P * dvt) * g.ihx};
+  const double uy[2] = {(P * dul + M * dur) * g.ihy, (M * dul + P * dur) * g.ihy};
+  const double vy[2] = {(P * dvl + M * dvr) * g.ihy, (M * dvl + P * dvr) * g.ihy};
+  // stress sums: sxx and txy paired by eta (x-derivative), syy and txy paired by xi
+  double ax[2], ay[2], aty[2], atx[2];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int a = q & 1, b = q >> 1;
+    const Qb qb = QB(q);
+    const double ex = ux[b], ey = vy[a], gm = uy[a] + vx[b];
+    const double sxx = qb.q11 * ex + qb.q12 * ey + qb.q16 * gm;
+    const double syy = qb.q12 * ex + qb.q22 * ey + qb.q26 * gm;
+    const double txy = qb.q16 * ex + qb.q26 * ey + qb.q66 * gm;
+    if (q == 0) {
+      ax[0] = sxx; ay[0] = syy; aty[0] = txy; atx[0] = txy;
+    } else if (q == 1) {
+      ax[0] += sxx; ay[1] = syy; aty[1] = txy; atx[0] += txy;
+    } else if (q == 2) {
+      ax[1] = sxx; ay[0] += syy; aty[0] += txy; atx[1] = txy;
+    } else {
+      ax[1] += sxx; ay[1] += syy; aty[1] += txy; atx[1] += txy;
+    }
   }
-  MLMC_GP_STRESS(0, uxL, vxL, uyL, vyL)
-  MLMC_GP_STRESS(1, uxL, vxL, uyH, vyH)
-  MLMC_GP_STRESS(2, uxH, vxH, uyL, vyL)
-  MLMC_GP_STRESS(3, uxH, vxH, uyH, vyH)
-#undef MLMC_GP_STRESS
   const double w = g.wdet;
-  const double axL = (sxx[0] + sxx[1]) * w, axH = (sxx[2] + sxx[3]) * w;
-  const double atyL = (txy[0] + txy[2]) * w, atyH = (txy[1] + txy[3]) * w;
-  const double ayL = (syy[0] + syy[2]) * w, ayH = (syy[1] + syy[3]) * w;
-  const double atxL = (txy[0] + txy[1]) * w, atxH = (txy[2] + txy[3]) * w;
+  const double axL = ax[0] * w, axH = ax[1] * w, atyL = aty[0] * w, atyH = aty[1] * w;
+  const double ayL = ay[0] * w, ayH = ay[1] * w, atxL = atx[0] * w, atxH = atx[1] * w;
   const double gub = (P * axL + M * axH) * g.ihx, gut = (M * axL + P * axH) * g.ihx;
   const double gul = (P * atyL + M * atyH) * g.ihy, gur = (M * atyL + P * atyH) * g.ihy;
   const double gvl = (P * ayL + M * ayH) * g.ihy, gvr = (M * ayL + P * ayH) * g.ihy;
@@ -80,6 +117,11 @@ __device__ __forceinline__ void elem_forces(const StripGeom &g, const Qb q[4], c
   fv[1] = gvb - gvr;
   fv[2] = gvt + gvr;
   fv[3] = -gvt + gvl;
+}
+
+__device__ __forceinline__ void elem_forces(const StripGeom &g, const Qb q[4], const double u[4],
+                                            const double v[4], double fu[4], double fv[4]) {
+  elem_forces_q(g, [&](int k) { return q[k]; }, u, v, fu, fv);
 }
 
 // largest compressive stress along the fibres at the four Gauss points:
@@ -98,7 +140,7 @@ __device__ __forceinline__ double elem_max_fibre_compression(const StripGeom &g,
   for (int q = 0; q < 4; ++q) {
     const int a = q & 1, b = q >> 1;
     double s2, c2;
-    sincos(2.0 * th[q], &s2, &c2);
+    sincos_small(2.0 * th[q], &s2, &c2);
     const double c4 = 2.0 * c2 * c2 - 1.0, s4 = 2.0 * s2 * c2;
     const double q11 = m.U1 + m.U2 * c2 + m.U3 * c4, q22 = m.U1 - m.U2 * c2 + m.U3 * c4;
     const double q12 = m.U4 - m.U3 * c4, q66 = m.U5 - m.U3 * c4;
@@ -121,14 +163,19 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ double block_sum(double v, double *red4) {
+// block of `waves` waves (blockDim = 64 * waves, waves <= 8): wave sums, then in order
+__device__ __forceinline__ double block_sum_w(double v, double *red, int waves) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
-  if (lane == 0) red4[wid] = v;
+  if (lane == 0) red[wid] = v;
   __syncthreads();
-  return ((red4[0] + red4[1]) + red4[2]) + red4[3];
+  double t = red[0];
+  for (int w = 1; w < waves; ++w) t += red[w];
+  return t;
 }
+
+__device__ __forceinline__ double block_sum(double v, double *red4) { return block_sum_w(v, red4, 4); }
 
 // sum of n values in fixed order: thread t adds entries t, t+256, ... then block_sum
 __device__ __forceinline__ double block_sum_strided(const double *a, int n, double *red4) {
@@ -136,6 +183,9 @@ __device__ __forceinline__ double block_sum_strided(const double *a, int n, doub
   for (int k = threadIdx.x; k < n; k += 256) s += a[k];
   return block_sum(s, red4);
 }
+
+// sum in a fixed order for TILE_THREADS-wide blocks
+__device__ __forceinline__ double tile_sum(double v, double *red) { return block_sum_w(v, red, TILE_WAVES); }
 
 __device__ __forceinline__ double wave_max(double v) {
   for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));

@@ -48,11 +48,11 @@ __device__ __forceinline__ void tile_elements(const StripGeom &g, const StripMat
       const double *tp = theta_s + 4 * ((size_t)ey * g.nx + ex);
       const double2 t01 = *reinterpret_cast<const double2 *>(tp);
       const double2 t23 = *reinterpret_cast<const double2 *>(tp + 2);
-      Qb q[4] = {qbar_of(m, t01.x), qbar_of(m, t01.y), qbar_of(m, t23.x), qbar_of(m, t23.y)};
+      const double th[4] = {t01.x, t01.y, t23.x, t23.y};
       const int n0 = ley * HALO_X + lex;
       const double u[4] = {nu[n0], nu[n0 + 1], nu[n0 + HALO_X + 1], nu[n0 + HALO_X]};
       const double v[4] = {nv[n0], nv[n0 + 1], nv[n0 + HALO_X + 1], nv[n0 + HALO_X]};
-      elem_forces(g, q, u, v, fu, fv);
+      elem_forces_q(g, [&](int q) { return qbar_of(m, th[q]); }, u, v, fu, fv);
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_apply(StripGeom g, StripMat m,
   __syncthreads();
   const int li = threadIdx.x % TILE_X, lj = threadIdx.x / TILE_X;
   const int i = tc.i0 + li, j = tc.j0 + lj;
-  if (i < g.nnx && j < g.nny) {
+  if (threadIdx.x < TILE_NODES && i < g.nnx && j < g.nny) {
     double yu, yv;
     gather_node(eo, li, lj, 0, yu, yv);
     const size_t o = vb + 2 * ((size_t)j * g.nnx + i);
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_apply(StripGeom g, StripMat m,
 __global__ __launch_bounds__(TILE_THREADS) void k_setup(StripGeom g, StripMat m, PcgSlots S,
                                                         double *__restrict__ b_out, double *__restrict__ dinv_out) {
   __shared__ double eo[16][TILE_ELEMS];
-  __shared__ double red4[4];
+  __shared__ double red4[TILE_WAVES];
   const int s = blockIdx.y, t = blockIdx.x;
   const TileCoord tc = tile_of(g, t);
   const double *theta_s = S.theta + (size_t)s * 4 * g.nelem;
@@ -233,8 +233,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_setup(StripGeom g, StripMat m,
   __syncthreads();
   const int li = threadIdx.x % TILE_X, lj = threadIdx.x / TILE_X;
   const int i = tc.i0 + li, j = tc.j0 + lj;
-  double prz = 0.0, prr = 0.0;
-  if (i < g.nnx && j < g.nny) {
+  if (threadIdx.x < TILE_NODES && i < g.nnx && j < g.nny) {
     double diu, div, kgu, kgv;
     gather_node(eo, li, lj, 0, diu, div);
     gather_node(eo, li, lj, 8, kgu, kgv);
@@ -247,48 +246,128 @@ __global__ __launch_bounds__(TILE_THREADS) void k_setup(StripGeom g, StripMat m,
     *reinterpret_cast<double2 *>(S.x + o) = make_double2(0.0, 0.0);
     if (b_out) *reinterpret_cast<double2 *>(b_out + o) = make_double2(bu, bv);
     if (dinv_out) *reinterpret_cast<double2 *>(dinv_out + o) = make_double2(du, dv);
-    prz = bu * (du * bu) + bv * (dv * bv);
-    prr = bu * bu + bv * bv;
+  }
+  if (t == 0 && threadIdx.x == 0) {
+    S.it_a[s] = 0;
+    S.status[s] = S_OK;
+    S.active[s] = 1;
+  }
+}
+
+// initial partial sums of r.z and r.r (z = dinv r) per vector-pass chunk,
+// into parity buffer 0
+__global__ __launch_bounds__(256) void k_init_partials(StripGeom g, PcgSlots S) {
+  __shared__ double red4[4];
+  const int s = blockIdx.y, c = blockIdx.x;
+  const size_t vb = (size_t)s * 2 * g.nnode;
+  double prz = 0.0, prr = 0.0;
+  for (int k = 0; k < CHUNK / 256; ++k) {
+    const int node = c * CHUNK + k * 256 + threadIdx.x;
+    if (node < g.nnode) {
+      const double2 rv = *reinterpret_cast<const double2 *>(S.r + vb + 2 * (size_t)node);
+      const double2 dv = *reinterpret_cast<const double2 *>(S.dinv + vb + 2 * (size_t)node);
+      prz += rv.x * (dv.x * rv.x) + rv.y * (dv.y * rv.y);
+      prr += rv.x * rv.x + rv.y * rv.y;
+    }
   }
   prz = block_sum(prz, red4);
   prr = block_sum(prr, red4);
   if (threadIdx.x == 0) {
-    S.part_rz[(size_t)s * g.ntiles + t] = prz;
-    S.part_rr[(size_t)s * g.ntiles + t] = prr;
-    if (t == 0) {
-      S.it_a[s] = 0;
-      S.status[s] = S_OK;
-      S.active[s] = 1;
-    }
+    S.part_rz[(size_t)s * g.nchunks + c] = prz;
+    S.part_rr[(size_t)s * g.nchunks + c] = prr;
   }
 }
 
+// blocks are dispatched round-robin over the 8 XCDs; give every XCD a
+// contiguous range of logical blocks so tiles that share halo rows and columns
+// (neighbours of the same sample) meet in the same L2
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+  return x * q + min(x, r) + k;
+}
+
 // ---------------------------------------------------------------- PCG pass 1
-// Convergence test on the reduced r.r, beta = rz_k / rz_{k-1},
-// p_k = z_k + beta p_{k-1} on the tile and its halo, Ap = A p_k on the owned
-// nodes, partial p.Ap.  p is double-buffered by iteration parity because
-// neighbouring tiles read p_{k-1} in their halos while this one writes p_k.
-__global__ __launch_bounds__(TILE_THREADS) void k_pass1(StripGeom g, StripMat m, PcgSlots S) {
-  __shared__ double nu[TILE_NODES_H], nv[TILE_NODES_H];
-  __shared__ double eo[8][TILE_ELEMS];
-  __shared__ double red4[4];
-  __shared__ int flag;
-  const int s = blockIdx.y, t = blockIdx.x;
-  // one read of the slot flag per block: tile 0 of this launch may clear it concurrently
-  if (threadIdx.x == 0) flag = S.active[s];
-  __syncthreads();
-  if (!flag) return;
-  const int it = S.it_a[s], par = it & 1;
-  const size_t pb = ((size_t)par * S.S + s) * g.ntiles;
-  const double rz = block_sum_strided(S.part_rz + pb, g.ntiles, red4);
-  const double rr = block_sum_strided(S.part_rr + pb, g.ntiles, red4);
-  const double bb = (it == 0) ? rr : S.bb[s];
+// Iteration `it` (all slots of a batch iterate in lock-step; par = it & 1).
+// One wave per column-sweep tile: lane l holds node column i0 - 1 + l (lanes
+// 1..TW own their column, lanes 0 and TW + 1 are halo) and the element whose
+// lower-left node is that column.  The wave walks up the element rows; the
+// right neighbour's nodal values and the left neighbour's element forces come
+// from lane shuffles, the previous row's forces stay in registers, and every
+// owned node's four contributions are summed in the fixed order
+// ((e(i-1,j-1).f2 + e(i,j-1).f3) + e(i-1,j).f1) + e(i,j).f0.
+// Per sample: convergence test on r.r, beta = rz_it / rz_{it-1},
+// p = z + beta p_old (not stored: pass 2 recomputes it bit-identically, so
+// neighbours read p_old in their halos), Ap = A p, partial p.Ap per tile.
+// The next row's loads are issued before the current row is computed.
+struct RowVals {
+  double zu, zv, qu, qv;
+};
+
+__device__ __forceinline__ RowVals load_row(const StripGeom &g, const PcgSlots &S, size_t vb, int i, bool colv,
+                                            int jr, bool with_p) {
+  RowVals v = {0.0, 0.0, 0.0, 0.0};
+  if (colv && jr >= 0 && jr < g.nny) {
+    const size_t o = vb + 2 * ((size_t)jr * g.nnx + i);
+    const double2 rv = *reinterpret_cast<const double2 *>(S.r + o);
+    const double2 dv = *reinterpret_cast<const double2 *>(S.dinv + o);
+    v.zu = dv.x * rv.x;
+    v.zv = dv.y * rv.y;
+    if (with_p) {
+      const double2 po = *reinterpret_cast<const double2 *>(S.p + o);
+      v.qu = po.x;
+      v.qv = po.y;
+    }
+  }
+  return v;
+}
+
+__device__ __forceinline__ double4 load_theta(const StripGeom &g, const double *theta_s, int i, bool elv, int ey) {
+  if (elv && ey >= 0 && ey < g.ny) {
+    const double *tp = theta_s + 4 * ((size_t)ey * g.nx + i);
+    const double2 a = *reinterpret_cast<const double2 *>(tp);
+    const double2 b = *reinterpret_cast<const double2 *>(tp + 2);
+    return make_double4(a.x, a.y, b.x, b.y);
+  }
+  return make_double4(0.0, 0.0, 0.0, 0.0);
+}
+
+__global__ __launch_bounds__(64) void k_pass1(StripGeom g, StripMat m, PcgSlots S, int it, int nblocks) {
+  const int lt = xcd_remap(blockIdx.x, nblocks);
+  const int s = lt / g.sw_ntiles, t = lt - s * g.sw_ntiles;
+  const int lane = threadIdx.x;
+  const int par = it & 1;
+  const size_t vb = (size_t)s * 2 * g.nnode;
+  const double *theta_s = S.theta + (size_t)s * 4 * g.nelem;
+  const int active = __builtin_amdgcn_readfirstlane(S.active[s]);
+  const size_t pb = ((size_t)par * S.S + s) * g.nchunks;
+  double prz = 0.0, prr = 0.0;
+  for (int k = lane; k < g.nchunks; k += 64) {
+    prz += S.part_rz[pb + k];
+    prr += S.part_rr[pb + k];
+  }
+  const double rz_prev = (it > 0) ? S.rzs[(size_t)(par ^ 1) * S.S + s] : 1.0;
+  const double bb_old = (it > 0) ? S.bb[s] : 0.0;
+  const int tx = t % g.sw_ntx, ty = t / g.sw_ntx;
+  const int i0 = tx * g.sw_tw, j0 = ty * g.sw_ty;
+  const int i = i0 - 1 + lane;
+  const bool colv = lane <= g.sw_tw + 1 && i >= 0 && i < g.nnx;
+  const bool elv = lane <= g.sw_tw && i >= 0 && i < g.nx;
+  const bool own = lane >= 1 && lane <= g.sw_tw && i < g.nnx;
+  const int row_end = min(j0 + g.sw_ty, g.nny);
+  const bool wp = it > 0;
+  RowVals lo = load_row(g, S, vb, i, colv, j0 - 1, wp);
+  RowVals nhi = load_row(g, S, vb, i, colv, j0, wp);
+  double4 nth = load_theta(g, theta_s, i, elv, j0 - 1);
+  const double rz = wave_sum(prz);
+  if (!active) return;
+  const double rr = wave_sum(prr);
+  const double bb = (it == 0) ? rr : bb_old;
   const double tol2 = S.rtol2 * bb;
   int verdict = -1;
   if (!isfinite(rr) || !isfinite(rz)) verdict = S_NAN;
   else if (rr <= tol2) verdict = S_OK;
   else if (it >= S.max_iter) verdict = S_NOCONV;
-  if (t == 0 && threadIdx.x == 0) {
+  if (t == 0 && lane == 0) {
     if (it == 0) S.bb[s] = rr;
     S.rzs[(size_t)par * S.S + s] = rz;
     S.relres[s] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
@@ -299,100 +378,118 @@ __global__ __launch_bounds__(TILE_THREADS) void k_pass1(StripGeom g, StripMat m,
     }
   }
   if (verdict >= 0) return;
-  const double beta = (it == 0) ? 0.0 : rz / S.rzs[(size_t)(par ^ 1) * S.S + s];
-  const TileCoord tc = tile_of(g, t);
-  const size_t vb = (size_t)s * 2 * g.nnode;
-  const double *p_old = S.p + (size_t)par * S.S * 2 * g.nnode + vb;
-  double *p_new = S.p + (size_t)(par ^ 1) * S.S * 2 * g.nnode + vb;
-  for (int k = threadIdx.x; k < TILE_NODES_H; k += TILE_THREADS) {
-    const int i = tc.i0 - 1 + k % HALO_X, j = tc.j0 - 1 + k / HALO_X;
-    double a = 0.0, b = 0.0;
-    if (node_in(g, i, j)) {
-      const size_t o = 2 * ((size_t)j * g.nnx + i);
-      const double2 rv = *reinterpret_cast<const double2 *>(S.r + vb + o);
-      const double2 dv = *reinterpret_cast<const double2 *>(S.dinv + vb + o);
-      a = dv.x * rv.x;
-      b = dv.y * rv.y;
-      if (it > 0) {
-        const double2 po = *reinterpret_cast<const double2 *>(p_old + o);
-        a = fma(beta, po.x, a);
-        b = fma(beta, po.y, b);
-      }
-    }
-    nu[k] = a;
-    nv[k] = b;
-  }
-  __syncthreads();
-  tile_elements(g, m, S.theta + (size_t)s * 4 * g.nelem, tc, nu, nv, eo);
-  __syncthreads();
-  const int li = threadIdx.x % TILE_X, lj = threadIdx.x / TILE_X;
-  const int i = tc.i0 + li, j = tc.j0 + lj;
+  const double beta = (it == 0) ? 0.0 : rz / rz_prev;
+  double plu = fma(beta, lo.qu, lo.zu), plv = fma(beta, lo.qv, lo.zv);
+  double f2u = 0.0, f2v = 0.0, f3u = 0.0, f3v = 0.0;  // previous element row: f2 of the left lane, own f3
   double part = 0.0;
-  if (i < g.nnx && j < g.nny) {
-    double yu, yv;
-    gather_node(eo, li, lj, 0, yu, yv);
-    const int h = (lj + 1) * HALO_X + li + 1;
-    const double pu = nu[h], pv = nv[h];
-    if (i == 0) { yu = pu; yv = pv; }
-    if (i == g.nx) yu = pu;
-    const size_t o = 2 * ((size_t)j * g.nnx + i);
-    *reinterpret_cast<double2 *>(p_new + o) = make_double2(pu, pv);
-    *reinterpret_cast<double2 *>(S.Ap + vb + o) = make_double2(yu, yv);
-    part = pu * yu + pv * yv;
+  const int nk = row_end - j0;
+  for (int k = 0; k <= nk; ++k) {
+    const int ey = j0 - 1 + k;
+    const RowVals hi = nhi;
+    const double4 th4 = nth;
+    if (k < nk) {
+      nhi = load_row(g, S, vb, i, colv, ey + 2, wp);
+      nth = load_theta(g, theta_s, i, elv, ey + 1);
+    }
+    const double phu = fma(beta, hi.qu, hi.zu), phv = fma(beta, hi.qv, hi.zv);
+    const double rlu = __shfl_down(plu, 1, 64), rlv = __shfl_down(plv, 1, 64);
+    const double rhu = __shfl_down(phu, 1, 64), rhv = __shfl_down(phv, 1, 64);
+    double fu[4] = {0.0, 0.0, 0.0, 0.0}, fv[4] = {0.0, 0.0, 0.0, 0.0};
+    if (elv && ey >= 0 && ey < g.ny) {
+      const double th[4] = {th4.x, th4.y, th4.z, th4.w};
+      const double u[4] = {plu, rlu, rhu, phu};
+      const double v[4] = {plv, rlv, rhv, phv};
+      elem_forces_q(g, [&](int q) { return qbar_of(m, th[q]); }, u, v, fu, fv);
+    }
+    const double f1lu = __shfl_up(fu[1], 1, 64), f1lv = __shfl_up(fv[1], 1, 64);
+    if (k >= 1 && own) {
+      double yu = ((f2u + f3u) + f1lu) + fu[0];
+      double yv = ((f2v + f3v) + f1lv) + fv[0];
+      if (i == 0) { yu = plu; yv = plv; }
+      if (i == g.nx) yu = plu;
+      *reinterpret_cast<double2 *>(S.Ap + vb + 2 * ((size_t)ey * g.nnx + i)) = make_double2(yu, yv);
+      part += plu * yu + plv * yv;
+    }
+    f2u = __shfl_up(fu[2], 1, 64);
+    f2v = __shfl_up(fv[2], 1, 64);
+    f3u = fu[3];
+    f3v = fv[3];
+    plu = phu;
+    plv = phv;
   }
-  part = block_sum(part, red4);
-  if (threadIdx.x == 0) S.part_pap[(size_t)s * g.ntiles + t] = part;
+  part = wave_sum(part);
+  if (lane == 0) S.part_pap[(size_t)s * g.sw_ntiles + t] = part;
 }
 
 // ---------------------------------------------------------------- PCG pass 2
-// alpha = rz / p.Ap; x += alpha p; r -= alpha Ap; partial r.z (z = dinv r) and r.r
-__global__ __launch_bounds__(TILE_THREADS) void k_pass2(StripGeom g, PcgSlots S) {
+// alpha = rz / p.Ap; p = z + beta p_old (bit-identical to pass 1); x += alpha p;
+// r -= alpha Ap; store p; partial r.z (z = dinv r) and r.r per chunk of CHUNK
+// consecutive nodes (all loads issued before the reduction of p.Ap)
+__global__ __launch_bounds__(256) void k_pass2(StripGeom g, PcgSlots S, int it) {
+  constexpr int PER = CHUNK / 256;
   __shared__ double red4[4];
   __shared__ int flag;
-  const int s = blockIdx.y, t = blockIdx.x;
+  const int s = blockIdx.y, c = blockIdx.x;
+  const int par = it & 1;
   if (threadIdx.x == 0) flag = S.active[s];
-  __syncthreads();
-  if (!flag) return;
-  const int it = S.it_b[s], par = it & 1;
-  const double pap = block_sum_strided(S.part_pap + (size_t)s * g.ntiles, g.ntiles, red4);
+  double ppap = 0.0;
+  for (int k = threadIdx.x; k < g.sw_ntiles; k += 256) ppap += S.part_pap[(size_t)s * g.sw_ntiles + k];
   const double rz = S.rzs[(size_t)par * S.S + s];
+  const double rz_prev = (it > 0) ? S.rzs[(size_t)(par ^ 1) * S.S + s] : 1.0;
+  const size_t vb = (size_t)s * 2 * g.nnode;
+  double2 pv[PER], av[PER], xv[PER], rv[PER], dv[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int node = c * CHUNK + k * 256 + threadIdx.x;
+    pv[k] = av[k] = xv[k] = rv[k] = dv[k] = make_double2(0.0, 0.0);
+    if (node < g.nnode) {
+      const size_t o = vb + 2 * (size_t)node;
+      if (it > 0) pv[k] = *reinterpret_cast<const double2 *>(S.p + o);
+      av[k] = *reinterpret_cast<const double2 *>(S.Ap + o);
+      xv[k] = *reinterpret_cast<const double2 *>(S.x + o);
+      rv[k] = *reinterpret_cast<const double2 *>(S.r + o);
+      dv[k] = *reinterpret_cast<const double2 *>(S.dinv + o);
+    }
+  }
+  const double pap = block_sum(ppap, red4);  // publishes flag
+  if (!flag) return;
   if (!(pap > 0.0) || !isfinite(pap)) {
-    if (t == 0 && threadIdx.x == 0) {
+    if (c == 0 && threadIdx.x == 0) {
       S.status[s] = isfinite(pap) ? S_BREAKDOWN : S_NAN;
       S.active[s] = 0;
     }
     return;
   }
   const double alpha = rz / pap;
-  const TileCoord tc = tile_of(g, t);
-  const size_t vb = (size_t)s * 2 * g.nnode;
-  const double *p_new = S.p + (size_t)(par ^ 1) * S.S * 2 * g.nnode + vb;
-  const int li = threadIdx.x % TILE_X, lj = threadIdx.x / TILE_X;
-  const int i = tc.i0 + li, j = tc.j0 + lj;
+  const double beta = (it == 0) ? 0.0 : rz / rz_prev;
   double prz = 0.0, prr = 0.0;
-  if (i < g.nnx && j < g.nny) {
-    const size_t o = 2 * ((size_t)j * g.nnx + i);
-    const double2 pv = *reinterpret_cast<const double2 *>(p_new + o);
-    const double2 av = *reinterpret_cast<const double2 *>(S.Ap + vb + o);
-    double2 xv = *reinterpret_cast<const double2 *>(S.x + vb + o);
-    double2 rv = *reinterpret_cast<const double2 *>(S.r + vb + o);
-    const double2 dv = *reinterpret_cast<const double2 *>(S.dinv + vb + o);
-    xv.x = fma(alpha, pv.x, xv.x);
-    xv.y = fma(alpha, pv.y, xv.y);
-    rv.x = fma(-alpha, av.x, rv.x);
-    rv.y = fma(-alpha, av.y, rv.y);
-    *reinterpret_cast<double2 *>(S.x + vb + o) = xv;
-    *reinterpret_cast<double2 *>(S.r + vb + o) = rv;
-    prz = rv.x * (dv.x * rv.x) + rv.y * (dv.y * rv.y);
-    prr = rv.x * rv.x + rv.y * rv.y;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int node = c * CHUNK + k * 256 + threadIdx.x;
+    if (node < g.nnode) {
+      const size_t o = vb + 2 * (size_t)node;
+      double2 pn;
+      pn.x = fma(beta, pv[k].x, dv[k].x * rv[k].x);
+      pn.y = fma(beta, pv[k].y, dv[k].y * rv[k].y);
+      double2 x2 = xv[k], r2 = rv[k];
+      x2.x = fma(alpha, pn.x, x2.x);
+      x2.y = fma(alpha, pn.y, x2.y);
+      r2.x = fma(-alpha, av[k].x, r2.x);
+      r2.y = fma(-alpha, av[k].y, r2.y);
+      *reinterpret_cast<double2 *>(S.p + o) = pn;
+      *reinterpret_cast<double2 *>(S.x + o) = x2;
+      *reinterpret_cast<double2 *>(S.r + o) = r2;
+      prz += r2.x * (dv[k].x * r2.x) + r2.y * (dv[k].y * r2.y);
+      prr += r2.x * r2.x + r2.y * r2.y;
+    }
   }
   prz = block_sum(prz, red4);
   prr = block_sum(prr, red4);
   if (threadIdx.x == 0) {
-    const size_t pb = ((size_t)(par ^ 1) * S.S + s) * g.ntiles + t;
+    const size_t pb = ((size_t)(par ^ 1) * S.S + s) * g.nchunks + c;
     S.part_rz[pb] = prz;
     S.part_rr[pb] = prr;
-    if (t == 0) S.it_a[s] = it + 1;
+    if (c == 0) S.it_a[s] = it + 1;
   }
 }
 
@@ -563,11 +660,21 @@ void launch_setup(const StripGeom &g, const StripMat &m, const PcgSlots &S, int 
                   hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_setup, tile_grid(g, n), dim3(TILE_THREADS), 0, st, g, m, S, b_out, dinv_out);
+  hipLaunchKernelGGL(k_init_partials, dim3(g.nchunks, n), dim3(256), 0, st, g, S);
 }
 
-void launch_pcg_iteration(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_pass1, tile_grid(g, n), dim3(TILE_THREADS), 0, st, g, m, S);
-  hipLaunchKernelGGL(k_pass2, tile_grid(g, n), dim3(TILE_THREADS), 0, st, g, S);
+void launch_pcg_pass1(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n, int it, hipStream_t st) {
+  const int nb = g.sw_ntiles * n;
+  hipLaunchKernelGGL(k_pass1, dim3(nb), dim3(64), 0, st, g, m, S, it, nb);
+}
+
+void launch_pcg_pass2(const StripGeom &g, const PcgSlots &S, int n, int it, hipStream_t st) {
+  hipLaunchKernelGGL(k_pass2, dim3(g.nchunks, n), dim3(256), 0, st, g, S, it);
+}
+
+void launch_pcg_iteration(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n, int it, hipStream_t st) {
+  launch_pcg_pass1(g, m, S, n, it, st);
+  launch_pcg_pass2(g, S, n, it, st);
 }
 
 int qoi_parts(const StripGeom &g) { return ((g.qx1 - g.qx0) * (g.qy1 - g.qy0) + 255) / 256; }

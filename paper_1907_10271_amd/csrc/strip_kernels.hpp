@@ -16,7 +16,9 @@ void launch_apply(const StripGeom &g, const StripMat &m, const double *theta, co
                   int n, hipStream_t st);
 void launch_setup(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n, double *b_out, double *dinv_out,
                   hipStream_t st);
-void launch_pcg_iteration(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n, hipStream_t st);
+void launch_pcg_pass1(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n, int it, hipStream_t st);
+void launch_pcg_pass2(const StripGeom &g, const PcgSlots &S, int n, int it, hipStream_t st);
+void launch_pcg_iteration(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n, int it, hipStream_t st);
 int qoi_parts(const StripGeom &g);
 void launch_qoi(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n, double *part, const int *out_idx,
                 double *q, mlmc_info_dev *info, int coarse, hipStream_t st);
