@@ -47,6 +47,10 @@ def parse():
                     help="oracle samples per level for the CPU baseline")
     ap.add_argument("--levels", type=str, default="",
                     help="run only these levels (comma list; profiling runs, the line is then not the benchmark)")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="mixed: FP32 operator on BF16 angles inside FP64 refinement")
+    ap.add_argument("--mixed", type=str, default="",
+                    help="overrides of the mixed-precision settings, e.g. update_factor=0.1,theta_storage=fp32")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
@@ -118,7 +122,14 @@ def main():
     import torch
     import paper_1907_10271_amd as pk
     dev = torch.device("cuda:0")
-    ctx = pk.Context(mi.config_text(WORKLOAD))
+    ccfg = dict(cfg)
+    if args.mixed:
+        mx = dict(ccfg.get("mixed", {}))
+        for kv in args.mixed.split(","):
+            k, v = kv.split("=")
+            mx[k] = v if k == "theta_storage" else float(v)
+        ccfg["mixed"] = mx
+    ctx = pk.Context(ccfg)
     nsteps = args.warmup + args.steps
     xi = []
     for l, n in enumerate(mix):
@@ -126,6 +137,7 @@ def main():
         xi.append(torch.from_numpy(rows).to(dev))
     torch.cuda.synchronize()
     reqs = [[(k, l, l > 0) for k in range(n)] for l, n in enumerate(mix)]
+    prec = pk.MIXED if args.precision == "mixed" else pk.FP64
     levels = [int(v) for v in args.levels.split(",")] if args.levels else list(range(len(mix)))
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -144,7 +156,7 @@ def main():
             x = xi[l][s * n:(s + 1) * n]
             if events is not None:
                 events[l][0].record(stream)
-            qf, qc, info = ctx.solve_batch(reqs[l], x)
+            qf, qc, info = ctx.solve_batch(reqs[l], x, precision=prec)
             acc = ctx.level_stats(l, qf, qc if l > 0 else None)
             if events is not None:
                 events[l][1].record(stream)
@@ -176,8 +188,8 @@ def main():
                           "coupled": l > 0, "ms": round(float(ms), 3),
                           "samples_per_s": round(n / (ms / 1e3), 1),
                           "pcg_iters_mean": round(float(its_f.mean()), 1), "all_converged": bool(ok)})
-    p1 = ctx.profile_read(0)
-    p2 = ctx.profile_read(1)
+    p1 = ctx.profile_read(0 if prec == pk.FP64 else 2)
+    p2 = ctx.profile_read(1 if prec == pk.FP64 else 3)
     achieved = p1["bytes"] / (p1["ms"] / 1e3) / 1e9
     total = sum(n for l, n in enumerate(mix) if l in levels)
     out = {
@@ -191,7 +203,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == pk.FP64 else "f32+bf16 inner, f64 refinement",
         "data": "synthetic (seeded KL parameters and wrinkles)",
         "config": {"workload": "waviness strip 20x5 mm, 4 levels 64x16..512x128, Matern-3/2 20 modes + wrinkle, "
                                "Jacobi-PCG rtol 1e-10, FP64",

@@ -32,6 +32,16 @@ struct StripPool {
   int *it_a = nullptr, *it_b = nullptr, *status = nullptr, *active = nullptr, *outidx = nullptr;
   int64_t *rows = nullptr;
   size_t bytes = 0;
+  // mixed precision (allocated on first use): FP64 rhs, BF16 angles, FP32 inner solver
+  bool has_mixed = false;
+  double *b64 = nullptr, *m_part_rr = nullptr, *m_relres = nullptr, *f_rr_ref = nullptr;
+  int *m_updates = nullptr, *f_ru = nullptr;
+  void *theta16 = nullptr;  // inner-solver angles: bfloat16 or FP32
+  float *fx = nullptr, *fr = nullptr, *fp = nullptr, *fAp = nullptr, *fdinv = nullptr;
+  double *f_pap = nullptr, *f_rz = nullptr, *f_rr = nullptr, *f_rzs = nullptr, *f_tol2 = nullptr, *f_bb = nullptr,
+         *f_relres = nullptr;
+  int *f_it_a = nullptr, *f_it_b = nullptr, *f_status = nullptr, *f_active = nullptr;
+  size_t mixed_bytes = 0;
 };
 
 struct StripLevel {
@@ -51,6 +61,9 @@ struct mlmc_ctx {
   StripMat mat{};
   double rtol = 1e-10;
   int max_iter = 100000;
+  double ru_factor = 0.1;   // reliable update when the FP32 residual fell by this factor
+  int ru_every = 4;         // FP64 residual checks every ru_every iterations
+  int theta_fp32 = 0;       // mixed: angles stored as FP32 instead of bfloat16
   std::vector<StripLevel> lv;
   size_t budget = 0, used = 0;
   int *h_active = nullptr;
@@ -61,8 +74,8 @@ struct mlmc_ctx {
   // diagnostics: event timing of the PCG passes
   bool prof = false;
   std::vector<hipEvent_t> ev;
-  double prof_ms[2] = {0, 0}, prof_bytes[2] = {0, 0};
-  int64_t prof_launches[2] = {0, 0};
+  double prof_ms[4] = {0, 0, 0, 0}, prof_bytes[4] = {0, 0, 0, 0};
+  int64_t prof_launches[4] = {0, 0, 0, 0};
   std::vector<int> h_iters;
 };
 
@@ -104,6 +117,14 @@ StripGeom make_geom(const Json &cfg, int level) {
   g.ihx = 1.0 / g.hx;
   g.ihy = 1.0 / g.hy;
   g.wdet = 0.25 * g.hx * g.hy;
+  g.pxi = GP_P * g.ihx;
+  g.mxi = GP_M * g.ihx;
+  g.pyi = GP_P * g.ihy;
+  g.myi = GP_M * g.ihy;
+  g.pxw = GP_P * g.ihx * g.wdet;
+  g.mxw = GP_M * g.ihx * g.wdet;
+  g.pyw = GP_P * g.ihy * g.wdet;
+  g.myw = GP_M * g.ihy * g.wdet;
   g.delta = cfg.number("delta");
   std::vector<double> reg = cfg.numbers("qoi_region");
   if (reg.size() != 4) throw std::runtime_error("qoi_region needs 4 numbers");
@@ -130,7 +151,20 @@ StripMat make_material(const Json &cfg) {
   s.U3 = (s.Q11 + s.Q22 - 2 * s.Q12 - 4 * s.Q66) / 8;
   s.U4 = (s.Q11 + s.Q22 + 6 * s.Q12 - 4 * s.Q66) / 8;
   s.U5 = (s.Q11 + s.Q22 - 2 * s.Q12 + 4 * s.Q66) / 8;
+  s.fU1 = (float)s.U1;
+  s.fU2 = (float)s.U2;
+  s.fU3 = (float)s.U3;
+  s.fU4 = (float)s.U4;
+  s.fU5 = (float)s.U5;
   return s;
+}
+
+size_t strip_mixed_slot_bytes(const StripGeom &g) {
+  const size_t n2 = (size_t)2 * g.nnode;
+  return n2 * sizeof(double)                               // b
+         + (size_t)4 * g.nelem * sizeof(float)             // inner angles (BF16 or FP32)
+         + 5 * n2 * sizeof(float)                          // FP32 x, r, p, Ap, dinv
+         + (size_t)(2 * g.sw_ntiles + 4 * g.nchunks) * sizeof(double) + 16 * sizeof(double);
 }
 
 size_t strip_slot_bytes(const StripGeom &g) {
@@ -144,10 +178,13 @@ size_t strip_slot_bytes(const StripGeom &g) {
 
 void free_pool(mlmc_ctx *c, StripPool &p) {
   void *bufs[] = {p.x, p.r, p.p, p.Ap, p.dinv, p.theta, p.part_pap, p.part_rz, p.part_rr, p.rzs, p.tol2, p.bb,
-                  p.relres, p.qpart, p.it_a, p.it_b, p.status, p.active, p.outidx, p.rows};
+                  p.relres, p.qpart, p.it_a, p.it_b, p.status, p.active, p.outidx, p.rows,
+                  p.b64, p.m_part_rr, p.m_relres, p.f_rr_ref, p.m_updates, p.f_ru,
+                  p.theta16, p.fx, p.fr, p.fp, p.fAp, p.fdinv, p.f_pap, p.f_rz, p.f_rr, p.f_rzs, p.f_tol2, p.f_bb,
+                  p.f_relres, p.f_it_a, p.f_it_b, p.f_status, p.f_active};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
-  c->used -= p.bytes;
+  c->used -= p.bytes + p.mixed_bytes;
   p = StripPool{};
 }
 
@@ -156,10 +193,14 @@ hipError_t dalloc(T **p, size_t n) {
   return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
 }
 
-// make sure the pool of `level` holds at least n slots (n <= max fitting)
-int ensure_pool(mlmc_ctx *c, int level, int n) {
+int alloc_mixed(mlmc_ctx *c, int level);
+
+// make sure the pool of `level` holds at least n slots (n <= max fitting) and,
+// if `mixed`, the buffers of the mixed-precision solver
+int ensure_pool(mlmc_ctx *c, int level, int n, bool mixed = false) {
   StripLevel &L = c->lv[level];
-  if (L.pool.cap >= n) return MLMC_OK;
+  if (L.pool.cap >= n) return mixed && !L.pool.has_mixed ? alloc_mixed(c, level) : MLMC_OK;
+  const bool had_mixed = L.pool.has_mixed;
   free_pool(c, L.pool);
   const StripGeom &g = L.g;
   const size_t need = strip_slot_bytes(g) * (size_t)n;
@@ -197,7 +238,90 @@ int ensure_pool(mlmc_ctx *c, int level, int n) {
     HIPCHK(c, hipHostMalloc((void **)&c->h_active, sizeof(int) * n));
     c->h_active_cap = n;
   }
+  if (mixed || had_mixed) return alloc_mixed(c, level);
   return MLMC_OK;
+}
+
+int alloc_mixed(mlmc_ctx *c, int level) {
+  StripLevel &L = c->lv[level];
+  StripPool &p = L.pool;
+  const StripGeom &g = L.g;
+  const int n = p.cap;
+  const size_t need = strip_mixed_slot_bytes(g) * (size_t)n;
+  if (c->used + need > c->budget)
+    return fail(c, MLMC_ENOMEM, "level " + std::to_string(level) + ": mixed-precision buffers exceed the budget");
+  const size_t n2 = (size_t)2 * g.nnode * n;
+  HIPCHK(c, dalloc(&p.b64, n2));
+  HIPCHK(c, dalloc(&p.m_part_rr, (size_t)g.sw_ntiles * n));
+  HIPCHK(c, dalloc(&p.m_relres, (size_t)n));
+  HIPCHK(c, dalloc(&p.f_rr_ref, (size_t)n));
+  HIPCHK(c, dalloc(&p.m_updates, (size_t)n));
+  HIPCHK(c, dalloc(&p.f_ru, (size_t)n));
+  HIPCHK(c, hipMalloc(&p.theta16, (size_t)4 * g.nelem * n * (c->theta_fp32 ? 4 : 2)));
+  HIPCHK(c, dalloc(&p.fx, n2));
+  HIPCHK(c, dalloc(&p.fr, n2));
+  HIPCHK(c, dalloc(&p.fp, n2));
+  HIPCHK(c, dalloc(&p.fAp, n2));
+  HIPCHK(c, dalloc(&p.fdinv, n2));
+  HIPCHK(c, dalloc(&p.f_pap, (size_t)g.sw_ntiles * n));
+  HIPCHK(c, dalloc(&p.f_rz, (size_t)2 * g.nchunks * n));
+  HIPCHK(c, dalloc(&p.f_rr, (size_t)2 * g.nchunks * n));
+  HIPCHK(c, dalloc(&p.f_rzs, (size_t)2 * n));
+  HIPCHK(c, dalloc(&p.f_tol2, (size_t)n));
+  HIPCHK(c, dalloc(&p.f_bb, (size_t)n));
+  HIPCHK(c, dalloc(&p.f_relres, (size_t)n));
+  HIPCHK(c, dalloc(&p.f_it_a, (size_t)n));
+  HIPCHK(c, dalloc(&p.f_it_b, (size_t)n));
+  HIPCHK(c, dalloc(&p.f_status, (size_t)n));
+  HIPCHK(c, dalloc(&p.f_active, (size_t)n));
+  HIPCHK(c, hipMemset(p.f_active, 0, sizeof(int) * n));
+  HIPCHK(c, hipMemset(p.f_ru, 0, sizeof(int) * n));
+  p.has_mixed = true;
+  p.mixed_bytes = need;
+  c->used += need;
+  return MLMC_OK;
+}
+
+PcgState<float> inner_of(mlmc_ctx *c, int level) {
+  StripPool &p = c->lv[level].pool;
+  PcgState<float> I{};
+  I.x = p.fx;
+  I.r = p.fr;
+  I.p = p.fp;
+  I.Ap = p.fAp;
+  I.dinv = p.fdinv;
+  I.theta = p.theta16;
+  I.part_pap = p.f_pap;
+  I.part_rz = p.f_rz;
+  I.part_rr = p.f_rr;
+  I.rzs = p.f_rzs;
+  I.tol2 = p.f_tol2;
+  I.bb = p.f_bb;
+  I.relres = p.f_relres;
+  I.it_a = p.f_it_a;
+  I.it_b = p.f_it_b;
+  I.status = p.f_status;
+  I.active = p.f_active;
+  I.S = p.cap;
+  I.max_iter = c->max_iter;
+  I.mixed = 1;
+  I.theta_fp32 = c->theta_fp32;
+  I.ru2 = c->ru_factor * c->ru_factor;
+  I.rr_ref = p.f_rr_ref;
+  I.ru = p.f_ru;
+  return I;
+}
+
+MixedState mixed_of(mlmc_ctx *c, int level, double rtol) {
+  StripPool &p = c->lv[level].pool;
+  MixedState M{};
+  M.b = p.b64;
+  M.part_rr = p.m_part_rr;
+  M.part_bb = p.part_rr;  // parity-0 partials of ||b||^2 written by the FP64 set-up
+  M.relres = p.m_relres;
+  M.updates = p.m_updates;
+  M.rtol2 = rtol * rtol;
+  return M;
 }
 
 PcgSlots slots_of(mlmc_ctx *c, int level, const double *theta, double rtol) {
@@ -227,18 +351,22 @@ PcgSlots slots_of(mlmc_ctx *c, int level, const double *theta, double rtol) {
 }
 
 // largest batch of `level` that fits next to the other pools
-int max_slots(mlmc_ctx *c, int level) {
-  const size_t per = strip_slot_bytes(c->lv[level].g);
-  const size_t other = c->used - c->lv[level].pool.bytes;
+int max_slots(mlmc_ctx *c, int level, bool mixed = false) {
+  const StripPool &p = c->lv[level].pool;
+  const size_t per = strip_slot_bytes(c->lv[level].g) +
+                     ((mixed || p.has_mixed) ? strip_mixed_slot_bytes(c->lv[level].g) : 0);
+  const size_t other = c->used - p.bytes - p.mixed_bytes;
   if (c->budget <= other) return 0;
   return (int)std::min<size_t>((c->budget - other) / per, 8192);
 }
 
-// run set-up + PCG to completion for n slots whose theta is ready
-int run_pcg(mlmc_ctx *c, int level, const PcgSlots &S, int n, hipStream_t st) {
+// lock-step PCG iterations until every slot of S (n slots) is inactive; the
+// host checks the slot flags every `block` iterations.  prof_k: profile
+// counters (2 per precision) of this solver.
+template <typename T, class Extra>
+int pcg_iterate(mlmc_ctx *c, int level, const PcgState<T> &S, int n, int *active_dev, hipStream_t st, int prof_k,
+                Extra extra) {
   const StripGeom &g = c->lv[level].g;
-  launch_setup(g, c->mat, S, n, nullptr, nullptr, st);
-  HIPCHK(c, hipGetLastError());
   const int block = 32;
   if (c->prof && c->ev.size() < 3 * block) {
     c->ev.resize(3 * block);
@@ -247,29 +375,26 @@ int run_pcg(mlmc_ctx *c, int level, const PcgSlots &S, int n, hipStream_t st) {
   for (long it = 0;; it += block) {
     for (int b = 0; b < block; ++b) {
       const int k = (int)(it + b);
-      if (c->prof) {
-        HIPCHK(c, hipEventRecord(c->ev[3 * b], st));
-        launch_pcg_pass1(g, c->mat, S, n, k, st);
-        HIPCHK(c, hipEventRecord(c->ev[3 * b + 1], st));
-        launch_pcg_pass2(g, S, n, k, st);
-        HIPCHK(c, hipEventRecord(c->ev[3 * b + 2], st));
-      } else {
-        launch_pcg_iteration(g, c->mat, S, n, k, st);
-      }
+      if (c->prof) HIPCHK(c, hipEventRecord(c->ev[3 * b], st));
+      launch_pcg_pass1<T>(g, c->mat, S, n, k, st);
+      if (c->prof) HIPCHK(c, hipEventRecord(c->ev[3 * b + 1], st));
+      launch_pcg_pass2<T>(g, S, n, k, st);
+      if (c->prof) HIPCHK(c, hipEventRecord(c->ev[3 * b + 2], st));
+      extra(k);
     }
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(c->h_active, S.active, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(c->h_active, active_dev, sizeof(int) * n, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     if (c->prof) {
       for (int b = 0; b < block; ++b) {
         float t1 = 0, t2 = 0;
         HIPCHK(c, hipEventElapsedTime(&t1, c->ev[3 * b], c->ev[3 * b + 1]));
         HIPCHK(c, hipEventElapsedTime(&t2, c->ev[3 * b + 1], c->ev[3 * b + 2]));
-        c->prof_ms[0] += t1;
-        c->prof_ms[1] += t2;
+        c->prof_ms[prof_k] += t1;
+        c->prof_ms[prof_k + 1] += t2;
       }
-      c->prof_launches[0] += block;
-      c->prof_launches[1] += block;
+      c->prof_launches[prof_k] += block;
+      c->prof_launches[prof_k + 1] += block;
     }
     bool any = false;
     for (int k = 0; k < n; ++k) any |= c->h_active[k] != 0;
@@ -281,10 +406,56 @@ int run_pcg(mlmc_ctx *c, int level, const PcgSlots &S, int n, hipStream_t st) {
     HIPCHK(c, hipMemcpy(c->h_iters.data(), S.it_b, sizeof(int) * n, hipMemcpyDeviceToHost));
     double its = 0;
     for (int k = 0; k < n; ++k) its += c->h_iters[k];
-    c->prof_bytes[0] += its * (4.0 * 16.0 * g.nnode + 32.0 * g.nelem);
-    c->prof_bytes[1] += its * (8.0 * 16.0 * g.nnode);
+    const double w = sizeof(T);
+    const double wt = (sizeof(T) == 8) ? 32.0 : 8.0;  // angle bytes per element
+    c->prof_bytes[prof_k] += its * (4.0 * 2 * w * g.nnode + wt * g.nelem);
+    c->prof_bytes[prof_k + 1] += its * (8.0 * 2 * w * g.nnode);
   }
   return MLMC_OK;
+}
+
+// FP64: set-up + PCG to completion for n slots whose theta is ready
+int run_pcg(mlmc_ctx *c, int level, const PcgSlots &S, int n, hipStream_t st) {
+  const StripGeom &g = c->lv[level].g;
+  launch_setup(g, c->mat, S, n, nullptr, nullptr, st);
+  HIPCHK(c, hipGetLastError());
+  return pcg_iterate<double>(c, level, S, n, S.active, st, 0, [](int) {});
+}
+
+// mixed precision: FP32 PCG (BF16 angles) with reliable updates in FP64 (the
+// residual b - A x recomputed with the FP64 angles whenever the FP32 residual
+// fell by the update factor, and as the only stopping test); x accumulates in
+// FP64.  On return the FP64 pool state holds x.
+int run_mixed(mlmc_ctx *c, int level, const PcgSlots &D, int n, hipStream_t st) {
+  const StripGeom &g = c->lv[level].g;
+  PcgState<float> I = inner_of(c, level);
+  MixedState M = mixed_of(c, level, std::sqrt(D.rtol2));
+  I.rtol2 = D.rtol2;
+  launch_setup(g, c->mat, D, n, M.b, nullptr, st);
+  launch_mixed_start(g, D, I, M, n, st);
+  HIPCHK(c, hipGetLastError());
+  const int every = c->ru_every;
+  int rc = pcg_iterate<float>(c, level, I, n, I.active, st, 2, [&](int k) {
+    if ((k + 1) % every == 0) {
+      launch_resid64(g, c->mat, D, I, M, n, k, every, st);
+      launch_ru_apply(g, D, I, M, n, k, every, st);
+    }
+  });
+  if (rc) return rc;
+  launch_mixed_flush(g, D, I, n, st);
+  HIPCHK(c, hipGetLastError());
+  return MLMC_OK;
+}
+
+// slot reports of the last solve in the given precision (for the QoI kernel)
+PcgSlots report_view(mlmc_ctx *c, int level, const PcgSlots &D, int precision) {
+  if (precision != MLMC_MIXED) return D;
+  StripPool &p = c->lv[level].pool;
+  PcgSlots V = D;
+  V.it_b = p.f_it_b;
+  V.relres = p.m_relres;
+  V.status = p.f_status;
+  return V;
 }
 
 int build_strip(mlmc_ctx *c) {
@@ -294,6 +465,16 @@ int build_strip(mlmc_ctx *c) {
   c->mat = make_material(cfg);
   c->rtol = cfg.number_or("rtol", 1e-10);
   c->max_iter = (int)cfg.number_or("max_iter", 100000);
+  if (cfg.has("mixed")) {
+    const Json &mx = cfg.at("mixed");
+    c->ru_factor = mx.number_or("update_factor", c->ru_factor);
+    c->ru_every = (int)mx.number_or("update_every", c->ru_every);
+    const std::string ts = mx.string_or("theta_storage", "bf16");
+    if (ts != "bf16" && ts != "fp32") throw std::runtime_error("mixed.theta_storage must be bf16 or fp32");
+    c->theta_fp32 = ts == "fp32";
+  }
+  if (c->ru_every < 1 || c->ru_every > 64) throw std::runtime_error("mixed.update_every must be in 1..64");
+  if (!(c->ru_factor > 0.0 && c->ru_factor < 1.0)) throw std::runtime_error("mixed.update_factor must be in (0, 1)");
   const Json &kl = cfg.at("kl");
   c->K = (int)kl.number("n_modes");
   if (c->K < 1 || c->K > 32) throw std::runtime_error("n_modes must be in 1..32");
@@ -448,7 +629,9 @@ int mlmc_footprint(const mlmc_ctx *c, int kind, int level, int precision, size_t
   if (kind != c->kind) return fail(m, MLMC_ESTATE, "kind does not match the context's model");
   if (bad_level(c, level)) return fail(m, MLMC_EINVAL, "level out of range");
   if (precision != MLMC_FP64 && precision != MLMC_MIXED) return fail(m, MLMC_EINVAL, "bad precision");
-  *bytes = (kind == 0) ? strip_slot_bytes(c->lv[level].g) : plate_slot_bytes(c->plate, level, precision);
+  *bytes = (kind == 0) ? strip_slot_bytes(c->lv[level].g) +
+                             (precision == MLMC_MIXED ? strip_mixed_slot_bytes(c->lv[level].g) : 0)
+                       : plate_slot_bytes(c->plate, level, precision);
   return MLMC_OK;
 }
 
@@ -463,7 +646,7 @@ int mlmc_sample_field(mlmc_ctx *c, int level, int n, const double *xi, int ld_xi
   if (!xi || !theta) return fail(c, MLMC_EINVAL, "null pointer");
   const StripGeom &g = c->lv[level].g;
   launch_kl_synth(c->lv[level].modes, c->K, g, xi, ld_xi, nullptr, n, dtype == 0 ? (double *)theta : nullptr,
-                  dtype == 1 ? (uint16_t *)theta : nullptr, 4 * g.nelem, (hipStream_t)stream);
+                  dtype == 1 ? theta : nullptr, 0, 4 * g.nelem, (hipStream_t)stream);
   HIPCHK(c, hipGetLastError());
   return MLMC_OK;
 }
@@ -505,17 +688,23 @@ int mlmc_strip_solve_theta(mlmc_ctx *c, int level, int n, const double *theta, d
   if (precision != MLMC_FP64 && precision != MLMC_MIXED) return fail(c, MLMC_EINVAL, "bad precision");
   if (n == 0) return MLMC_OK;
   if (!theta || !q) return fail(c, MLMC_EINVAL, "null pointer");
-  if (precision == MLMC_MIXED) return fail(c, MLMC_EINVAL, "mixed precision is not built for strip_solve_theta");
-  const int cap = max_slots(c, level);
+  const bool mixed = precision == MLMC_MIXED;
+  const int cap = max_slots(c, level, mixed);
   if (n > cap) return fail(c, MLMC_ENOMEM, "batch exceeds the memory budget");
   hipStream_t st = (hipStream_t)stream;
-  int rc = ensure_pool(c, level, n);
+  int rc = ensure_pool(c, level, n, mixed);
   if (rc) return rc;
   if (info) launch_info_init(info, nullptr, n, st);
   PcgSlots S = slots_of(c, level, theta, rtol > 0 ? rtol : c->rtol);
-  rc = run_pcg(c, level, S, n, st);
+  if (mixed) {
+    launch_to_lo(theta, c->lv[level].pool.theta16, c->theta_fp32, (size_t)n * 4 * c->lv[level].g.nelem, st);
+    rc = run_mixed(c, level, S, n, st);
+  } else {
+    rc = run_pcg(c, level, S, n, st);
+  }
   if (rc) return rc;
-  launch_qoi(c->lv[level].g, c->mat, S, n, c->lv[level].pool.qpart, nullptr, q, info, 0, st);
+  launch_qoi(c->lv[level].g, c->mat, report_view(c, level, S, precision), n, c->lv[level].pool.qpart, nullptr, q,
+             info, 0, st);
   if (d) launch_total_disp(c->lv[level].g, S.x, d, n, st);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(st));
@@ -531,7 +720,6 @@ int mlmc_solve_batch(mlmc_ctx *c, int n_req, const mlmc_request *req, const doub
   if (!req || !xi || !q_fine || !q_coarse || !info) return fail(c, MLMC_EINVAL, "null pointer");
   if (ld_xi < c->K + 3) return fail(c, MLMC_EINVAL, "ld_xi < n_modes + 3");
   if (precision != MLMC_FP64 && precision != MLMC_MIXED) return fail(c, MLMC_EINVAL, "bad precision");
-  if (precision == MLMC_MIXED) return fail(c, MLMC_EINVAL, "mixed precision is not built yet");
   for (int i = 0; i < n_req; ++i) {
     if (bad_level(c, req[i].level)) return fail(c, MLMC_EINVAL, "request " + std::to_string(i) + ": bad level");
     if (req[i].sample < 0 || req[i].sample >= n_rows)
@@ -559,20 +747,23 @@ int mlmc_solve_batch(mlmc_ctx *c, int n_req, const mlmc_request *req, const doub
       const auto &O = outs[2 * l + coarse];
       const int total = (int)R.size();
       if (!total) continue;
-      const int cap = std::min(max_slots(c, l), total);
+      const bool mixed = precision == MLMC_MIXED;
+      const int cap = std::min(max_slots(c, l, mixed), total);
       if (cap < 1) return fail(c, MLMC_ENOMEM, "level " + std::to_string(l) + ": no slot fits the budget");
-      int rc = ensure_pool(c, l, cap);
+      int rc = ensure_pool(c, l, cap, mixed);
       if (rc) return rc;
       StripLevel &L = c->lv[l];
       for (int off = 0; off < total; off += cap) {
         const int n = std::min(cap, total - off);
         HIPCHK(c, hipMemcpyAsync(L.pool.rows, R.data() + off, sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
         HIPCHK(c, hipMemcpyAsync(L.pool.outidx, O.data() + off, sizeof(int) * n, hipMemcpyHostToDevice, st));
-        launch_kl_synth(L.modes, c->K, L.g, xi, ld_xi, L.pool.rows, n, L.pool.theta, nullptr, 4 * L.g.nelem, st);
+        launch_kl_synth(L.modes, c->K, L.g, xi, ld_xi, L.pool.rows, n, L.pool.theta, mixed ? L.pool.theta16 : nullptr,
+                        c->theta_fp32, 4 * L.g.nelem, st);
         PcgSlots S = slots_of(c, l, L.pool.theta, rt);
-        rc = run_pcg(c, l, S, n, st);
+        rc = mixed ? run_mixed(c, l, S, n, st) : run_pcg(c, l, S, n, st);
         if (rc) return rc;
-        launch_qoi(L.g, c->mat, S, n, L.pool.qpart, L.pool.outidx, coarse ? q_coarse : q_fine, info, coarse, st);
+        launch_qoi(L.g, c->mat, report_view(c, l, S, precision), n, L.pool.qpart, L.pool.outidx,
+                   coarse ? q_coarse : q_fine, info, coarse, st);
         HIPCHK(c, hipGetLastError());
         // the row/index buffers are reused by the next chunk
         HIPCHK(c, hipStreamSynchronize(st));
@@ -627,7 +818,7 @@ int mlmc_level_stats(mlmc_ctx *c, int level, int n, const double *q_fine, const 
 int mlmc_profile_enable(mlmc_ctx *c, int on) {
   if (!c) return MLMC_EINVAL;
   c->prof = on != 0;
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 4; ++k) {
     c->prof_ms[k] = 0;
     c->prof_bytes[k] = 0;
     c->prof_launches[k] = 0;
@@ -637,7 +828,7 @@ int mlmc_profile_enable(mlmc_ctx *c, int on) {
 
 int mlmc_profile_read(mlmc_ctx *c, int kernel, double *total_ms, int64_t *launches, double *alg_bytes) {
   if (!c) return MLMC_EINVAL;
-  if (kernel < 0 || kernel > 1) return fail(c, MLMC_EINVAL, "kernel must be 0 or 1");
+  if (kernel < 0 || kernel > 3) return fail(c, MLMC_EINVAL, "kernel must be 0..3");
   if (total_ms) *total_ms = c->prof_ms[kernel];
   if (launches) *launches = c->prof_launches[kernel];
   if (alg_bytes) *alg_bytes = c->prof_bytes[kernel];

@@ -43,6 +43,9 @@ struct StripGeom {
   int nchunks;                     // contiguous node chunks of the PCG vector pass
   int qx0, qx1, qy0, qy1;  // QoI element index ranges [q*0, q*1)
   double hx, hy, ihx, ihy, wdet;  // wdet = Gauss weight x det J = hx hy / 4
+  // interpolation weights with the 1/h of the derivative folded in (strain),
+  // and with the quadrature weight as well (transposed operator)
+  double pxi, mxi, pyi, myi, pxw, mxw, pyw, myw;
   double delta;                   // u = -delta on x = Lx
   double Lx, Ly;
 };
@@ -52,12 +55,15 @@ struct StripGeom {
 struct StripMat {
   double U1, U2, U3, U4, U5;
   double Q11, Q22, Q12, Q66;
+  float fU1, fU2, fU3, fU4, fU5;   // the same invariants rounded to FP32
 };
 
-// per-slot PCG state of a level pool (device pointers)
-struct PcgSlots {
-  double *x, *r, *p, *Ap, *dinv;   // [S][2 nnode]; all slots iterate in lock-step
-  const double *theta;             // [S][4 nelem]
+// per-slot PCG state of a level pool (device pointers); T = double for the
+// FP64 solver, float for the inner solver of the mixed-precision form
+template <typename T>
+struct PcgState {
+  T *x, *r, *p, *Ap, *dinv;        // [S][2 nnode]; all slots iterate in lock-step
+  const void *theta;               // [S][4 nelem]: double (FP64) or bfloat16 bits (float solver)
   double *part_pap;                // [S][sw_ntiles]
   double *part_rz, *part_rr;       // [2][S][nchunks]
   double *rzs;                     // [2][S]
@@ -65,6 +71,25 @@ struct PcgSlots {
   int *it_a, *it_b, *status, *active;  // [S]
   int S;
   int max_iter;
+  double rtol2;
+  // reliable updates (inner solver of the mixed form only; unused when mixed == 0):
+  // a slot whose FP32 residual fell by ru2 since its last FP64 residual, or
+  // meets the stopping test, records ru[s] = it + 1 and pauses for one iteration
+  int mixed;
+  int theta_fp32;                  // float solver: angles stored as FP32 instead of bfloat16
+  double ru2;
+  double *rr_ref;                  // [S] ||r||^2 at the last FP64 residual
+  int *ru;                         // [S]
+};
+using PcgSlots = PcgState<double>;
+
+// FP64 side of the mixed-precision solver
+struct MixedState {
+  double *b;                       // [S][2 nnode] right-hand side
+  double *part_rr;                 // [S][sw_ntiles] partial ||b - A x||^2
+  double *part_bb;                 // [S][nchunks] partial ||b||^2 (from the FP64 set-up)
+  double *relres;                  // [S] last FP64 relative residual
+  int *updates;                    // [S] FP64 residuals computed
   double rtol2;
 };
 

@@ -8,9 +8,11 @@
 namespace mlmc {
 
 // rotated plane-stress stiffness at one Gauss point (global axes, engineering shear)
-struct Qb {
-  double q11, q22, q12, q66, q16, q26;
+template <typename T>
+struct QbT {
+  T q11, q22, q12, q66, q16, q26;
 };
+using Qb = QbT<double>;
 
 // sin and cos of a small angle from their Taylor series (Horner in x^2): for
 // |x| <= 1 the first omitted terms are below x^19/19! < 1e-17 and x^20/20! <
@@ -72,26 +74,27 @@ __device__ __forceinline__ Qb qbar_of(const StripMat &m, double th) {
 // derivative is shared by two Gauss points; the transposed operator uses the
 // same pairs.  Gauss points are processed one at a time so only one rotated
 // stiffness is live.  QB(q) must yield the Qb of Gauss point q.
-template <class QbAt>
-__device__ __forceinline__ void elem_forces_q(const StripGeom &g, QbAt QB, const double u[4], const double v[4],
-                                              double fu[4], double fv[4]) {
-  const double P = GP_P, M = GP_M;
-  const double dub = u[1] - u[0], dut = u[2] - u[3], dul = u[3] - u[0], dur = u[2] - u[1];
-  const double dvb = v[1] - v[0], dvt = v[2] - v[3], dvl = v[3] - v[0], dvr = v[2] - v[1];
-  const double ux[2] = {(P * dub + M * dut) * g.ihx, (M * dub + P * dut) * g.ihx};
-  const double vx[2] = {(P * dvb + M * dvt) * g.ihx, (M * dvb + P * dvt) * g.ihx};
-  const double uy[2] = {(P * dul + M * dur) * g.ihy, (M * dul + P * dur) * g.ihy};
-  const double vy[2] = {(P * dvl + M * dvr) * g.ihy, (M * dvl + P * dvr) * g.ihy};
+template <typename T, class QbAt>
+__device__ __forceinline__ void elem_forces_q(const StripGeom &g, QbAt QB, const T u[4], const T v[4], T fu[4],
+                                              T fv[4]) {
+  const T pxi = (T)g.pxi, mxi = (T)g.mxi, pyi = (T)g.pyi, myi = (T)g.myi;
+  const T pxw = (T)g.pxw, mxw = (T)g.mxw, pyw = (T)g.pyw, myw = (T)g.myw;
+  const T dub = u[1] - u[0], dut = u[2] - u[3], dul = u[3] - u[0], dur = u[2] - u[1];
+  const T dvb = v[1] - v[0], dvt = v[2] - v[3], dvl = v[3] - v[0], dvr = v[2] - v[1];
+  const T ux[2] = {fma(pxi, dub, mxi * dut), fma(mxi, dub, pxi * dut)};
+  const T vx[2] = {fma(pxi, dvb, mxi * dvt), fma(mxi, dvb, pxi * dvt)};
+  const T uy[2] = {fma(pyi, dul, myi * dur), fma(myi, dul, pyi * dur)};
+  const T vy[2] = {fma(pyi, dvl, myi * dvr), fma(myi, dvl, pyi * dvr)};
   // stress sums: sxx and txy paired by eta (x-derivative), syy and txy paired by xi
-  double ax[2], ay[2], aty[2], atx[2];
+  T ax[2], ay[2], aty[2], atx[2];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int a = q & 1, b = q >> 1;
-    const Qb qb = QB(q);
-    const double ex = ux[b], ey = vy[a], gm = uy[a] + vx[b];
-    const double sxx = qb.q11 * ex + qb.q12 * ey + qb.q16 * gm;
-    const double syy = qb.q12 * ex + qb.q22 * ey + qb.q26 * gm;
-    const double txy = qb.q16 * ex + qb.q26 * ey + qb.q66 * gm;
+    const QbT<T> qb = QB(q);
+    const T ex = ux[b], ey = vy[a], gm = uy[a] + vx[b];
+    const T sxx = qb.q11 * ex + qb.q12 * ey + qb.q16 * gm;
+    const T syy = qb.q12 * ex + qb.q22 * ey + qb.q26 * gm;
+    const T txy = qb.q16 * ex + qb.q26 * ey + qb.q66 * gm;
     if (q == 0) {
       ax[0] = sxx; ay[0] = syy; aty[0] = txy; atx[0] = txy;
     } else if (q == 1) {
@@ -102,13 +105,11 @@ __device__ __forceinline__ void elem_forces_q(const StripGeom &g, QbAt QB, const
       ax[1] += sxx; ay[1] += syy; aty[1] += txy; atx[1] += txy;
     }
   }
-  const double w = g.wdet;
-  const double axL = ax[0] * w, axH = ax[1] * w, atyL = aty[0] * w, atyH = aty[1] * w;
-  const double ayL = ay[0] * w, ayH = ay[1] * w, atxL = atx[0] * w, atxH = atx[1] * w;
-  const double gub = (P * axL + M * axH) * g.ihx, gut = (M * axL + P * axH) * g.ihx;
-  const double gul = (P * atyL + M * atyH) * g.ihy, gur = (M * atyL + P * atyH) * g.ihy;
-  const double gvl = (P * ayL + M * ayH) * g.ihy, gvr = (M * ayL + P * ayH) * g.ihy;
-  const double gvb = (P * atxL + M * atxH) * g.ihx, gvt = (M * atxL + P * atxH) * g.ihx;
+  // transposed derivative operators with the quadrature weight folded in
+  const T gub = fma(pxw, ax[0], mxw * ax[1]), gut = fma(mxw, ax[0], pxw * ax[1]);
+  const T gul = fma(pyw, aty[0], myw * aty[1]), gur = fma(myw, aty[0], pyw * aty[1]);
+  const T gvl = fma(pyw, ay[0], myw * ay[1]), gvr = fma(myw, ay[0], pyw * ay[1]);
+  const T gvb = fma(pxw, atx[0], mxw * atx[1]), gvt = fma(mxw, atx[0], pxw * atx[1]);
   fu[0] = -gub - gul;
   fu[1] = gub - gur;
   fu[2] = gut + gur;
@@ -121,8 +122,27 @@ __device__ __forceinline__ void elem_forces_q(const StripGeom &g, QbAt QB, const
 
 __device__ __forceinline__ void elem_forces(const StripGeom &g, const Qb q[4], const double u[4],
                                             const double v[4], double fu[4], double fv[4]) {
-  elem_forces_q(g, [&](int k) { return q[k]; }, u, v, fu, fv);
+  elem_forces_q<double>(g, [&](int k) { return q[k]; }, u, v, fu, fv);
 }
+
+// FP32 rotated stiffness from a bfloat16 angle (mixed-precision inner operator)
+__device__ __forceinline__ QbT<float> qbar_f32(const StripMat &m, float th) {
+  float s2, c2;
+  __sincosf(2.0f * th, &s2, &c2);
+  const float c4 = 2.0f * c2 * c2 - 1.0f;
+  const float s4 = 2.0f * s2 * c2;
+  QbT<float> q;
+  q.q11 = m.fU1 + m.fU2 * c2 + m.fU3 * c4;
+  q.q22 = m.fU1 - m.fU2 * c2 + m.fU3 * c4;
+  q.q12 = m.fU4 - m.fU3 * c4;
+  q.q66 = m.fU5 - m.fU3 * c4;
+  const float h = 0.5f * m.fU2 * s2;
+  q.q16 = h + m.fU3 * s4;
+  q.q26 = h - m.fU3 * s4;
+  return q;
+}
+
+__device__ __forceinline__ float bf16_to_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // largest compressive stress along the fibres at the four Gauss points:
 // sigma_11 = cos^2 sxx + sin^2 syy + 2 sin cos txy, written with cos 2theta, sin 2theta

@@ -52,7 +52,7 @@ __device__ __forceinline__ void tile_elements(const StripGeom &g, const StripMat
       const int n0 = ley * HALO_X + lex;
       const double u[4] = {nu[n0], nu[n0 + 1], nu[n0 + HALO_X + 1], nu[n0 + HALO_X]};
       const double v[4] = {nv[n0], nv[n0 + 1], nv[n0 + HALO_X + 1], nv[n0 + HALO_X]};
-      elem_forces_q(g, [&](int q) { return qbar_of(m, th[q]); }, u, v, fu, fv);
+      elem_forces_q<double>(g, [&](int q) { return qbar_of(m, th[q]); }, u, v, fu, fv);
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -83,8 +83,8 @@ constexpr int MAX_MODES = 32;
 __global__ __launch_bounds__(256) void k_kl_synth(const double *__restrict__ modes, int K, StripGeom g,
                                                   const double *__restrict__ xi, int ld_xi,
                                                   const int64_t *__restrict__ rows, int n,
-                                                  double *__restrict__ th64, uint16_t *__restrict__ th16,
-                                                  int ld_out) {
+                                                  double *__restrict__ th64, void *__restrict__ thlo,
+                                                  int lo_fp32, int ld_out) {
   const int ngp = 4 * g.nelem;
   const int gp = blockIdx.x * 256 + threadIdx.x;
   if (gp >= ngp) return;
@@ -109,12 +109,16 @@ __global__ __launch_bounds__(256) void k_kl_synth(const double *__restrict__ mod
       th += A / (c * c);
     }
     if (th64) th64[(size_t)s * ld_out + gp] = th;
-    if (th16) {
-      // round to float, then to bfloat16 with round-to-nearest-even
+    if (thlo) {
+      // round to float, then (bfloat16 storage) to bfloat16 with round-to-nearest-even
       const float f = (float)th;
-      uint32_t b = __float_as_uint(f);
-      b += 0x7FFFu + ((b >> 16) & 1u);
-      th16[(size_t)s * ld_out + gp] = (uint16_t)(b >> 16);
+      if (lo_fp32) {
+        ((float *)thlo)[(size_t)s * ld_out + gp] = f;
+      } else {
+        uint32_t b = __float_as_uint(f);
+        b += 0x7FFFu + ((b >> 16) & 1u);
+        ((uint16_t *)thlo)[(size_t)s * ld_out + gp] = (uint16_t)(b >> 16);
+      }
     }
   }
 }
@@ -198,7 +202,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_setup(StripGeom g, StripMat m,
   __shared__ double red4[TILE_WAVES];
   const int s = blockIdx.y, t = blockIdx.x;
   const TileCoord tc = tile_of(g, t);
-  const double *theta_s = S.theta + (size_t)s * 4 * g.nelem;
+  const double *theta_s = (const double *)S.theta + (size_t)s * 4 * g.nelem;
   for (int k = threadIdx.x; k < TILE_ELEMS; k += TILE_THREADS) {
     const int lex = k % ELEM_X, ley = k / ELEM_X;
     const int ex = tc.i0 - 1 + lex, ey = tc.j0 - 1 + ley;
@@ -286,6 +290,96 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return x * q + min(x, r) + k;
 }
 
+template <typename T>
+struct PairOf;
+template <>
+struct PairOf<double> {
+  using type = double2;
+};
+template <>
+struct PairOf<float> {
+  using type = float2;
+};
+
+template <typename T>
+__device__ __forceinline__ typename PairOf<T>::type ld2(const T *p) {
+  return *reinterpret_cast<const typename PairOf<T>::type *>(p);
+}
+template <typename T>
+__device__ __forceinline__ void st2(T *p, T a, T b) {
+  typename PairOf<T>::type v;
+  v.x = a;
+  v.y = b;
+  *reinterpret_cast<typename PairOf<T>::type *>(p) = v;
+}
+
+template <typename T>
+struct RowVals {
+  T zu, zv, qu, qv;
+};
+
+// z = dinv r and p_old of node (i, jr) (zero outside the mesh or the window)
+template <typename T>
+__device__ __forceinline__ RowVals<T> load_row(const StripGeom &g, const PcgState<T> &S, size_t vb, int i, bool colv,
+                                               int jr, bool with_p) {
+  RowVals<T> v = {T(0), T(0), T(0), T(0)};
+  if (colv && jr >= 0 && jr < g.nny) {
+    const size_t o = vb + 2 * ((size_t)jr * g.nnx + i);
+    const auto rv = ld2(S.r + o);
+    const auto dv = ld2(S.dinv + o);
+    v.zu = dv.x * rv.x;
+    v.zv = dv.y * rv.y;
+    if (with_p) {
+      const auto po = ld2(S.p + o);
+      v.qu = po.x;
+      v.qv = po.y;
+    }
+  }
+  return v;
+}
+
+// the four Gauss-point angles of element (i, ey) and the rotated stiffness at one of them
+template <typename T>
+struct Angles;
+template <>
+struct Angles<double> {
+  double t[4];
+  __device__ __forceinline__ void load(const void *theta, size_t eb, const StripGeom &g, int i, bool ok, int ey,
+                                       int = 0) {
+    t[0] = t[1] = t[2] = t[3] = 0.0;
+    if (ok && ey >= 0 && ey < g.ny) {
+      const double *tp = (const double *)theta + eb + 4 * ((size_t)ey * g.nx + i);
+      const double2 a = *reinterpret_cast<const double2 *>(tp);
+      const double2 b = *reinterpret_cast<const double2 *>(tp + 2);
+      t[0] = a.x; t[1] = a.y; t[2] = b.x; t[3] = b.y;
+    }
+  }
+  __device__ __forceinline__ QbT<double> qb(const StripMat &m, int q) const { return qbar_of(m, t[q]); }
+};
+template <>
+struct Angles<float> {
+  float t[4];
+  // angles stored as bfloat16 (theta_fp32 == 0) or FP32
+  __device__ __forceinline__ void load(const void *theta, size_t eb, const StripGeom &g, int i, bool ok, int ey,
+                                       int theta_fp32) {
+    t[0] = t[1] = t[2] = t[3] = 0.0f;
+    if (ok && ey >= 0 && ey < g.ny) {
+      const size_t e = eb + 4 * ((size_t)ey * g.nx + i);
+      if (theta_fp32) {
+        const float4 w = *reinterpret_cast<const float4 *>((const float *)theta + e);
+        t[0] = w.x; t[1] = w.y; t[2] = w.z; t[3] = w.w;
+      } else {
+        const uint2 w = *reinterpret_cast<const uint2 *>((const uint16_t *)theta + e);
+        t[0] = __uint_as_float(w.x << 16);
+        t[1] = __uint_as_float(w.x & 0xFFFF0000u);
+        t[2] = __uint_as_float(w.y << 16);
+        t[3] = __uint_as_float(w.y & 0xFFFF0000u);
+      }
+    }
+  }
+  __device__ __forceinline__ QbT<float> qb(const StripMat &m, int q) const { return qbar_f32(m, t[q]); }
+};
+
 // ---------------------------------------------------------------- PCG pass 1
 // Iteration `it` (all slots of a batch iterate in lock-step; par = it & 1).
 // One wave per column-sweep tile: lane l holds node column i0 - 1 + l (lanes
@@ -298,46 +392,16 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // Per sample: convergence test on r.r, beta = rz_it / rz_{it-1},
 // p = z + beta p_old (not stored: pass 2 recomputes it bit-identically, so
 // neighbours read p_old in their halos), Ap = A p, partial p.Ap per tile.
-// The next row's loads are issued before the current row is computed.
-struct RowVals {
-  double zu, zv, qu, qv;
-};
-
-__device__ __forceinline__ RowVals load_row(const StripGeom &g, const PcgSlots &S, size_t vb, int i, bool colv,
-                                            int jr, bool with_p) {
-  RowVals v = {0.0, 0.0, 0.0, 0.0};
-  if (colv && jr >= 0 && jr < g.nny) {
-    const size_t o = vb + 2 * ((size_t)jr * g.nnx + i);
-    const double2 rv = *reinterpret_cast<const double2 *>(S.r + o);
-    const double2 dv = *reinterpret_cast<const double2 *>(S.dinv + o);
-    v.zu = dv.x * rv.x;
-    v.zv = dv.y * rv.y;
-    if (with_p) {
-      const double2 po = *reinterpret_cast<const double2 *>(S.p + o);
-      v.qu = po.x;
-      v.qv = po.y;
-    }
-  }
-  return v;
-}
-
-__device__ __forceinline__ double4 load_theta(const StripGeom &g, const double *theta_s, int i, bool elv, int ey) {
-  if (elv && ey >= 0 && ey < g.ny) {
-    const double *tp = theta_s + 4 * ((size_t)ey * g.nx + i);
-    const double2 a = *reinterpret_cast<const double2 *>(tp);
-    const double2 b = *reinterpret_cast<const double2 *>(tp + 2);
-    return make_double4(a.x, a.y, b.x, b.y);
-  }
-  return make_double4(0.0, 0.0, 0.0, 0.0);
-}
-
-__global__ __launch_bounds__(64) void k_pass1(StripGeom g, StripMat m, PcgSlots S, int it, int nblocks) {
+// The next node row is loaded while the current row is computed.  Dot
+// products are accumulated in FP64 for both precisions.
+template <typename T>
+__global__ __launch_bounds__(64) void k_pass1(StripGeom g, StripMat m, PcgState<T> S, int it, int nblocks) {
   const int lt = xcd_remap(blockIdx.x, nblocks);
   const int s = lt / g.sw_ntiles, t = lt - s * g.sw_ntiles;
   const int lane = threadIdx.x;
   const int par = it & 1;
   const size_t vb = (size_t)s * 2 * g.nnode;
-  const double *theta_s = S.theta + (size_t)s * 4 * g.nelem;
+  const size_t eb = (size_t)s * 4 * g.nelem;
   const int active = __builtin_amdgcn_readfirstlane(S.active[s]);
   const size_t pb = ((size_t)par * S.S + s) * g.nchunks;
   double prz = 0.0, prr = 0.0;
@@ -347,6 +411,7 @@ __global__ __launch_bounds__(64) void k_pass1(StripGeom g, StripMat m, PcgSlots 
   }
   const double rz_prev = (it > 0) ? S.rzs[(size_t)(par ^ 1) * S.S + s] : 1.0;
   const double bb_old = (it > 0) ? S.bb[s] : 0.0;
+  const double rr_ref = (S.mixed && it > 0) ? S.rr_ref[s] : 0.0;
   const int tx = t % g.sw_ntx, ty = t / g.sw_ntx;
   const int i0 = tx * g.sw_tw, j0 = ty * g.sw_ty;
   const int i = i0 - 1 + lane;
@@ -355,60 +420,70 @@ __global__ __launch_bounds__(64) void k_pass1(StripGeom g, StripMat m, PcgSlots 
   const bool own = lane >= 1 && lane <= g.sw_tw && i < g.nnx;
   const int row_end = min(j0 + g.sw_ty, g.nny);
   const bool wp = it > 0;
-  RowVals lo = load_row(g, S, vb, i, colv, j0 - 1, wp);
-  RowVals nhi = load_row(g, S, vb, i, colv, j0, wp);
-  double4 nth = load_theta(g, theta_s, i, elv, j0 - 1);
+  RowVals<T> lo = load_row(g, S, vb, i, colv, j0 - 1, wp);
+  RowVals<T> nhi = load_row(g, S, vb, i, colv, j0, wp);
   const double rz = wave_sum(prz);
   if (!active) return;
   const double rr = wave_sum(prr);
   const double bb = (it == 0) ? rr : bb_old;
   const double tol2 = S.rtol2 * bb;
   int verdict = -1;
+  bool upd = false;
   if (!isfinite(rr) || !isfinite(rz)) verdict = S_NAN;
-  else if (rr <= tol2) verdict = S_OK;
   else if (it >= S.max_iter) verdict = S_NOCONV;
+  // mixed: ask for an FP64 residual when the FP32 one has fallen by the update
+  // factor, or is 10% below the stopping threshold (the margin keeps a slot
+  // whose FP64 residual just failed the test from asking again at once)
+  else if (S.mixed) upd = rr <= 0.81 * tol2 || (it > 0 && rr <= S.ru2 * rr_ref);
+  else if (rr <= tol2) verdict = S_OK;
   if (t == 0 && lane == 0) {
-    if (it == 0) S.bb[s] = rr;
-    S.rzs[(size_t)par * S.S + s] = rz;
+    if (it == 0) {
+      S.bb[s] = rr;
+      if (S.mixed) S.rr_ref[s] = rr;
+    }
+    // a paused iteration keeps the last r.z so beta stays consistent with p
+    S.rzs[(size_t)par * S.S + s] = (upd && it > 0) ? rz_prev : rz;
     S.relres[s] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
     S.it_b[s] = it;
     if (verdict >= 0) {
       S.status[s] = verdict;
       S.active[s] = 0;
     }
+    if (upd) {
+      S.ru[s] = it + 1;
+      S.active[s] = 0;
+    }
   }
-  if (verdict >= 0) return;
-  const double beta = (it == 0) ? 0.0 : rz / rz_prev;
-  double plu = fma(beta, lo.qu, lo.zu), plv = fma(beta, lo.qv, lo.zv);
-  double f2u = 0.0, f2v = 0.0, f3u = 0.0, f3v = 0.0;  // previous element row: f2 of the left lane, own f3
+  if (verdict >= 0 || upd) return;
+  const double beta_d = (it == 0) ? 0.0 : rz / rz_prev;
+  const T beta = (T)beta_d;
+  T plu = fma(beta, lo.qu, lo.zu), plv = fma(beta, lo.qv, lo.zv);
+  T f2u = 0, f2v = 0, f3u = 0, f3v = 0;  // previous element row: f2 of the left lane, own f3
   double part = 0.0;
   const int nk = row_end - j0;
   for (int k = 0; k <= nk; ++k) {
     const int ey = j0 - 1 + k;
-    const RowVals hi = nhi;
-    const double4 th4 = nth;
-    if (k < nk) {
-      nhi = load_row(g, S, vb, i, colv, ey + 2, wp);
-      nth = load_theta(g, theta_s, i, elv, ey + 1);
-    }
-    const double phu = fma(beta, hi.qu, hi.zu), phv = fma(beta, hi.qv, hi.zv);
-    const double rlu = __shfl_down(plu, 1, 64), rlv = __shfl_down(plv, 1, 64);
-    const double rhu = __shfl_down(phu, 1, 64), rhv = __shfl_down(phv, 1, 64);
-    double fu[4] = {0.0, 0.0, 0.0, 0.0}, fv[4] = {0.0, 0.0, 0.0, 0.0};
+    const RowVals<T> hi = nhi;
+    Angles<T> th;
+    th.load(S.theta, eb, g, i, elv, ey, S.theta_fp32);
+    if (k < nk) nhi = load_row(g, S, vb, i, colv, ey + 2, wp);
+    const T phu = fma(beta, hi.qu, hi.zu), phv = fma(beta, hi.qv, hi.zv);
+    const T rlu = __shfl_down(plu, 1, 64), rlv = __shfl_down(plv, 1, 64);
+    const T rhu = __shfl_down(phu, 1, 64), rhv = __shfl_down(phv, 1, 64);
+    T fu[4] = {0, 0, 0, 0}, fv[4] = {0, 0, 0, 0};
     if (elv && ey >= 0 && ey < g.ny) {
-      const double th[4] = {th4.x, th4.y, th4.z, th4.w};
-      const double u[4] = {plu, rlu, rhu, phu};
-      const double v[4] = {plv, rlv, rhv, phv};
-      elem_forces_q(g, [&](int q) { return qbar_of(m, th[q]); }, u, v, fu, fv);
+      const T u[4] = {plu, rlu, rhu, phu};
+      const T v[4] = {plv, rlv, rhv, phv};
+      elem_forces_q<T>(g, [&](int q) { return th.qb(m, q); }, u, v, fu, fv);
     }
-    const double f1lu = __shfl_up(fu[1], 1, 64), f1lv = __shfl_up(fv[1], 1, 64);
+    const T f1lu = __shfl_up(fu[1], 1, 64), f1lv = __shfl_up(fv[1], 1, 64);
     if (k >= 1 && own) {
-      double yu = ((f2u + f3u) + f1lu) + fu[0];
-      double yv = ((f2v + f3v) + f1lv) + fv[0];
+      T yu = ((f2u + f3u) + f1lu) + fu[0];
+      T yv = ((f2v + f3v) + f1lv) + fv[0];
       if (i == 0) { yu = plu; yv = plv; }
       if (i == g.nx) yu = plu;
-      *reinterpret_cast<double2 *>(S.Ap + vb + 2 * ((size_t)ey * g.nnx + i)) = make_double2(yu, yv);
-      part += plu * yu + plv * yv;
+      st2(S.Ap + vb + 2 * ((size_t)ey * g.nnx + i), yu, yv);
+      part += (double)plu * (double)yu + (double)plv * (double)yv;
     }
     f2u = __shfl_up(fu[2], 1, 64);
     f2v = __shfl_up(fv[2], 1, 64);
@@ -425,8 +500,10 @@ __global__ __launch_bounds__(64) void k_pass1(StripGeom g, StripMat m, PcgSlots 
 // alpha = rz / p.Ap; p = z + beta p_old (bit-identical to pass 1); x += alpha p;
 // r -= alpha Ap; store p; partial r.z (z = dinv r) and r.r per chunk of CHUNK
 // consecutive nodes (all loads issued before the reduction of p.Ap)
-__global__ __launch_bounds__(256) void k_pass2(StripGeom g, PcgSlots S, int it) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_pass2(StripGeom g, PcgState<T> S, int it) {
   constexpr int PER = CHUNK / 256;
+  using P2 = typename PairOf<T>::type;
   __shared__ double red4[4];
   __shared__ int flag;
   const int s = blockIdx.y, c = blockIdx.x;
@@ -437,18 +514,18 @@ __global__ __launch_bounds__(256) void k_pass2(StripGeom g, PcgSlots S, int it) 
   const double rz = S.rzs[(size_t)par * S.S + s];
   const double rz_prev = (it > 0) ? S.rzs[(size_t)(par ^ 1) * S.S + s] : 1.0;
   const size_t vb = (size_t)s * 2 * g.nnode;
-  double2 pv[PER], av[PER], xv[PER], rv[PER], dv[PER];
+  P2 pv[PER], av[PER], xv[PER], rv[PER], dv[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int node = c * CHUNK + k * 256 + threadIdx.x;
-    pv[k] = av[k] = xv[k] = rv[k] = dv[k] = make_double2(0.0, 0.0);
+    pv[k].x = pv[k].y = av[k].x = av[k].y = xv[k].x = xv[k].y = rv[k].x = rv[k].y = dv[k].x = dv[k].y = T(0);
     if (node < g.nnode) {
       const size_t o = vb + 2 * (size_t)node;
-      if (it > 0) pv[k] = *reinterpret_cast<const double2 *>(S.p + o);
-      av[k] = *reinterpret_cast<const double2 *>(S.Ap + o);
-      xv[k] = *reinterpret_cast<const double2 *>(S.x + o);
-      rv[k] = *reinterpret_cast<const double2 *>(S.r + o);
-      dv[k] = *reinterpret_cast<const double2 *>(S.dinv + o);
+      if (it > 0) pv[k] = ld2(S.p + o);
+      av[k] = ld2(S.Ap + o);
+      xv[k] = ld2(S.x + o);
+      rv[k] = ld2(S.r + o);
+      dv[k] = ld2(S.dinv + o);
     }
   }
   const double pap = block_sum(ppap, red4);  // publishes flag
@@ -460,27 +537,24 @@ __global__ __launch_bounds__(256) void k_pass2(StripGeom g, PcgSlots S, int it) 
     }
     return;
   }
-  const double alpha = rz / pap;
-  const double beta = (it == 0) ? 0.0 : rz / rz_prev;
+  const T alpha = (T)(rz / pap);
+  const T beta = (T)((it == 0) ? 0.0 : rz / rz_prev);
   double prz = 0.0, prr = 0.0;
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int node = c * CHUNK + k * 256 + threadIdx.x;
     if (node < g.nnode) {
       const size_t o = vb + 2 * (size_t)node;
-      double2 pn;
-      pn.x = fma(beta, pv[k].x, dv[k].x * rv[k].x);
-      pn.y = fma(beta, pv[k].y, dv[k].y * rv[k].y);
-      double2 x2 = xv[k], r2 = rv[k];
-      x2.x = fma(alpha, pn.x, x2.x);
-      x2.y = fma(alpha, pn.y, x2.y);
-      r2.x = fma(-alpha, av[k].x, r2.x);
-      r2.y = fma(-alpha, av[k].y, r2.y);
-      *reinterpret_cast<double2 *>(S.p + o) = pn;
-      *reinterpret_cast<double2 *>(S.x + o) = x2;
-      *reinterpret_cast<double2 *>(S.r + o) = r2;
-      prz += r2.x * (dv[k].x * r2.x) + r2.y * (dv[k].y * r2.y);
-      prr += r2.x * r2.x + r2.y * r2.y;
+      const T pnx = fma(beta, pv[k].x, dv[k].x * rv[k].x);
+      const T pny = fma(beta, pv[k].y, dv[k].y * rv[k].y);
+      const T xx = fma(alpha, pnx, xv[k].x), xy = fma(alpha, pny, xv[k].y);
+      const T rx = fma(-alpha, av[k].x, rv[k].x), ry = fma(-alpha, av[k].y, rv[k].y);
+      st2(S.p + o, pnx, pny);
+      st2(S.x + o, xx, xy);
+      st2(S.r + o, rx, ry);
+      const double drx = rx, dry = ry;
+      prz += drx * ((double)dv[k].x * drx) + dry * ((double)dv[k].y * dry);
+      prr += drx * drx + dry * dry;
     }
   }
   prz = block_sum(prz, red4);
@@ -490,6 +564,192 @@ __global__ __launch_bounds__(256) void k_pass2(StripGeom g, PcgSlots S, int it) 
     S.part_rz[pb] = prz;
     S.part_rr[pb] = prr;
     if (c == 0) S.it_a[s] = it + 1;
+  }
+}
+
+// ---------------------------------------------------------------- mixed precision
+// Reliable update of slot s (requested by pass 1 of iteration it): the FP64
+// residual r = b - A (x64 + x32) with the FP64 angles (column sweep as in
+// pass 1, node values = x), partial ||r||^2 per sweep tile.
+__global__ __launch_bounds__(64) void k_resid64(StripGeom g, StripMat m, PcgSlots D, PcgState<float> I, MixedState M,
+                                                int it, int every, int nblocks) {
+  const int lt = xcd_remap(blockIdx.x, nblocks);
+  const int s = lt / g.sw_ntiles, t = lt - s * g.sw_ntiles;
+  const int lane = threadIdx.x;
+  // slots that asked during the last `every` iterations (each is served once)
+  const int ask = __builtin_amdgcn_readfirstlane(I.ru[s]);
+  if (ask < it + 2 - every || ask > it + 1) return;
+  const size_t vb = (size_t)s * 2 * g.nnode;
+  const size_t eb = (size_t)s * 4 * g.nelem;
+  const int tx = t % g.sw_ntx, ty = t / g.sw_ntx;
+  const int i0 = tx * g.sw_tw, j0 = ty * g.sw_ty;
+  const int i = i0 - 1 + lane;
+  const bool colv = lane <= g.sw_tw + 1 && i >= 0 && i < g.nnx;
+  const bool elv = lane <= g.sw_tw && i >= 0 && i < g.nx;
+  const bool own = lane >= 1 && lane <= g.sw_tw && i < g.nnx;
+  const int row_end = min(j0 + g.sw_ty, g.nny);
+  auto xrow = [&](int jr, double &a, double &b) {
+    a = b = 0.0;
+    if (colv && jr >= 0 && jr < g.nny) {
+      const size_t o = vb + 2 * ((size_t)jr * g.nnx + i);
+      const double2 v = *reinterpret_cast<const double2 *>(D.x + o);
+      const float2 d = *reinterpret_cast<const float2 *>(I.x + o);
+      a = v.x + (double)d.x;
+      b = v.y + (double)d.y;
+    }
+  };
+  double plu, plv, nhu, nhv;
+  xrow(j0 - 1, plu, plv);
+  xrow(j0, nhu, nhv);
+  double f2u = 0, f2v = 0, f3u = 0, f3v = 0, part = 0.0;
+  const int nk = row_end - j0;
+  for (int k = 0; k <= nk; ++k) {
+    const int ey = j0 - 1 + k;
+    const double phu = nhu, phv = nhv;
+    Angles<double> th;
+    th.load(D.theta, eb, g, i, elv, ey);
+    if (k < nk) xrow(ey + 2, nhu, nhv);
+    const double rlu = __shfl_down(plu, 1, 64), rlv = __shfl_down(plv, 1, 64);
+    const double rhu = __shfl_down(phu, 1, 64), rhv = __shfl_down(phv, 1, 64);
+    double fu[4] = {0, 0, 0, 0}, fv[4] = {0, 0, 0, 0};
+    if (elv && ey >= 0 && ey < g.ny) {
+      const double u[4] = {plu, rlu, rhu, phu};
+      const double v[4] = {plv, rlv, rhv, phv};
+      elem_forces_q<double>(g, [&](int q) { return th.qb(m, q); }, u, v, fu, fv);
+    }
+    const double f1lu = __shfl_up(fu[1], 1, 64), f1lv = __shfl_up(fv[1], 1, 64);
+    if (k >= 1 && own) {
+      double yu = ((f2u + f3u) + f1lu) + fu[0];
+      double yv = ((f2v + f3v) + f1lv) + fv[0];
+      if (i == 0) { yu = plu; yv = plv; }
+      if (i == g.nx) yu = plu;
+      const size_t o = vb + 2 * ((size_t)ey * g.nnx + i);
+      const double2 bv = *reinterpret_cast<const double2 *>(M.b + o);
+      const double ru = bv.x - yu, rv = bv.y - yv;
+      *reinterpret_cast<double2 *>(D.r + o) = make_double2(ru, rv);
+      part += ru * ru + rv * rv;
+    }
+    f2u = __shfl_up(fu[2], 1, 64);
+    f2v = __shfl_up(fv[2], 1, 64);
+    f3u = fu[3];
+    f3v = fv[3];
+    plu = phu;
+    plv = phv;
+  }
+  part = wave_sum(part);
+  if (lane == 0) M.part_rr[(size_t)s * g.sw_ntiles + t] = part;
+}
+
+// Second half of a reliable update: x64 += x32, x32 = 0, r32 = r64; the FP64
+// stopping test ||r|| <= rtol ||b||; the inner partial sums for the next
+// iteration (parity of it + 1) and the slot's restart.
+__global__ __launch_bounds__(256) void k_ru_apply(StripGeom g, PcgSlots D, PcgState<float> I, MixedState M, int it,
+                                                  int every) {
+  __shared__ double red4[4];
+  __shared__ int flag;
+  const int s = blockIdx.y, c = blockIdx.x;
+  if (threadIdx.x == 0) {
+    const int ask = I.ru[s];
+    flag = ask >= it + 2 - every && ask <= it + 1;
+  }
+  double prr = 0.0, pbb = 0.0;
+  for (int k = threadIdx.x; k < g.sw_ntiles; k += 256) prr += M.part_rr[(size_t)s * g.sw_ntiles + k];
+  for (int k = threadIdx.x; k < g.nchunks; k += 256) pbb += M.part_bb[(size_t)s * g.nchunks + k];
+  const double rr = block_sum(prr, red4);
+  if (!flag) return;
+  const double bb = block_sum(pbb, red4);
+  const bool done = !(rr > M.rtol2 * bb);
+  const size_t vb = (size_t)s * 2 * g.nnode;
+  double prz = 0.0, pr2 = 0.0;
+  for (int k = 0; k < CHUNK / 256; ++k) {
+    const int node = c * CHUNK + k * 256 + threadIdx.x;
+    if (node < g.nnode) {
+      const size_t o = vb + 2 * (size_t)node;
+      const float2 d = *reinterpret_cast<const float2 *>(I.x + o);
+      double2 x = *reinterpret_cast<const double2 *>(D.x + o);
+      x.x += (double)d.x;
+      x.y += (double)d.y;
+      *reinterpret_cast<double2 *>(D.x + o) = x;
+      *reinterpret_cast<float2 *>(I.x + o) = make_float2(0.0f, 0.0f);
+      const double2 rv = *reinterpret_cast<const double2 *>(D.r + o);
+      const float2 r32 = make_float2((float)rv.x, (float)rv.y);
+      *reinterpret_cast<float2 *>(I.r + o) = r32;
+      const float2 d32 = *reinterpret_cast<const float2 *>(I.dinv + o);
+      const double a = r32.x, b = r32.y;
+      prz += a * ((double)d32.x * a) + b * ((double)d32.y * b);
+      pr2 += a * a + b * b;
+    }
+  }
+  prz = block_sum(prz, red4);
+  pr2 = block_sum(pr2, red4);
+  if (threadIdx.x == 0) {
+    const size_t pb = ((size_t)((it + 1) & 1) * I.S + s) * g.nchunks + c;
+    I.part_rz[pb] = prz;
+    I.part_rr[pb] = pr2;
+    if (c == 0) {
+      M.relres[s] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+      M.updates[s] += 1;
+      I.rr_ref[s] = rr;
+      if (!isfinite(rr)) I.status[s] = S_NAN;
+      else if (done) I.status[s] = S_OK;
+      I.active[s] = (done || !isfinite(rr)) ? 0 : 1;
+    }
+  }
+}
+
+// start of a mixed-precision solve (after the FP64 set-up): FP32 copies of
+// r = b and dinv, x32 = 0, initial inner partial sums; slot flags
+__global__ __launch_bounds__(256) void k_mixed_start(StripGeom g, PcgSlots D, PcgState<float> I, MixedState M) {
+  __shared__ double red4[4];
+  const int s = blockIdx.y, c = blockIdx.x;
+  const size_t vb = (size_t)s * 2 * g.nnode;
+  double prz = 0.0, pr2 = 0.0;
+  for (int k = 0; k < CHUNK / 256; ++k) {
+    const int node = c * CHUNK + k * 256 + threadIdx.x;
+    if (node < g.nnode) {
+      const size_t o = vb + 2 * (size_t)node;
+      const double2 rv = *reinterpret_cast<const double2 *>(D.r + o);
+      const double2 dv = *reinterpret_cast<const double2 *>(D.dinv + o);
+      const float2 d32 = make_float2((float)dv.x, (float)dv.y);
+      const float2 r32 = make_float2((float)rv.x, (float)rv.y);
+      *reinterpret_cast<float2 *>(I.dinv + o) = d32;
+      *reinterpret_cast<float2 *>(I.r + o) = r32;
+      *reinterpret_cast<float2 *>(I.x + o) = make_float2(0.0f, 0.0f);
+      const double a = r32.x, b = r32.y;
+      prz += a * ((double)d32.x * a) + b * ((double)d32.y * b);
+      pr2 += a * a + b * b;
+    }
+  }
+  prz = block_sum(prz, red4);
+  pr2 = block_sum(pr2, red4);
+  if (threadIdx.x == 0) {
+    I.part_rz[(size_t)s * g.nchunks + c] = prz;
+    I.part_rr[(size_t)s * g.nchunks + c] = pr2;
+    if (c == 0) {
+      I.active[s] = 1;
+      I.status[s] = S_OK;
+      I.ru[s] = 0;
+      M.updates[s] = 0;
+      M.relres[s] = 1.0;
+    }
+  }
+}
+
+// x64 += x32 for slots that stopped without a final reliable update
+__global__ __launch_bounds__(256) void k_mixed_flush(StripGeom g, PcgSlots D, PcgState<float> I) {
+  const int s = blockIdx.y, c = blockIdx.x;
+  const size_t vb = (size_t)s * 2 * g.nnode;
+  for (int k = 0; k < CHUNK / 256; ++k) {
+    const int node = c * CHUNK + k * 256 + threadIdx.x;
+    if (node < g.nnode) {
+      const size_t o = vb + 2 * (size_t)node;
+      float2 d = *reinterpret_cast<const float2 *>(I.x + o);
+      double2 x = *reinterpret_cast<const double2 *>(D.x + o);
+      x.x += (double)d.x;
+      x.y += (double)d.y;
+      *reinterpret_cast<double2 *>(D.x + o) = x;
+      *reinterpret_cast<float2 *>(I.x + o) = make_float2(0.0f, 0.0f);
+    }
   }
 }
 
@@ -638,10 +898,10 @@ __global__ __launch_bounds__(256) void k_level_stats(const double *__restrict__ 
 static inline dim3 tile_grid(const StripGeom &g, int n) { return dim3(g.ntiles, n); }
 
 void launch_kl_synth(const double *modes, int K, const StripGeom &g, const double *xi, int ld_xi,
-                     const int64_t *rows, int n, double *th64, uint16_t *th16, int ld_out, hipStream_t st) {
+                     const int64_t *rows, int n, double *th64, void *thlo, int lo_fp32, int ld_out, hipStream_t st) {
   if (n <= 0) return;
   dim3 grid((4 * g.nelem + 255) / 256, (n + SYN_SAMPLES - 1) / SYN_SAMPLES);
-  hipLaunchKernelGGL(k_kl_synth, grid, dim3(256), 0, st, modes, K, g, xi, ld_xi, rows, n, th64, th16, ld_out);
+  hipLaunchKernelGGL(k_kl_synth, grid, dim3(256), 0, st, modes, K, g, xi, ld_xi, rows, n, th64, thlo, lo_fp32, ld_out);
 }
 
 void launch_modes_nystrom(const double *gx, const double *gy, const double *coef, int ngrid, int K, double var,
@@ -663,18 +923,42 @@ void launch_setup(const StripGeom &g, const StripMat &m, const PcgSlots &S, int 
   hipLaunchKernelGGL(k_init_partials, dim3(g.nchunks, n), dim3(256), 0, st, g, S);
 }
 
-void launch_pcg_pass1(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n, int it, hipStream_t st) {
+template <typename T>
+void launch_pcg_pass1(const StripGeom &g, const StripMat &m, const PcgState<T> &S, int n, int it, hipStream_t st) {
   const int nb = g.sw_ntiles * n;
-  hipLaunchKernelGGL(k_pass1, dim3(nb), dim3(64), 0, st, g, m, S, it, nb);
+  hipLaunchKernelGGL(k_pass1<T>, dim3(nb), dim3(64), 0, st, g, m, S, it, nb);
 }
 
-void launch_pcg_pass2(const StripGeom &g, const PcgSlots &S, int n, int it, hipStream_t st) {
-  hipLaunchKernelGGL(k_pass2, dim3(g.nchunks, n), dim3(256), 0, st, g, S, it);
+template <typename T>
+void launch_pcg_pass2(const StripGeom &g, const PcgState<T> &S, int n, int it, hipStream_t st) {
+  hipLaunchKernelGGL(k_pass2<T>, dim3(g.nchunks, n), dim3(256), 0, st, g, S, it);
 }
 
-void launch_pcg_iteration(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n, int it, hipStream_t st) {
-  launch_pcg_pass1(g, m, S, n, it, st);
-  launch_pcg_pass2(g, S, n, it, st);
+template void launch_pcg_pass1<double>(const StripGeom &, const StripMat &, const PcgState<double> &, int, int,
+                                       hipStream_t);
+template void launch_pcg_pass1<float>(const StripGeom &, const StripMat &, const PcgState<float> &, int, int,
+                                      hipStream_t);
+template void launch_pcg_pass2<double>(const StripGeom &, const PcgState<double> &, int, int, hipStream_t);
+template void launch_pcg_pass2<float>(const StripGeom &, const PcgState<float> &, int, int, hipStream_t);
+
+void launch_resid64(const StripGeom &g, const StripMat &m, const PcgSlots &D, const PcgState<float> &I,
+                    const MixedState &M, int n, int it, int every, hipStream_t st) {
+  const int nb = g.sw_ntiles * n;
+  hipLaunchKernelGGL(k_resid64, dim3(nb), dim3(64), 0, st, g, m, D, I, M, it, every, nb);
+}
+
+void launch_ru_apply(const StripGeom &g, const PcgSlots &D, const PcgState<float> &I, const MixedState &M, int n,
+                     int it, int every, hipStream_t st) {
+  hipLaunchKernelGGL(k_ru_apply, dim3(g.nchunks, n), dim3(256), 0, st, g, D, I, M, it, every);
+}
+
+void launch_mixed_start(const StripGeom &g, const PcgSlots &D, const PcgState<float> &I, const MixedState &M, int n,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_mixed_start, dim3(g.nchunks, n), dim3(256), 0, st, g, D, I, M);
+}
+
+void launch_mixed_flush(const StripGeom &g, const PcgSlots &D, const PcgState<float> &I, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_mixed_flush, dim3(g.nchunks, n), dim3(256), 0, st, g, D, I);
 }
 
 int qoi_parts(const StripGeom &g) { return ((g.qx1 - g.qx0) * (g.qy1 - g.qy0) + 255) / 256; }
@@ -683,7 +967,7 @@ void launch_qoi(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n,
                 double *q, mlmc_info_dev *info, int coarse, hipStream_t st) {
   if (n <= 0) return;
   const int np = qoi_parts(g);
-  hipLaunchKernelGGL(k_qoi_part, dim3(np, n), dim3(256), 0, st, g, m, S.theta, S.x, np, part);
+  hipLaunchKernelGGL(k_qoi_part, dim3(np, n), dim3(256), 0, st, g, m, (const double *)S.theta, S.x, np, part);
   hipLaunchKernelGGL(k_qoi_final, dim3((n + 127) / 128), dim3(128), 0, st, part, np, n, out_idx, q, S, info,
                      coarse, nullptr, g.nnode, g.delta, g.nnx);
 }
@@ -692,6 +976,24 @@ void launch_total_disp(const StripGeom &g, const double *x, double *d, int n, hi
   const size_t tot = (size_t)n * 2 * g.nnode;
   if (!tot) return;
   hipLaunchKernelGGL(k_total_disp, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, g, x, d, n);
+}
+
+__global__ void k_to_lo(const double *__restrict__ a, void *__restrict__ b, int lo_fp32, size_t n) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const float f = (float)a[k];
+  if (lo_fp32) {
+    ((float *)b)[k] = f;
+  } else {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    ((uint16_t *)b)[k] = (uint16_t)(u >> 16);
+  }
+}
+
+void launch_to_lo(const double *a, void *b, int lo_fp32, size_t n, hipStream_t st) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_to_lo, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, lo_fp32, n);
 }
 
 void launch_info_init(mlmc_info_dev *info, double *q_coarse, int n, hipStream_t st) {

@@ -1,0 +1,214 @@
+"""MLMC drivers over the HIP sample-solve library (Section 2 of the paper).
+
+* :func:`adaptive_mlmc` is Algorithm 1 (adaptive MLMC) written over per-level
+  FP64 accumulators (``N_l``, ``sum Y``, ``sum Y^2``): sample means,
+  Eq. varianceestim for ``V_l``, Eq. optimal_Nl for the sample numbers,
+  Eq. bias_estimate for the stopping test and Eq. tausplit for the split of
+  the tolerance.  Readings where the paper is ambiguous: the level counter
+  is incremented at the top of every pass (the printed loop never does it);
+  the bias estimate uses ``|Yhat_L|``; ``alpha`` is fitted on the levels
+  ``l >= 1`` once two exist (otherwise a default); the run stops at the top
+  configured level with ``converged = False`` if the bias test never passes.
+* :class:`StripSampler` draws strip samples (seeded parameter rows), solves
+  coupled fine/coarse pairs on the GPU and accumulates the level sums on the
+  GPU; the cost ``C_l`` of a sample is the measured wall time per sample.
+
+The sampler interface is ``sample(level, n) -> None`` (adds ``n`` samples to
+the level's accumulator) plus ``acc[level]`` and ``cost(level)``, so the same
+algorithm drives any sampler (tests use synthetic ones).
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+
+from ._lib import FP64, LevelAcc
+
+
+@dataclass
+class LevelSums:
+    """FP64 level accumulator (host side): N, sum Y, sum Y^2 and the cost spent."""
+    n: int = 0
+    sum_y: float = 0.0
+    sum_y2: float = 0.0
+    seconds: float = 0.0
+
+    @property
+    def mean(self) -> float:
+        return self.sum_y / self.n
+
+    @property
+    def var(self) -> float:
+        """Population variance (1/N), Eq. varianceestim."""
+        m = self.mean
+        return self.sum_y2 / self.n - m * m
+
+    @property
+    def var_unbiased(self) -> float:
+        return self.var * self.n / (self.n - 1) if self.n > 1 else float("nan")
+
+    @staticmethod
+    def from_acc(acc: LevelAcc, seconds: float) -> "LevelSums":
+        return LevelSums(int(acc.n), acc.sum_y + acc.comp_y, acc.sum_y2 + acc.comp_y2, seconds)
+
+
+@dataclass
+class MLMCResult:
+    estimate: float
+    levels: List[Dict]
+    L: int
+    converged: bool
+    e_abs: float
+    bias: float
+    sampling_err2: float
+    alpha: float
+    passes: int
+    seconds: float
+    history: List[Dict] = field(default_factory=list)
+
+    def as_dict(self) -> Dict:
+        return {"estimate": self.estimate, "L": self.L, "converged": self.converged, "e_abs": self.e_abs,
+                "bias_estimate": self.bias, "sampling_err2": self.sampling_err2, "alpha": self.alpha,
+                "passes": self.passes, "seconds": self.seconds, "levels": self.levels}
+
+
+def _alpha_fit(M: List[float], yhat: List[float]) -> float:
+    x = np.log(np.asarray(M, float))
+    y = np.log(np.abs(np.asarray(yhat, float)))
+    slope = np.polyfit(x, y, 1)[0]
+    return float(-slope)
+
+
+def adaptive_mlmc(sampler, L_max: int, eps_abs: Optional[float] = None, eps_rel: Optional[float] = None,
+                  theta: float = 0.5, n_star: int = 100, m: float = 4.0, alpha_default: float = 1.0,
+                  dofs: Optional[List[float]] = None, max_new: int = 10 ** 9,
+                  log: Optional[Callable[[Dict], None]] = None) -> MLMCResult:
+    """Algorithm 1.  The tolerance is ``eps_abs`` or ``eps_rel * |estimate|``
+    (re-evaluated after every pass).  ``dofs[l]`` (M_l) enables the fit of alpha."""
+    if (eps_abs is None) == (eps_rel is None):
+        raise ValueError("give exactly one of eps_abs, eps_rel")
+    t0 = time.perf_counter()
+    L = -1
+    passes = 0
+    alpha = alpha_default
+    converged = False
+    hist: List[Dict] = []
+    e_abs = eps_abs
+    bias = math.inf
+    while True:
+        L += 1
+        passes += 1
+        sampler.sample(L, n_star)
+        est = sum(sampler.acc(l).mean for l in range(L + 1))
+        if eps_rel is not None:
+            e_abs = eps_rel * abs(est)
+        e_s2 = theta * e_abs * e_abs
+        e_b = math.sqrt(1.0 - theta) * e_abs
+        V = [max(sampler.acc(l).var, 0.0) for l in range(L + 1)]
+        C = [sampler.cost(l) for l in range(L + 1)]
+        s = sum(math.sqrt(v * c) for v, c in zip(V, C))
+        for l in range(L + 1):
+            n_opt = math.ceil(s * math.sqrt(V[l] / C[l]) / e_s2) if C[l] > 0 else 0
+            have = sampler.acc(l).n
+            if have < n_opt:
+                sampler.sample(l, int(min(n_opt - have, max_new)))
+        yhat = [sampler.acc(l).mean for l in range(L + 1)]
+        if dofs is not None and L >= 2:
+            alpha = _alpha_fit(dofs[1:L + 1], yhat[1:L + 1])
+        bias = abs(yhat[L]) / (m ** alpha - 1.0)
+        rec = {"pass": passes, "L": L, "N": [sampler.acc(l).n for l in range(L + 1)], "yhat": yhat,
+               "V": [sampler.acc(l).var for l in range(L + 1)], "C": C, "e_abs": e_abs, "bias": bias,
+               "e_b": e_b, "alpha": alpha, "t": time.perf_counter() - t0}
+        hist.append(rec)
+        if log:
+            log(rec)
+        if bias < e_b:
+            converged = True
+            break
+        if L >= L_max:
+            break
+    levels = []
+    for l in range(L + 1):
+        a = sampler.acc(l)
+        levels.append({"level": l, "N": a.n, "mean": a.mean, "var": a.var, "var_unbiased": a.var_unbiased,
+                       "cost_per_sample_s": sampler.cost(l)})
+    est = sum(lv["mean"] for lv in levels)
+    samp = sum(lv["var"] / lv["N"] for lv in levels)
+    return MLMCResult(est, levels, L, converged, e_abs, bias, samp, alpha, passes,
+                      time.perf_counter() - t0, hist)
+
+
+class StripSampler:
+    """Coupled strip samples on the GPU: Y_0 = Q_0, Y_l = Q_l - Q_{l-1} (same row)."""
+
+    def __init__(self, ctx, cfg: Dict, precision: int = FP64, rtol: float = 0.0, max_batch: int = 4096,
+                 cost_model: Optional[Callable[[int], float]] = None):
+        import torch
+        import mlmc_inputs as mi
+        self.torch = torch
+        self.mi = mi
+        self.ctx = ctx
+        self.cfg = cfg
+        self.precision = precision
+        self.rtol = rtol
+        self.max_batch = max_batch
+        self.cost_model = cost_model
+        self.next_row = {}
+        self._acc: Dict[int, LevelAcc] = {}
+        self._sec: Dict[int, float] = {}
+        self.failures = 0
+        self.solves = {}
+
+    def acc(self, level: int) -> LevelSums:
+        return LevelSums.from_acc(self._acc[level], self._sec.get(level, 0.0))
+
+    def cost(self, level: int) -> float:
+        if self.cost_model is not None:
+            return self.cost_model(level)
+        a = self._acc[level]
+        return self._sec[level] / max(a.n, 1)
+
+    def sample(self, level: int, n: int) -> None:
+        torch = self.torch
+        done = 0
+        while done < n:
+            k = min(self.max_batch, n - done)
+            start = self.next_row.get(level, 0)
+            rows = self.mi.strip_xi(self.cfg, level, start, k)
+            xi = torch.from_numpy(rows).to("cuda")
+            req = [(j, level, level > 0) for j in range(k)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            qf, qc, info = self.ctx.solve_batch(req, xi, precision=self.precision, rtol=self.rtol)
+            acc = self._acc.setdefault(level, LevelAcc())
+            self.ctx.level_stats(level, qf, qc if level > 0 else None, acc=acc)
+            dt = time.perf_counter() - t0
+            bad = int(np.sum(info["status_f"] != 0) + (np.sum(info["status_c"] != 0) if level > 0 else 0))
+            if bad:
+                self.failures += bad
+                raise RuntimeError(f"level {level}: {bad} solves did not converge (rows {start}..{start + k})")
+            self._sec[level] = self._sec.get(level, 0.0) + dt
+            self.next_row[level] = start + k
+            self.solves[level] = self.solves.get(level, 0) + k * (2 if level > 0 else 1)
+            done += k
+
+
+def run_strip_mlmc(ctx, cfg: Dict, precision: int = FP64, eps_rel: Optional[float] = None,
+                   eps_abs: Optional[float] = None, L_max: Optional[int] = None, log=None,
+                   cost_model=None) -> MLMCResult:
+    """Algorithm 1 on the strip workload ``cfg`` with the GPU sampler."""
+    ml = cfg.get("mlmc", {})
+    if eps_rel is None and eps_abs is None:
+        eps_rel = ml.get("eps_rel", 1e-3)
+    L_max = cfg["n_levels"] - 1 if L_max is None else L_max
+    sampler = StripSampler(ctx, cfg, precision=precision, cost_model=cost_model)
+    dofs = [ctx.level_info(l)["n_dofs"] for l in range(cfg["n_levels"])]
+    res = adaptive_mlmc(sampler, L_max, eps_abs=eps_abs, eps_rel=eps_rel, theta=ml.get("theta", 0.5),
+                        n_star=ml.get("n_star", 100), m=ml.get("m", 4), alpha_default=ml.get("alpha_default", 1.0),
+                        dofs=dofs, log=log)
+    res.history.append({"solves_per_level": dict(sampler.solves)})
+    return res

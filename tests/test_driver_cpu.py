@@ -1,0 +1,71 @@
+"""Host logic of the product's Algorithm 1 against the oracle's Algorithm 1.
+
+Both run on the same synthetic sampler (no GPU): the product keeps FP64
+level sums, the oracle keeps the samples; their decisions (levels added,
+sample numbers, stopping) and estimates must agree."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlmc as omlmc
+from paper_1907_10271_amd.driver import LevelSums, adaptive_mlmc
+
+
+def synthetic(level, start, n, mu0=10.0, c_mean=0.4, c_var=0.5, alpha=1.0, beta=1.5, v0=4.0, seed=7):
+    out = np.empty(n)
+    for i, j in enumerate(range(start, start + n)):
+        g = np.random.default_rng([seed, level, int(j)])
+        if level == 0:
+            out[i] = mu0 + math.sqrt(v0) * g.standard_normal()
+        else:
+            out[i] = c_mean * 4.0 ** (-alpha * level) + math.sqrt(c_var * 4.0 ** (-beta * level)) * g.standard_normal()
+    return out
+
+
+class SumSampler:
+    def __init__(self, gen, cost):
+        self.gen, self._cost, self.s = gen, cost, {}
+
+    def sample(self, level, n):
+        ls = self.s.setdefault(level, LevelSums())
+        y = self.gen(level, ls.n, n)
+        ls.n += n
+        ls.sum_y += float(np.sum(y))
+        ls.sum_y2 += float(np.sum(y * y))
+
+    def acc(self, level):
+        return self.s[level]
+
+    def cost(self, level):
+        return self._cost(level)
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(alpha=0.6, beta=1.0), dict(v0=0.5, c_mean=1.0)])
+@pytest.mark.parametrize("eps", [0.05, 0.02])
+def test_algorithm1_matches_oracle(kw, eps):
+    gen = lambda l, s, n: synthetic(l, s, n, **kw)
+    cost = lambda l: 4.0 ** l
+    ref = omlmc.algorithm1(gen, cost, e=eps, theta=0.5, n_star=100, m=4, L_max=6)
+    res = adaptive_mlmc(SumSampler(gen, cost), L_max=6, eps_abs=eps, theta=0.5, n_star=100, m=4)
+    assert res.L == ref.L and res.converged == ref.converged
+    assert [lv["N"] for lv in res.levels] == ref.N
+    assert abs(res.estimate - ref.estimate) <= 1e-12 * abs(ref.estimate)
+    for lv, v in zip(res.levels, ref.V):
+        assert abs(lv["var"] - v) <= 1e-9 * abs(v)
+
+
+def test_relative_tolerance_and_alpha_fit_match_oracle():
+    gen = lambda l, s, n: synthetic(l, s, n, alpha=0.8)
+    cost = lambda l: 4.0 ** (1.2 * l)
+    M = [100.0 * 4 ** l for l in range(7)]
+    ref = omlmc.algorithm1(gen, cost, e=None, eps_rel=3e-3, theta=0.5, n_star=50, m=4, L_max=6, M=M)
+    res = adaptive_mlmc(SumSampler(gen, cost), L_max=6, eps_rel=3e-3, theta=0.5, n_star=50, m=4, dofs=M)
+    assert res.L == ref.L and [lv["N"] for lv in res.levels] == ref.N
+    assert abs(res.alpha - ref.alpha) < 1e-9
+    assert abs(res.e_abs - ref.e_abs) <= 1e-12 * ref.e_abs
+
+
+def test_population_variance():
+    s = LevelSums(4, 14.0, 70.0)
+    assert s.mean == 3.5 and s.var == np.var([1.0, 2.0, 4.0, 7.0])

@@ -201,3 +201,34 @@ def test_nan_and_iteration_limit_reported_per_sample():
     c2 = pk.Context(cfg)
     _, _, info2 = c2.solve_batch([(0, 0, False)], dev(_rows("strip_c1", 0, 1)))
     assert info2[0]["status_f"] == 1 and info2[0]["iters_f"] == 3
+
+
+# ------------------------------------------------------------------ mixed precision
+@pytest.mark.parametrize("name,level", [("strip_c1", 1), ("strip_c2", 0), ("strip_c2", 2)])
+def test_mixed_precision_qoi_and_fp64_residual(name, level):
+    """FP32/BF16 inner solves under FP64 refinement: the refinement residual is
+    computed with the FP64 angles, so the FP64 true residual reaches rtol and the
+    QoI agrees with the oracle's direct solve to well within the stated 1e-6."""
+    import paper_1907_10271_amd as pk
+    from oracle.strip import assemble, reduce_system
+    ctx = context(name)
+    om = oracle_strip(name, level)
+    xi = _rows(name, level, 4)
+    thetas = np.stack([om.theta(r).ravel() for r in xi])
+    rtol = mi.load_config(name)["rtol"]
+    q, d, info = ctx.strip_solve_theta(level, dev(thetas), precision=pk.MIXED, rtol=rtol, want_d=True)
+    q, d = q.cpu().numpy(), d.cpu().numpy()
+    for k in range(4):
+        assert info[k]["status_f"] == 0
+        K = assemble(om.mesh, om.Q, thetas[k].reshape(-1, 4))
+        free, Kff, b = reduce_system(K, om.bc)
+        true_res = np.linalg.norm(b - Kff @ d[k][free]) / np.linalg.norm(b)
+        assert true_res <= 1.01 * rtol, true_res
+        ref = om.solve_theta(thetas[k].reshape(-1, 4), method="direct").q
+        err = abs(q[k] - ref) / abs(ref)
+        assert err <= 1e-6, err
+    # through the sample path as well (BF16 angles synthesised on the GPU)
+    qf, qc, inf2 = ctx.solve_batch([(k, level, level > 0) for k in range(4)], dev(xi), precision=pk.MIXED)
+    q64, qc64, _ = ctx.solve_batch([(k, level, level > 0) for k in range(4)], dev(xi))
+    assert np.all(inf2["status_f"] == 0)
+    assert np.max(np.abs(qf.cpu().numpy() - q64.cpu().numpy()) / np.abs(q64.cpu().numpy())) <= 1e-6
