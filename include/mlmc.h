@@ -177,6 +177,16 @@ int mlmc_buckle_batch(mlmc_ctx *ctx, int n_req, const mlmc_request *req, const d
                       int64_t n_rows, double *lam_fine, double *lam_coarse, mlmc_info *info, int precision,
                       double tol, void *stream);
 
+/* Matrix-free plate operators for one sample per row of ply_offsets (dev
+ * [n][n_plies], radians): y = P K P x (geometric == 0) or y = P K_G P x
+ * (geometric != 0), with P the projector on the unconstrained unknowns
+ * (Section 4.1: Reissner-Mindlin Q4, selective reduced integration;
+ * K_G = int N0 w_x w_x).  x, y: dev [n][5 n_nodes], unknowns (u, v, w,
+ * theta_x, theta_y) per node, node (i, j) at j (nx + 1) + i; y = 0 on
+ * constrained unknowns. */
+int mlmc_plate_apply(mlmc_ctx *ctx, int level, int n, const double *ply_offsets, int geometric, const double *x,
+                     double *y, void *stream);
+
 /* ------------------------------------------------------------- level sums */
 
 /* Accumulate one batch of a level into `acc` (host, in/out), in FP64 with a

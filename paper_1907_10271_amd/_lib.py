@@ -25,7 +25,7 @@ S_OK, S_NOCONV, S_NAN, S_BREAKDOWN, S_SKIPPED = 0, 1, 2, 3, 4
 EXPORTS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_level_info", "mlmc_num_levels",
            "mlmc_footprint", "mlmc_sample_field", "mlmc_strip_apply", "mlmc_strip_rhs_diag",
            "mlmc_strip_solve_theta", "mlmc_solve_batch", "mlmc_buckle_batch", "mlmc_level_stats",
-           "mlmc_profile_enable", "mlmc_profile_read"]
+           "mlmc_profile_enable", "mlmc_profile_read", "mlmc_plate_apply"]
 
 
 class Request(C.Structure):
@@ -85,6 +85,7 @@ def load() -> C.CDLL:
     lib.mlmc_solve_batch.argtypes = [vp, i, C.POINTER(Request), vp, C.c_int64, i, vp, vp, vp, i, d, vp]
     lib.mlmc_buckle_batch.argtypes = [vp, i, C.POINTER(Request), vp, C.c_int64, vp, vp, vp, i, d, vp]
     lib.mlmc_level_stats.argtypes = [vp, i, i, vp, vp, d, d, C.POINTER(LevelAcc), vp]
+    lib.mlmc_plate_apply.argtypes = [vp, i, i, vp, i, vp, vp, vp]
     lib.mlmc_profile_enable.argtypes = [vp, i]
     lib.mlmc_profile_read.argtypes = [vp, i, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     _lib = lib
@@ -232,6 +233,13 @@ class Context:
         ms, n, b = C.c_double(), C.c_int64(), C.c_double()
         self._check(self.lib.mlmc_profile_read(self.h, kernel, C.byref(ms), C.byref(n), C.byref(b)))
         return {"ms": ms.value, "launches": n.value, "bytes": b.value}
+
+    def plate_apply(self, level: int, offsets, x, geometric: bool = False, stream=None):
+        torch = _torch()
+        y = torch.empty_like(x)
+        self._check(self.lib.mlmc_plate_apply(self.h, level, x.shape[0], _ptr(offsets), int(geometric), _ptr(x),
+                                              _ptr(y), _stream(stream)))
+        return y
 
     # ------------------------------------------------------------ sums
     def level_stats(self, level: int, q_fine, q_coarse=None, cost_per_sample: float = 0.0,

@@ -815,6 +815,14 @@ int mlmc_level_stats(mlmc_ctx *c, int level, int n, const double *q_fine, const 
   return MLMC_OK;
 }
 
+int mlmc_plate_apply(mlmc_ctx *c, int level, int n, const double *ply_offsets, int geometric, const double *x,
+                     double *y, void *stream) {
+  if (!c) return MLMC_EINVAL;
+  if (c->kind != 1) return fail(c, MLMC_ESTATE, "plate_apply needs a plate context");
+  if (n > 0 && (!ply_offsets || !x || !y)) return fail(c, MLMC_EINVAL, "null pointer");
+  return plate_apply_diag(c->plate, c->err, level, n, ply_offsets, geometric, x, y, (hipStream_t)stream);
+}
+
 int mlmc_profile_enable(mlmc_ctx *c, int on) {
   if (!c) return MLMC_EINVAL;
   c->prof = on != 0;

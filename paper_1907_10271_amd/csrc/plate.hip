@@ -1,47 +1,866 @@
-// Plate buckling (Section 4.1): placeholder until the batched eigen-solver lands.
+// Buckling of a laminated Reissner-Mindlin plate (Section 4.1 of the paper):
+// classical laminate theory (Eq. CLTABD) for each sample's perturbed ply
+// angles, bilinear Q4 elements with selective reduced integration (membrane,
+// coupling and bending 2x2, transverse shear 1x1), the geometric stiffness of
+// a unit compressive edge load, and the smallest positive lambda of
+// K phi = lambda K_G phi (Eq. matrixeig), found as the largest mu of
+// K_G x = mu K x by block LOBPCG.
+//
+// One work-group solves one sample from start to finish (a persistent launch
+// per level batch): laminate, element matrices, lower band of K on the free
+// unknowns, banded Cholesky factor (the LOBPCG preconditioner T = K^-1), then
+// LOBPCG with block size 2 and a Rayleigh-Ritz step in FP64.  In the mixed
+// form the factor and the triangular solves are FP32; the operators,
+// residuals and the Rayleigh-Ritz step stay FP64.  Every reduction runs in a
+// fixed order inside the work-group, so a sample's result does not depend on
+// the batch.
 #include "plate.hpp"
+#include "strip_kernels.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
 
 namespace mlmc {
 
+constexpr int PT = 256;      // threads per work-group
+constexpr int NB = 2;        // LOBPCG block size
+constexpr int NS = 3 * NB;   // Rayleigh-Ritz basis size [X, W, P]
+constexpr int MAXPLY = 32;
+
+struct PlateGeom {
+  int nx, ny, nnx, nny, nn, nfull, nfree, bw;
+  double hx, hy, a, b;
+  const int *free_of_full;  // [nfull] free index or -1
+  const int *full_of_free;  // [nfree]
+};
+
+struct PlateMat {
+  double Q11, Q22, Q12, Q66;
+  double shear_k_G_t;  // k G t
+  double N0;
+  int nply;
+  double t_ply;
+  double layup[MAXPLY];
+};
+
+// per-sample scratch of a level batch (device pointers, sample stride given)
+struct PlateWork {
+  double *band;    // [S][nfree][bw+1] FP64 factor (FP64 solves)
+  float *bandf;    // [S][nfree][bw+1] FP32 factor (mixed)
+  double *vec;     // [S][NVEC][nfree]
+  int nvec;
+  size_t band_stride, vec_stride;
+};
+
+enum { V_X = 0, V_W = NB, V_P = 2 * NB, V_KX = 3 * NB, V_KW = 4 * NB, V_KP = 5 * NB, V_GX = 6 * NB, V_GW = 7 * NB,
+       V_GP = 8 * NB, V_R = 9 * NB, V_T = 10 * NB, NVEC = 11 * NB };
+
+// ---------------------------------------------------------------- small helpers
+__device__ double block_reduce(double v, double *red) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  return ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// rotated ply stiffness (fibres at angle th from x), engineering shear
+__device__ void qbar_ply(const PlateMat &m, double th, double q[6]) {
+  double s, c;
+  sincos(th, &s, &c);
+  const double c2 = c * c, s2 = s * s, cs = c * s;
+  // Qbar = T^T Q T with T the engineering-strain rotation to fibre axes
+  q[0] = m.Q11 * c2 * c2 + 2.0 * (m.Q12 + 2.0 * m.Q66) * s2 * c2 + m.Q22 * s2 * s2;        // 11
+  q[1] = (m.Q11 + m.Q22 - 4.0 * m.Q66) * s2 * c2 + m.Q12 * (s2 * s2 + c2 * c2);             // 12
+  q[2] = m.Q11 * s2 * s2 + 2.0 * (m.Q12 + 2.0 * m.Q66) * s2 * c2 + m.Q22 * c2 * c2;        // 22
+  q[3] = (m.Q11 - m.Q12 - 2.0 * m.Q66) * c2 * cs + (m.Q12 - m.Q22 + 2.0 * m.Q66) * s2 * cs; // 16
+  q[4] = (m.Q11 - m.Q12 - 2.0 * m.Q66) * s2 * cs + (m.Q12 - m.Q22 + 2.0 * m.Q66) * c2 * cs; // 26
+  q[5] = (m.Q11 + m.Q22 - 2.0 * m.Q12 - 2.0 * m.Q66) * s2 * c2 + m.Q66 * (s2 * s2 + c2 * c2);  // 66
+}
+
+// generalised strain vector of unknown (node a, component c) at a point with
+// shape derivatives (dNx, dNy): (eps_x, eps_y, gamma_xy, kappa_x, kappa_y, kappa_xy)
+__device__ void gen_strain(int c, double dNx, double dNy, double e[6]) {
+  for (int k = 0; k < 6; ++k) e[k] = 0.0;
+  if (c == 0) { e[0] = dNx; e[2] = dNy; }
+  else if (c == 1) { e[1] = dNy; e[2] = dNx; }
+  else if (c == 3) { e[3] = dNx; e[5] = dNy; }
+  else if (c == 4) { e[4] = dNy; e[5] = dNx; }
+}
+
+// K_e and K_G,e of the uniform element of a sample (20 x 20, unknowns 5 a + c,
+// nodes counter-clockwise from the lower-left corner); Dmb = [[A, B], [B, D]]
+__device__ void element_matrices(const PlateGeom &g, const PlateMat &m, const double *Dmb /*6x6*/, double *Ke,
+                                 double *KGe) {
+  const double gq = 0.57735026918962576451;
+  const double jx = 0.5 * g.hx, jy = 0.5 * g.hy, det = jx * jy;
+  const double xa[4] = {-1, 1, 1, -1}, ya[4] = {-1, -1, 1, 1};
+  for (int idx = threadIdx.x; idx < 400; idx += PT) {
+    const int I = idx / 20, J = idx % 20;
+    const int a = I / 5, c = I % 5, b2 = J / 5, d = J % 5;
+    double kv = 0.0, kg = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      const double xi = (q & 1) ? gq : -gq, eta = (q & 2) ? gq : -gq;
+      const double dNxa = 0.25 * xa[a] * (1 + ya[a] * eta) / jx, dNya = 0.25 * ya[a] * (1 + xa[a] * xi) / jy;
+      const double dNxb = 0.25 * xa[b2] * (1 + ya[b2] * eta) / jx, dNyb = 0.25 * ya[b2] * (1 + xa[b2] * xi) / jy;
+      double ea[6], eb[6];
+      gen_strain(c, dNxa, dNya, ea);
+      gen_strain(d, dNxb, dNyb, eb);
+      double s = 0.0;
+      for (int r = 0; r < 6; ++r)
+        for (int t = 0; t < 6; ++t) s += ea[r] * Dmb[6 * r + t] * eb[t];
+      kv += det * s;
+      if (c == 2 && d == 2) kg += det * m.N0 * dNxa * dNxb;
+    }
+    // transverse shear at the centre (weight 4): gamma = (w_x - theta_x, w_y - theta_y)
+    const double Na = 0.25, Nb = 0.25;
+    const double dNxa = 0.25 * xa[a] / jx, dNya = 0.25 * ya[a] / jy;
+    const double dNxb = 0.25 * xa[b2] / jx, dNyb = 0.25 * ya[b2] / jy;
+    double sa[2] = {0, 0}, sb[2] = {0, 0};
+    if (c == 2) { sa[0] = dNxa; sa[1] = dNya; }
+    if (c == 3) sa[0] = -Na;
+    if (c == 4) sa[1] = -Na;
+    if (d == 2) { sb[0] = dNxb; sb[1] = dNyb; }
+    if (d == 3) sb[0] = -Nb;
+    if (d == 4) sb[1] = -Nb;
+    kv += 4.0 * det * m.shear_k_G_t * (sa[0] * sb[0] + sa[1] * sb[1]);
+    Ke[idx] = kv;
+    KGe[idx] = kg;
+  }
+}
+
+// y = P K P x on the free unknowns (element-by-element gather at every node)
+template <bool GEOM>
+__device__ void plate_apply(const PlateGeom &g, const double *Ke, const double *x, double *y) {
+  for (int r = threadIdx.x; r < g.nfree; r += PT) {
+    const int full = g.full_of_free[r];
+    const int node = full / 5, c = full % 5;
+    double acc = 0.0;
+    if (!GEOM || c == 2) {
+      const int i = node % g.nnx, j = node / g.nnx;
+      // elements around the node in a fixed order: (i-1,j-1), (i,j-1), (i-1,j), (i,j)
+      for (int e = 0; e < 4; ++e) {
+        const int ex = i - 1 + (e & 1), ey = j - 1 + (e >> 1);
+        if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny) continue;
+        const int n0 = ey * g.nnx + ex;
+        const int nodes[4] = {n0, n0 + 1, n0 + g.nnx + 1, n0 + g.nnx};
+        const int a = (e == 0) ? 2 : (e == 1) ? 3 : (e == 2) ? 1 : 0;  // local index of the node
+        const double *row = Ke + 20 * (5 * a + c);
+        for (int b2 = 0; b2 < 4; ++b2)
+          for (int d = (GEOM ? 2 : 0); d < (GEOM ? 3 : 5); ++d) {
+            const int f = g.free_of_full[5 * nodes[b2] + d];
+            if (f >= 0) acc += row[5 * b2 + d] * x[f];
+          }
+      }
+    }
+    y[r] = acc;
+  }
+}
+
+// lower band of K on the free unknowns: band[r][d] = K[r][r - d], d = 0..bw
+template <typename B>
+__device__ void assemble_band(const PlateGeom &g, const double *Ke, B *band) {
+  const int w = g.bw + 1;
+  for (int idx = threadIdx.x; idx < g.nfree * w; idx += PT) {
+    const int r = idx / w, d = idx % w;
+    double v = 0.0;
+    const int cfree = r - d;
+    if (cfree >= 0) {
+      const int fr = g.full_of_free[r], fc = g.full_of_free[cfree];
+      const int nr = fr / 5, cr = fr % 5, nc = fc / 5, cc = fc % 5;
+      const int ir = nr % g.nnx, jr = nr / g.nnx, ic = nc % g.nnx, jc = nc / g.nnx;
+      if (abs(ir - ic) <= 1 && abs(jr - jc) <= 1) {
+        for (int e = 0; e < 4; ++e) {
+          const int ex = ir - 1 + (e & 1), ey = jr - 1 + (e >> 1);
+          if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny) continue;
+          if (ic < ex || ic > ex + 1 || jc < ey || jc > ey + 1) continue;
+          const int a = (e == 0) ? 2 : (e == 1) ? 3 : (e == 2) ? 1 : 0;
+          const int lx = ic - ex, ly = jc - ey;
+          const int b2 = (ly == 0) ? lx : 3 - lx;
+          v += Ke[20 * (5 * a + cr) + 5 * b2 + cc];
+        }
+      }
+    }
+    band[idx] = (B)v;
+  }
+}
+
+// right-looking banded Cholesky in place: band[k][0] <- L_kk, band[k + d][d] <- L_{k+d,k}
+template <typename B>
+__device__ bool band_cholesky(const PlateGeom &g, B *band, B *col /*LDS, bw + 1*/) {
+  const int w = g.bw + 1, n = g.nfree;
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  for (int k = 0; k < n; ++k) {
+    __syncthreads();
+    const B piv2 = band[(size_t)k * w];
+    if (!(piv2 > B(0))) {
+      if (threadIdx.x == 0) bad = 1;
+      __syncthreads();
+      return false;
+    }
+    const B piv = sqrt(piv2);
+    const int dmax = min(g.bw, n - 1 - k);
+    for (int d = threadIdx.x; d <= dmax; d += PT) {
+      const B v = (d == 0) ? piv : band[(size_t)(k + d) * w + d] / piv;
+      col[d] = v;
+      band[(size_t)(k + d) * w + d] = v;
+    }
+    __syncthreads();
+    // A[k+d1][k+d2] -= L_{k+d1,k} L_{k+d2,k}, 1 <= d2 <= d1 <= dmax
+    const int npair = dmax * (dmax + 1) / 2;
+    for (int p = threadIdx.x; p < npair; p += PT) {
+      // p -> (d1, d2): rows d1 = 1..dmax hold d1 entries each
+      int d1 = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+      while ((d1 + 1) * (d1 + 2) / 2 <= p) ++d1;
+      while (d1 * (d1 + 1) / 2 > p) --d1;
+      const int d2 = p - d1 * (d1 + 1) / 2;  // 0..d1
+      const int D1 = d1 + 1, D2 = d2 + 1;     // 1-based offsets
+      band[(size_t)(k + D1) * w + (D1 - D2)] -= col[D1] * col[D2];
+    }
+  }
+  __syncthreads();
+  return bad == 0;
+}
+
+// z = (L L^T)^-1 r for NB right-hand sides (column-oriented sweeps)
+template <typename B>
+__device__ void band_solve(const PlateGeom &g, const B *band, const double *r, double *z, int ld, B *tmp) {
+  const int w = g.bw + 1, n = g.nfree;
+  for (int v = 0; v < NB; ++v)
+    for (int i = threadIdx.x; i < n; i += PT) tmp[(size_t)v * n + i] = (B)r[(size_t)v * ld + i];
+  // forward: L y = r
+  for (int k = 0; k < n; ++k) {
+    __syncthreads();
+    const B lkk = band[(size_t)k * w];
+    B yk[NB];
+    for (int v = 0; v < NB; ++v) yk[v] = tmp[(size_t)v * n + k] / lkk;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int v = 0; v < NB; ++v) tmp[(size_t)v * n + k] = yk[v];
+    const int dmax = min(g.bw, n - 1 - k);
+    for (int d = 1 + threadIdx.x; d <= dmax; d += PT) {
+      const B l = band[(size_t)(k + d) * w + d];
+      for (int v = 0; v < NB; ++v) tmp[(size_t)v * n + k + d] -= l * yk[v];
+    }
+  }
+  // backward: L^T z = y
+  for (int k = n - 1; k >= 0; --k) {
+    __syncthreads();
+    const B lkk = band[(size_t)k * w];
+    B zk[NB];
+    for (int v = 0; v < NB; ++v) zk[v] = tmp[(size_t)v * n + k] / lkk;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int v = 0; v < NB; ++v) tmp[(size_t)v * n + k] = zk[v];
+    const int dmax = min(g.bw, k);
+    for (int d = 1 + threadIdx.x; d <= dmax; d += PT) {
+      const B l = band[(size_t)k * w + d];
+      for (int v = 0; v < NB; ++v) tmp[(size_t)v * n + k - d] -= l * zk[v];
+    }
+  }
+  __syncthreads();
+  for (int v = 0; v < NB; ++v)
+    for (int i = threadIdx.x; i < n; i += PT) z[(size_t)v * ld + i] = (double)tmp[(size_t)v * n + i];
+  __syncthreads();
+}
+
+// symmetric eigen-decomposition of a small dense matrix (cyclic Jacobi), one thread
+__device__ void jacobi_small(double *A, double *V, int m) {
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) V[i * m + j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, nrm = 0.0;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        nrm += A[i * m + j] * A[i * m + j];
+        if (i != j) off += A[i * m + j] * A[i * m + j];
+      }
+    if (off <= 1e-30 * nrm) break;
+    for (int p = 0; p < m; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        const double apq = A[p * m + q];
+        if (apq == 0.0) continue;
+        const double tau = (A[q * m + q] - A[p * m + p]) / (2.0 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+        for (int k = 0; k < m; ++k) {
+          const double akp = A[k * m + p], akq = A[k * m + q];
+          A[k * m + p] = cs * akp - sn * akq;
+          A[k * m + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < m; ++k) {
+          const double apk = A[p * m + k], aqk = A[q * m + k];
+          A[p * m + k] = cs * apk - sn * aqk;
+          A[q * m + k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < m; ++k) {
+          const double vkp = V[k * m + p], vkq = V[k * m + q];
+          V[k * m + p] = cs * vkp - sn * vkq;
+          V[k * m + q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+}
+
+// Rayleigh-Ritz on span(S) (m columns): largest NB eigenpairs of GA c = mu GB c.
+// GB = R^T R (Cholesky), C = R^-T GA R^-1.  Returns the usable basis size
+// (columns whose Cholesky pivot is too small are dropped: m_used <= m).
+__device__ int rayleigh_ritz(const double *GA, const double *GB, int m, double *coef /*m x NB*/, double *mu) {
+  double R[NS * NS], Ri[NS * NS], C[NS * NS], V[NS * NS];
+  int keep[NS], mk = 0;
+  // pivoted-free Cholesky with column dropping (columns are ordered X, W, P)
+  for (int j = 0; j < m; ++j) {
+    // tentative column j against the kept ones
+    double rj[NS];
+    for (int i = 0; i < mk; ++i) {
+      double s = GB[keep[i] * m + j];
+      for (int k = 0; k < i; ++k) s -= R[k * NS + i] * rj[k];
+      rj[i] = s / R[i * NS + i];
+    }
+    double d = GB[j * m + j];
+    for (int k = 0; k < mk; ++k) d -= rj[k] * rj[k];
+    if (d > 1e-13 * GB[j * m + j] && d > 0.0) {
+      for (int k = 0; k < mk; ++k) R[k * NS + mk] = rj[k];
+      R[mk * NS + mk] = sqrt(d);
+      for (int k = mk + 1; k < NS; ++k) R[k * NS + mk] = 0.0;
+      keep[mk++] = j;
+    }
+  }
+  // Ri = R^-1 (upper triangular)
+  for (int i = 0; i < mk; ++i)
+    for (int j = 0; j < mk; ++j) Ri[i * NS + j] = 0.0;
+  for (int j = 0; j < mk; ++j) {
+    Ri[j * NS + j] = 1.0 / R[j * NS + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int k = i + 1; k <= j; ++k) s += R[i * NS + k] * Ri[k * NS + j];
+      Ri[i * NS + j] = -s / R[i * NS + i];
+    }
+  }
+  // C = Ri^T GA_kept Ri
+  for (int i = 0; i < mk; ++i)
+    for (int j = 0; j < mk; ++j) {
+      double s = 0.0;
+      for (int k = 0; k <= i; ++k)
+        for (int l = 0; l <= j; ++l) s += Ri[k * NS + i] * GA[keep[k] * m + keep[l]] * Ri[l * NS + j];
+      C[i * mk + j] = s;
+    }
+  jacobi_small(C, V, mk);
+  // sort eigenvalues descending
+  int order[NS];
+  for (int i = 0; i < mk; ++i) order[i] = i;
+  for (int i = 0; i < mk; ++i)
+    for (int j = i + 1; j < mk; ++j)
+      if (C[order[j] * mk + order[j]] > C[order[i] * mk + order[i]]) {
+        const int t = order[i];
+        order[i] = order[j];
+        order[j] = t;
+      }
+  for (int v = 0; v < NB; ++v) {
+    const int e = order[min(v, mk - 1)];
+    mu[v] = C[e * mk + e];
+    for (int j = 0; j < m; ++j) coef[j * NB + v] = 0.0;
+    for (int i = 0; i < mk; ++i) {
+      double s = 0.0;
+      for (int k = i; k < mk; ++k) s += Ri[i * NS + k] * V[k * mk + e];
+      coef[keep[i] * NB + v] = s;
+    }
+  }
+  return mk;
+}
+
+// ---------------------------------------------------------------- the solver
+struct PlateJob {
+  const double *offsets;  // [rows][nply]
+  const int64_t *rows;    // [n]
+  const int *out_idx;     // [n]
+  double *lam;            // output (indexed by out_idx)
+  mlmc_info *info;
+  int coarse;
+  int n;
+};
+
+template <typename B>
+__global__ __launch_bounds__(PT) void k_buckle(PlateGeom g, PlateMat m, PlateWork W, PlateJob J, double tol,
+                                               int max_iter) {
+  __shared__ double Ke[400], KGe[400], Dmb[36];
+  __shared__ double red[4];
+  __shared__ double gram[2 * NS * NS];
+  __shared__ double coef[NS * NB], mu[NB], resn[NB];
+  __shared__ int mk_sh, done_sh;
+  __shared__ B col[1024];
+  const int s = blockIdx.x;
+  if (s >= J.n) return;
+  const int n = g.nfree;
+  double *vec = W.vec + (size_t)s * W.vec_stride;
+  auto V = [&](int k) { return vec + (size_t)k * n; };
+  // ---- laminate (Eq. CLTABD) and element matrices
+  if (threadIdx.x == 0) {
+    const double *off = J.offsets + (size_t)J.rows[s] * m.nply;
+    double A[6] = {0, 0, 0, 0, 0, 0}, Bm[6] = {0, 0, 0, 0, 0, 0}, D[6] = {0, 0, 0, 0, 0, 0};
+    const double z0 = -0.5 * m.nply * m.t_ply;
+    for (int k = 0; k < m.nply; ++k) {
+      double q[6];
+      qbar_ply(m, m.layup[k] + off[k], q);
+      const double za = z0 + k * m.t_ply, zb = za + m.t_ply;
+      for (int t = 0; t < 6; ++t) {
+        A[t] += q[t] * (zb - za);
+        Bm[t] += q[t] * (zb * zb - za * za) * 0.5;
+        D[t] += q[t] * (zb * zb * zb - za * za * za) / 3.0;
+      }
+    }
+    // 3x3 blocks from (11, 12, 22, 16, 26, 66)
+    auto put = [&](const double *v, int r0, int c0) {
+      const double M3[9] = {v[0], v[1], v[3], v[1], v[2], v[4], v[3], v[4], v[5]};
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Dmb[6 * (r0 + i) + c0 + j] = M3[3 * i + j];
+    };
+    put(A, 0, 0);
+    put(Bm, 0, 3);
+    put(Bm, 3, 0);
+    put(D, 3, 3);
+  }
+  __syncthreads();
+  element_matrices(g, m, Dmb, Ke, KGe);
+  __syncthreads();
+  // ---- preconditioner: banded Cholesky factor of K
+  B *band = sizeof(B) == 8 ? (B *)(W.band + (size_t)s * W.band_stride) : (B *)(W.bandf + (size_t)s * W.band_stride);
+  assemble_band<B>(g, Ke, band);
+  __syncthreads();
+  const bool ok = band_cholesky<B>(g, band, col);
+  if (!ok) {
+    if (threadIdx.x == 0) {
+      const int o = J.out_idx[s];
+      J.lam[o] = NAN;
+      if (J.coarse) { J.info[o].status_c = 3; J.info[o].iters_c = 0; }
+      else { J.info[o].status_f = 3; J.info[o].iters_f = 0; }
+    }
+    return;
+  }
+  // ---- initial block: smooth mode shapes w = sin(p pi x/a) sin(q pi y/b), theta = grad w
+  for (int r = threadIdx.x; r < n; r += PT) {
+    const int full = g.full_of_free[r], node = full / 5, c = full % 5;
+    const double x = (node % g.nnx) * g.hx, y = (node / g.nnx) * g.hy;
+    for (int v = 0; v < NB; ++v) {
+      const double px = M_PI * (v + 1) / g.a, py = M_PI / g.b;
+      double val = 0.0;
+      if (c == 2) val = sin(px * x) * sin(py * y);
+      if (c == 3) val = px * cos(px * x) * sin(py * y);
+      if (c == 4) val = py * sin(px * x) * cos(py * y);
+      V(V_X + v)[r] = val;
+    }
+  }
+  __syncthreads();
+  for (int v = 0; v < NB; ++v) {
+    plate_apply<false>(g, Ke, V(V_X + v), V(V_KX + v));
+    plate_apply<true>(g, KGe, V(V_X + v), V(V_GX + v));
+  }
+  __syncthreads();
+  int it = 0, have_p = 0;
+  double mu0 = 0.0, res0 = 1.0;
+  for (;; ++it) {
+    // Rayleigh quotients of the current block and residuals R = G X - mu K X
+    double acc[2 * NB];
+    for (int v = 0; v < NB; ++v) {
+      double a = 0.0, b = 0.0;
+      for (int r = threadIdx.x; r < n; r += PT) {
+        a += V(V_X + v)[r] * V(V_GX + v)[r];
+        b += V(V_X + v)[r] * V(V_KX + v)[r];
+      }
+      acc[2 * v] = block_reduce(a, red);
+      acc[2 * v + 1] = block_reduce(b, red);
+    }
+    double rq[NB];
+    for (int v = 0; v < NB; ++v) rq[v] = acc[2 * v] / acc[2 * v + 1];
+    for (int v = 0; v < NB; ++v) {
+      double rn = 0.0, kn = 0.0;
+      for (int r = threadIdx.x; r < n; r += PT) {
+        const double rv = V(V_GX + v)[r] - rq[v] * V(V_KX + v)[r];
+        V(V_R + v)[r] = rv;
+        rn += rv * rv;
+        kn += V(V_KX + v)[r] * V(V_KX + v)[r];
+      }
+      rn = block_reduce(rn, red);
+      kn = block_reduce(kn, red);
+      if (threadIdx.x == 0) resn[v] = sqrt(rn) / (fabs(rq[v]) * sqrt(kn));
+    }
+    __syncthreads();
+    mu0 = rq[0];
+    res0 = resn[0];
+    if (!(res0 > tol) || it >= max_iter || !isfinite(res0)) break;
+    // W = T R with T = K^-1 (banded Cholesky)
+    band_solve<B>(g, band, V(V_R), V(V_W), n, (B *)V(V_T));
+    for (int v = 0; v < NB; ++v) {
+      plate_apply<false>(g, Ke, V(V_W + v), V(V_KW + v));
+      plate_apply<true>(g, KGe, V(V_W + v), V(V_GW + v));
+    }
+    __syncthreads();
+    // Gram matrices of S = [X, W, P]
+    const int ms = have_p ? NS : 2 * NB;
+    for (int i = 0; i < ms; ++i)
+      for (int j = i; j < ms; ++j) {
+        const int vi = (i < NB) ? V_X + i : (i < 2 * NB) ? V_W + i - NB : V_P + i - 2 * NB;
+        const int vj = (j < NB) ? V_X + j : (j < 2 * NB) ? V_W + j - NB : V_P + j - 2 * NB;
+        const int gj = vj + (V_GX - V_X), kj = vj + (V_KX - V_X);
+        double a = 0.0, b = 0.0;
+        for (int r = threadIdx.x; r < n; r += PT) {
+          a += V(vi)[r] * V(gj)[r];
+          b += V(vi)[r] * V(kj)[r];
+        }
+        a = block_reduce(a, red);
+        b = block_reduce(b, red);
+        if (threadIdx.x == 0) {
+          gram[i * ms + j] = gram[j * ms + i] = a;
+          gram[NS * NS + i * ms + j] = gram[NS * NS + j * ms + i] = b;
+        }
+      }
+    __syncthreads();
+    if (threadIdx.x == 0) mk_sh = rayleigh_ritz(gram, gram + NS * NS, ms, coef, mu);
+    __syncthreads();
+    // new X = S c, new P = [W, P] c_{W,P}; images follow by linear combination
+    for (int r = threadIdx.x; r < n; r += PT) {
+      for (int grp = 0; grp < 3; ++grp) {
+        const int base = grp == 0 ? 0 : grp == 1 ? V_KX : V_GX;
+        double xs[NS];
+        for (int i = 0; i < ms; ++i) {
+          const int vi = (i < NB) ? V_X + i : (i < 2 * NB) ? V_W + i - NB : V_P + i - 2 * NB;
+          xs[i] = V(vi + base)[r];
+        }
+        for (int v = 0; v < NB; ++v) {
+          double nx = 0.0, np = 0.0;
+          for (int i = 0; i < ms; ++i) {
+            nx += coef[i * NB + v] * xs[i];
+            if (i >= NB) np += coef[i * NB + v] * xs[i];
+          }
+          V(V_X + v + base)[r] = nx;
+          V(V_P + v + base)[r] = np;
+        }
+      }
+    }
+    have_p = 1;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int o = J.out_idx[s];
+    const bool good = isfinite(mu0) && mu0 > 0.0 && isfinite(res0);
+    J.lam[o] = good ? 1.0 / mu0 : NAN;
+    const int st = !isfinite(res0) ? 2 : !(mu0 > 0.0) ? 3 : (res0 > tol) ? 1 : 0;
+    if (J.coarse) {
+      J.info[o].iters_c = it;
+      J.info[o].relres_c = res0;
+      J.info[o].status_c = st;
+    } else {
+      J.info[o].iters_f = it;
+      J.info[o].relres_f = res0;
+      J.info[o].status_f = st;
+    }
+  }
+}
+
+// diagnostic: y = K x or K_G x on full-dof vectors (constrained unknowns: y = 0)
+__global__ __launch_bounds__(PT) void k_plate_apply(PlateGeom g, PlateMat m, const double *offsets, int geom,
+                                                    const double *x, double *y, double *xf, double *yf) {
+  __shared__ double Ke[400], KGe[400], Dmb[36];
+  const int s = blockIdx.x;
+  if (threadIdx.x == 0) {
+    const double *off = offsets + (size_t)s * m.nply;
+    double A[6] = {0, 0, 0, 0, 0, 0}, Bm[6] = {0, 0, 0, 0, 0, 0}, D[6] = {0, 0, 0, 0, 0, 0};
+    const double z0 = -0.5 * m.nply * m.t_ply;
+    for (int k = 0; k < m.nply; ++k) {
+      double q[6];
+      qbar_ply(m, m.layup[k] + off[k], q);
+      const double za = z0 + k * m.t_ply, zb = za + m.t_ply;
+      for (int t = 0; t < 6; ++t) {
+        A[t] += q[t] * (zb - za);
+        Bm[t] += q[t] * (zb * zb - za * za) * 0.5;
+        D[t] += q[t] * (zb * zb * zb - za * za * za) / 3.0;
+      }
+    }
+    auto put = [&](const double *v, int r0, int c0) {
+      const double M3[9] = {v[0], v[1], v[3], v[1], v[2], v[4], v[3], v[4], v[5]};
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Dmb[6 * (r0 + i) + c0 + j] = M3[3 * i + j];
+    };
+    put(A, 0, 0);
+    put(Bm, 0, 3);
+    put(Bm, 3, 0);
+    put(D, 3, 3);
+  }
+  __syncthreads();
+  element_matrices(g, m, Dmb, Ke, KGe);
+  __syncthreads();
+  double *xs = xf + (size_t)s * g.nfree, *ys = yf + (size_t)s * g.nfree;
+  for (int r = threadIdx.x; r < g.nfree; r += PT) xs[r] = x[(size_t)s * g.nfull + g.full_of_free[r]];
+  __syncthreads();
+  if (geom) plate_apply<true>(g, KGe, xs, ys);
+  else plate_apply<false>(g, Ke, xs, ys);
+  __syncthreads();
+  for (int r = threadIdx.x; r < g.nfull; r += PT) {
+    const int f = g.free_of_full[r];
+    y[(size_t)s * g.nfull + r] = f >= 0 ? ys[f] : 0.0;
+  }
+}
+
+// ====================================================================== host
+struct PlateLevelH {
+  PlateGeom g{};
+  int *d_free_of_full = nullptr, *d_full_of_free = nullptr;
+  // batch workspace
+  int cap = 0;
+  double *band = nullptr, *vec = nullptr;
+  float *bandf = nullptr;
+  int64_t *rows = nullptr;
+  int *outidx = nullptr;
+};
+
 struct PlateCtx {
   int nlev = 0;
-  int nx0 = 0, ny0 = 0;
+  PlateMat mat{};
+  double tol = 1e-8;
+  int max_iter = 500;
+  std::vector<PlateLevelH> lv;
+  double *d_xf = nullptr, *d_yf = nullptr;
+  size_t xf_cap = 0;
 };
+
+static PlateGeom plate_geom(const Json &cfg, int level) {
+  PlateGeom g{};
+  g.nx = (int)cfg.number("nx0") << level;
+  g.ny = (int)cfg.number("ny0") << level;
+  g.nnx = g.nx + 1;
+  g.nny = g.ny + 1;
+  g.nn = g.nnx * g.nny;
+  g.nfull = 5 * g.nn;
+  g.a = cfg.number("a");
+  g.b = cfg.number("b");
+  g.hx = g.a / g.nx;
+  g.hy = g.b / g.ny;
+  return g;
+}
+
+// hard simply-supported edges: w = 0 on all edges, tangential rotation = 0,
+// u = 0 on x = 0 and v = 0 on y = 0 (removes the in-plane rigid motions)
+static bool constrained(const PlateGeom &g, int full) {
+  const int node = full / 5, c = full % 5, i = node % g.nnx, j = node / g.nnx;
+  const bool xe = (i == 0 || i == g.nx), ye = (j == 0 || j == g.ny);
+  if (c == 2) return xe || ye;
+  if (c == 4) return xe;
+  if (c == 3) return ye;
+  if (c == 0) return i == 0;
+  if (c == 1) return j == 0;
+  return false;
+}
 
 PlateCtx *plate_create(const Json &cfg, std::string &err) {
   PlateCtx *p = new PlateCtx();
   try {
     p->nlev = (int)cfg.number("n_levels");
-    p->nx0 = (int)cfg.number("nx0");
-    p->ny0 = (int)cfg.number("ny0");
+    if (p->nlev < 1 || p->nlev > 8) throw std::runtime_error("n_levels out of range");
+    const Json &mm = cfg.at("material");
+    const double E1 = mm.number("E11"), E2 = mm.number("E22"), G = mm.number("G12"), nu12 = mm.number("nu12");
+    const double nu21 = nu12 * E2 / E1, den = 1.0 - nu12 * nu21;
+    p->mat.Q11 = E1 / den;
+    p->mat.Q22 = E2 / den;
+    p->mat.Q12 = nu12 * E2 / den;
+    p->mat.Q66 = G;
+    std::vector<double> lay = cfg.numbers("layup_deg");
+    if (lay.empty() || (int)lay.size() > MAXPLY) throw std::runtime_error("layup_deg needs 1..32 plies");
+    p->mat.nply = (int)lay.size();
+    for (size_t k = 0; k < lay.size(); ++k) p->mat.layup[k] = lay[k] * M_PI / 180.0;
+    p->mat.t_ply = cfg.number("ply_t");
+    const double t = p->mat.t_ply * p->mat.nply;
+    p->mat.shear_k_G_t = cfg.number_or("shear_k", 5.0 / 6.0) * G * t;
+    p->mat.N0 = cfg.number_or("N0", 1.0);
+    p->tol = cfg.number_or("eig_tol", 1e-8);
+    p->max_iter = (int)cfg.number_or("eig_max_iter", 500);
+    p->lv.resize(p->nlev);
+    for (int l = 0; l < p->nlev; ++l) {
+      PlateLevelH &L = p->lv[l];
+      L.g = plate_geom(cfg, l);
+      std::vector<int> fof(L.g.nfull, -1), fo;
+      for (int f = 0; f < L.g.nfull; ++f)
+        if (!constrained(L.g, f)) {
+          fof[f] = (int)fo.size();
+          fo.push_back(f);
+        }
+      L.g.nfree = (int)fo.size();
+      int bw = 0;
+      for (int r = 0; r < L.g.nfree; ++r) {
+        const int nr = fo[r] / 5, ir = nr % L.g.nnx, jr = nr / L.g.nnx;
+        // furthest coupled free unknown below r: node (i-1, j-1), component 0
+        for (int dj = -1; dj <= 0; ++dj)
+          for (int di = -1; di <= 1; ++di) {
+            const int ic = ir + di, jc = jr + dj;
+            if (ic < 0 || ic >= L.g.nnx || jc < 0) continue;
+            for (int c = 0; c < 5; ++c) {
+              const int f = fof[5 * (jc * L.g.nnx + ic) + c];
+              if (f >= 0 && f < r) bw = std::max(bw, r - f);
+            }
+          }
+      }
+      L.g.bw = bw;
+      if (bw + 1 > 1024) throw std::runtime_error("plate bandwidth exceeds the column buffer");
+      if (hipMalloc(&L.d_free_of_full, sizeof(int) * L.g.nfull) != hipSuccess ||
+          hipMalloc(&L.d_full_of_free, sizeof(int) * L.g.nfree) != hipSuccess)
+        throw std::runtime_error("device allocation failed");
+      (void)hipMemcpy(L.d_free_of_full, fof.data(), sizeof(int) * L.g.nfull, hipMemcpyHostToDevice);
+      (void)hipMemcpy(L.d_full_of_free, fo.data(), sizeof(int) * L.g.nfree, hipMemcpyHostToDevice);
+      L.g.free_of_full = L.d_free_of_full;
+      L.g.full_of_free = L.d_full_of_free;
+    }
   } catch (const std::exception &e) {
     err = e.what();
-    delete p;
+    plate_destroy(p);
     return nullptr;
   }
   return p;
 }
 
-void plate_destroy(PlateCtx *p) { delete p; }
+static void free_work(PlateLevelH &L) {
+  if (L.band) (void)hipFree(L.band);
+  if (L.bandf) (void)hipFree(L.bandf);
+  if (L.vec) (void)hipFree(L.vec);
+  if (L.rows) (void)hipFree(L.rows);
+  if (L.outidx) (void)hipFree(L.outidx);
+  L.band = L.vec = nullptr;
+  L.bandf = nullptr;
+  L.rows = nullptr;
+  L.outidx = nullptr;
+  L.cap = 0;
+}
+
+void plate_destroy(PlateCtx *p) {
+  if (!p) return;
+  for (auto &L : p->lv) {
+    free_work(L);
+    if (L.d_free_of_full) (void)hipFree(L.d_free_of_full);
+    if (L.d_full_of_free) (void)hipFree(L.d_full_of_free);
+  }
+  if (p->d_xf) (void)hipFree(p->d_xf);
+  if (p->d_yf) (void)hipFree(p->d_yf);
+  delete p;
+}
+
 int plate_num_levels(const PlateCtx *p) { return p->nlev; }
 
 void plate_level_sizes(const PlateCtx *p, int level, int64_t *nn, int64_t *nd, int64_t *ne) {
-  const int64_t nx = (int64_t)p->nx0 << level, ny = (int64_t)p->ny0 << level;
-  *nn = (nx + 1) * (ny + 1);
-  *nd = 5 * *nn;
-  *ne = nx * ny;
+  const PlateGeom &g = p->lv[level].g;
+  *nn = g.nn;
+  *nd = g.nfull;
+  *ne = (int64_t)g.nx * g.ny;
 }
 
-size_t plate_slot_bytes(const PlateCtx *p, int level, int) {
-  int64_t nn, nd, ne;
-  plate_level_sizes(p, level, &nn, &nd, &ne);
-  return (size_t)nd * 8 * 16;
+size_t plate_slot_bytes(const PlateCtx *p, int level, int precision) {
+  const PlateGeom &g = p->lv[level].g;
+  const size_t band = (size_t)g.nfree * (g.bw + 1) * (precision == MLMC_MIXED ? 4 : 8);
+  return band + (size_t)NVEC * g.nfree * sizeof(double) + 64;
 }
 
-int plate_buckle_batch(PlateCtx *, std::string &err, int, const mlmc_request *, const double *, int64_t, double *, double *,
-                       mlmc_info *, int, double, hipStream_t) {
-  err = "plate buckling solver is not built";
-  return MLMC_ESTATE;
+int plate_buckle_batch(PlateCtx *p, std::string &err, int n_req, const mlmc_request *req, const double *offsets,
+                       int64_t n_rows, double *lam_fine, double *lam_coarse, mlmc_info *info, int precision,
+                       double tol, hipStream_t st) {
+  if (n_req < 0) { err = "n_req < 0"; return MLMC_EINVAL; }
+  if (n_req == 0) return MLMC_OK;
+  if (!req || !offsets || !lam_fine || !lam_coarse || !info) { err = "null pointer"; return MLMC_EINVAL; }
+  if (precision != MLMC_FP64 && precision != MLMC_MIXED) { err = "bad precision"; return MLMC_EINVAL; }
+  for (int i = 0; i < n_req; ++i) {
+    if (req[i].level < 0 || req[i].level >= p->nlev) { err = "request " + std::to_string(i) + ": bad level"; return MLMC_EINVAL; }
+    if (req[i].sample < 0 || req[i].sample >= n_rows) {
+      err = "request " + std::to_string(i) + ": sample row outside [0, n_rows)";
+      return MLMC_EINVAL;
+    }
+  }
+  const double tl = tol > 0 ? tol : p->tol;
+  launch_info_init(info, lam_coarse, n_req, st);
+  std::vector<std::vector<int64_t>> rows(2 * p->nlev);
+  std::vector<std::vector<int>> outs(2 * p->nlev);
+  for (int i = 0; i < n_req; ++i) {
+    const int l = req[i].level;
+    rows[2 * l].push_back(req[i].sample);
+    outs[2 * l].push_back(i);
+    if (req[i].coupled && l > 0) {
+      rows[2 * (l - 1) + 1].push_back(req[i].sample);
+      outs[2 * (l - 1) + 1].push_back(i);
+    }
+  }
+  const bool mixed = precision == MLMC_MIXED;
+  for (int l = 0; l < p->nlev; ++l) {
+    PlateLevelH &L = p->lv[l];
+    for (int coarse = 0; coarse < 2; ++coarse) {
+      const auto &R = rows[2 * l + coarse];
+      const auto &O = outs[2 * l + coarse];
+      const int total = (int)R.size();
+      if (!total) continue;
+      // batch capacity: at most 2048 samples or 16 GiB of workspace per launch
+      const size_t per = plate_slot_bytes(p, l, MLMC_FP64) + plate_slot_bytes(p, l, MLMC_MIXED);
+      const int cap = (int)std::max<size_t>(1, std::min<size_t>(std::min(total, 2048), (16ull << 30) / per));
+      if (L.cap < cap) {
+        free_work(L);
+        const size_t bs = (size_t)L.g.nfree * (L.g.bw + 1);
+        if (hipMalloc(&L.band, bs * sizeof(double) * cap) != hipSuccess ||
+            hipMalloc(&L.bandf, bs * sizeof(float) * cap) != hipSuccess ||
+            hipMalloc(&L.vec, (size_t)NVEC * L.g.nfree * sizeof(double) * cap) != hipSuccess ||
+            hipMalloc(&L.rows, sizeof(int64_t) * cap) != hipSuccess ||
+            hipMalloc(&L.outidx, sizeof(int) * cap) != hipSuccess) {
+          free_work(L);
+          err = "plate workspace allocation failed";
+          return MLMC_ENOMEM;
+        }
+        L.cap = cap;
+      }
+      PlateWork Wk{};
+      Wk.band = L.band;
+      Wk.bandf = L.bandf;
+      Wk.vec = L.vec;
+      Wk.band_stride = (size_t)L.g.nfree * (L.g.bw + 1);
+      Wk.vec_stride = (size_t)NVEC * L.g.nfree;
+      for (int off = 0; off < total; off += cap) {
+        const int n = std::min(cap, total - off);
+        if (hipMemcpyAsync(L.rows, R.data() + off, sizeof(int64_t) * n, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(L.outidx, O.data() + off, sizeof(int) * n, hipMemcpyHostToDevice, st) != hipSuccess) {
+          err = "copy failed";
+          return MLMC_EHIP;
+        }
+        PlateJob J{offsets, L.rows, L.outidx, coarse ? lam_coarse : lam_fine, info, coarse, n};
+        if (mixed)
+          hipLaunchKernelGGL(k_buckle<float>, dim3(n), dim3(PT), 0, st, L.g, p->mat, Wk, J, tl, p->max_iter);
+        else
+          hipLaunchKernelGGL(k_buckle<double>, dim3(n), dim3(PT), 0, st, L.g, p->mat, Wk, J, tl, p->max_iter);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+          err = std::string("buckle kernel: ") + hipGetErrorString(e);
+          return MLMC_EHIP;
+        }
+      }
+    }
+  }
+  return MLMC_OK;
+}
+
+int plate_apply_diag(PlateCtx *p, std::string &err, int level, int n, const double *offsets, int geom,
+                     const double *x, double *y, hipStream_t st) {
+  if (level < 0 || level >= p->nlev || n < 0) { err = "level out of range or n < 0"; return MLMC_EINVAL; }
+  if (n == 0) return MLMC_OK;
+  PlateLevelH &L = p->lv[level];
+  const size_t need = (size_t)n * L.g.nfree;
+  if (p->xf_cap < need) {
+    if (p->d_xf) (void)hipFree(p->d_xf);
+    if (p->d_yf) (void)hipFree(p->d_yf);
+    if (hipMalloc(&p->d_xf, need * sizeof(double)) != hipSuccess ||
+        hipMalloc(&p->d_yf, need * sizeof(double)) != hipSuccess) {
+      err = "allocation failed";
+      return MLMC_ENOMEM;
+    }
+    p->xf_cap = need;
+  }
+  hipLaunchKernelGGL(k_plate_apply, dim3(n), dim3(PT), 0, st, L.g, p->mat, offsets, geom, x, y, p->d_xf, p->d_yf);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) { err = hipGetErrorString(e); return MLMC_EHIP; }
+  return MLMC_OK;
 }
 
 }  // namespace mlmc

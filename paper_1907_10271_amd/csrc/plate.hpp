@@ -23,4 +23,7 @@ int plate_buckle_batch(PlateCtx *p, std::string &err, int n_req, const mlmc_requ
                        int64_t n_rows, double *lam_fine, double *lam_coarse, mlmc_info *info, int precision, double tol,
                        hipStream_t st);
 
+int plate_apply_diag(PlateCtx *p, std::string &err, int level, int n, const double *offsets, int geom,
+                     const double *x, double *y, hipStream_t st);
+
 }  // namespace mlmc

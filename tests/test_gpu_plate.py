@@ -1,0 +1,98 @@
+"""GPU parity of the plate buckling path against the FP64 oracle, through the C ABI.
+
+Tolerances: operators <= 1e-13 relative to the max-norm; buckling load
+lambda <= 1e-10 relative in FP64 (LOBPCG residual 1e-8, so the eigenvalue
+error is of the order of the squared residual) and <= 1e-6 in mixed mode
+(FP32 Cholesky preconditioner, FP64 Rayleigh-Ritz)."""
+import functools
+
+import numpy as np
+import pytest
+
+import mlmc_inputs as mi
+from tests.conftest import gpu_available
+from tests.gpu_util import context, dev
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+C4 = mi.load_config("plate_c4")
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_plate(level):
+    from oracle.plate import PlateModel
+    return PlateModel(C4, level)
+
+
+def full_from_free(s, xf):
+    x = np.zeros(s.n_full)
+    x[s.free] = xf
+    return x
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_plate_operators_parity(level):
+    ctx = context("plate_c4")
+    om = oracle_plate(level)
+    off = mi.plate_offsets(C4, level, 0, 3)
+    rng = np.random.default_rng(3)
+    nfull = 5 * om.mesh.n_nodes
+    x = rng.standard_normal((3, nfull))
+    yk = ctx.plate_apply(level, dev(off), dev(x), geometric=False).cpu().numpy()
+    yg = ctx.plate_apply(level, dev(off), dev(x), geometric=True).cpu().numpy()
+    for k in range(3):
+        s = om.system(off[k])
+        ref_k = full_from_free(s, s.K @ x[k][s.free])
+        ref_g = full_from_free(s, s.KG @ x[k][s.free])
+        assert np.abs(yk[k] - ref_k).max() <= 1e-13 * np.abs(ref_k).max()
+        assert np.abs(yg[k] - ref_g).max() <= 1e-13 * np.abs(ref_g).max()
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_buckling_load_parity_fp64(level):
+    ctx = context("plate_c4")
+    om = oracle_plate(level)
+    n = 4
+    off = mi.plate_offsets(C4, level, 0, n)
+    lf, lc, info = ctx.buckle_batch([(k, level, False) for k in range(n)], dev(off))
+    lf = lf.cpu().numpy()
+    for k in range(n):
+        assert info[k]["status_f"] == 0, info[k]
+        ref = om.buckling_load(off[k])
+        assert abs(lf[k] - ref) <= 1e-10 * ref, (k, lf[k], ref)
+
+
+def test_buckling_mixed_and_coupled():
+    import paper_1907_10271_amd as pk
+    ctx = context("plate_c4")
+    n = 3
+    off = mi.plate_offsets(C4, 1, 0, n)
+    lf, lc, info = ctx.buckle_batch([(k, 1, True) for k in range(n)], dev(off), precision=pk.MIXED)
+    lf, lc = lf.cpu().numpy(), lc.cpu().numpy()
+    for k in range(n):
+        assert info[k]["status_f"] == 0 and info[k]["status_c"] == 0
+        rf = oracle_plate(1).buckling_load(off[k])
+        rc = oracle_plate(0).buckling_load(off[k])
+        assert abs(lf[k] - rf) <= 1e-6 * rf and abs(lc[k] - rc) <= 1e-6 * rc
+        assert lc[k] > lf[k]            # the coarse mesh is stiffer here
+
+
+def test_buckling_batch_invariance():
+    ctx = context("plate_c4")
+    off = mi.plate_offsets(C4, 0, 0, 8)
+    reqs = [(k, 0, False) for k in range(8)]
+    a, _, _ = ctx.buckle_batch(reqs, dev(off))
+    b, _, _ = ctx.buckle_batch([reqs[5]], dev(off))
+    assert a.cpu().numpy()[5] == b.cpu().numpy()[0]
+    c, _, _ = ctx.buckle_batch(reqs, dev(off))
+    assert np.array_equal(a.cpu().numpy(), c.cpu().numpy())
+
+
+def test_plate_error_paths():
+    import paper_1907_10271_amd as pk
+    ctx = context("plate_c4")
+    off = dev(mi.plate_offsets(C4, 0, 0, 2))
+    with pytest.raises(pk.MLMCError):
+        ctx.buckle_batch([(5, 0, False)], off)
+    with pytest.raises(pk.MLMCError) as e:
+        ctx.solve_batch([(0, 0, False)], off)
+    assert e.value.code == -4
