@@ -51,6 +51,8 @@ def parse():
                     help="mixed: FP32 operator on BF16 angles inside FP64 refinement")
     ap.add_argument("--mixed", type=str, default="",
                     help="overrides of the mixed-precision settings, e.g. update_factor=0.1,theta_storage=fp32")
+    ap.add_argument("--plate", type=str, default="",
+                    help="also time the buckling solver: samples per plate level, e.g. 1024,256,32,4")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
@@ -105,6 +107,29 @@ def cpu_baseline(cfg, mix, counts):
 
 
 # ------------------------------------------------------------------ GPU
+def plate_leg(pk, torch, counts, prec):
+    """Buckling loads per level of the panel workload (one timed batch per level)."""
+    pcfg = mi.load_config("plate_c4")
+    pctx = pk.Context(mi.config_text("plate_c4"))
+    res = []
+    for l, n in enumerate(counts):
+        if n <= 0:
+            continue
+        off = torch.from_numpy(mi.plate_offsets(pcfg, l, 0, n)).to("cuda")
+        reqs = [(k, l, False) for k in range(n)]
+        pctx.buckle_batch(reqs[:1], off, precision=prec)     # set-up of the level's workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lf, _, info = pctx.buckle_batch(reqs, off, precision=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res.append({"level": l, "mesh": f"{pcfg['nx0'] << l}x{pcfg['ny0'] << l}", "samples": n,
+                    "ms": round(dt * 1e3, 3), "samples_per_s": round(n / dt, 1),
+                    "lobpcg_iters_mean": round(float(info["iters_f"].mean()), 1),
+                    "all_converged": bool(np.all(info["status_f"] == 0))})
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -218,6 +243,8 @@ def main():
                         "avg_launch_us": round(p2["ms"] * 1e3 / p2["launches"], 3)},
         "cpu_baseline": None if cpu is None else {k: v for k, v in cpu.items() if k != "per_level_s_per_sample"},
     }
+    if args.plate:
+        out["plate"] = plate_leg(pk, torch, [int(v) for v in args.plate.split(",")], prec)
     if len(levels) != len(mix):
         out["metric"] = "profiling run on levels " + args.levels + " only (not the benchmark)"
     if cpu is not None:

@@ -27,6 +27,7 @@ constexpr int PT = 256;      // threads per work-group
 constexpr int NB = 2;        // LOBPCG block size
 constexpr int NS = 3 * NB;   // Rayleigh-Ritz basis size [X, W, P]
 constexpr int MAXPLY = 32;
+constexpr int MAXBW = 664;  // largest band half-width (128 x 128 mesh: 654)
 
 struct PlateGeom {
   int nx, ny, nnx, nny, nn, nfull, nfree, bw;
@@ -187,78 +188,174 @@ __device__ void assemble_band(const PlateGeom &g, const double *Ke, B *band) {
   }
 }
 
-// right-looking banded Cholesky in place: band[k][0] <- L_kk, band[k + d][d] <- L_{k+d,k}
+// Blocked right-looking banded Cholesky in place (band[r][d] = A[r][r - d]):
+// a panel of NBK columns is factored in LDS, then the trailing band window is
+// updated once by the rank-NBK product of the panel (4 x 4 register tiles per
+// thread).  On return band[k][0] = L_kk and band[k + d][d] = L_{k+d,k}.
+constexpr int NBK = 8;
+
 template <typename B>
-__device__ bool band_cholesky(const PlateGeom &g, B *band, B *col /*LDS, bw + 1*/) {
+__device__ bool band_cholesky(const PlateGeom &g, B *band, B *P /* LDS [(NBK + bw) * NBK] */) {
   const int w = g.bw + 1, n = g.nfree;
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
-  for (int k = 0; k < n; ++k) {
+  for (int k0 = 0; k0 < n; k0 += NBK) {
+    const int nb = min(NBK, n - k0);
+    const int rows = min(nb + g.bw, n - k0);  // panel rows k0 .. k0 + rows - 1
     __syncthreads();
-    const B piv2 = band[(size_t)k * w];
-    if (!(piv2 > B(0))) {
-      if (threadIdx.x == 0) bad = 1;
+    for (int idx = threadIdx.x; idx < rows * NBK; idx += PT) {
+      const int i = idx / NBK, j = idx % NBK;
+      B v = B(0);
+      if (j < nb && i >= j && i - j <= g.bw) v = band[(size_t)(k0 + i) * w + (i - j)];
+      P[idx] = v;
+    }
+    // panel factorisation (unblocked, in LDS)
+    for (int j = 0; j < nb; ++j) {
       __syncthreads();
-      return false;
-    }
-    const B piv = sqrt(piv2);
-    const int dmax = min(g.bw, n - 1 - k);
-    for (int d = threadIdx.x; d <= dmax; d += PT) {
-      const B v = (d == 0) ? piv : band[(size_t)(k + d) * w + d] / piv;
-      col[d] = v;
-      band[(size_t)(k + d) * w + d] = v;
+      const B piv2 = P[j * NBK + j];
+      if (!(piv2 > B(0))) {
+        if (threadIdx.x == 0) bad = 1;
+        __syncthreads();
+        return false;
+      }
+      const B piv = sqrt(piv2);
+      __syncthreads();
+      for (int i = j + threadIdx.x; i < rows; i += PT) P[i * NBK + j] = (i == j) ? piv : P[i * NBK + j] / piv;
+      __syncthreads();
+      const int ncols = nb - 1 - j;
+      for (int idx = threadIdx.x; idx < (rows - j - 1) * ncols; idx += PT) {
+        const int i = j + 1 + idx / ncols, jj = j + 1 + idx % ncols;
+        if (i >= jj) P[i * NBK + jj] -= P[i * NBK + j] * P[jj * NBK + j];
+      }
     }
     __syncthreads();
-    // A[k+d1][k+d2] -= L_{k+d1,k} L_{k+d2,k}, 1 <= d2 <= d1 <= dmax
-    const int npair = dmax * (dmax + 1) / 2;
-    for (int p = threadIdx.x; p < npair; p += PT) {
-      // p -> (d1, d2): rows d1 = 1..dmax hold d1 entries each
-      int d1 = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
-      while ((d1 + 1) * (d1 + 2) / 2 <= p) ++d1;
-      while (d1 * (d1 + 1) / 2 > p) --d1;
-      const int d2 = p - d1 * (d1 + 1) / 2;  // 0..d1
-      const int D1 = d1 + 1, D2 = d2 + 1;     // 1-based offsets
-      band[(size_t)(k + D1) * w + (D1 - D2)] -= col[D1] * col[D2];
+    for (int idx = threadIdx.x; idx < rows * NBK; idx += PT) {
+      const int i = idx / NBK, j = idx % NBK;
+      if (j < nb && i >= j && i - j <= g.bw) band[(size_t)(k0 + i) * w + (i - j)] = P[idx];
+    }
+    // trailing update of rows/columns R .. R + m - 1 (all inside the band)
+    const int R = k0 + nb, m = min(g.bw, n - R);
+    if (m <= 0) continue;
+    const int mt = (m + 3) / 4, ntile = mt * (mt + 1) / 2;
+    for (int tix = threadIdx.x; tix < ntile; tix += PT) {
+      int ti = (int)((sqrt(8.0 * tix + 1.0) - 1.0) * 0.5);
+      while ((ti + 1) * (ti + 2) / 2 <= tix) ++ti;
+      while (ti * (ti + 1) / 2 > tix) --ti;
+      const int tj = tix - ti * (ti + 1) / 2;
+      const int r0 = 4 * ti, c0 = 4 * tj;  // offsets from R
+      B acc[4][4];
+      for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 4; ++c) acc[a][c] = B(0);
+      for (int j = 0; j < nb; ++j) {
+        B pr[4], pc[4];
+        for (int a = 0; a < 4; ++a) {
+          const int ir = nb + r0 + a, ic = nb + c0 + a;
+          pr[a] = (r0 + a < m) ? P[ir * NBK + j] : B(0);
+          pc[a] = (c0 + a < m) ? P[ic * NBK + j] : B(0);
+        }
+        for (int a = 0; a < 4; ++a)
+          for (int c = 0; c < 4; ++c) acc[a][c] += pr[a] * pc[c];
+      }
+      for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 4; ++c) {
+          const int r = r0 + a, cc = c0 + c;
+          if (r < m && cc <= r) band[(size_t)(R + r) * w + (r - cc)] -= acc[a][c];
+        }
     }
   }
   __syncthreads();
   return bad == 0;
 }
 
-// z = (L L^T)^-1 r for NB right-hand sides (column-oriented sweeps)
+// z = (L L^T)^-1 r for NB right-hand sides, blocked by NBK rows: the small
+// diagonal triangle is solved by one thread, the band part of the block's
+// columns is applied by all threads
 template <typename B>
 __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, double *z, int ld, B *tmp) {
   const int w = g.bw + 1, n = g.nfree;
+  __shared__ B Lb[NBK * NBK], yb[NB * NBK];
   for (int v = 0; v < NB; ++v)
     for (int i = threadIdx.x; i < n; i += PT) tmp[(size_t)v * n + i] = (B)r[(size_t)v * ld + i];
   // forward: L y = r
-  for (int k = 0; k < n; ++k) {
+  for (int k0 = 0; k0 < n; k0 += NBK) {
+    const int nb = min(NBK, n - k0);
     __syncthreads();
-    const B lkk = band[(size_t)k * w];
-    B yk[NB];
-    for (int v = 0; v < NB; ++v) yk[v] = tmp[(size_t)v * n + k] / lkk;
+    // stage the diagonal triangle and the right-hand sides of the block in LDS
+    for (int idx = threadIdx.x; idx < NBK * NBK; idx += PT) {
+      const int j = idx / NBK, jj = idx % NBK;
+      Lb[idx] = (j < nb && jj <= j) ? band[(size_t)(k0 + j) * w + (j - jj)] : B(1);
+    }
+    for (int idx = threadIdx.x; idx < NB * NBK; idx += PT) {
+      const int v = idx / NBK, j = idx % NBK;
+      yb[idx] = (j < nb) ? tmp[(size_t)v * n + k0 + j] : B(0);
+    }
     __syncthreads();
-    if (threadIdx.x == 0)
-      for (int v = 0; v < NB; ++v) tmp[(size_t)v * n + k] = yk[v];
-    const int dmax = min(g.bw, n - 1 - k);
-    for (int d = 1 + threadIdx.x; d <= dmax; d += PT) {
-      const B l = band[(size_t)(k + d) * w + d];
-      for (int v = 0; v < NB; ++v) tmp[(size_t)v * n + k + d] -= l * yk[v];
+    if (threadIdx.x < NB) {
+      const int v = threadIdx.x;
+      for (int j = 0; j < nb; ++j) {
+        B s = yb[v * NBK + j];
+        for (int jj = 0; jj < j; ++jj) s -= Lb[j * NBK + jj] * yb[v * NBK + jj];
+        yb[v * NBK + j] = s / Lb[j * NBK + j];
+      }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NB * nb; idx += PT) {
+      const int v = idx / nb, j = idx % nb;
+      tmp[(size_t)v * n + k0 + j] = yb[v * NBK + j];
+    }
+    const int hi = min(n, k0 + nb + g.bw);
+    for (int rr = k0 + nb + threadIdx.x; rr < hi; rr += PT) {
+      B acc[NB];
+      for (int v = 0; v < NB; ++v) acc[v] = B(0);
+      for (int j = 0; j < nb; ++j) {
+        const int d = rr - (k0 + j);
+        if (d <= g.bw) {
+          const B l = band[(size_t)rr * w + d];
+          for (int v = 0; v < NB; ++v) acc[v] += l * yb[v * NBK + j];
+        }
+      }
+      for (int v = 0; v < NB; ++v) tmp[(size_t)v * n + rr] -= acc[v];
     }
   }
   // backward: L^T z = y
-  for (int k = n - 1; k >= 0; --k) {
+  const int last = ((n - 1) / NBK) * NBK;
+  for (int k0 = last; k0 >= 0; k0 -= NBK) {
+    const int nb = min(NBK, n - k0);
     __syncthreads();
-    const B lkk = band[(size_t)k * w];
-    B zk[NB];
-    for (int v = 0; v < NB; ++v) zk[v] = tmp[(size_t)v * n + k] / lkk;
+    for (int idx = threadIdx.x; idx < NBK * NBK; idx += PT) {
+      const int j = idx / NBK, jj = idx % NBK;
+      Lb[idx] = (j < nb && jj <= j) ? band[(size_t)(k0 + j) * w + (j - jj)] : B(1);
+    }
+    for (int idx = threadIdx.x; idx < NB * NBK; idx += PT) {
+      const int v = idx / NBK, j = idx % NBK;
+      yb[idx] = (j < nb) ? tmp[(size_t)v * n + k0 + j] : B(0);
+    }
     __syncthreads();
-    if (threadIdx.x == 0)
-      for (int v = 0; v < NB; ++v) tmp[(size_t)v * n + k] = zk[v];
-    const int dmax = min(g.bw, k);
-    for (int d = 1 + threadIdx.x; d <= dmax; d += PT) {
-      const B l = band[(size_t)k * w + d];
-      for (int v = 0; v < NB; ++v) tmp[(size_t)v * n + k - d] -= l * zk[v];
+    if (threadIdx.x < NB) {
+      const int v = threadIdx.x;
+      for (int j = nb - 1; j >= 0; --j) {
+        B s = yb[v * NBK + j];
+        for (int jj = j + 1; jj < nb; ++jj) s -= Lb[jj * NBK + j] * yb[v * NBK + jj];
+        yb[v * NBK + j] = s / Lb[j * NBK + j];
+      }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NB * nb; idx += PT) {
+      const int v = idx / nb, j = idx % nb;
+      tmp[(size_t)v * n + k0 + j] = yb[v * NBK + j];
+    }
+    const int lo = max(0, k0 - g.bw);
+    for (int c = lo + threadIdx.x; c < k0; c += PT) {
+      B acc[NB];
+      for (int v = 0; v < NB; ++v) acc[v] = B(0);
+      for (int j = 0; j < nb; ++j) {
+        const int d = k0 + j - c;
+        if (d <= g.bw) {
+          const B l = band[(size_t)(k0 + j) * w + d];
+          for (int v = 0; v < NB; ++v) acc[v] += l * yb[v * NBK + j];
+        }
+      }
+      for (int v = 0; v < NB; ++v) tmp[(size_t)v * n + c] -= acc[v];
     }
   }
   __syncthreads();
@@ -391,7 +488,7 @@ __global__ __launch_bounds__(PT) void k_buckle(PlateGeom g, PlateMat m, PlateWor
   __shared__ double gram[2 * NS * NS];
   __shared__ double coef[NS * NB], mu[NB], resn[NB];
   __shared__ int mk_sh, done_sh;
-  __shared__ B col[1024];
+  __shared__ B panel[(NBK + MAXBW) * NBK];
   const int s = blockIdx.x;
   if (s >= J.n) return;
   const int n = g.nfree;
@@ -430,7 +527,7 @@ __global__ __launch_bounds__(PT) void k_buckle(PlateGeom g, PlateMat m, PlateWor
   B *band = sizeof(B) == 8 ? (B *)(W.band + (size_t)s * W.band_stride) : (B *)(W.bandf + (size_t)s * W.band_stride);
   assemble_band<B>(g, Ke, band);
   __syncthreads();
-  const bool ok = band_cholesky<B>(g, band, col);
+  const bool ok = band_cholesky<B>(g, band, panel);
   if (!ok) {
     if (threadIdx.x == 0) {
       const int o = J.out_idx[s];
@@ -702,7 +799,7 @@ PlateCtx *plate_create(const Json &cfg, std::string &err) {
           }
       }
       L.g.bw = bw;
-      if (bw + 1 > 1024) throw std::runtime_error("plate bandwidth exceeds the column buffer");
+      if (bw > MAXBW) throw std::runtime_error("plate band too wide (mesh finer than 128 x 128 per side)");
       if (hipMalloc(&L.d_free_of_full, sizeof(int) * L.g.nfull) != hipSuccess ||
           hipMalloc(&L.d_full_of_free, sizeof(int) * L.g.nfree) != hipSuccess)
         throw std::runtime_error("device allocation failed");

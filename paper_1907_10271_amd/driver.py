@@ -212,3 +212,179 @@ def run_strip_mlmc(ctx, cfg: Dict, precision: int = FP64, eps_rel: Optional[floa
                         dofs=dofs, log=log)
     res.history.append({"solves_per_level": dict(sampler.solves)})
     return res
+
+
+# ---------------------------------------------------------------------- plate
+def sr_exit_levels(lam: np.ndarray, lam_star: float, m: float, alpha: float, j_min: int = 1) -> np.ndarray:
+    """Exit level of the selective-refinement chain (Algorithm 2) for each row of
+    ``lam`` (``[n, ell + 1]``, NaN where not computed): the first ``j >= j_min``
+    with ``|lam_j - lam*| >= |lam_j - lam_{j-1}| / (m^alpha - 1)`` (Eqs.
+    sampleBias, testFailure), else the last level."""
+    n, L1 = lam.shape
+    fac = 1.0 / (m ** alpha - 1.0)
+    out = np.full(n, L1 - 1, dtype=np.int64)
+    alive = np.ones(n, dtype=bool)
+    for j in range(max(j_min, 1), L1):
+        stop = alive & (np.abs(lam[:, j] - lam_star) >= np.abs(lam[:, j] - lam[:, j - 1]) * fac)
+        out[stop] = j
+        alive &= ~stop
+    return out
+
+
+@dataclass
+class IndicatorSums:
+    """Level accumulator of a failure-indicator difference Y in {-1, 0, 1}."""
+    n: int = 0
+    n_plus: int = 0
+    n_minus: int = 0
+    k: int = 1
+    seconds: float = 0.0
+    use_biased_below: int = 10
+
+    @property
+    def mean(self) -> float:
+        return (self.n_plus - self.n_minus) / self.n
+
+    @property
+    def var(self) -> float:
+        """Variance of the trinomial Y, V = p+ + p- - (p+ - p-)^2, with each rate
+        estimated by the frequency, or, when fewer than ``use_biased_below``
+        events were seen, by the biased p~ = (x + k)/(N + k) of Eq.
+        biased_estimator (an upper bound for rare events)."""
+        def rate(x: int) -> float:
+            return (x + self.k) / (self.n + self.k) if x < self.use_biased_below else x / self.n
+        pp, pm = rate(self.n_plus), rate(self.n_minus)
+        return pp + pm - (pp - pm) ** 2
+
+    @property
+    def var_unbiased(self) -> float:
+        m = self.mean
+        return (self.n_plus + self.n_minus - self.n * m * m) / max(self.n - 1, 1)
+
+
+class PlateSRSampler:
+    """Samples of Y_l = 1(lam_l < lam*) - 1(lam_{l-1} < lam*) with selective
+    refinement (Algorithm 2): the chain of each sample is solved level by level
+    on the GPU (the surviving samples of a level form one batch), and both terms
+    come from the same chain, the second truncated at l - 1."""
+
+    def __init__(self, ctx, cfg: Dict, lam_star: float, precision: int = FP64, j_min: Optional[int] = None,
+                 alpha: Optional[float] = None, m: Optional[float] = None, max_batch: int = 2048, k_biased: int = 1,
+                 stream_offset: int = 0):
+        import torch
+        import mlmc_inputs as mi
+        self.torch, self.mi, self.ctx, self.cfg = torch, mi, ctx, cfg
+        sr = cfg.get("sr", {})
+        self.lam_star = lam_star
+        self.j_min = sr.get("j_min", 1) if j_min is None else j_min
+        self.alpha = sr.get("alpha", 1.0) if alpha is None else alpha
+        self.m = sr.get("m", 4) if m is None else m
+        self.precision = precision
+        self.max_batch = max_batch
+        self.k_biased = k_biased
+        self.stream_offset = stream_offset
+        self.next_row: Dict[int, int] = {}
+        self._acc: Dict[int, IndicatorSums] = {}
+        self.solves = np.zeros(cfg["n_levels"], dtype=np.int64)
+        self.failures = 0
+
+    def acc(self, level: int) -> IndicatorSums:
+        return self._acc[level]
+
+    def cost(self, level: int) -> float:
+        a = self._acc[level]
+        return a.seconds / max(a.n, 1)
+
+    def chains(self, level: int, offsets: np.ndarray):
+        """Solve the chains of ``offsets`` rows up to ``level``; returns
+        ``(lam [n, level + 1], exit_level [n])``."""
+        torch = self.torch
+        n = len(offsets)
+        lam = np.full((n, level + 1), np.nan)
+        off_d = torch.from_numpy(np.ascontiguousarray(offsets)).to("cuda")
+        alive = np.arange(n)
+        exit_lv = np.full(n, level, dtype=np.int64)
+        fac = 1.0 / (self.m ** self.alpha - 1.0)
+        for j in range(level + 1):
+            if len(alive) == 0:
+                break
+            lf, _, info = self.ctx.buckle_batch([(int(i), j, False) for i in alive], off_d,
+                                                precision=self.precision)
+            vals = lf.cpu().numpy()
+            bad = np.sum(info["status_f"] != 0)
+            if bad:
+                self.failures += int(bad)
+                raise RuntimeError(f"level {j}: {bad} eigen-solves failed")
+            lam[alive, j] = vals
+            self.solves[j] += len(alive)
+            if j >= max(self.j_min, 1) and j < level:
+                stop = np.abs(vals - self.lam_star) >= np.abs(vals - lam[alive, j - 1]) * fac
+                exit_lv[alive[stop]] = j
+                alive = alive[~stop]
+        return lam, exit_lv
+
+    def sample(self, level: int, n: int) -> None:
+        torch = self.torch
+        done = 0
+        while done < n:
+            k = min(self.max_batch, n - done)
+            start = self.next_row.get(level, 0)
+            rows = self.mi.plate_offsets(self.cfg, level, start, k, stream=level + self.stream_offset)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lam, ex = self.chains(level, rows)
+            idx = np.arange(k)
+            lam_f = lam[idx, ex]
+            acc = self._acc.setdefault(level, IndicatorSums(k=self.k_biased))
+            if level > 0:
+                lam_c = lam[idx, np.minimum(ex, level - 1)]
+                qd = torch.from_numpy(np.stack([lam_f, lam_c])).to("cuda")
+                la = self.ctx.level_stats(level, qd[0], qd[1], lambda_star=self.lam_star)
+            else:
+                qd = torch.from_numpy(lam_f).to("cuda")
+                la = self.ctx.level_stats(level, qd, None, lambda_star=self.lam_star)
+            dt = time.perf_counter() - t0
+            acc.n += int(la.n)
+            acc.n_plus += int(la.n_plus)
+            acc.n_minus += int(la.n_minus)
+            acc.seconds += dt
+            self.next_row[level] = start + k
+            done += k
+
+
+def run_plate_mlmc_sr(ctx, cfg: Dict, lam_star: Optional[float] = None, tau_rel: Optional[float] = None,
+                      precision: int = FP64, L_max: Optional[int] = None, n_star: Optional[int] = None,
+                      log=None) -> MLMCResult:
+    """MLMC with selective refinement for P(lambda < lambda*) (Sections 2.3-2.4):
+    Algorithm 1 over the SR sampler, tolerance ``tau_rel * p_hat``."""
+    ml = cfg.get("mlmc", {})
+    lam_star = cfg["lambda_crit"] if lam_star is None else lam_star
+    tau_rel = ml.get("tau_rel", 0.043) if tau_rel is None else tau_rel
+    L_max = cfg["n_levels"] - 1 if L_max is None else L_max
+    sampler = PlateSRSampler(ctx, cfg, lam_star, precision=precision)
+    dofs = [ctx.level_info(l)["n_dofs"] for l in range(cfg["n_levels"])]
+    res = adaptive_mlmc(sampler, L_max, eps_rel=tau_rel, theta=ml.get("theta", 0.5),
+                        n_star=ml.get("n_star", 100) if n_star is None else n_star, m=cfg.get("sr", {}).get("m", 4),
+                        alpha_default=cfg.get("sr", {}).get("alpha", 1.0), dofs=None, log=log)
+    res.history.append({"solves_per_level": sampler.solves.tolist()})
+    return res
+
+
+def two_level_rare_event(ctx, cfg: Dict, L: int, n0: int, n1: int, lam_star: Optional[float] = None,
+                         precision: int = FP64) -> Dict:
+    """The two-level estimator E[Q] ~ Qhat_0 + Yhat_{L,0}, Y_{L,0} = Q_L - Q_0 with
+    Q_L from the full selective-refinement chain (Section 4.3)."""
+    lam_star = cfg["lambda_crit"] if lam_star is None else lam_star
+    s = PlateSRSampler(ctx, cfg, lam_star, precision=precision, stream_offset=100)
+    t0 = time.perf_counter()
+    rows0 = s.mi.plate_offsets(cfg, 0, 0, n0, stream=100)
+    lam0, _ = s.chains(0, rows0)
+    q0 = (lam0[:, 0] < lam_star).astype(float)
+    rows1 = s.mi.plate_offsets(cfg, L, 0, n1, stream=101)
+    lam1, ex = s.chains(L, rows1)
+    qL = (lam1[np.arange(n1), ex] < lam_star).astype(float)
+    y = qL - (lam1[:, 0] < lam_star).astype(float)
+    est = q0.mean() + y.mean()
+    var = q0.var() / n0 + y.var() / n1
+    return {"estimate": est, "rmse": math.sqrt(var), "n0": n0, "n1": n1, "L": L, "solves": s.solves.tolist(),
+            "seconds": time.perf_counter() - t0, "p0": q0.mean(), "yhat": y.mean()}

@@ -69,3 +69,31 @@ def test_relative_tolerance_and_alpha_fit_match_oracle():
 def test_population_variance():
     s = LevelSums(4, 14.0, 70.0)
     assert s.mean == 3.5 and s.var == np.var([1.0, 2.0, 4.0, 7.0])
+
+
+def test_sr_exit_levels_match_oracle_chain():
+    from oracle.sr import sr_chain, sr_pair
+    from paper_1907_10271_amd.driver import sr_exit_levels
+    rng = np.random.default_rng(9)
+    for trial in range(300):
+        ell = int(rng.integers(1, 5))
+        base = 0.88 + 0.05 * rng.standard_normal()
+        lam = base + 0.02 * 4.0 ** -np.arange(ell + 1) * rng.uniform(0.5, 2.0)
+        lam_star = 0.88 + 0.01 * rng.standard_normal()
+        ex = sr_exit_levels(lam[None, :], lam_star, 4.0, 1.0, 1)[0]
+        val, j, _ = sr_chain(lambda k: lam[k], ell, lam_star, 4.0, 1.0, 1)
+        assert j == ex and val == lam[ex]
+        # Y from the same chain, truncated at ell - 1
+        qf, qc, y, _ = sr_pair(lambda k: lam[k], ell, lam_star, 4.0, 1.0, 1)
+        lam_c = lam[min(ex, ell - 1)]
+        assert qf == int(lam[ex] < lam_star) and qc == int(lam_c < lam_star)
+
+
+def test_indicator_sums_biased_variance():
+    from oracle import mlmc as omlmc
+    from paper_1907_10271_amd.driver import IndicatorSums
+    a = IndicatorSums(n=1000, n_plus=3, n_minus=0, k=1)
+    pp, pm = omlmc.biased_p(3, 1000, 1), omlmc.biased_p(0, 1000, 1)
+    assert abs(a.var - omlmc.trinomial_moments(pp, pm)[1]) < 1e-15
+    b = IndicatorSums(n=1000, n_plus=40, n_minus=12)
+    assert abs(b.var - omlmc.trinomial_moments(0.04, 0.012)[1]) < 1e-15

@@ -96,3 +96,23 @@ def test_plate_error_paths():
     with pytest.raises(pk.MLMCError) as e:
         ctx.solve_batch([(0, 0, False)], off)
     assert e.value.code == -4
+
+
+def test_selective_refinement_chain_matches_oracle():
+    """Algorithm 2 on the GPU: per-level loads agree with the oracle, and exit
+    levels agree with the oracle's chain run on the oracle's loads."""
+    from oracle.sr import sr_chain
+    from paper_1907_10271_amd.driver import PlateSRSampler
+    ctx = context("plate_c4")
+    off = mi.plate_offsets(C4, 2, 0, 4)
+    ref = np.array([[oracle_plate(l).buckling_load(r) for l in range(3)] for r in off])
+    # threshold near sample 0's level-1 load, so it refines while others exit early
+    lam_star = ref[0, 1] - 0.1 * (ref[0, 0] - ref[0, 1])
+    s = PlateSRSampler(ctx, C4, lam_star, j_min=1, alpha=1.0, m=4)
+    lam, ex = s.chains(2, off)
+    for k in range(4):
+        _, j, lams = sr_chain(lambda l: ref[k, l], 2, lam_star, 4, 1.0, 1)
+        assert ex[k] == j
+        np.testing.assert_allclose(lam[k, :j + 1], ref[k, :j + 1], rtol=1e-10)
+        assert np.all(np.isnan(lam[k, j + 1:]))
+    assert ex[0] == 2
