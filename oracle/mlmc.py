@@ -8,6 +8,9 @@ paper is ambiguous:
 * Algorithm 1 starts with ``L = -1`` and never increments it; the level is
   incremented at the top of every pass, and the loop also stops at the
   configured top level (the bias is then reported as uncertified);
+* the bias estimate (Eq. bias_estimate) is derived for level differences
+  ``Y_l, l >= 1``; at ``L = 0`` (where ``Y_0 = Q_0``) the test is not
+  applied and the loop always continues;
 * trinomial moments: ``E[Y] = p+ - p-`` and
   ``V[Y] = p+ + p- - (p+ - p-)^2`` (the printed signs are inconsistent
   with ``Y`` taking the values +1 and -1);
@@ -170,7 +173,7 @@ def algorithm1(sampler: Callable[[int, int, int], np.ndarray], cost: Callable[[i
         Yhat = [mc_estimate(y) for y in samples]
         if M is not None and L >= 2:
             alpha = fit_rate(M[1:L + 1], Yhat[1:L + 1])
-        bias = bias_estimate(Yhat[L], alpha, m)
+        bias = bias_estimate(Yhat[L], alpha, m) if L >= 1 else math.inf
         if bias < e_b:
             converged = True
         elif L >= L_max:

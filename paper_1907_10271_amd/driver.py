@@ -6,7 +6,8 @@
   Eq. bias_estimate for the stopping test and Eq. tausplit for the split of
   the tolerance.  Readings where the paper is ambiguous: the level counter
   is incremented at the top of every pass (the printed loop never does it);
-  the bias estimate uses ``|Yhat_L|``; ``alpha`` is fitted on the levels
+  the bias estimate uses ``|Yhat_L|`` and, being derived for level
+  differences, is not applied at ``L = 0``; ``alpha`` is fitted on the levels
   ``l >= 1`` once two exist (otherwise a default); the run stops at the top
   configured level with ``converged = False`` if the bias test never passes.
 * :class:`StripSampler` draws strip samples (seeded parameter rows), solves
@@ -86,9 +87,12 @@ def _alpha_fit(M: List[float], yhat: List[float]) -> float:
 def adaptive_mlmc(sampler, L_max: int, eps_abs: Optional[float] = None, eps_rel: Optional[float] = None,
                   theta: float = 0.5, n_star: int = 100, m: float = 4.0, alpha_default: float = 1.0,
                   dofs: Optional[List[float]] = None, max_new: int = 10 ** 9,
-                  log: Optional[Callable[[Dict], None]] = None) -> MLMCResult:
-    """Algorithm 1.  The tolerance is ``eps_abs`` or ``eps_rel * |estimate|``
-    (re-evaluated after every pass).  ``dofs[l]`` (M_l) enables the fit of alpha."""
+                  log: Optional[Callable[[Dict], None]] = None, eps_floor: float = 0.0) -> MLMCResult:
+    """Algorithm 1.  The tolerance is ``eps_abs`` or ``eps_rel * max(|estimate|,
+    eps_floor)`` (re-evaluated after every pass; the floor gives a relative
+    tolerance a scale while the estimate is still zero, e.g. a failure
+    probability before the first failure).  ``dofs[l]`` (M_l) enables the fit
+    of alpha."""
     if (eps_abs is None) == (eps_rel is None):
         raise ValueError("give exactly one of eps_abs, eps_rel")
     t0 = time.perf_counter()
@@ -105,7 +109,9 @@ def adaptive_mlmc(sampler, L_max: int, eps_abs: Optional[float] = None, eps_rel:
         sampler.sample(L, n_star)
         est = sum(sampler.acc(l).mean for l in range(L + 1))
         if eps_rel is not None:
-            e_abs = eps_rel * abs(est)
+            e_abs = eps_rel * max(abs(est), eps_floor)
+        if not e_abs > 0.0:
+            raise ValueError("tolerance is zero: give eps_abs or a positive eps_floor")
         e_s2 = theta * e_abs * e_abs
         e_b = math.sqrt(1.0 - theta) * e_abs
         V = [max(sampler.acc(l).var, 0.0) for l in range(L + 1)]
@@ -119,7 +125,7 @@ def adaptive_mlmc(sampler, L_max: int, eps_abs: Optional[float] = None, eps_rel:
         yhat = [sampler.acc(l).mean for l in range(L + 1)]
         if dofs is not None and L >= 2:
             alpha = _alpha_fit(dofs[1:L + 1], yhat[1:L + 1])
-        bias = abs(yhat[L]) / (m ** alpha - 1.0)
+        bias = abs(yhat[L]) / (m ** alpha - 1.0) if L >= 1 else math.inf
         rec = {"pass": passes, "L": L, "N": [sampler.acc(l).n for l in range(L + 1)], "yhat": yhat,
                "V": [sampler.acc(l).var for l in range(L + 1)], "C": C, "e_abs": e_abs, "bias": bias,
                "e_b": e_b, "alpha": alpha, "t": time.perf_counter() - t0}
@@ -365,7 +371,8 @@ def run_plate_mlmc_sr(ctx, cfg: Dict, lam_star: Optional[float] = None, tau_rel:
     dofs = [ctx.level_info(l)["n_dofs"] for l in range(cfg["n_levels"])]
     res = adaptive_mlmc(sampler, L_max, eps_rel=tau_rel, theta=ml.get("theta", 0.5),
                         n_star=ml.get("n_star", 100) if n_star is None else n_star, m=cfg.get("sr", {}).get("m", 4),
-                        alpha_default=cfg.get("sr", {}).get("alpha", 1.0), dofs=None, log=log)
+                        alpha_default=cfg.get("sr", {}).get("alpha", 1.0), dofs=None, log=log,
+                        eps_floor=cfg.get("p_target", 0.0))
     res.history.append({"solves_per_level": sampler.solves.tolist()})
     return res
 
