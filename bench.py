@@ -53,6 +53,15 @@ def parse():
                     help="overrides of the mixed-precision settings, e.g. update_factor=0.1,theta_storage=fp32")
     ap.add_argument("--plate", type=str, default="",
                     help="also time the buckling solver: samples per plate level, e.g. 1024,256,32,4")
+    ap.add_argument("--serve", type=str, default="",
+                    help="also run the serving loop over the mixed request stream at these arrival rates "
+                         "(requests/s, comma list)")
+    ap.add_argument("--serve-duration", type=float, default=0.0,
+                    help="seconds of arrivals per rate (default: the serving configuration's)")
+    ap.add_argument("--time-to-eps", type=float, default=0.0,
+                    help="also run adaptive MLMC (Algorithm 1) to this relative RMSE, FP64 and mixed precision")
+    ap.add_argument("--tte-config", type=str, default="strip_c2",
+                    help="strip workload of the time-to-epsilon runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
@@ -128,6 +137,44 @@ def plate_leg(pk, torch, counts, prec):
                     "lobpcg_iters_mean": round(float(info["iters_f"].mean()), 1),
                     "all_converged": bool(np.all(info["status_f"] == 0))})
     return res
+
+
+def serve_leg(pk, rates, duration, prec):
+    """Serving loop over the mixed strip/panel request stream at each arrival rate."""
+    from paper_1907_10271_amd.serve import serve_sweep
+    scfg = mi.load_config("serve_c5")
+    stats = serve_sweep(scfg, prec, rates, duration or None,
+                        log=lambda m: print("serve: " + m, file=sys.stderr, flush=True))
+    return {"workload": "Poisson requests, 70% strip (5 levels 64x16..1024x256) / 30% panel (4 levels 16^2..128^2), "
+                        "level mix strip " + str(scfg["strip_level_weights"]) + " panel " +
+                        str(scfg["plate_level_weights"]),
+            "workers": scfg["workers"], "max_batch": scfg["max_batch"], "mem_budget_gib": scfg["mem_budget_gib"],
+            "rates": [{"offered_per_s": r, "requests": s.requests, "served_per_s": round(s.throughput, 1),
+                       "p50_ms": round(s.p50_ms, 2), "p99_ms": round(s.p99_ms, 2),
+                       "mean_batch": round(s.mean_batch, 2), "failed": s.failed,
+                       "per_class": s.per_class} for r, s in zip(rates, stats)]}
+
+
+def tte_leg(pk, torch, name, eps_rel):
+    """Wall time of adaptive MLMC (Algorithm 1) to a relative RMSE, FP64 and mixed precision."""
+    from paper_1907_10271_amd.driver import run_strip_mlmc
+    cfg = mi.load_config(name)
+    out = {"workload": name, "eps_rel": eps_rel}
+    for label, prec in (("fp64", pk.FP64), ("mixed", pk.MIXED)):
+        ctx = pk.Context(mi.config_text(name))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = run_strip_mlmc(ctx, cfg, precision=prec, eps_rel=eps_rel,
+                             log=lambda m: print(f"tte {label}: " + m, file=sys.stderr, flush=True))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        d = res.as_dict()
+        out[label] = {"seconds": round(dt, 2), "estimate": d["estimate"], "L": d["L"], "converged": d["converged"],
+                      "e_abs": d["e_abs"], "bias_estimate": d["bias_estimate"],
+                      "sampling_err2": d["sampling_err2"], "levels": d["levels"]}
+        ctx.close()
+    out["speedup_mixed"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
+    return out
 
 
 def main():
@@ -245,6 +292,10 @@ def main():
     }
     if args.plate:
         out["plate"] = plate_leg(pk, torch, [int(v) for v in args.plate.split(",")], prec)
+    if args.serve:
+        out["serving"] = serve_leg(pk, [float(v) for v in args.serve.split(",")], args.serve_duration, prec)
+    if args.time_to_eps > 0:
+        out["time_to_eps"] = tte_leg(pk, torch, args.tte_config, args.time_to_eps)
     if len(levels) != len(mix):
         out["metric"] = "profiling run on levels " + args.levels + " only (not the benchmark)"
     if cpu is not None:

@@ -117,6 +117,15 @@ int mlmc_num_levels(const mlmc_ctx *ctx);
  * Used for admission by memory footprint. */
 int mlmc_footprint(const mlmc_ctx *ctx, int kind, int level, int precision, size_t *bytes_per_request);
 
+/* Allocate the workspace for `n` requests of `level` in `precision` now, so that
+ * later batches of up to `n` requests of that level allocate nothing (a level's
+ * workspace serves both the fine solves of its requests and the coarse solves
+ * of coupled requests one level up).  The workspace only grows; the total of
+ * all levels stays within the context's budget.
+ * Errors: MLMC_EINVAL (level, n < 0, precision), MLMC_ENOMEM (budget or
+ * device memory), MLMC_EHIP. */
+int mlmc_reserve(mlmc_ctx *ctx, int level, int n, int precision);
+
 /* ----------------------------------------------------------- strip (Test I) */
 
 /* KL synthesis (Eq. inftyKL truncated after the configured number of modes,

@@ -25,7 +25,7 @@ S_OK, S_NOCONV, S_NAN, S_BREAKDOWN, S_SKIPPED = 0, 1, 2, 3, 4
 EXPORTS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_level_info", "mlmc_num_levels",
            "mlmc_footprint", "mlmc_sample_field", "mlmc_strip_apply", "mlmc_strip_rhs_diag",
            "mlmc_strip_solve_theta", "mlmc_solve_batch", "mlmc_buckle_batch", "mlmc_level_stats",
-           "mlmc_profile_enable", "mlmc_profile_read", "mlmc_plate_apply"]
+           "mlmc_profile_enable", "mlmc_profile_read", "mlmc_plate_apply", "mlmc_reserve"]
 
 
 class Request(C.Structure):
@@ -78,6 +78,7 @@ def load() -> C.CDLL:
     lib.mlmc_level_info.argtypes = [vp, i] + [C.POINTER(C.c_int64)] * 4
     lib.mlmc_num_levels.argtypes = [vp]
     lib.mlmc_footprint.argtypes = [vp, i, i, i, C.POINTER(sz)]
+    lib.mlmc_reserve.argtypes = [vp, i, i, i]
     lib.mlmc_sample_field.argtypes = [vp, i, i, vp, i, vp, i, vp]
     lib.mlmc_strip_apply.argtypes = [vp, i, i, vp, vp, vp, i, vp]
     lib.mlmc_strip_rhs_diag.argtypes = [vp, i, i, vp, vp, vp, vp]
@@ -156,6 +157,10 @@ class Context:
         b = C.c_size_t()
         self._check(self.lib.mlmc_footprint(self.h, kind, level, precision, C.byref(b)))
         return b.value
+
+    def reserve(self, level: int, n: int, precision: int = FP64) -> None:
+        """Allocate the workspace for ``n`` requests of ``level`` now."""
+        self._check(self.lib.mlmc_reserve(self.h, level, n, precision))
 
     # ------------------------------------------------------------ strip
     def sample_field(self, level: int, xi, dtype: int = 0, stream=None):

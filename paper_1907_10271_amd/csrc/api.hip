@@ -565,8 +565,12 @@ int mlmc_create(const char *config_json, size_t mem_budget_bytes, mlmc_ctx **out
     } else if (kind == "plate") {
       c->kind = 1;
       c->plate = plate_create(c->cfg, c->err);
-      if (!c->plate) rc = MLMC_EINVAL;
-      else c->nlev = plate_num_levels(c->plate);
+      if (!c->plate) {
+        rc = MLMC_EINVAL;
+      } else {
+        c->nlev = plate_num_levels(c->plate);
+        plate_set_budget(c->plate, c->budget);
+      }
     } else {
       throw std::runtime_error("config 'kind' must be \"strip\" or \"plate\"");
     }
@@ -633,6 +637,19 @@ int mlmc_footprint(const mlmc_ctx *c, int kind, int level, int precision, size_t
                              (precision == MLMC_MIXED ? strip_mixed_slot_bytes(c->lv[level].g) : 0)
                        : plate_slot_bytes(c->plate, level, precision);
   return MLMC_OK;
+}
+
+int mlmc_reserve(mlmc_ctx *c, int level, int n, int precision) {
+  if (!c) return MLMC_EINVAL;
+  if (bad_level(c, level) || n < 0) return fail(c, MLMC_EINVAL, "level out of range or n < 0");
+  if (precision != MLMC_FP64 && precision != MLMC_MIXED) return fail(c, MLMC_EINVAL, "bad precision");
+  if (n == 0) return MLMC_OK;
+  if (c->kind == 1) return plate_reserve(c->plate, c->err, level, n);
+  const bool mixed = precision == MLMC_MIXED;
+  if (n > max_slots(c, level, mixed))
+    return fail(c, MLMC_ENOMEM, "level " + std::to_string(level) + ": " + std::to_string(n) +
+                                    " slots exceed the memory budget");
+  return ensure_pool(c, level, n, mixed);
 }
 
 int mlmc_sample_field(mlmc_ctx *c, int level, int n, const double *xi, int ld_xi, void *theta, int dtype,

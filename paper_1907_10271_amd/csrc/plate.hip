@@ -707,6 +707,7 @@ struct PlateLevelH {
   int *d_free_of_full = nullptr, *d_full_of_free = nullptr;
   // batch workspace
   int cap = 0;
+  size_t bytes = 0;
   double *band = nullptr, *vec = nullptr;
   float *bandf = nullptr;
   int64_t *rows = nullptr;
@@ -721,6 +722,7 @@ struct PlateCtx {
   std::vector<PlateLevelH> lv;
   double *d_xf = nullptr, *d_yf = nullptr;
   size_t xf_cap = 0;
+  size_t budget = 0;               // bound on the batch workspaces of all levels
 };
 
 static PlateGeom plate_geom(const Json &cfg, int level) {
@@ -827,6 +829,52 @@ static void free_work(PlateLevelH &L) {
   L.rows = nullptr;
   L.outidx = nullptr;
   L.cap = 0;
+  L.bytes = 0;
+}
+
+// workspace of one in-flight sample: FP64 and FP32 band factors plus the
+// LOBPCG vectors (both precisions share one allocation so that a level's
+// workspace serves either)
+static size_t work_bytes(const PlateLevelH &L) {
+  const size_t bs = (size_t)L.g.nfree * (L.g.bw + 1);
+  return bs * (sizeof(double) + sizeof(float)) + (size_t)NVEC * L.g.nfree * sizeof(double) + sizeof(int64_t) +
+         sizeof(int);
+}
+
+// grow the workspace of level l to at least n samples within the budget
+static int ensure_work(PlateCtx *p, std::string &err, int l, int n) {
+  PlateLevelH &L = p->lv[l];
+  if (L.cap >= n) return MLMC_OK;
+  size_t other = 0;
+  for (int k = 0; k < p->nlev; ++k)
+    if (k != l) other += p->lv[k].bytes;
+  const size_t need = work_bytes(L) * (size_t)n;
+  if (other + need > p->budget) {
+    err = "plate level " + std::to_string(l) + ": " + std::to_string(n) + " samples exceed the memory budget";
+    return MLMC_ENOMEM;
+  }
+  free_work(L);
+  const size_t bs = (size_t)L.g.nfree * (L.g.bw + 1);
+  if (hipMalloc(&L.band, bs * sizeof(double) * n) != hipSuccess ||
+      hipMalloc(&L.bandf, bs * sizeof(float) * n) != hipSuccess ||
+      hipMalloc(&L.vec, (size_t)NVEC * L.g.nfree * sizeof(double) * n) != hipSuccess ||
+      hipMalloc(&L.rows, sizeof(int64_t) * n) != hipSuccess || hipMalloc(&L.outidx, sizeof(int) * n) != hipSuccess) {
+    free_work(L);
+    err = "plate workspace allocation failed";
+    return MLMC_ENOMEM;
+  }
+  L.cap = n;
+  L.bytes = need;
+  return MLMC_OK;
+}
+
+// largest batch of level l that fits beside the other levels' workspaces
+static int max_work(const PlateCtx *p, int l) {
+  size_t other = 0;
+  for (int k = 0; k < p->nlev; ++k)
+    if (k != l) other += p->lv[k].bytes;
+  if (p->budget <= other) return 0;
+  return (int)std::min<size_t>((p->budget - other) / work_bytes(p->lv[l]), 2048);
 }
 
 void plate_destroy(PlateCtx *p) {
@@ -850,11 +898,14 @@ void plate_level_sizes(const PlateCtx *p, int level, int64_t *nn, int64_t *nd, i
   *ne = (int64_t)g.nx * g.ny;
 }
 
-size_t plate_slot_bytes(const PlateCtx *p, int level, int precision) {
-  const PlateGeom &g = p->lv[level].g;
-  const size_t band = (size_t)g.nfree * (g.bw + 1) * (precision == MLMC_MIXED ? 4 : 8);
-  return band + (size_t)NVEC * g.nfree * sizeof(double) + 64;
+size_t plate_slot_bytes(const PlateCtx *p, int level, int /*precision*/) { return work_bytes(p->lv[level]); }
+
+int plate_reserve(PlateCtx *p, std::string &err, int level, int n) {
+  if (level < 0 || level >= p->nlev || n < 0) { err = "level out of range or n < 0"; return MLMC_EINVAL; }
+  return ensure_work(p, err, level, n);
 }
+
+void plate_set_budget(PlateCtx *p, size_t bytes) { p->budget = bytes; }
 
 int plate_buckle_batch(PlateCtx *p, std::string &err, int n_req, const mlmc_request *req, const double *offsets,
                        int64_t n_rows, double *lam_fine, double *lam_coarse, mlmc_info *info, int precision,
@@ -891,23 +942,13 @@ int plate_buckle_batch(PlateCtx *p, std::string &err, int n_req, const mlmc_requ
       const auto &O = outs[2 * l + coarse];
       const int total = (int)R.size();
       if (!total) continue;
-      // batch capacity: at most 2048 samples or 16 GiB of workspace per launch
-      const size_t per = plate_slot_bytes(p, l, MLMC_FP64) + plate_slot_bytes(p, l, MLMC_MIXED);
-      const int cap = (int)std::max<size_t>(1, std::min<size_t>(std::min(total, 2048), (16ull << 30) / per));
-      if (L.cap < cap) {
-        free_work(L);
-        const size_t bs = (size_t)L.g.nfree * (L.g.bw + 1);
-        if (hipMalloc(&L.band, bs * sizeof(double) * cap) != hipSuccess ||
-            hipMalloc(&L.bandf, bs * sizeof(float) * cap) != hipSuccess ||
-            hipMalloc(&L.vec, (size_t)NVEC * L.g.nfree * sizeof(double) * cap) != hipSuccess ||
-            hipMalloc(&L.rows, sizeof(int64_t) * cap) != hipSuccess ||
-            hipMalloc(&L.outidx, sizeof(int) * cap) != hipSuccess) {
-          free_work(L);
-          err = "plate workspace allocation failed";
-          return MLMC_ENOMEM;
-        }
-        L.cap = cap;
+      // batch capacity: what is reserved, else what fits the budget (at most 2048)
+      const int cap = std::max(L.cap, std::min(total, max_work(p, l)));
+      if (cap < 1) {
+        err = "plate level " + std::to_string(l) + ": no sample fits the memory budget";
+        return MLMC_ENOMEM;
       }
+      if (int rc = ensure_work(p, err, l, cap)) return rc;
       PlateWork Wk{};
       Wk.band = L.band;
       Wk.bandf = L.bandf;

@@ -19,6 +19,8 @@ void plate_destroy(PlateCtx *p);
 int plate_num_levels(const PlateCtx *p);
 void plate_level_sizes(const PlateCtx *p, int level, int64_t *n_nodes, int64_t *n_dofs, int64_t *n_elem);
 size_t plate_slot_bytes(const PlateCtx *p, int level, int precision);
+int plate_reserve(PlateCtx *p, std::string &err, int level, int n);
+void plate_set_budget(PlateCtx *p, size_t bytes);
 int plate_buckle_batch(PlateCtx *p, std::string &err, int n_req, const mlmc_request *req, const double *offsets,
                        int64_t n_rows, double *lam_fine, double *lam_coarse, mlmc_info *info, int precision, double tol,
                        hipStream_t st);
