@@ -86,8 +86,9 @@ def cpu_baseline(cfg, mix, counts):
     """The oracle (FP64 numpy/scipy, single-threaded BLAS per worker) on a bounded
     sample of the same workload, one worker process per host core."""
     global _ORACLE_MODELS
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
     import multiprocessing as mp
+
+    from threadpoolctl import threadpool_limits
 
     from oracle.kl import KL
     from oracle.strip import StripModel
@@ -100,10 +101,16 @@ def cpu_baseline(cfg, mix, counts):
     _ORACLE_MODELS = (models, rows)
     cores = min(len(os.sched_getaffinity(0)), 16)
     jobs = [(l, k) for l in reversed(range(nl)) for k in range(counts[l])]
-    t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(cores) as pool:
-        res = pool.map(_oracle_job, jobs, chunksize=1)
-    wall = time.perf_counter() - t0
+    res = []
+    # one BLAS thread per worker process (the forked workers inherit the limit)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        with mp.get_context("fork").Pool(cores) as pool:
+            for r in pool.imap_unordered(_oracle_job, jobs, chunksize=1):
+                res.append(r)
+                if len(res) % 4 == 0 or len(res) == len(jobs):
+                    print(f"cpu baseline: {len(res)}/{len(jobs)} oracle samples done", file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t0
     per_level = [np.mean([t for l, t in res if l == lv]) for lv in range(nl)]
     # throughput on the benchmark's mix: cores workers sharing the per-sample costs
     step_cpu_s = sum(n * t for n, t in zip(mix, per_level))
@@ -116,6 +123,30 @@ def cpu_baseline(cfg, mix, counts):
 
 
 # ------------------------------------------------------------------ GPU
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_pass1_strip4lvl_fp64_hbm_traffic.md")
+KERNEL_SOURCES = ["common.hpp", "strip_device.hpp", "strip_kernels.hip", "strip_kernels.hpp"]
+
+
+def profiled_traffic():
+    """HBM bytes per operator-pass launch from the committed hardware-counter
+    summary of this benchmark, or None when the kernel sources changed since."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_PROFILE):
+        if " = " in line:
+            k, v = line.split(" = ", 1)
+            vals[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1907_10271_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if vals.get("kernel_sources_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def plate_leg(pk, torch, counts, prec):
     """Buckling loads per level of the panel workload (one timed batch per level)."""
     pcfg = mi.load_config("plate_c4")
@@ -263,6 +294,8 @@ def main():
     p1 = ctx.profile_read(0 if prec == pk.FP64 else 2)
     p2 = ctx.profile_read(1 if prec == pk.FP64 else 3)
     achieved = p1["bytes"] / (p1["ms"] / 1e3) / 1e9
+    default_run = mix == DEFAULT_MIX and prec == pk.FP64 and not args.mixed and len(levels) == len(mix)
+    traffic = profiled_traffic() if default_run else None
     total = sum(n for l, n in enumerate(mix) if l in levels)
     out = {
         "metric": "coupled-sample solves/s (4-level FP64 waviness strip, one MLMC batch round per step)",
@@ -283,7 +316,8 @@ def main():
         "per_level": per_level,
         "roofline": {"bound": "hbm", "kernel": "k_pass1 (PCG operator pass)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
                      "launches": p1["launches"], "avg_launch_us": round(p1["ms"] * 1e3 / p1["launches"], 3),
                      "alg_bytes_per_launch": round(p1["bytes"] / p1["launches"], 1)},
         "vector_pass": {"kernel": "k_pass2", "achieved_GBs": round(p2["bytes"] / (p2["ms"] / 1e3) / 1e9, 1),
