@@ -124,12 +124,12 @@ def cpu_baseline(cfg, mix, counts):
 
 # ------------------------------------------------------------------ GPU
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_pass1_strip4lvl_fp64_hbm_traffic.md")
-KERNEL_SOURCES = ["common.hpp", "strip_device.hpp", "strip_kernels.hip", "strip_kernels.hpp"]
+CSRC = os.path.join(ROOT, "paper_1907_10271_amd", "csrc")
 
 
 def profiled_traffic():
     """HBM bytes per operator-pass launch from the committed hardware-counter
-    summary of this benchmark, or None when the kernel sources changed since."""
+    summary of this benchmark, or None when the library sources changed since."""
     import hashlib
     if not os.path.exists(TRAFFIC_PROFILE):
         return None
@@ -139,8 +139,8 @@ def profiled_traffic():
             k, v = line.split(" = ", 1)
             vals[k.strip()] = v.strip()
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1907_10271_amd", "csrc", f), "rb") as fh:
+    for f in sorted(os.listdir(CSRC)):          # any change to the library invalidates the counters
+        with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     if vals.get("kernel_sources_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in vals:
         return None
@@ -196,7 +196,7 @@ def tte_leg(pk, torch, name, eps_rel):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = run_strip_mlmc(ctx, cfg, precision=prec, eps_rel=eps_rel,
-                             log=lambda m: print(f"tte {label}: " + m, file=sys.stderr, flush=True))
+                             log=lambda m: print(f"tte {label}: {m}", file=sys.stderr, flush=True))
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         d = res.as_dict()

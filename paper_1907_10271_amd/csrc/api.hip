@@ -17,6 +17,7 @@
 #include "mlmc.h"
 #include "plate.hpp"
 #include "strip_kernels.hpp"
+#include "strip_small.hpp"
 
 using namespace mlmc;
 
@@ -48,6 +49,7 @@ struct StripLevel {
   StripGeom g{};
   double *modes = nullptr;  // dev [4 nelem][K], sqrt(mu) folded in
   StripPool pool;
+  bool small = false;       // solved by the one-work-group-per-sample kernel
 };
 
 }  // namespace
@@ -422,6 +424,14 @@ int run_pcg(mlmc_ctx *c, int level, const PcgSlots &S, int n, hipStream_t st) {
   return pcg_iterate<double>(c, level, S, n, S.active, st, 0, [](int) {});
 }
 
+// coarse level: set-up + PCG to completion by one work-group per sample, FP64
+int run_small(mlmc_ctx *c, int level, const PcgSlots &S, int n, hipStream_t st) {
+  launch_setup(c->lv[level].g, c->mat, S, n, nullptr, nullptr, st);
+  launch_small_solve(c->lv[level].g, c->mat, S, n, st);
+  HIPCHK(c, hipGetLastError());
+  return MLMC_OK;
+}
+
 // mixed precision: FP32 PCG (BF16 angles) with reliable updates in FP64 (the
 // residual b - A x recomputed with the FP64 angles whenever the FP32 residual
 // fell by the update factor, and as the only stopping test); x accumulates in
@@ -482,6 +492,17 @@ int build_strip(mlmc_ctx *c) {
   const std::string type = kl.string_or("type", "");
   c->lv.resize(c->nlev);
   for (int l = 0; l < c->nlev; ++l) c->lv[l].g = make_geom(cfg, l);
+  // coarse levels whose PCG state fits one work-group's LDS are solved whole
+  // by one work-group per sample ("small_solver": "auto" or "off"); the
+  // choice depends on the level only, never on the batch
+  const std::string sm = cfg.string_or("small_solver", "auto");
+  if (sm != "auto" && sm != "off") throw std::runtime_error("small_solver must be auto or off");
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
+    throw std::runtime_error("hipDeviceGetAttribute failed");
+  const int small_max_nodes = (int)cfg.number_or("small_max_nodes", 1 << 30);
+  for (int l = 0; l < c->nlev; ++l)
+    c->lv[l].small = sm == "auto" && c->lv[l].g.nnode <= small_max_nodes && small_fits(c->lv[l].g, (size_t)lds);
   const int K = c->K;
   if (type == "exp_separable") {
     SeparableKL sk = separable_kl(cfg.number("Lx"), cfg.number("Ly"), var, kl.number("corr_x"),
@@ -634,7 +655,8 @@ int mlmc_footprint(const mlmc_ctx *c, int kind, int level, int precision, size_t
   if (bad_level(c, level)) return fail(m, MLMC_EINVAL, "level out of range");
   if (precision != MLMC_FP64 && precision != MLMC_MIXED) return fail(m, MLMC_EINVAL, "bad precision");
   *bytes = (kind == 0) ? strip_slot_bytes(c->lv[level].g) +
-                             (precision == MLMC_MIXED ? strip_mixed_slot_bytes(c->lv[level].g) : 0)
+                             (precision == MLMC_MIXED && !c->lv[level].small ? strip_mixed_slot_bytes(c->lv[level].g)
+                                                                            : 0)
                        : plate_slot_bytes(c->plate, level, precision);
   return MLMC_OK;
 }
@@ -645,7 +667,7 @@ int mlmc_reserve(mlmc_ctx *c, int level, int n, int precision) {
   if (precision != MLMC_FP64 && precision != MLMC_MIXED) return fail(c, MLMC_EINVAL, "bad precision");
   if (n == 0) return MLMC_OK;
   if (c->kind == 1) return plate_reserve(c->plate, c->err, level, n);
-  const bool mixed = precision == MLMC_MIXED;
+  const bool mixed = precision == MLMC_MIXED && !c->lv[level].small;
   if (n > max_slots(c, level, mixed))
     return fail(c, MLMC_ENOMEM, "level " + std::to_string(level) + ": " + std::to_string(n) +
                                     " slots exceed the memory budget");
@@ -705,7 +727,8 @@ int mlmc_strip_solve_theta(mlmc_ctx *c, int level, int n, const double *theta, d
   if (precision != MLMC_FP64 && precision != MLMC_MIXED) return fail(c, MLMC_EINVAL, "bad precision");
   if (n == 0) return MLMC_OK;
   if (!theta || !q) return fail(c, MLMC_EINVAL, "null pointer");
-  const bool mixed = precision == MLMC_MIXED;
+  const bool small = c->lv[level].small;
+  const bool mixed = precision == MLMC_MIXED && !small;
   const int cap = max_slots(c, level, mixed);
   if (n > cap) return fail(c, MLMC_ENOMEM, "batch exceeds the memory budget");
   hipStream_t st = (hipStream_t)stream;
@@ -713,15 +736,17 @@ int mlmc_strip_solve_theta(mlmc_ctx *c, int level, int n, const double *theta, d
   if (rc) return rc;
   if (info) launch_info_init(info, nullptr, n, st);
   PcgSlots S = slots_of(c, level, theta, rtol > 0 ? rtol : c->rtol);
-  if (mixed) {
+  if (small) {
+    rc = run_small(c, level, S, n, st);
+  } else if (mixed) {
     launch_to_lo(theta, c->lv[level].pool.theta16, c->theta_fp32, (size_t)n * 4 * c->lv[level].g.nelem, st);
     rc = run_mixed(c, level, S, n, st);
   } else {
     rc = run_pcg(c, level, S, n, st);
   }
   if (rc) return rc;
-  launch_qoi(c->lv[level].g, c->mat, report_view(c, level, S, precision), n, c->lv[level].pool.qpart, nullptr, q,
-             info, 0, st);
+  launch_qoi(c->lv[level].g, c->mat, report_view(c, level, S, mixed ? MLMC_MIXED : MLMC_FP64), n,
+             c->lv[level].pool.qpart, nullptr, q, info, 0, st);
   if (d) launch_total_disp(c->lv[level].g, S.x, d, n, st);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(st));
@@ -764,7 +789,8 @@ int mlmc_solve_batch(mlmc_ctx *c, int n_req, const mlmc_request *req, const doub
       const auto &O = outs[2 * l + coarse];
       const int total = (int)R.size();
       if (!total) continue;
-      const bool mixed = precision == MLMC_MIXED;
+      // coarse levels solved whole per work-group run in FP64 in either precision
+      const bool mixed = precision == MLMC_MIXED && !c->lv[l].small;
       const int cap = std::min(max_slots(c, l, mixed), total);
       if (cap < 1) return fail(c, MLMC_ENOMEM, "level " + std::to_string(l) + ": no slot fits the budget");
       int rc = ensure_pool(c, l, cap, mixed);
@@ -777,9 +803,9 @@ int mlmc_solve_batch(mlmc_ctx *c, int n_req, const mlmc_request *req, const doub
         launch_kl_synth(L.modes, c->K, L.g, xi, ld_xi, L.pool.rows, n, L.pool.theta, mixed ? L.pool.theta16 : nullptr,
                         c->theta_fp32, 4 * L.g.nelem, st);
         PcgSlots S = slots_of(c, l, L.pool.theta, rt);
-        rc = mixed ? run_mixed(c, l, S, n, st) : run_pcg(c, l, S, n, st);
+        rc = L.small ? run_small(c, l, S, n, st) : mixed ? run_mixed(c, l, S, n, st) : run_pcg(c, l, S, n, st);
         if (rc) return rc;
-        launch_qoi(L.g, c->mat, report_view(c, l, S, precision), n, L.pool.qpart, L.pool.outidx,
+        launch_qoi(L.g, c->mat, report_view(c, l, S, mixed ? MLMC_MIXED : MLMC_FP64), n, L.pool.qpart, L.pool.outidx,
                    coarse ? q_coarse : q_fine, info, coarse, st);
         HIPCHK(c, hipGetLastError());
         // the row/index buffers are reused by the next chunk

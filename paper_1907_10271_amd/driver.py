@@ -152,7 +152,7 @@ class StripSampler:
     """Coupled strip samples on the GPU: Y_0 = Q_0, Y_l = Q_l - Q_{l-1} (same row)."""
 
     def __init__(self, ctx, cfg: Dict, precision: int = FP64, rtol: float = 0.0, max_batch: int = 4096,
-                 cost_model: Optional[Callable[[int], float]] = None):
+                 cost_model: Optional[Callable[[int], float]] = None, log: Optional[Callable] = None):
         import torch
         import mlmc_inputs as mi
         self.torch = torch
@@ -168,6 +168,7 @@ class StripSampler:
         self._sec: Dict[int, float] = {}
         self.failures = 0
         self.solves = {}
+        self.log = log
 
     def acc(self, level: int) -> LevelSums:
         return LevelSums.from_acc(self._acc[level], self._sec.get(level, 0.0))
@@ -201,6 +202,8 @@ class StripSampler:
             self.next_row[level] = start + k
             self.solves[level] = self.solves.get(level, 0) + k * (2 if level > 0 else 1)
             done += k
+            if self.log:
+                self.log({"level": level, "batch": k, "done": done, "of": n, "seconds": round(dt, 3)})
 
 
 def run_strip_mlmc(ctx, cfg: Dict, precision: int = FP64, eps_rel: Optional[float] = None,
@@ -211,7 +214,7 @@ def run_strip_mlmc(ctx, cfg: Dict, precision: int = FP64, eps_rel: Optional[floa
     if eps_rel is None and eps_abs is None:
         eps_rel = ml.get("eps_rel", 1e-3)
     L_max = cfg["n_levels"] - 1 if L_max is None else L_max
-    sampler = StripSampler(ctx, cfg, precision=precision, cost_model=cost_model)
+    sampler = StripSampler(ctx, cfg, precision=precision, cost_model=cost_model, log=log)
     dofs = [ctx.level_info(l)["n_dofs"] for l in range(cfg["n_levels"])]
     res = adaptive_mlmc(sampler, L_max, eps_abs=eps_abs, eps_rel=eps_rel, theta=ml.get("theta", 0.5),
                         n_star=ml.get("n_star", 100), m=ml.get("m", 4), alpha_default=ml.get("alpha_default", 1.0),

@@ -7,9 +7,15 @@ import mlmc_inputs as mi
 
 
 @functools.lru_cache(maxsize=None)
-def context(name: str):
+def context(name: str, engine: str = "auto"):
+    """Context of a workload; engine "lockstep" turns the one-work-group-per-
+    sample solver of the coarse levels off, so every level runs the lock-step
+    engine."""
     import paper_1907_10271_amd as pk
-    return pk.Context(mi.config_text(name))
+    if engine == "auto":
+        return pk.Context(mi.config_text(name))
+    assert engine == "lockstep"
+    return pk.Context(dict(mi.load_config(name), small_solver="off"))
 
 
 @functools.lru_cache(maxsize=None)

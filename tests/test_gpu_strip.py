@@ -88,9 +88,10 @@ def test_rhs_and_diagonal_parity(name, level):
         assert np.all(dinv[k][om.bc.dofs] == 1.0)
 
 
+@pytest.mark.parametrize("engine", ["auto", "lockstep"])
 @pytest.mark.parametrize("name,level", [("strip_c1", 0), ("strip_c1", 1), ("strip_c2", 0), ("strip_c2", 1)])
-def test_qoi_parity_tight(name, level):
-    ctx = context(name)
+def test_qoi_parity_tight(name, level, engine):
+    ctx = context(name, engine)
     om = oracle_strip(name, level)
     n = 6
     xi = _rows(name, level, n)
@@ -102,10 +103,11 @@ def test_qoi_parity_tight(name, level):
         assert abs(qf[k] - ref) <= 1e-10 * abs(ref), (k, qf[k], ref)
 
 
+@pytest.mark.parametrize("engine", ["auto", "lockstep"])
 @pytest.mark.parametrize("name,level", [("strip_c1", 1), ("strip_c2", 1)])
-def test_production_rtol_residual_and_iterations(name, level):
+def test_production_rtol_residual_and_iterations(name, level, engine):
     from oracle.strip import assemble, jacobi_pcg, reduce_system
-    ctx = context(name)
+    ctx = context(name, engine)
     om = oracle_strip(name, level)
     xi = _rows(name, level, 3)
     thetas = np.stack([om.theta(r).ravel() for r in xi])
@@ -139,9 +141,10 @@ def test_coupled_pairs_telescoping_bitwise():
     assert np.all(info["status_f"] == 0) and np.all(info["status_c"] == 0)
 
 
-def test_batch_composition_invariance_and_determinism():
+@pytest.mark.parametrize("engine", ["auto", "lockstep"])
+def test_batch_composition_invariance_and_determinism(engine):
     name = "strip_c1"
-    ctx = context(name)
+    ctx = context(name, engine)
     xi = _rows(name, 1, 12)
     mix = [(k, k % 2, bool(k % 3)) for k in range(12)]
     a_f, a_c, _ = ctx.solve_batch(mix, dev(xi))
@@ -190,13 +193,16 @@ def test_error_paths():
         pk.Context('{"kind": "strip"}')
 
 
-def test_nan_and_iteration_limit_reported_per_sample():
-    ctx = context("strip_c1")
+@pytest.mark.parametrize("engine", ["auto", "lockstep"])
+def test_nan_and_iteration_limit_reported_per_sample(engine):
+    ctx = context("strip_c1", engine)
     xi = _rows("strip_c1", 0, 3)
     xi[1, 0] = np.nan
     qf, _, info = ctx.solve_batch([(k, 0, False) for k in range(3)], dev(xi))
     assert info[1]["status_f"] == 2 and info[0]["status_f"] == 0 and info[2]["status_f"] == 0
     cfg = dict(mi.load_config("strip_c1"), max_iter=3)
+    if engine == "lockstep":
+        cfg["small_solver"] = "off"
     import paper_1907_10271_amd as pk
     c2 = pk.Context(cfg)
     _, _, info2 = c2.solve_batch([(0, 0, False)], dev(_rows("strip_c1", 0, 1)))
@@ -211,7 +217,7 @@ def test_mixed_precision_qoi_and_fp64_residual(name, level):
     QoI agrees with the oracle's direct solve to well within the stated 1e-6."""
     import paper_1907_10271_amd as pk
     from oracle.strip import assemble, reduce_system
-    ctx = context(name)
+    ctx = context(name, "lockstep")       # the FP32 inner solver runs on every level
     om = oracle_strip(name, level)
     xi = _rows(name, level, 4)
     thetas = np.stack([om.theta(r).ravel() for r in xi])
@@ -232,3 +238,30 @@ def test_mixed_precision_qoi_and_fp64_residual(name, level):
     q64, qc64, _ = ctx.solve_batch([(k, level, level > 0) for k in range(4)], dev(xi))
     assert np.all(inf2["status_f"] == 0)
     assert np.max(np.abs(qf.cpu().numpy() - q64.cpu().numpy()) / np.abs(q64.cpu().numpy())) <= 1e-6
+
+
+@pytest.mark.parametrize("name,level", [("strip_c1", 0), ("strip_c1", 1), ("strip_c2", 0), ("strip_c2", 1)])
+def test_coarse_levels_use_the_whole_solve_kernel(name, level):
+    """Coarse levels run one work-group per sample (no lock-step PCG launches);
+    both engines agree to the tight-tolerance bar and the whole-solve kernel
+    reports the same iteration counts within rounding."""
+    ctx = context(name)
+    lock = context(name, "lockstep")
+    xi = dev(_rows(name, level, 5))
+    reqs = [(k, level, False) for k in range(5)]
+    ctx.profile(True)
+    qa, _, ia = ctx.solve_batch(reqs, xi, rtol=1e-13)
+    assert ctx.profile_read(0)["launches"] == 0
+    ctx.profile(False)
+    lock.profile(True)
+    qb, _, ib = lock.solve_batch(reqs, xi, rtol=1e-13)
+    assert lock.profile_read(0)["launches"] > 0
+    lock.profile(False)
+    qa, qb = qa.cpu().numpy(), qb.cpu().numpy()
+    assert np.all(ia["status_f"] == 0) and np.all(ib["status_f"] == 0)
+    assert np.max(np.abs(qa - qb) / np.abs(qb)) <= 1e-10
+    assert np.all(np.abs(ia["iters_f"].astype(int) - ib["iters_f"].astype(int)) <= 2)
+    # mixed precision on a coarse level runs the FP64 whole-solve kernel
+    import paper_1907_10271_amd as pk
+    qm, _, im = ctx.solve_batch(reqs, xi, precision=pk.MIXED, rtol=1e-13)
+    assert np.array_equal(qm.cpu().numpy(), qa)
