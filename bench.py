@@ -62,6 +62,9 @@ def parse():
                     help="also run adaptive MLMC (Algorithm 1) to this relative RMSE, FP64 and mixed precision")
     ap.add_argument("--tte-config", type=str, default="strip_c2",
                     help="strip workload of the time-to-epsilon runs")
+    ap.add_argument("--set", action="append", default=[], metavar="KEY=JSON",
+                    help="override a key of the strip workload definition (tuning runs; the line is then "
+                         "not the default benchmark), e.g. --set angle_storage='\"cs\"'")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
@@ -232,6 +235,9 @@ def main():
             k, v = kv.split("=")
             mx[k] = v if k == "theta_storage" else float(v)
         ccfg["mixed"] = mx
+    for kv in args.set:
+        k, v = kv.split("=", 1)
+        ccfg[k] = json.loads(v)
     ctx = pk.Context(ccfg)
     nsteps = args.warmup + args.steps
     xi = []
@@ -294,7 +300,8 @@ def main():
     p1 = ctx.profile_read(0 if prec == pk.FP64 else 2)
     p2 = ctx.profile_read(1 if prec == pk.FP64 else 3)
     achieved = p1["bytes"] / (p1["ms"] / 1e3) / 1e9
-    default_run = mix == DEFAULT_MIX and prec == pk.FP64 and not args.mixed and len(levels) == len(mix)
+    default_run = (mix == DEFAULT_MIX and prec == pk.FP64 and not args.mixed and not args.set
+                   and len(levels) == len(mix))
     traffic = profiled_traffic() if default_run else None
     total = sum(n for l, n in enumerate(mix) if l in levels)
     out = {

@@ -17,6 +17,8 @@ import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "lib", "libmlmc.so")
+# per-mesh engine and angle-storage choices written by the autotuner
+TUNING_PATH = os.path.join(_PKG, "tuning", "mi355x.json")
 
 MLMC_OK, MLMC_EINVAL, MLMC_ENOMEM, MLMC_EHIP, MLMC_ESTATE = 0, -1, -2, -3, -4
 FP64, MIXED = 0, 1
@@ -93,6 +95,17 @@ def load() -> C.CDLL:
     return lib
 
 
+def with_tuning(cfg: dict) -> dict:
+    """The strip workload with the autotuner's per-mesh choices as
+    ``level_options`` (unless it has its own, or no tuning file exists)."""
+    if cfg.get("kind") != "strip" or "level_options" in cfg or not os.path.exists(TUNING_PATH):
+        return cfg
+    with open(TUNING_PATH) as f:
+        doc = json.load(f)
+    opts = {k: {"engine": v["engine"], "angles": v["angles"]} for k, v in doc.get("choices", {}).items()}
+    return dict(cfg, level_options=opts)
+
+
 def _torch():
     import torch
     return torch
@@ -119,12 +132,9 @@ class Context:
 
     def __init__(self, config: Union[str, dict], mem_budget_bytes: int = 0):
         self.lib = load()
-        if isinstance(config, dict):
-            self.cfg = config
-            text = json.dumps(config)
-        else:
-            text = config
-            self.cfg = json.loads(config)
+        cfg = dict(config) if isinstance(config, dict) else json.loads(config)
+        self.cfg = with_tuning(cfg)
+        text = json.dumps(self.cfg)
         h = C.c_void_p()
         rc = self.lib.mlmc_create(text.encode(), mem_budget_bytes, C.byref(h))
         if rc != MLMC_OK:

@@ -50,6 +50,7 @@ struct StripLevel {
   double *modes = nullptr;  // dev [4 nelem][K], sqrt(mu) folded in
   StripPool pool;
   bool small = false;       // solved by the one-work-group-per-sample kernel
+  bool cs = false;          // FP64 angle data stored as (cos 2theta, sin 2theta) pairs
 };
 
 }  // namespace
@@ -79,6 +80,9 @@ struct mlmc_ctx {
   double prof_ms[4] = {0, 0, 0, 0}, prof_bytes[4] = {0, 0, 0, 0};
   int64_t prof_launches[4] = {0, 0, 0, 0};
   std::vector<int> h_iters;
+  // group descriptors of the lock-step launches (device copy + pinned staging)
+  PcgGroup<double> *d_grp64 = nullptr, *h_grp64 = nullptr;
+  PcgGroup<float> *d_grp32 = nullptr, *h_grp32 = nullptr;
 };
 
 namespace {
@@ -172,7 +176,7 @@ size_t strip_mixed_slot_bytes(const StripGeom &g) {
 size_t strip_slot_bytes(const StripGeom &g) {
   const size_t vec = (size_t)2 * g.nnode * sizeof(double);
   return 5 * vec                                      // x, r, p, Ap, dinv
-         + (size_t)4 * g.nelem * sizeof(double)       // theta
+         + (size_t)8 * g.nelem * sizeof(double)       // (cos 2theta, sin 2theta) per Gauss point
          + (size_t)(g.sw_ntiles + 4 * g.nchunks) * sizeof(double)  // partials
          + (size_t)qoi_parts(g) * sizeof(double)      // QoI partial maxima
          + 8 * sizeof(double) + 8 * sizeof(int) + sizeof(int64_t);
@@ -216,7 +220,7 @@ int ensure_pool(mlmc_ctx *c, int level, int n, bool mixed = false) {
   HIPCHK(c, dalloc(&p.p, vec));
   HIPCHK(c, dalloc(&p.Ap, vec));
   HIPCHK(c, dalloc(&p.dinv, vec));
-  HIPCHK(c, dalloc(&p.theta, (size_t)4 * g.nelem * n));
+  HIPCHK(c, dalloc(&p.theta, (size_t)8 * g.nelem * n));
   HIPCHK(c, dalloc(&p.part_pap, (size_t)g.sw_ntiles * n));
   HIPCHK(c, dalloc(&p.part_rz, (size_t)2 * g.nchunks * n));
   HIPCHK(c, dalloc(&p.part_rr, (size_t)2 * g.nchunks * n));
@@ -326,7 +330,9 @@ MixedState mixed_of(mlmc_ctx *c, int level, double rtol) {
   return M;
 }
 
-PcgSlots slots_of(mlmc_ctx *c, int level, const double *theta, double rtol) {
+// FP64 solver state of the level's pool; the angle data is the pool's
+// (cos 2theta, sin 2theta) buffer
+PcgSlots slots_of(mlmc_ctx *c, int level, double rtol) {
   StripPool &p = c->lv[level].pool;
   PcgSlots S{};
   S.x = p.x;
@@ -334,7 +340,8 @@ PcgSlots slots_of(mlmc_ctx *c, int level, const double *theta, double rtol) {
   S.p = p.p;
   S.Ap = p.Ap;
   S.dinv = p.dinv;
-  S.theta = theta;
+  S.theta = p.theta;
+  S.cs = c->lv[level].cs ? 1 : 0;
   S.part_pap = p.part_pap;
   S.part_rz = p.part_rz;
   S.part_rr = p.part_rr;
@@ -352,6 +359,16 @@ PcgSlots slots_of(mlmc_ctx *c, int level, const double *theta, double rtol) {
   return S;
 }
 
+// caller angles [n][4 nelem] into the pool's angle data (copied, or as pairs)
+int stage_angles(mlmc_ctx *c, int level, const double *theta, int n, hipStream_t st) {
+  StripLevel &L = c->lv[level];
+  const size_t ngp = (size_t)n * 4 * L.g.nelem;
+  if (L.cs) launch_theta_cs(theta, L.pool.theta, ngp, st);
+  else HIPCHK(c, hipMemcpyAsync(L.pool.theta, theta, ngp * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipGetLastError());
+  return MLMC_OK;
+}
+
 // largest batch of `level` that fits next to the other pools
 int max_slots(mlmc_ctx *c, int level, bool mixed = false) {
   const StripPool &p = c->lv[level].pool;
@@ -362,30 +379,103 @@ int max_slots(mlmc_ctx *c, int level, bool mixed = false) {
   return (int)std::min<size_t>((c->budget - other) / per, 8192);
 }
 
-// lock-step PCG iterations until every slot of S (n slots) is inactive; the
-// host checks the slot flags every `block` iterations.  prof_k: profile
-// counters (2 per precision) of this solver.
+// one level's batch in a lock-step solve
+template <typename T>
+struct IterGroup {
+  int level;
+  PcgState<T> S;     // the solver state that iterates (FP32 inner state in mixed mode)
+  int n;
+};
+
+template <typename T>
+PcgGroup<T> *dev_groups(mlmc_ctx *c);
+template <>
+PcgGroup<double> *dev_groups<double>(mlmc_ctx *c) { return c->d_grp64; }
+template <>
+PcgGroup<float> *dev_groups<float>(mlmc_ctx *c) { return c->d_grp32; }
+template <typename T>
+PcgGroup<T> *host_groups(mlmc_ctx *c);
+template <>
+PcgGroup<double> *host_groups<double>(mlmc_ctx *c) { return c->h_grp64; }
+template <>
+PcgGroup<float> *host_groups<float>(mlmc_ctx *c) { return c->h_grp32; }
+
+int ensure_host_active(mlmc_ctx *c, int n) {
+  if (c->h_active_cap >= n) return MLMC_OK;
+  if (c->h_active) (void)hipHostFree(c->h_active);
+  c->h_active = nullptr;
+  c->h_active_cap = 0;
+  HIPCHK(c, hipHostMalloc((void **)&c->h_active, sizeof(int) * n));
+  c->h_active_cap = n;
+  return MLMC_OK;
+}
+
+// Lock-step PCG iterations of up to MAX_GROUPS level batches in shared
+// launches (one operator pass and one vector pass per iteration for all of
+// them) until every slot is inactive.  The host checks the slot flags every
+// `block` iterations and drops finished groups from the launch.  extra(k,
+// alive) runs after iteration k.  prof_k: profile counters (2 per precision).
 template <typename T, class Extra>
-int pcg_iterate(mlmc_ctx *c, int level, const PcgState<T> &S, int n, int *active_dev, hipStream_t st, int prof_k,
-                Extra extra) {
-  const StripGeom &g = c->lv[level].g;
+int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t st, int prof_k, Extra extra) {
+  const int ng_all = (int)grp.size();
+  if (ng_all == 0) return MLMC_OK;
+  if (ng_all > MAX_GROUPS) return fail(c, MLMC_EINVAL, "too many level groups in one lock-step solve");
   const int block = 32;
   if (c->prof && c->ev.size() < 3 * block) {
     c->ev.resize(3 * block);
     for (auto &e : c->ev) HIPCHK(c, hipEventCreate(&e));
   }
+  int tot = 0;
+  for (const auto &gr : grp) tot += gr.n;
+  if (int rc = ensure_host_active(c, tot)) return rc;
+  std::vector<char> alive(ng_all, 1);
+  PcgGroup<T> *hg = host_groups<T>(c), *dg = dev_groups<T>(c);
+  int ng = 0, nb2 = 0;
+  int ngm[2] = {0, 0}, nb1m[2] = {0, 0};   // operator-pass groups and blocks per angle mode
+  // compact the live groups into the descriptor array, groups with stored
+  // angles first, then those with stored (cos, sin) pairs (each mode has its
+  // own operator-pass kernel; the vector pass takes all groups).  The staging
+  // buffer is only rewritten after the stream has been synchronised.
+  auto upload = [&]() -> int {
+    ng = nb2 = 0;
+    for (int mode = 0; mode < 2; ++mode) {
+      ngm[mode] = nb1m[mode] = 0;
+      for (int k = 0; k < ng_all; ++k) {
+        if (!alive[k] || (grp[k].S.cs != 0) != (mode == 1)) continue;
+        PcgGroup<T> &D = hg[ng++];
+        D.g = c->lv[grp[k].level].g;
+        D.S = grp[k].S;
+        D.n = grp[k].n;
+        D.blk0 = nb1m[mode];
+        D.cblk0 = nb2;
+        nb1m[mode] += D.g.sw_ntiles * D.n;
+        nb2 += D.g.nchunks * D.n;
+        ngm[mode]++;
+      }
+    }
+    HIPCHK(c, hipMemcpyAsync(dg, hg, sizeof(PcgGroup<T>) * ng, hipMemcpyHostToDevice, st));
+    return MLMC_OK;
+  };
+  if (int rc = upload()) return rc;
   for (long it = 0;; it += block) {
     for (int b = 0; b < block; ++b) {
       const int k = (int)(it + b);
       if (c->prof) HIPCHK(c, hipEventRecord(c->ev[3 * b], st));
-      launch_pcg_pass1<T>(g, c->mat, S, n, k, st);
+      if (ngm[0]) launch_pcg_pass1<T>(dg, ngm[0], nb1m[0], c->mat, k, 0, st);
+      if (ngm[1]) launch_pcg_pass1<T>(dg + ngm[0], ngm[1], nb1m[1], c->mat, k, 1, st);
       if (c->prof) HIPCHK(c, hipEventRecord(c->ev[3 * b + 1], st));
-      launch_pcg_pass2<T>(g, S, n, k, st);
+      launch_pcg_pass2<T>(dg, ng, nb2, k, st);
       if (c->prof) HIPCHK(c, hipEventRecord(c->ev[3 * b + 2], st));
-      extra(k);
+      extra(k, alive);
     }
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(c->h_active, active_dev, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+    int off = 0;
+    for (int g = 0; g < ng_all; ++g) {
+      if (alive[g])
+        HIPCHK(c, hipMemcpyAsync(c->h_active + off, grp[g].S.active, sizeof(int) * grp[g].n, hipMemcpyDeviceToHost,
+                                 st));
+      off += grp[g].n;
+    }
     HIPCHK(c, hipStreamSynchronize(st));
     if (c->prof) {
       for (int b = 0; b < block; ++b) {
@@ -398,30 +488,58 @@ int pcg_iterate(mlmc_ctx *c, int level, const PcgState<T> &S, int n, int *active
       c->prof_launches[prof_k] += block;
       c->prof_launches[prof_k + 1] += block;
     }
-    bool any = false;
-    for (int k = 0; k < n; ++k) any |= c->h_active[k] != 0;
+    bool changed = false, any = false;
+    off = 0;
+    for (int g = 0; g < ng_all; ++g) {
+      if (alive[g]) {
+        bool a = false;
+        for (int k = 0; k < grp[g].n; ++k) a |= c->h_active[off + k] != 0;
+        if (!a) {
+          alive[g] = 0;
+          changed = true;
+        }
+        any |= a;
+      }
+      off += grp[g].n;
+    }
     if (!any) break;
     if (it > (long)c->max_iter + 4 * block) return fail(c, MLMC_EHIP, "PCG loop did not terminate");
+    if (changed)
+      if (int rc = upload()) return rc;
   }
   if (c->prof) {
-    c->h_iters.resize(n);
-    HIPCHK(c, hipMemcpy(c->h_iters.data(), S.it_b, sizeof(int) * n, hipMemcpyDeviceToHost));
-    double its = 0;
-    for (int k = 0; k < n; ++k) its += c->h_iters[k];
-    const double w = sizeof(T);
-    const double wt = (sizeof(T) == 8) ? 32.0 : 8.0;  // angle bytes per element
-    c->prof_bytes[prof_k] += its * (4.0 * 2 * w * g.nnode + wt * g.nelem);
-    c->prof_bytes[prof_k + 1] += its * (8.0 * 2 * w * g.nnode);
+    for (const auto &gr : grp) {
+      const StripGeom &g = c->lv[gr.level].g;
+      c->h_iters.resize(gr.n);
+      HIPCHK(c, hipMemcpyAsync(c->h_iters.data(), gr.S.it_b, sizeof(int) * gr.n, hipMemcpyDeviceToHost, st));
+      HIPCHK(c, hipStreamSynchronize(st));
+      double its = 0;
+      for (int k = 0; k < gr.n; ++k) its += c->h_iters[k];
+      const double w = sizeof(T);
+      const double wt = (sizeof(T) == 8) ? (gr.S.cs ? 64.0 : 32.0) : 8.0;  // angle data bytes per element
+      c->prof_bytes[prof_k] += its * (4.0 * 2 * w * g.nnode + wt * g.nelem);
+      c->prof_bytes[prof_k + 1] += its * (8.0 * 2 * w * g.nnode);
+    }
   }
   return MLMC_OK;
 }
 
-// FP64: set-up + PCG to completion for n slots whose theta is ready
-int run_pcg(mlmc_ctx *c, int level, const PcgSlots &S, int n, hipStream_t st) {
-  const StripGeom &g = c->lv[level].g;
-  launch_setup(g, c->mat, S, n, nullptr, nullptr, st);
+// a level batch whose angles are ready in S.theta
+struct SolveGroup {
+  int level;
+  PcgSlots S;
+  int n;
+};
+
+// FP64: set-up + lock-step PCG to completion for the groups
+int run_pcg(mlmc_ctx *c, const std::vector<SolveGroup> &sg, hipStream_t st) {
+  std::vector<IterGroup<double>> ig;
+  for (const auto &x : sg) {
+    launch_setup(c->lv[x.level].g, c->mat, x.S, x.n, nullptr, nullptr, st);
+    ig.push_back({x.level, x.S, x.n});
+  }
   HIPCHK(c, hipGetLastError());
-  return pcg_iterate<double>(c, level, S, n, S.active, st, 0, [](int) {});
+  return pcg_iterate<double>(c, ig, st, 0, [](int, const std::vector<char> &) {});
 }
 
 // coarse level: set-up + PCG to completion by one work-group per sample, FP64
@@ -435,24 +553,33 @@ int run_small(mlmc_ctx *c, int level, const PcgSlots &S, int n, hipStream_t st) 
 // mixed precision: FP32 PCG (BF16 angles) with reliable updates in FP64 (the
 // residual b - A x recomputed with the FP64 angles whenever the FP32 residual
 // fell by the update factor, and as the only stopping test); x accumulates in
-// FP64.  On return the FP64 pool state holds x.
-int run_mixed(mlmc_ctx *c, int level, const PcgSlots &D, int n, hipStream_t st) {
-  const StripGeom &g = c->lv[level].g;
-  PcgState<float> I = inner_of(c, level);
-  MixedState M = mixed_of(c, level, std::sqrt(D.rtol2));
-  I.rtol2 = D.rtol2;
-  launch_setup(g, c->mat, D, n, M.b, nullptr, st);
-  launch_mixed_start(g, D, I, M, n, st);
+// FP64.  On return the FP64 pool state of every group holds x.
+int run_mixed(mlmc_ctx *c, const std::vector<SolveGroup> &sg, hipStream_t st) {
+  std::vector<IterGroup<float>> ig;
+  std::vector<MixedState> ms;
+  for (const auto &x : sg) {
+    const StripGeom &g = c->lv[x.level].g;
+    PcgState<float> I = inner_of(c, x.level);
+    MixedState M = mixed_of(c, x.level, std::sqrt(x.S.rtol2));
+    I.rtol2 = x.S.rtol2;
+    launch_setup(g, c->mat, x.S, x.n, M.b, nullptr, st);
+    launch_mixed_start(g, x.S, I, M, x.n, st);
+    ig.push_back({x.level, I, x.n});
+    ms.push_back(M);
+  }
   HIPCHK(c, hipGetLastError());
   const int every = c->ru_every;
-  int rc = pcg_iterate<float>(c, level, I, n, I.active, st, 2, [&](int k) {
-    if ((k + 1) % every == 0) {
-      launch_resid64(g, c->mat, D, I, M, n, k, every, st);
-      launch_ru_apply(g, D, I, M, n, k, every, st);
+  int rc = pcg_iterate<float>(c, ig, st, 2, [&](int k, const std::vector<char> &alive) {
+    if ((k + 1) % every != 0) return;
+    for (size_t q = 0; q < sg.size(); ++q) {
+      if (!alive[q]) continue;
+      const StripGeom &g = c->lv[sg[q].level].g;
+      launch_resid64(g, c->mat, sg[q].S, ig[q].S, ms[q], sg[q].n, k, every, st);
+      launch_ru_apply(g, sg[q].S, ig[q].S, ms[q], sg[q].n, k, every, st);
     }
   });
   if (rc) return rc;
-  launch_mixed_flush(g, D, I, n, st);
+  for (size_t q = 0; q < sg.size(); ++q) launch_mixed_flush(c->lv[sg[q].level].g, sg[q].S, ig[q].S, sg[q].n, st);
   HIPCHK(c, hipGetLastError());
   return MLMC_OK;
 }
@@ -483,7 +610,8 @@ int build_strip(mlmc_ctx *c) {
     if (ts != "bf16" && ts != "fp32") throw std::runtime_error("mixed.theta_storage must be bf16 or fp32");
     c->theta_fp32 = ts == "fp32";
   }
-  if (c->ru_every < 1 || c->ru_every > 64) throw std::runtime_error("mixed.update_every must be in 1..64");
+  if (c->ru_every < 1 || 32 % c->ru_every != 0)
+    throw std::runtime_error("mixed.update_every must divide 32 (1, 2, 4, 8, 16 or 32)");
   if (!(c->ru_factor > 0.0 && c->ru_factor < 1.0)) throw std::runtime_error("mixed.update_factor must be in (0, 1)");
   const Json &kl = cfg.at("kl");
   c->K = (int)kl.number("n_modes");
@@ -501,8 +629,33 @@ int build_strip(mlmc_ctx *c) {
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
     throw std::runtime_error("hipDeviceGetAttribute failed");
   const int small_max_nodes = (int)cfg.number_or("small_max_nodes", 1 << 30);
-  for (int l = 0; l < c->nlev; ++l)
-    c->lv[l].small = sm == "auto" && c->lv[l].g.nnode <= small_max_nodes && small_fits(c->lv[l].g, (size_t)lds);
+  // FP64 angle data: stored angles (the solver evaluates cos/sin 2theta every
+  // iteration) or stored (cos 2theta, sin 2theta) pairs (twice the bytes, no
+  // trigonometry in the loop); both give bit-identical results.  Default: pairs
+  // for the coarse levels solved whole per work-group (arithmetic-bound),
+  // angles for the lock-step levels (bandwidth-bound).  "level_options" keyed
+  // by mesh ("NXxNY") overrides engine and angle storage per level.
+  const std::string as = cfg.string_or("angle_storage", "auto");
+  if (as != "auto" && as != "cs" && as != "theta") throw std::runtime_error("angle_storage must be auto, cs or theta");
+  for (int l = 0; l < c->nlev; ++l) {
+    StripLevel &L = c->lv[l];
+    const bool fits = L.g.nnode <= small_max_nodes && small_fits(L.g, (size_t)lds);
+    L.small = sm == "auto" && fits;
+    L.cs = as == "cs" || (as == "auto" && L.small);
+    const std::string key = std::to_string(L.g.nx) + "x" + std::to_string(L.g.ny);
+    if (cfg.has("level_options") && cfg.at("level_options").has(key)) {
+      const Json &o = cfg.at("level_options").at(key);
+      const std::string eng = o.string_or("engine", "");
+      if (eng == "small") L.small = fits;
+      else if (eng == "lockstep") L.small = false;
+      else if (!eng.empty()) throw std::runtime_error("level_options engine must be small or lockstep");
+      const std::string an = o.string_or("angles", "");
+      if (an == "cs") L.cs = true;
+      else if (an == "theta") L.cs = false;
+      else if (!an.empty()) throw std::runtime_error("level_options angles must be cs or theta");
+    }
+    if (sm == "off") L.small = false;   // an explicit "off" wins over per-level options
+  }
   const int K = c->K;
   if (type == "exp_separable") {
     SeparableKL sk = separable_kl(cfg.number("Lx"), cfg.number("Ly"), var, kl.number("corr_x"),
@@ -578,7 +731,11 @@ int mlmc_create(const char *config_json, size_t mem_budget_bytes, mlmc_ctx **out
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) throw std::runtime_error("hipMemGetInfo failed");
     c->budget = mem_budget_bytes ? mem_budget_bytes : (size_t)(0.9 * (double)fr);
     if (hipMalloc((void **)&c->d_stats, 16 * sizeof(double)) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_stats, 16 * sizeof(double)) != hipSuccess)
+        hipHostMalloc((void **)&c->h_stats, 16 * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->d_grp64, MAX_GROUPS * sizeof(PcgGroup<double>)) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_grp64, MAX_GROUPS * sizeof(PcgGroup<double>)) != hipSuccess ||
+        hipMalloc((void **)&c->d_grp32, MAX_GROUPS * sizeof(PcgGroup<float>)) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_grp32, MAX_GROUPS * sizeof(PcgGroup<float>)) != hipSuccess)
       throw std::runtime_error("allocation of the stats buffers failed");
     if (kind == "strip") {
       c->kind = 0;
@@ -617,6 +774,10 @@ void mlmc_destroy(mlmc_ctx *c) {
   if (c->h_active) (void)hipHostFree(c->h_active);
   if (c->d_stats) (void)hipFree(c->d_stats);
   if (c->h_stats) (void)hipHostFree(c->h_stats);
+  if (c->d_grp64) (void)hipFree(c->d_grp64);
+  if (c->h_grp64) (void)hipHostFree(c->h_grp64);
+  if (c->d_grp32) (void)hipFree(c->d_grp32);
+  if (c->h_grp32) (void)hipHostFree(c->h_grp32);
   if (c->plate) plate_destroy(c->plate);
   for (auto &e : c->ev) (void)hipEventDestroy(e);
   delete c;
@@ -685,7 +846,7 @@ int mlmc_sample_field(mlmc_ctx *c, int level, int n, const double *xi, int ld_xi
   if (!xi || !theta) return fail(c, MLMC_EINVAL, "null pointer");
   const StripGeom &g = c->lv[level].g;
   launch_kl_synth(c->lv[level].modes, c->K, g, xi, ld_xi, nullptr, n, dtype == 0 ? (double *)theta : nullptr,
-                  dtype == 1 ? theta : nullptr, 0, 4 * g.nelem, (hipStream_t)stream);
+                  dtype == 1 ? theta : nullptr, 0, 4 * g.nelem, nullptr, (hipStream_t)stream);
   HIPCHK(c, hipGetLastError());
   return MLMC_OK;
 }
@@ -713,7 +874,8 @@ int mlmc_strip_rhs_diag(mlmc_ctx *c, int level, int n, const double *theta, doub
   if (n > max_slots(c, level)) return fail(c, MLMC_ENOMEM, "batch exceeds the memory budget");
   int rc = ensure_pool(c, level, n);
   if (rc) return rc;
-  PcgSlots S = slots_of(c, level, theta, c->rtol);
+  if (int rc2 = stage_angles(c, level, theta, n, (hipStream_t)stream)) return rc2;
+  PcgSlots S = slots_of(c, level, c->rtol);
   launch_setup(c->lv[level].g, c->mat, S, n, b, dinv, (hipStream_t)stream);
   HIPCHK(c, hipGetLastError());
   return MLMC_OK;
@@ -735,18 +897,19 @@ int mlmc_strip_solve_theta(mlmc_ctx *c, int level, int n, const double *theta, d
   int rc = ensure_pool(c, level, n, mixed);
   if (rc) return rc;
   if (info) launch_info_init(info, nullptr, n, st);
-  PcgSlots S = slots_of(c, level, theta, rtol > 0 ? rtol : c->rtol);
+  if ((rc = stage_angles(c, level, theta, n, st))) return rc;
+  PcgSlots S = slots_of(c, level, rtol > 0 ? rtol : c->rtol);
   if (small) {
     rc = run_small(c, level, S, n, st);
   } else if (mixed) {
     launch_to_lo(theta, c->lv[level].pool.theta16, c->theta_fp32, (size_t)n * 4 * c->lv[level].g.nelem, st);
-    rc = run_mixed(c, level, S, n, st);
+    rc = run_mixed(c, {{level, S, n}}, st);
   } else {
-    rc = run_pcg(c, level, S, n, st);
+    rc = run_pcg(c, {{level, S, n}}, st);
   }
   if (rc) return rc;
   launch_qoi(c->lv[level].g, c->mat, report_view(c, level, S, mixed ? MLMC_MIXED : MLMC_FP64), n,
-             c->lv[level].pool.qpart, nullptr, q, info, 0, st);
+             c->lv[level].pool.qpart, nullptr, q, nullptr, info, 1 << 30, st);
   if (d) launch_total_disp(c->lv[level].g, S.x, d, n, st);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(st));
@@ -771,49 +934,76 @@ int mlmc_solve_batch(mlmc_ctx *c, int n_req, const mlmc_request *req, const doub
   const double rt = rtol > 0 ? rtol : c->rtol;
   launch_info_init(info, q_coarse, n_req, st);
   HIPCHK(c, hipGetLastError());
-  // jobs per level: (row, output index) for fine (coarse = 0) and coarse (1) solves
-  std::vector<std::vector<int64_t>> rows(c->nlev * 2);
-  std::vector<std::vector<int>> outs(c->nlev * 2);
+  // jobs per level: the fine solves of its requests and the coarse solves of
+  // coupled requests one level up share the level's slots; output index i
+  // stands for the fine result of request i, n_req + i for its coarse result
+  std::vector<std::vector<int64_t>> rows(c->nlev);
+  std::vector<std::vector<int>> outs(c->nlev);
   for (int i = 0; i < n_req; ++i) {
     const int l = req[i].level;
-    rows[2 * l].push_back(req[i].sample);
-    outs[2 * l].push_back(i);
+    rows[l].push_back(req[i].sample);
+    outs[l].push_back(i);
+  }
+  for (int i = 0; i < n_req; ++i) {
+    const int l = req[i].level;
     if (req[i].coupled && l > 0) {
-      rows[2 * (l - 1) + 1].push_back(req[i].sample);
-      outs[2 * (l - 1) + 1].push_back(i);
+      rows[l - 1].push_back(req[i].sample);
+      outs[l - 1].push_back(n_req + i);
     }
   }
+  // slots per level (coarse levels solved whole per work-group run in FP64 in either precision)
+  std::vector<int> cap(c->nlev, 0), done(c->nlev, 0);
   for (int l = 0; l < c->nlev; ++l) {
-    for (int coarse = 0; coarse < 2; ++coarse) {
-      const auto &R = rows[2 * l + coarse];
-      const auto &O = outs[2 * l + coarse];
-      const int total = (int)R.size();
-      if (!total) continue;
-      // coarse levels solved whole per work-group run in FP64 in either precision
-      const bool mixed = precision == MLMC_MIXED && !c->lv[l].small;
-      const int cap = std::min(max_slots(c, l, mixed), total);
-      if (cap < 1) return fail(c, MLMC_ENOMEM, "level " + std::to_string(l) + ": no slot fits the budget");
-      int rc = ensure_pool(c, l, cap, mixed);
-      if (rc) return rc;
-      StripLevel &L = c->lv[l];
-      for (int off = 0; off < total; off += cap) {
-        const int n = std::min(cap, total - off);
-        HIPCHK(c, hipMemcpyAsync(L.pool.rows, R.data() + off, sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
-        HIPCHK(c, hipMemcpyAsync(L.pool.outidx, O.data() + off, sizeof(int) * n, hipMemcpyHostToDevice, st));
-        launch_kl_synth(L.modes, c->K, L.g, xi, ld_xi, L.pool.rows, n, L.pool.theta, mixed ? L.pool.theta16 : nullptr,
-                        c->theta_fp32, 4 * L.g.nelem, st);
-        PcgSlots S = slots_of(c, l, L.pool.theta, rt);
-        rc = L.small ? run_small(c, l, S, n, st) : mixed ? run_mixed(c, l, S, n, st) : run_pcg(c, l, S, n, st);
-        if (rc) return rc;
-        launch_qoi(L.g, c->mat, report_view(c, l, S, mixed ? MLMC_MIXED : MLMC_FP64), n, L.pool.qpart, L.pool.outidx,
-                   coarse ? q_coarse : q_fine, info, coarse, st);
-        HIPCHK(c, hipGetLastError());
-        // the row/index buffers are reused by the next chunk
-        HIPCHK(c, hipStreamSynchronize(st));
-      }
-    }
+    const int total = (int)rows[l].size();
+    if (!total) continue;
+    const bool mixed = precision == MLMC_MIXED && !c->lv[l].small;
+    cap[l] = std::min(max_slots(c, l, mixed), total);
+    if (cap[l] < 1) return fail(c, MLMC_ENOMEM, "level " + std::to_string(l) + ": no slot fits the budget");
+    if (int rc = ensure_pool(c, l, cap[l], mixed)) return rc;
   }
-  HIPCHK(c, hipStreamSynchronize(st));
+  // rounds: every level with work left takes its next chunk; the coarse levels
+  // run whole per work-group, the others share lock-step launches
+  for (;;) {
+    std::vector<int> lvls, cnt;
+    for (int l = 0; l < c->nlev; ++l)
+      if (done[l] < (int)rows[l].size()) lvls.push_back(l);
+    if (lvls.empty()) break;
+    std::vector<SolveGroup> lock;
+    for (int l : lvls) {
+      StripLevel &L = c->lv[l];
+      const int n = std::min(cap[l], (int)rows[l].size() - done[l]);
+      const bool mixed = precision == MLMC_MIXED && !L.small;
+      HIPCHK(c, hipMemcpyAsync(L.pool.rows, rows[l].data() + done[l], sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
+      HIPCHK(c, hipMemcpyAsync(L.pool.outidx, outs[l].data() + done[l], sizeof(int) * n, hipMemcpyHostToDevice, st));
+      launch_kl_synth(L.modes, c->K, L.g, xi, ld_xi, L.pool.rows, n, L.cs ? nullptr : L.pool.theta,
+                      mixed ? L.pool.theta16 : nullptr, c->theta_fp32, 4 * L.g.nelem, L.cs ? L.pool.theta : nullptr,
+                      st);
+      PcgSlots S = slots_of(c, l, rt);
+      if (L.small) {
+        if (int rc = run_small(c, l, S, n, st)) return rc;
+      } else {
+        lock.push_back({l, S, n});
+      }
+      cnt.push_back(n);
+    }
+    for (size_t k0 = 0; k0 < lock.size(); k0 += MAX_GROUPS) {
+      std::vector<SolveGroup> part(lock.begin() + k0, lock.begin() + std::min(lock.size(), k0 + MAX_GROUPS));
+      const int rc = precision == MLMC_MIXED ? run_mixed(c, part, st) : run_pcg(c, part, st);
+      if (rc) return rc;
+    }
+    for (size_t k = 0; k < lvls.size(); ++k) {
+      const int l = lvls[k];
+      StripLevel &L = c->lv[l];
+      const bool mixed = precision == MLMC_MIXED && !L.small;
+      PcgSlots S = slots_of(c, l, rt);
+      launch_qoi(L.g, c->mat, report_view(c, l, S, mixed ? MLMC_MIXED : MLMC_FP64), cnt[k], L.pool.qpart,
+                 L.pool.outidx, q_fine, q_coarse, info, n_req, st);
+      done[l] += cnt[k];
+    }
+    HIPCHK(c, hipGetLastError());
+    // the row/index buffers are reused by the next round
+    HIPCHK(c, hipStreamSynchronize(st));
+  }
   return MLMC_OK;
 }
 

@@ -77,11 +77,26 @@ struct PcgState {
   // meets the stopping test, records ru[s] = it + 1 and pauses for one iteration
   int mixed;
   int theta_fp32;                  // float solver: angles stored as FP32 instead of bfloat16
+  int cs;                          // FP64 solver: angle data holds (cos 2theta, sin 2theta) pairs
+                                   // [nelem][4][2] (1) or the angles [nelem][4] (0)
   double ru2;
   double *rr_ref;                  // [S] ||r||^2 at the last FP64 residual
   int *ru;                         // [S]
 };
 using PcgSlots = PcgState<double>;
+
+// one level's batch inside a lock-step launch that serves several levels at
+// once (fine and coarse solves of coupled samples, uneven batch sizes): the
+// launch's blocks are laid out group after group
+constexpr int MAX_GROUPS = 4;
+template <typename T>
+struct PcgGroup {
+  StripGeom g;
+  PcgState<T> S;
+  int n;        // slots of the group
+  int blk0;     // first operator-pass block (sweep tiles x slots)
+  int cblk0;    // first vector-pass block (chunks x slots)
+};
 
 // FP64 side of the mixed-precision solver
 struct MixedState {

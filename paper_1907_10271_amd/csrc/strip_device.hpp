@@ -14,14 +14,10 @@ struct QbT {
 };
 using Qb = QbT<double>;
 
-// sin and cos of a small angle from their Taylor series (Horner in x^2): for
-// |x| <= 1 the first omitted terms are below x^19/19! < 1e-17 and x^20/20! <
-// 1e-18, so the result is within a few ulp; larger arguments use sincos().
-__device__ __forceinline__ void sincos_small(double x, double *s, double *c) {
-  if (fabs(x) > 1.0) {
-    sincos(x, s, c);
-    return;
-  }
+// sin and cos from their Taylor series (Horner in x^2): for |x| <= 1 the first
+// omitted terms are below x^19/19! < 1e-17 and x^20/20! < 1e-18, so the result
+// is within a few ulp.
+__device__ __forceinline__ void sincos_poly(double x, double *s, double *c) {
   const double z = x * x;
   double ps = -1.0 / 355687428096000.0;  // -1/17!
   ps = fma(ps, z, 1.0 / 1307674368000.0);
@@ -44,8 +40,48 @@ __device__ __forceinline__ void sincos_small(double x, double *s, double *c) {
   *c = fma(-z, pc, 1.0);                 // 1 - x^2/2! + ...
 }
 
-// Qbar(theta) from the rotation invariants: the fibre axes are turned by +theta
-// from x; entries are linear in cos 2theta, sin 2theta, cos 4theta, sin 4theta.
+// sin and cos of any angle: |x| <= 1 directly; otherwise Cody-Waite reduction
+// by pi/2 (pi/2 split into three doubles, subtracted with FMA) to |r| <= pi/4
+// and the quadrant's sign and swap.  Accurate while k pi/2 is well inside the
+// double range of exact integers (|x| up to ~1e9); non-finite x gives NaN.
+__device__ __forceinline__ void sincos_small(double x, double *s, double *c) {
+  if (fabs(x) <= 1.0) {
+    sincos_poly(x, s, c);
+    return;
+  }
+  constexpr double TWO_OVER_PI = 0.6366197723675814;
+  constexpr double P1 = 1.5707963267948966, P2 = 6.123233995736766e-17, P3 = -1.4973849048591698e-33;
+  const double k = rint(x * TWO_OVER_PI);
+  double r = fma(-k, P1, x);
+  r = fma(-k, P2, r);
+  r = fma(-k, P3, r);
+  double sr, cr;
+  sincos_poly(r, &sr, &cr);
+  const long long qk = isfinite(k) ? (long long)fmod(k, 4.0) : 0;
+  const int q = (int)(qk & 3);
+  const double ss = (q & 1) ? cr : sr, cc = (q & 1) ? sr : cr;
+  *s = (q & 2) ? -ss : ss;
+  *c = ((q + 1) & 2) ? -cc : cc;
+}
+
+// Qbar from c2 = cos 2theta and s2 = sin 2theta (rotation invariants: the
+// fibre axes are turned by +theta from x; entries are linear in cos 2theta,
+// sin 2theta, cos 4theta, sin 4theta)
+__device__ __forceinline__ Qb qbar_cs(const StripMat &m, double s2, double c2) {
+  const double c4 = 2.0 * c2 * c2 - 1.0;
+  const double s4 = 2.0 * s2 * c2;
+  Qb q;
+  q.q11 = m.U1 + m.U2 * c2 + m.U3 * c4;
+  q.q22 = m.U1 - m.U2 * c2 + m.U3 * c4;
+  q.q12 = m.U4 - m.U3 * c4;
+  q.q66 = m.U5 - m.U3 * c4;
+  const double h = 0.5 * m.U2 * s2;
+  q.q16 = h + m.U3 * s4;
+  q.q26 = h - m.U3 * s4;
+  return q;
+}
+
+// Qbar(theta): the same from the angle itself
 __device__ __forceinline__ Qb qbar_of(const StripMat &m, double th) {
   double s2, c2;
   sincos_small(2.0 * th, &s2, &c2);
@@ -60,6 +96,23 @@ __device__ __forceinline__ Qb qbar_of(const StripMat &m, double th) {
   q.q16 = h + m.U3 * s4;
   q.q26 = h - m.U3 * s4;
   return q;
+}
+
+// (cos 2theta, sin 2theta) at the four Gauss points of element e (index within
+// the sample's data `ang`), read as stored pairs (cs != 0) or evaluated from
+// the stored angles
+__device__ __forceinline__ void elem_cs(const double *__restrict__ ang, int cs, size_t e, double2 out[4]) {
+  if (cs) {
+    const double2 *cp = reinterpret_cast<const double2 *>(ang) + 4 * e;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = cp[q];
+  } else {
+    const double2 a = *reinterpret_cast<const double2 *>(ang + 4 * e);
+    const double2 b = *reinterpret_cast<const double2 *>(ang + 4 * e + 2);
+    const double t[4] = {a.x, a.y, b.x, b.y};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sincos_small(2.0 * t[q], &out[q].y, &out[q].x);
+  }
 }
 
 // Element forces f = sum_q w_q detJ B_q^T Qbar_q B_q d_e for one bilinear
@@ -146,8 +199,9 @@ __device__ __forceinline__ float bf16_to_float(uint16_t b) { return __uint_as_fl
 
 // largest compressive stress along the fibres at the four Gauss points:
 // sigma_11 = cos^2 sxx + sin^2 syy + 2 sin cos txy, written with cos 2theta, sin 2theta
+// cs[2q], cs[2q + 1] = cos 2theta, sin 2theta at Gauss point q
 __device__ __forceinline__ double elem_max_fibre_compression(const StripGeom &g, const StripMat &m,
-                                                             const double th[4], const double u[4],
+                                                             const double cs[8], const double u[4],
                                                              const double v[4]) {
   const double P = GP_P, M = GP_M;
   const double dub = u[1] - u[0], dut = u[2] - u[3], dul = u[3] - u[0], dur = u[2] - u[1];
@@ -160,7 +214,8 @@ __device__ __forceinline__ double elem_max_fibre_compression(const StripGeom &g,
   for (int q = 0; q < 4; ++q) {
     const int a = q & 1, b = q >> 1;
     double s2, c2;
-    sincos_small(2.0 * th[q], &s2, &c2);
+    c2 = cs[2 * q];
+    s2 = cs[2 * q + 1];
     const double c4 = 2.0 * c2 * c2 - 1.0, s4 = 2.0 * s2 * c2;
     const double q11 = m.U1 + m.U2 * c2 + m.U3 * c4, q22 = m.U1 - m.U2 * c2 + m.U3 * c4;
     const double q12 = m.U4 - m.U3 * c4, q66 = m.U5 - m.U3 * c4;

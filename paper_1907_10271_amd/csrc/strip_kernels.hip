@@ -77,6 +77,10 @@ __device__ __forceinline__ void gather_node(const double (*eo)[TILE_ELEMS], int 
 // theta[s][gp] = sum_k modes[gp][k] xi[row_s][k] + A sech^2((x_gp - x0)/w)
 // (modes pre-multiplied by sqrt(mu_k)); one thread per Gauss point, a group of
 // SYN_SAMPLES samples per block so the mode row is read once per group.
+// Outputs (each optional): theta in FP64; theta rounded to bfloat16 or FP32;
+// and (cos 2theta, sin 2theta) per Gauss point, which is what the solver's
+// rotated stiffness needs, evaluated once per sample instead of every
+// iteration.
 constexpr int SYN_SAMPLES = 8;
 constexpr int MAX_MODES = 32;
 
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(256) void k_kl_synth(const double *__restrict__ mod
                                                   const double *__restrict__ xi, int ld_xi,
                                                   const int64_t *__restrict__ rows, int n,
                                                   double *__restrict__ th64, void *__restrict__ thlo,
-                                                  int lo_fp32, int ld_out) {
+                                                  int lo_fp32, int ld_out, double *__restrict__ cs) {
   const int ngp = 4 * g.nelem;
   const int gp = blockIdx.x * 256 + threadIdx.x;
   if (gp >= ngp) return;
@@ -109,6 +113,11 @@ __global__ __launch_bounds__(256) void k_kl_synth(const double *__restrict__ mod
       th += A / (c * c);
     }
     if (th64) th64[(size_t)s * ld_out + gp] = th;
+    if (cs) {
+      double s2, c2;
+      sincos_small(2.0 * th, &s2, &c2);
+      *reinterpret_cast<double2 *>(cs + (size_t)s * 2 * ngp + 2 * (size_t)gp) = make_double2(c2, s2);
+    }
     if (thlo) {
       // round to float, then (bfloat16 storage) to bfloat16 with round-to-nearest-even
       const float f = (float)th;
@@ -199,17 +208,18 @@ __global__ __launch_bounds__(TILE_THREADS) void k_apply(StripGeom g, StripMat m,
 __global__ __launch_bounds__(TILE_THREADS) void k_setup(StripGeom g, StripMat m, PcgSlots S,
                                                         double *__restrict__ b_out, double *__restrict__ dinv_out) {
   __shared__ double eo[16][TILE_ELEMS];
-  __shared__ double red4[TILE_WAVES];
   const int s = blockIdx.y, t = blockIdx.x;
   const TileCoord tc = tile_of(g, t);
-  const double *theta_s = (const double *)S.theta + (size_t)s * 4 * g.nelem;
+  const double *ang_s = (const double *)S.theta + (size_t)s * (S.cs ? 8 : 4) * g.nelem;
   for (int k = threadIdx.x; k < TILE_ELEMS; k += TILE_THREADS) {
     const int lex = k % ELEM_X, ley = k / ELEM_X;
     const int ex = tc.i0 - 1 + lex, ey = tc.j0 - 1 + ley;
     double du[4] = {0, 0, 0, 0}, dv[4] = {0, 0, 0, 0}, gu[4] = {0, 0, 0, 0}, gv[4] = {0, 0, 0, 0};
     if (elem_in(g, ex, ey)) {
-      const double *tp = theta_s + 4 * ((size_t)ey * g.nx + ex);
-      Qb q[4] = {qbar_of(m, tp[0]), qbar_of(m, tp[1]), qbar_of(m, tp[2]), qbar_of(m, tp[3])};
+      double2 cp[4];
+      elem_cs(ang_s, S.cs, (size_t)ey * g.nx + ex, cp);
+      Qb q[4] = {qbar_cs(m, cp[0].y, cp[0].x), qbar_cs(m, cp[1].y, cp[1].x), qbar_cs(m, cp[2].y, cp[2].x),
+                 qbar_cs(m, cp[3].y, cp[3].x)};
       // diagonal entries: the element operator applied to unit vectors
       for (int a = 0; a < 4; ++a) {
         double u[4] = {0, 0, 0, 0}, v[4] = {0, 0, 0, 0}, fu[4], fv[4];
@@ -338,33 +348,56 @@ __device__ __forceinline__ RowVals<T> load_row(const StripGeom &g, const PcgStat
   return v;
 }
 
-// the four Gauss-point angles of element (i, ey) and the rotated stiffness at one of them
-template <typename T>
+// the four Gauss-point angles of element (i, ey) and the rotated stiffness at
+// one of them.  FP64: CSM = 1 reads stored (cos 2theta, sin 2theta) pairs
+// (64 B per element), CSM = 0 reads the angles (32 B) and evaluates the pairs
+// one Gauss point at a time; both give the same bits.
+template <typename T, int CSM = 0>
 struct Angles;
 template <>
-struct Angles<double> {
+struct Angles<double, 1> {
+  double2 cs[4];
+  __device__ __forceinline__ void load(const void *theta, size_t eb, const StripGeom &g, int i, bool ok, int ey,
+                                       int = 0) {
+    if (ok && ey >= 0 && ey < g.ny) {
+      const double2 *cp = (const double2 *)theta + 4 * (eb + (size_t)ey * g.nx + i);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cs[q] = cp[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cs[q] = make_double2(1.0, 0.0);
+    }
+  }
+  __device__ __forceinline__ QbT<double> qb(const StripMat &m, int q) const { return qbar_cs(m, cs[q].y, cs[q].x); }
+};
+template <>
+struct Angles<double, 0> {
   double t[4];
   __device__ __forceinline__ void load(const void *theta, size_t eb, const StripGeom &g, int i, bool ok, int ey,
                                        int = 0) {
     t[0] = t[1] = t[2] = t[3] = 0.0;
     if (ok && ey >= 0 && ey < g.ny) {
-      const double *tp = (const double *)theta + eb + 4 * ((size_t)ey * g.nx + i);
+      const double *tp = (const double *)theta + 4 * (eb + (size_t)ey * g.nx + i);
       const double2 a = *reinterpret_cast<const double2 *>(tp);
       const double2 b = *reinterpret_cast<const double2 *>(tp + 2);
       t[0] = a.x; t[1] = a.y; t[2] = b.x; t[3] = b.y;
     }
   }
-  __device__ __forceinline__ QbT<double> qb(const StripMat &m, int q) const { return qbar_of(m, t[q]); }
+  __device__ __forceinline__ QbT<double> qb(const StripMat &m, int q) const {
+    double s2, c2;
+    sincos_small(2.0 * t[q], &s2, &c2);
+    return qbar_cs(m, s2, c2);
+  }
 };
 template <>
-struct Angles<float> {
+struct Angles<float, 0> {
   float t[4];
   // angles stored as bfloat16 (theta_fp32 == 0) or FP32
   __device__ __forceinline__ void load(const void *theta, size_t eb, const StripGeom &g, int i, bool ok, int ey,
                                        int theta_fp32) {
     t[0] = t[1] = t[2] = t[3] = 0.0f;
     if (ok && ey >= 0 && ey < g.ny) {
-      const size_t e = eb + 4 * ((size_t)ey * g.nx + i);
+      const size_t e = 4 * (eb + (size_t)ey * g.nx + i);
       if (theta_fp32) {
         const float4 w = *reinterpret_cast<const float4 *>((const float *)theta + e);
         t[0] = w.x; t[1] = w.y; t[2] = w.z; t[3] = w.w;
@@ -394,14 +427,22 @@ struct Angles<float> {
 // neighbours read p_old in their halos), Ap = A p, partial p.Ap per tile.
 // The next node row is loaded while the current row is computed.  Dot
 // products are accumulated in FP64 for both precisions.
-template <typename T>
-__global__ __launch_bounds__(64) void k_pass1(StripGeom g, StripMat m, PcgState<T> S, int it, int nblocks) {
-  const int lt = xcd_remap(blockIdx.x, nblocks);
+template <typename T, int CSM>
+__global__ __launch_bounds__(64) void k_pass1(const PcgGroup<T> *__restrict__ G, int ng, StripMat m, int it,
+                                             int nblocks) {
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  int gi = 0;
+  for (int k = 1; k < ng; ++k)
+    if (lb >= G[k].blk0) gi = k;
+  gi = __builtin_amdgcn_readfirstlane(gi);
+  const StripGeom g = G[gi].g;
+  const PcgState<T> S = G[gi].S;
+  const int lt = lb - G[gi].blk0;
   const int s = lt / g.sw_ntiles, t = lt - s * g.sw_ntiles;
   const int lane = threadIdx.x;
   const int par = it & 1;
   const size_t vb = (size_t)s * 2 * g.nnode;
-  const size_t eb = (size_t)s * 4 * g.nelem;
+  const size_t eb = (size_t)s * g.nelem;   // first element of the sample
   const int active = __builtin_amdgcn_readfirstlane(S.active[s]);
   const size_t pb = ((size_t)par * S.S + s) * g.nchunks;
   double prz = 0.0, prr = 0.0;
@@ -464,7 +505,7 @@ __global__ __launch_bounds__(64) void k_pass1(StripGeom g, StripMat m, PcgState<
   for (int k = 0; k <= nk; ++k) {
     const int ey = j0 - 1 + k;
     const RowVals<T> hi = nhi;
-    Angles<T> th;
+    Angles<T, CSM> th;
     th.load(S.theta, eb, g, i, elv, ey, S.theta_fp32);
     if (k < nk) nhi = load_row(g, S, vb, i, colv, ey + 2, wp);
     const T phu = fma(beta, hi.qu, hi.zu), phv = fma(beta, hi.qv, hi.zv);
@@ -501,12 +542,19 @@ __global__ __launch_bounds__(64) void k_pass1(StripGeom g, StripMat m, PcgState<
 // r -= alpha Ap; store p; partial r.z (z = dinv r) and r.r per chunk of CHUNK
 // consecutive nodes (all loads issued before the reduction of p.Ap)
 template <typename T>
-__global__ __launch_bounds__(256) void k_pass2(StripGeom g, PcgState<T> S, int it) {
+__global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G, int ng, int it) {
   constexpr int PER = CHUNK / 256;
   using P2 = typename PairOf<T>::type;
   __shared__ double red4[4];
   __shared__ int flag;
-  const int s = blockIdx.y, c = blockIdx.x;
+  int gi = 0;
+  for (int k = 1; k < ng; ++k)
+    if ((int)blockIdx.x >= G[k].cblk0) gi = k;
+  gi = __builtin_amdgcn_readfirstlane(gi);
+  const StripGeom g = G[gi].g;
+  const PcgState<T> S = G[gi].S;
+  const int lb = blockIdx.x - G[gi].cblk0;
+  const int s = lb / g.nchunks, c = lb - s * g.nchunks;
   const int par = it & 1;
   if (threadIdx.x == 0) flag = S.active[s];
   double ppap = 0.0;
@@ -580,7 +628,7 @@ __global__ __launch_bounds__(64) void k_resid64(StripGeom g, StripMat m, PcgSlot
   const int ask = __builtin_amdgcn_readfirstlane(I.ru[s]);
   if (ask < it + 2 - every || ask > it + 1) return;
   const size_t vb = (size_t)s * 2 * g.nnode;
-  const size_t eb = (size_t)s * 4 * g.nelem;
+  const size_t eb = (size_t)s * g.nelem;   // first element of the sample
   const int tx = t % g.sw_ntx, ty = t / g.sw_ntx;
   const int i0 = tx * g.sw_tw, j0 = ty * g.sw_ty;
   const int i = i0 - 1 + lane;
@@ -606,8 +654,12 @@ __global__ __launch_bounds__(64) void k_resid64(StripGeom g, StripMat m, PcgSlot
   for (int k = 0; k <= nk; ++k) {
     const int ey = j0 - 1 + k;
     const double phu = nhu, phv = nhv;
-    Angles<double> th;
-    th.load(D.theta, eb, g, i, elv, ey);
+    double2 csq[4];
+    if (elv && ey >= 0 && ey < g.ny) {
+      elem_cs((const double *)D.theta + (D.cs ? 8 : 4) * eb, D.cs, (size_t)ey * g.nx + i, csq);
+    } else {
+      for (int q = 0; q < 4; ++q) csq[q] = make_double2(1.0, 0.0);
+    }
     if (k < nk) xrow(ey + 2, nhu, nhv);
     const double rlu = __shfl_down(plu, 1, 64), rlv = __shfl_down(plv, 1, 64);
     const double rhu = __shfl_down(phu, 1, 64), rhv = __shfl_down(phv, 1, 64);
@@ -615,7 +667,7 @@ __global__ __launch_bounds__(64) void k_resid64(StripGeom g, StripMat m, PcgSlot
     if (elv && ey >= 0 && ey < g.ny) {
       const double u[4] = {plu, rlu, rhu, phu};
       const double v[4] = {plv, rlv, rhv, phv};
-      elem_forces_q<double>(g, [&](int q) { return th.qb(m, q); }, u, v, fu, fv);
+      elem_forces_q<double>(g, [&](int q) { return qbar_cs(m, csq[q].y, csq[q].x); }, u, v, fu, fv);
     }
     const double f1lu = __shfl_up(fu[1], 1, 64), f1lv = __shfl_up(fv[1], 1, 64);
     if (k >= 1 && own) {
@@ -756,7 +808,7 @@ __global__ __launch_bounds__(256) void k_mixed_flush(StripGeom g, PcgSlots D, Pc
 // ---------------------------------------------------------------- QoI
 // partial max of -sigma_11 over the Gauss points of the QoI-region elements
 // (256 elements per block); final per-slot max written through an index map
-__global__ __launch_bounds__(256) void k_qoi_part(StripGeom g, StripMat m, const double *__restrict__ theta,
+__global__ __launch_bounds__(256) void k_qoi_part(StripGeom g, StripMat m, const double *__restrict__ ang, int csm,
                                                   const double *__restrict__ x, int nparts,
                                                   double *__restrict__ part) {
   __shared__ double red4[4];
@@ -777,22 +829,28 @@ __global__ __launch_bounds__(256) void k_qoi_part(StripGeom g, StripMat m, const
     }
     // prescribed values are not stored in x: u = -delta on the loaded edge
     if (ex + 1 == g.nx) { u[1] = -g.delta; u[2] = -g.delta; }
-    const double *tp = theta + (size_t)s * 4 * g.nelem + 4 * ((size_t)ey * g.nx + ex);
-    const double th[4] = {tp[0], tp[1], tp[2], tp[3]};
-    best = elem_max_fibre_compression(g, m, th, u, v);
+    double2 cp[4];
+    elem_cs(ang + (size_t)s * (csm ? 8 : 4) * g.nelem, csm, (size_t)ey * g.nx + ex, cp);
+    const double c[8] = {cp[0].x, cp[0].y, cp[1].x, cp[1].y, cp[2].x, cp[2].y, cp[3].x, cp[3].y};
+    best = elem_max_fibre_compression(g, m, c, u, v);
   }
   best = block_max(best, red4);
   if (threadIdx.x == 0) part[(size_t)s * nparts + blockIdx.x] = best;
 }
 
+// out_idx[s] < coarse_base: fine result of request out_idx[s]; otherwise the
+// coarse result of request out_idx[s] - coarse_base
 __global__ void k_qoi_final(const double *__restrict__ part, int nparts, int n, const int *__restrict__ out_idx,
-                            double *__restrict__ q, PcgSlots S, mlmc_info_dev *__restrict__ info, int coarse,
-                            double *__restrict__ d_out, int nnode, double delta, int nnx) {
+                            double *__restrict__ q_fine, double *__restrict__ q_coarse, PcgSlots S,
+                            mlmc_info_dev *__restrict__ info, int coarse_base) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   double best = -1.0 / 0.0;
   for (int k = 0; k < nparts; ++k) best = fmax(best, part[(size_t)s * nparts + k]);
-  const int o = out_idx ? out_idx[s] : s;
+  int o = out_idx ? out_idx[s] : s;
+  const bool coarse = o >= coarse_base;
+  if (coarse) o -= coarse_base;
+  double *q = coarse ? q_coarse : q_fine;
   if (q) q[o] = best;
   if (info) {
     if (coarse) {
@@ -898,10 +956,26 @@ __global__ __launch_bounds__(256) void k_level_stats(const double *__restrict__ 
 static inline dim3 tile_grid(const StripGeom &g, int n) { return dim3(g.ntiles, n); }
 
 void launch_kl_synth(const double *modes, int K, const StripGeom &g, const double *xi, int ld_xi,
-                     const int64_t *rows, int n, double *th64, void *thlo, int lo_fp32, int ld_out, hipStream_t st) {
+                     const int64_t *rows, int n, double *th64, void *thlo, int lo_fp32, int ld_out, double *cs,
+                     hipStream_t st) {
   if (n <= 0) return;
   dim3 grid((4 * g.nelem + 255) / 256, (n + SYN_SAMPLES - 1) / SYN_SAMPLES);
-  hipLaunchKernelGGL(k_kl_synth, grid, dim3(256), 0, st, modes, K, g, xi, ld_xi, rows, n, th64, thlo, lo_fp32, ld_out);
+  hipLaunchKernelGGL(k_kl_synth, grid, dim3(256), 0, st, modes, K, g, xi, ld_xi, rows, n, th64, thlo, lo_fp32, ld_out,
+                     cs);
+}
+
+// (cos 2theta, sin 2theta) per Gauss point from given angles
+__global__ void k_theta_cs(const double *__restrict__ th, double *__restrict__ cs, size_t n) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double s2, c2;
+  sincos_small(2.0 * th[k], &s2, &c2);
+  *reinterpret_cast<double2 *>(cs + 2 * k) = make_double2(c2, s2);
+}
+
+void launch_theta_cs(const double *theta, double *cs, size_t n, hipStream_t st) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_theta_cs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, theta, cs, n);
 }
 
 void launch_modes_nystrom(const double *gx, const double *gy, const double *coef, int ngrid, int K, double var,
@@ -924,22 +998,27 @@ void launch_setup(const StripGeom &g, const StripMat &m, const PcgSlots &S, int 
 }
 
 template <typename T>
-void launch_pcg_pass1(const StripGeom &g, const StripMat &m, const PcgState<T> &S, int n, int it, hipStream_t st) {
-  const int nb = g.sw_ntiles * n;
-  hipLaunchKernelGGL(k_pass1<T>, dim3(nb), dim3(64), 0, st, g, m, S, it, nb);
+void launch_pcg_pass1(const PcgGroup<T> *groups, int ng, int nblocks, const StripMat &m, int it, int cs,
+                      hipStream_t st) {
+  if constexpr (sizeof(T) == 8) {
+    if (cs) {
+      hipLaunchKernelGGL((k_pass1<T, 1>), dim3(nblocks), dim3(64), 0, st, groups, ng, m, it, nblocks);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_pass1<T, 0>), dim3(nblocks), dim3(64), 0, st, groups, ng, m, it, nblocks);
 }
 
 template <typename T>
-void launch_pcg_pass2(const StripGeom &g, const PcgState<T> &S, int n, int it, hipStream_t st) {
-  hipLaunchKernelGGL(k_pass2<T>, dim3(g.nchunks, n), dim3(256), 0, st, g, S, it);
+void launch_pcg_pass2(const PcgGroup<T> *groups, int ng, int nblocks, int it, hipStream_t st) {
+  hipLaunchKernelGGL(k_pass2<T>, dim3(nblocks), dim3(256), 0, st, groups, ng, it);
 }
 
-template void launch_pcg_pass1<double>(const StripGeom &, const StripMat &, const PcgState<double> &, int, int,
+template void launch_pcg_pass1<double>(const PcgGroup<double> *, int, int, const StripMat &, int, int,
                                        hipStream_t);
-template void launch_pcg_pass1<float>(const StripGeom &, const StripMat &, const PcgState<float> &, int, int,
-                                      hipStream_t);
-template void launch_pcg_pass2<double>(const StripGeom &, const PcgState<double> &, int, int, hipStream_t);
-template void launch_pcg_pass2<float>(const StripGeom &, const PcgState<float> &, int, int, hipStream_t);
+template void launch_pcg_pass1<float>(const PcgGroup<float> *, int, int, const StripMat &, int, int, hipStream_t);
+template void launch_pcg_pass2<double>(const PcgGroup<double> *, int, int, int, hipStream_t);
+template void launch_pcg_pass2<float>(const PcgGroup<float> *, int, int, int, hipStream_t);
 
 void launch_resid64(const StripGeom &g, const StripMat &m, const PcgSlots &D, const PcgState<float> &I,
                     const MixedState &M, int n, int it, int every, hipStream_t st) {
@@ -964,12 +1043,12 @@ void launch_mixed_flush(const StripGeom &g, const PcgSlots &D, const PcgState<fl
 int qoi_parts(const StripGeom &g) { return ((g.qx1 - g.qx0) * (g.qy1 - g.qy0) + 255) / 256; }
 
 void launch_qoi(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n, double *part, const int *out_idx,
-                double *q, mlmc_info_dev *info, int coarse, hipStream_t st) {
+                double *q_fine, double *q_coarse, mlmc_info_dev *info, int coarse_base, hipStream_t st) {
   if (n <= 0) return;
   const int np = qoi_parts(g);
-  hipLaunchKernelGGL(k_qoi_part, dim3(np, n), dim3(256), 0, st, g, m, (const double *)S.theta, S.x, np, part);
-  hipLaunchKernelGGL(k_qoi_final, dim3((n + 127) / 128), dim3(128), 0, st, part, np, n, out_idx, q, S, info,
-                     coarse, nullptr, g.nnode, g.delta, g.nnx);
+  hipLaunchKernelGGL(k_qoi_part, dim3(np, n), dim3(256), 0, st, g, m, (const double *)S.theta, S.cs, S.x, np, part);
+  hipLaunchKernelGGL(k_qoi_final, dim3((n + 127) / 128), dim3(128), 0, st, part, np, n, out_idx, q_fine, q_coarse,
+                     S, info, coarse_base);
 }
 
 void launch_total_disp(const StripGeom &g, const double *x, double *d, int n, hipStream_t st) {

@@ -8,18 +8,28 @@ namespace mlmc {
 
 using mlmc_info_dev = ::mlmc_info;
 
+// KL synthesis of n samples (parameter rows rows[s], or s); optional outputs:
+// th64 [n][ld_out] FP64 angles, thlo [n][ld_out] bfloat16/FP32 angles, cs
+// [n][4 nelem][2] (cos 2theta, sin 2theta)
 void launch_kl_synth(const double *modes, int K, const StripGeom &g, const double *xi, int ld_xi,
-                     const int64_t *rows, int n, double *th64, void *thlo, int lo_fp32, int ld_out, hipStream_t st);
+                     const int64_t *rows, int n, double *th64, void *thlo, int lo_fp32, int ld_out, double *cs,
+                     hipStream_t st);
+// (cos 2theta, sin 2theta) of n angles
+void launch_theta_cs(const double *theta, double *cs, size_t n, hipStream_t st);
 void launch_modes_nystrom(const double *gx, const double *gy, const double *coef, int ngrid, int K, double var,
                           double kappa, const StripGeom &g, double *modes, hipStream_t st);
 void launch_apply(const StripGeom &g, const StripMat &m, const double *theta, const double *x, double *y, int raw,
                   int n, hipStream_t st);
 void launch_setup(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n, double *b_out, double *dinv_out,
                   hipStream_t st);
+// one lock-step PCG iteration over the groups of a device descriptor array
+// (nblocks = sum of sweep tiles x slots, resp. chunks x slots)
+// (cs: the groups' FP64 angle data holds (cos 2theta, sin 2theta) pairs)
 template <typename T>
-void launch_pcg_pass1(const StripGeom &g, const StripMat &m, const PcgState<T> &S, int n, int it, hipStream_t st);
+void launch_pcg_pass1(const PcgGroup<T> *groups, int ng, int nblocks, const StripMat &m, int it, int cs,
+                      hipStream_t st);
 template <typename T>
-void launch_pcg_pass2(const StripGeom &g, const PcgState<T> &S, int n, int it, hipStream_t st);
+void launch_pcg_pass2(const PcgGroup<T> *groups, int ng, int nblocks, int it, hipStream_t st);
 void launch_resid64(const StripGeom &g, const StripMat &m, const PcgSlots &D, const PcgState<float> &I,
                     const MixedState &M, int n, int it, int every, hipStream_t st);
 void launch_ru_apply(const StripGeom &g, const PcgSlots &D, const PcgState<float> &I, const MixedState &M, int n,
@@ -28,8 +38,10 @@ void launch_mixed_start(const StripGeom &g, const PcgSlots &D, const PcgState<fl
                         hipStream_t st);
 void launch_mixed_flush(const StripGeom &g, const PcgSlots &D, const PcgState<float> &I, int n, hipStream_t st);
 int qoi_parts(const StripGeom &g);
+// QoI of n slots, written through out_idx: entries below coarse_base go to
+// q_fine, the others (minus coarse_base) to q_coarse and the coarse info fields
 void launch_qoi(const StripGeom &g, const StripMat &m, const PcgSlots &S, int n, double *part, const int *out_idx,
-                double *q, mlmc_info_dev *info, int coarse, hipStream_t st);
+                double *q_fine, double *q_coarse, mlmc_info_dev *info, int coarse_base, hipStream_t st);
 void launch_total_disp(const StripGeom &g, const double *x, double *d, int n, hipStream_t st);
 void launch_to_lo(const double *a, void *b, int lo_fp32, size_t n, hipStream_t st);
 void launch_info_init(mlmc_info_dev *info, double *q_coarse, int n, hipStream_t st);

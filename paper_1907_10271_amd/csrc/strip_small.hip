@@ -3,9 +3,9 @@
 // b and the Jacobi diagonal, one work-group owns one sample for every PCG
 // iteration, with the search direction p and the operator output Ap in LDS
 // and x, r and the Jacobi diagonal in registers.
-// Only the Gauss-point angles are read from memory each iteration (they stay
-// in L2), so a coarse level costs FP64 arithmetic instead of HBM traffic and
-// no launch or host round-trip per iteration.
+// Only the Gauss-point (cos 2theta, sin 2theta) pairs are read from memory each
+// iteration (they stay in L2), so a coarse level costs FP64 arithmetic instead
+// of HBM traffic and no launch or host round-trip per iteration.
 //
 // The element loop runs in four colour phases (element (ex, ey) has colour
 // (ex & 1) + 2 (ey & 1)); elements of one colour share no node, so each phase
@@ -32,14 +32,10 @@ __device__ __forceinline__ void elem_nodes(const StripGeom &g, int ex, int ey, i
   nd[3] = n0 + g.nnx;
 }
 
-__device__ __forceinline__ void load_angles(const double *th_s, const StripGeom &g, int ex, int ey, double a[4]) {
-  const double *tp = th_s + 4 * ((size_t)ey * g.nx + ex);
-  const double2 t01 = *reinterpret_cast<const double2 *>(tp);
-  const double2 t23 = *reinterpret_cast<const double2 *>(tp + 2);
-  a[0] = t01.x;
-  a[1] = t01.y;
-  a[2] = t23.x;
-  a[3] = t23.y;
+// (cos 2theta, sin 2theta) at the element's four Gauss points
+__device__ __forceinline__ void load_angles(const double *ang_s, int cs, const StripGeom &g, int ex, int ey,
+                                            double2 a[4]) {
+  elem_cs(ang_s, cs, (size_t)ey * g.nx + ex, a);
 }
 
 // MAXN: owned nodes per thread (node k belongs to thread k mod blockDim)
@@ -50,7 +46,7 @@ __global__ __launch_bounds__(SMALL_MAX_THREADS) void k_small_solve(StripGeom g, 
   double *al = lds + 2 * g.nnode;       // [2 nnode] A p
   double *red = lds + 4 * g.nnode;      // [8] work-group sums
   const int s = blockIdx.x, tid = threadIdx.x, nt = blockDim.x, waves = nt >> 6;
-  const double *th_s = (const double *)S.theta + (size_t)s * 4 * g.nelem;
+  const double *th_s = (const double *)S.theta + (size_t)s * (S.cs ? 8 : 4) * g.nelem;
   const int hx = g.nx / 2, ncol = hx * (g.ny / 2);  // elements per colour
 
   // set-up state from the lifting kernel: r = b, dinv, x = 0
@@ -101,14 +97,14 @@ __global__ __launch_bounds__(SMALL_MAX_THREADS) void k_small_solve(StripGeom g, 
     for (int c = 0; c < 4; ++c) {
       for (int q = tid; q < ncol; q += nt) {
         const int ex = 2 * (q % hx) + (c & 1), ey = 2 * (q / hx) + (c >> 1);
-        double a[4];
-        load_angles(th_s, g, ex, ey, a);
+        double2 a[4];
+        load_angles(th_s, S.cs, g, ex, ey, a);
         int nd[4];
         elem_nodes(g, ex, ey, nd);
         const double u[4] = {pl[2 * nd[0]], pl[2 * nd[1]], pl[2 * nd[2]], pl[2 * nd[3]]};
         const double v[4] = {pl[2 * nd[0] + 1], pl[2 * nd[1] + 1], pl[2 * nd[2] + 1], pl[2 * nd[3] + 1]};
         double fu[4], fv[4];
-        elem_forces_q<double>(g, [&](int k) { return qbar_of(m, a[k]); }, u, v, fu, fv);
+        elem_forces_q<double>(g, [&](int k) { return qbar_cs(m, a[k].y, a[k].x); }, u, v, fu, fv);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           al[2 * nd[k]] += fu[k];

@@ -245,7 +245,10 @@ def test_coarse_levels_use_the_whole_solve_kernel(name, level):
     """Coarse levels run one work-group per sample (no lock-step PCG launches);
     both engines agree to the tight-tolerance bar and the whole-solve kernel
     reports the same iteration counts within rounding."""
-    ctx = context(name)
+    import paper_1907_10271_amd as pk
+    cfg = mi.load_config(name)
+    key = f"{cfg['nx0'] << level}x{cfg['ny0'] << level}"
+    ctx = pk.Context(dict(cfg, level_options={key: {"engine": "small"}}))
     lock = context(name, "lockstep")
     xi = dev(_rows(name, level, 5))
     reqs = [(k, level, False) for k in range(5)]
@@ -262,6 +265,27 @@ def test_coarse_levels_use_the_whole_solve_kernel(name, level):
     assert np.max(np.abs(qa - qb) / np.abs(qb)) <= 1e-10
     assert np.all(np.abs(ia["iters_f"].astype(int) - ib["iters_f"].astype(int)) <= 2)
     # mixed precision on a coarse level runs the FP64 whole-solve kernel
-    import paper_1907_10271_amd as pk
     qm, _, im = ctx.solve_batch(reqs, xi, precision=pk.MIXED, rtol=1e-13)
     assert np.array_equal(qm.cpu().numpy(), qa)
+    ctx.close()
+
+
+@pytest.mark.parametrize("engine", ["small", "lockstep"])
+def test_angle_storage_gives_identical_bits(engine):
+    """Stored (cos 2theta, sin 2theta) pairs and stored angles evaluated in the
+    loop are the same arithmetic: every result is bit-identical."""
+    import paper_1907_10271_amd as pk
+    name, level = "strip_c2", 1
+    cfg = mi.load_config(name)
+    key = f"{cfg['nx0'] << level}x{cfg['ny0'] << level}"
+    xi = dev(_rows(name, level, 6))
+    reqs = [(k, level, True) for k in range(6)]
+    out = []
+    for angles in ("theta", "cs"):
+        c = pk.Context(dict(cfg, level_options={key: {"engine": engine, "angles": angles},
+                                                "64x16": {"engine": engine, "angles": angles}}))
+        qf, qc, info = c.solve_batch(reqs, xi)
+        out.append((qf.cpu().numpy(), qc.cpu().numpy(), info["iters_f"].copy()))
+        c.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][2], out[1][2])
