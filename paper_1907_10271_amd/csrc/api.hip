@@ -83,6 +83,17 @@ struct mlmc_ctx {
   // group descriptors of the lock-step launches (device copy + pinned staging)
   PcgGroup<double> *d_grp64 = nullptr, *h_grp64 = nullptr;
   PcgGroup<float> *d_grp32 = nullptr, *h_grp32 = nullptr;
+  // graph replay of iteration blocks: capture stream, device iteration base,
+  // and instantiated graphs keyed by the launch configuration they captured
+  bool graphs = true;
+  hipStream_t cap_stream = nullptr;
+  int *d_itb = nullptr;
+  struct CachedGraph {
+    std::vector<char> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<CachedGraph> gcache;
 };
 
 namespace {
@@ -414,9 +425,13 @@ int ensure_host_active(mlmc_ctx *c, int n) {
 // launches (one operator pass and one vector pass per iteration for all of
 // them) until every slot is inactive.  The host checks the slot flags every
 // `block` iterations and drops finished groups from the launch.  extra(k,
-// alive) runs after iteration k.  prof_k: profile counters (2 per precision).
+// alive, itb, stream) launches what runs after iteration k.  prof_k: profile
+// counters (2 per precision).  Unless profiling, a block of iterations is
+// captured once as a graph (keyed by its launch configuration and `sig`, the
+// bytes of any arguments `extra` bakes in) and replayed.
 template <typename T, class Extra>
-int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t st, int prof_k, Extra extra) {
+int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t st, int prof_k, Extra extra,
+                const std::vector<char> &sig = {}) {
   const int ng_all = (int)grp.size();
   if (ng_all == 0) return MLMC_OK;
   if (ng_all > MAX_GROUPS) return fail(c, MLMC_EINVAL, "too many level groups in one lock-step solve");
@@ -457,16 +472,65 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
     return MLMC_OK;
   };
   if (int rc = upload()) return rc;
-  for (long it = 0;; it += block) {
+  // one block of iterations: kernel launches for iterations base + 0..block-1
+  // (itb null: `base` is passed directly; otherwise it is read from *itb)
+  auto launch_block = [&](int base, const int *itb, hipStream_t s, bool timed) -> int {
     for (int b = 0; b < block; ++b) {
-      const int k = (int)(it + b);
-      if (c->prof) HIPCHK(c, hipEventRecord(c->ev[3 * b], st));
-      if (ngm[0]) launch_pcg_pass1<T>(dg, ngm[0], nb1m[0], c->mat, k, 0, st);
-      if (ngm[1]) launch_pcg_pass1<T>(dg + ngm[0], ngm[1], nb1m[1], c->mat, k, 1, st);
-      if (c->prof) HIPCHK(c, hipEventRecord(c->ev[3 * b + 1], st));
-      launch_pcg_pass2<T>(dg, ng, nb2, k, st);
-      if (c->prof) HIPCHK(c, hipEventRecord(c->ev[3 * b + 2], st));
-      extra(k, alive);
+      const int k = base + b;
+      if (timed) HIPCHK(c, hipEventRecord(c->ev[3 * b], s));
+      if (ngm[0]) launch_pcg_pass1<T>(dg, ngm[0], nb1m[0], c->mat, k, 0, itb, s);
+      if (ngm[1]) launch_pcg_pass1<T>(dg + ngm[0], ngm[1], nb1m[1], c->mat, k, 1, itb, s);
+      if (timed) HIPCHK(c, hipEventRecord(c->ev[3 * b + 1], s));
+      launch_pcg_pass2<T>(dg, ng, nb2, k, itb, s);
+      if (timed) HIPCHK(c, hipEventRecord(c->ev[3 * b + 2], s));
+      extra(k, alive, itb, s);
+    }
+    return MLMC_OK;
+  };
+  // graph replay (not while profiling: the passes are then timed one by one)
+  const bool use_graph = c->graphs && !c->prof;
+  hipGraphExec_t exec = nullptr;
+  auto prepare_graph = [&]() -> int {
+    std::vector<char> key(sig.begin(), sig.end());
+    auto put = [&](const void *p, size_t n) { key.insert(key.end(), (const char *)p, (const char *)p + n); };
+    const int tsz = (int)sizeof(T);
+    put(&tsz, sizeof tsz);
+    put(ngm, sizeof ngm);
+    put(nb1m, sizeof nb1m);
+    put(&nb2, sizeof nb2);
+    for (char a : alive) key.push_back(a);
+    for (auto &e : c->gcache)
+      if (e.key == key) {
+        exec = e.exec;
+        return MLMC_OK;
+      }
+    mlmc_ctx::CachedGraph e;
+    e.key = key;
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = launch_block(0, c->d_itb, c->cap_stream, false);
+    launch_add_int(c->d_itb, block, c->cap_stream);
+    const hipError_t ec = hipStreamEndCapture(c->cap_stream, &e.graph);
+    if (rc) return rc;
+    HIPCHK(c, ec);
+    HIPCHK(c, hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0));
+    if (c->gcache.size() >= 16) {
+      (void)hipGraphExecDestroy(c->gcache.front().exec);
+      (void)hipGraphDestroy(c->gcache.front().graph);
+      c->gcache.erase(c->gcache.begin());
+    }
+    c->gcache.push_back(e);
+    exec = e.exec;
+    return MLMC_OK;
+  };
+  if (use_graph) {
+    launch_set_int(c->d_itb, 0, st);
+    if (int rc = prepare_graph()) return rc;
+  }
+  for (long it = 0;; it += block) {
+    if (use_graph) {
+      HIPCHK(c, hipGraphLaunch(exec, st));
+    } else {
+      if (int rc = launch_block((int)it, nullptr, st, c->prof)) return rc;
     }
     HIPCHK(c, hipGetLastError());
     int off = 0;
@@ -504,8 +568,11 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
     }
     if (!any) break;
     if (it > (long)c->max_iter + 4 * block) return fail(c, MLMC_EHIP, "PCG loop did not terminate");
-    if (changed)
+    if (changed) {
       if (int rc = upload()) return rc;
+      if (use_graph)
+        if (int rc = prepare_graph()) return rc;
+    }
   }
   if (c->prof) {
     for (const auto &gr : grp) {
@@ -539,7 +606,7 @@ int run_pcg(mlmc_ctx *c, const std::vector<SolveGroup> &sg, hipStream_t st) {
     ig.push_back({x.level, x.S, x.n});
   }
   HIPCHK(c, hipGetLastError());
-  return pcg_iterate<double>(c, ig, st, 0, [](int, const std::vector<char> &) {});
+  return pcg_iterate<double>(c, ig, st, 0, [](int, const std::vector<char> &, const int *, hipStream_t) {});
 }
 
 // coarse level: set-up + PCG to completion by one work-group per sample, FP64
@@ -569,15 +636,28 @@ int run_mixed(mlmc_ctx *c, const std::vector<SolveGroup> &sg, hipStream_t st) {
   }
   HIPCHK(c, hipGetLastError());
   const int every = c->ru_every;
-  int rc = pcg_iterate<float>(c, ig, st, 2, [&](int k, const std::vector<char> &alive) {
-    if ((k + 1) % every != 0) return;
-    for (size_t q = 0; q < sg.size(); ++q) {
-      if (!alive[q]) continue;
-      const StripGeom &g = c->lv[sg[q].level].g;
-      launch_resid64(g, c->mat, sg[q].S, ig[q].S, ms[q], sg[q].n, k, every, st);
-      launch_ru_apply(g, sg[q].S, ig[q].S, ms[q], sg[q].n, k, every, st);
-    }
-  });
+  // the graph key covers the per-group arguments the reliable-update launches bake in
+  std::vector<char> sig;
+  auto put = [&](const void *p, size_t n) { sig.insert(sig.end(), (const char *)p, (const char *)p + n); };
+  put(&every, sizeof every);
+  for (size_t q = 0; q < sg.size(); ++q) {
+    put(&sg[q].S, sizeof(PcgSlots));
+    put(&ig[q].S, sizeof(PcgState<float>));
+    put(&ms[q], sizeof(MixedState));
+    put(&sg[q].n, sizeof(int));
+  }
+  int rc = pcg_iterate<float>(
+      c, ig, st, 2,
+      [&](int k, const std::vector<char> &alive, const int *itb, hipStream_t s) {
+        if ((k + 1) % every != 0) return;
+        for (size_t q = 0; q < sg.size(); ++q) {
+          if (!alive[q]) continue;
+          const StripGeom &g = c->lv[sg[q].level].g;
+          launch_resid64(g, c->mat, sg[q].S, ig[q].S, ms[q], sg[q].n, k, every, itb, s);
+          launch_ru_apply(g, sg[q].S, ig[q].S, ms[q], sg[q].n, k, every, itb, s);
+        }
+      },
+      sig);
   if (rc) return rc;
   for (size_t q = 0; q < sg.size(); ++q) launch_mixed_flush(c->lv[sg[q].level].g, sg[q].S, ig[q].S, sg[q].n, st);
   HIPCHK(c, hipGetLastError());
@@ -623,6 +703,10 @@ int build_strip(mlmc_ctx *c) {
   // coarse levels whose PCG state fits one work-group's LDS are solved whole
   // by one work-group per sample ("small_solver": "auto" or "off"); the
   // choice depends on the level only, never on the batch
+  if (cfg.has("graphs")) {
+    if (cfg.at("graphs").type != Json::Bool) throw std::runtime_error("graphs must be true or false");
+    c->graphs = cfg.at("graphs").b;
+  }
   const std::string sm = cfg.string_or("small_solver", "auto");
   if (sm != "auto" && sm != "off") throw std::runtime_error("small_solver must be auto or off");
   int lds = 0;
@@ -735,7 +819,9 @@ int mlmc_create(const char *config_json, size_t mem_budget_bytes, mlmc_ctx **out
         hipMalloc((void **)&c->d_grp64, MAX_GROUPS * sizeof(PcgGroup<double>)) != hipSuccess ||
         hipHostMalloc((void **)&c->h_grp64, MAX_GROUPS * sizeof(PcgGroup<double>)) != hipSuccess ||
         hipMalloc((void **)&c->d_grp32, MAX_GROUPS * sizeof(PcgGroup<float>)) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_grp32, MAX_GROUPS * sizeof(PcgGroup<float>)) != hipSuccess)
+        hipHostMalloc((void **)&c->h_grp32, MAX_GROUPS * sizeof(PcgGroup<float>)) != hipSuccess ||
+        hipMalloc((void **)&c->d_itb, sizeof(int)) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
       throw std::runtime_error("allocation of the stats buffers failed");
     if (kind == "strip") {
       c->kind = 0;
@@ -778,6 +864,12 @@ void mlmc_destroy(mlmc_ctx *c) {
   if (c->h_grp64) (void)hipHostFree(c->h_grp64);
   if (c->d_grp32) (void)hipFree(c->d_grp32);
   if (c->h_grp32) (void)hipHostFree(c->h_grp32);
+  for (auto &e : c->gcache) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+  }
+  if (c->d_itb) (void)hipFree(c->d_itb);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->plate) plate_destroy(c->plate);
   for (auto &e : c->ev) (void)hipEventDestroy(e);
   delete c;

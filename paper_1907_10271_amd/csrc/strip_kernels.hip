@@ -428,8 +428,9 @@ struct Angles<float, 0> {
 // The next node row is loaded while the current row is computed.  Dot
 // products are accumulated in FP64 for both precisions.
 template <typename T, int CSM>
-__global__ __launch_bounds__(64) void k_pass1(const PcgGroup<T> *__restrict__ G, int ng, StripMat m, int it,
-                                             int nblocks) {
+__global__ __launch_bounds__(64) void k_pass1(const PcgGroup<T> *__restrict__ G, int ng, StripMat m, int it_off,
+                                             int nblocks, const int *__restrict__ itb) {
+  const int it = itb ? __builtin_amdgcn_readfirstlane(*itb) + it_off : it_off;
   const int lb = xcd_remap(blockIdx.x, nblocks);
   int gi = 0;
   for (int k = 1; k < ng; ++k)
@@ -542,7 +543,9 @@ __global__ __launch_bounds__(64) void k_pass1(const PcgGroup<T> *__restrict__ G,
 // r -= alpha Ap; store p; partial r.z (z = dinv r) and r.r per chunk of CHUNK
 // consecutive nodes (all loads issued before the reduction of p.Ap)
 template <typename T>
-__global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G, int ng, int it) {
+__global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G, int ng, int it_off,
+                                              const int *__restrict__ itb) {
+  const int it = itb ? __builtin_amdgcn_readfirstlane(*itb) + it_off : it_off;
   constexpr int PER = CHUNK / 256;
   using P2 = typename PairOf<T>::type;
   __shared__ double red4[4];
@@ -620,7 +623,8 @@ __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G
 // residual r = b - A (x64 + x32) with the FP64 angles (column sweep as in
 // pass 1, node values = x), partial ||r||^2 per sweep tile.
 __global__ __launch_bounds__(64) void k_resid64(StripGeom g, StripMat m, PcgSlots D, PcgState<float> I, MixedState M,
-                                                int it, int every, int nblocks) {
+                                                int it_off, int every, int nblocks, const int *__restrict__ itb) {
+  const int it = itb ? __builtin_amdgcn_readfirstlane(*itb) + it_off : it_off;
   const int lt = xcd_remap(blockIdx.x, nblocks);
   const int s = lt / g.sw_ntiles, t = lt - s * g.sw_ntiles;
   const int lane = threadIdx.x;
@@ -695,8 +699,9 @@ __global__ __launch_bounds__(64) void k_resid64(StripGeom g, StripMat m, PcgSlot
 // Second half of a reliable update: x64 += x32, x32 = 0, r32 = r64; the FP64
 // stopping test ||r|| <= rtol ||b||; the inner partial sums for the next
 // iteration (parity of it + 1) and the slot's restart.
-__global__ __launch_bounds__(256) void k_ru_apply(StripGeom g, PcgSlots D, PcgState<float> I, MixedState M, int it,
-                                                  int every) {
+__global__ __launch_bounds__(256) void k_ru_apply(StripGeom g, PcgSlots D, PcgState<float> I, MixedState M, int it_off,
+                                                  int every, const int *__restrict__ itb) {
+  const int it = itb ? __builtin_amdgcn_readfirstlane(*itb) + it_off : it_off;
   __shared__ double red4[4];
   __shared__ int flag;
   const int s = blockIdx.y, c = blockIdx.x;
@@ -999,37 +1004,49 @@ void launch_setup(const StripGeom &g, const StripMat &m, const PcgSlots &S, int 
 
 template <typename T>
 void launch_pcg_pass1(const PcgGroup<T> *groups, int ng, int nblocks, const StripMat &m, int it, int cs,
-                      hipStream_t st) {
+                      const int *itb, hipStream_t st) {
   if constexpr (sizeof(T) == 8) {
     if (cs) {
-      hipLaunchKernelGGL((k_pass1<T, 1>), dim3(nblocks), dim3(64), 0, st, groups, ng, m, it, nblocks);
+      hipLaunchKernelGGL((k_pass1<T, 1>), dim3(nblocks), dim3(64), 0, st, groups, ng, m, it, nblocks, itb);
       return;
     }
   }
-  hipLaunchKernelGGL((k_pass1<T, 0>), dim3(nblocks), dim3(64), 0, st, groups, ng, m, it, nblocks);
+  hipLaunchKernelGGL((k_pass1<T, 0>), dim3(nblocks), dim3(64), 0, st, groups, ng, m, it, nblocks, itb);
 }
 
 template <typename T>
-void launch_pcg_pass2(const PcgGroup<T> *groups, int ng, int nblocks, int it, hipStream_t st) {
-  hipLaunchKernelGGL(k_pass2<T>, dim3(nblocks), dim3(256), 0, st, groups, ng, it);
+void launch_pcg_pass2(const PcgGroup<T> *groups, int ng, int nblocks, int it, const int *itb, hipStream_t st) {
+  hipLaunchKernelGGL(k_pass2<T>, dim3(nblocks), dim3(256), 0, st, groups, ng, it, itb);
 }
 
-template void launch_pcg_pass1<double>(const PcgGroup<double> *, int, int, const StripMat &, int, int,
+template void launch_pcg_pass1<double>(const PcgGroup<double> *, int, int, const StripMat &, int, int, const int *,
                                        hipStream_t);
-template void launch_pcg_pass1<float>(const PcgGroup<float> *, int, int, const StripMat &, int, int, hipStream_t);
-template void launch_pcg_pass2<double>(const PcgGroup<double> *, int, int, int, hipStream_t);
-template void launch_pcg_pass2<float>(const PcgGroup<float> *, int, int, int, hipStream_t);
+template void launch_pcg_pass1<float>(const PcgGroup<float> *, int, int, const StripMat &, int, int, const int *,
+                                      hipStream_t);
+template void launch_pcg_pass2<double>(const PcgGroup<double> *, int, int, int, const int *, hipStream_t);
+template void launch_pcg_pass2<float>(const PcgGroup<float> *, int, int, int, const int *, hipStream_t);
 
 void launch_resid64(const StripGeom &g, const StripMat &m, const PcgSlots &D, const PcgState<float> &I,
-                    const MixedState &M, int n, int it, int every, hipStream_t st) {
+                    const MixedState &M, int n, int it, int every, const int *itb, hipStream_t st) {
   const int nb = g.sw_ntiles * n;
-  hipLaunchKernelGGL(k_resid64, dim3(nb), dim3(64), 0, st, g, m, D, I, M, it, every, nb);
+  hipLaunchKernelGGL(k_resid64, dim3(nb), dim3(64), 0, st, g, m, D, I, M, it, every, nb, itb);
 }
 
 void launch_ru_apply(const StripGeom &g, const PcgSlots &D, const PcgState<float> &I, const MixedState &M, int n,
-                     int it, int every, hipStream_t st) {
-  hipLaunchKernelGGL(k_ru_apply, dim3(g.nchunks, n), dim3(256), 0, st, g, D, I, M, it, every);
+                     int it, int every, const int *itb, hipStream_t st) {
+  hipLaunchKernelGGL(k_ru_apply, dim3(g.nchunks, n), dim3(256), 0, st, g, D, I, M, it, every, itb);
 }
+
+// iteration base of graph-replayed blocks: set, and advance after a block
+__global__ void k_set_int(int *p, int v) {
+  if (threadIdx.x == 0) *p = v;
+}
+__global__ void k_add_int(int *p, int v) {
+  if (threadIdx.x == 0) *p += v;
+}
+
+void launch_set_int(int *p, int v, hipStream_t st) { hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, p, v); }
+void launch_add_int(int *p, int v, hipStream_t st) { hipLaunchKernelGGL(k_add_int, dim3(1), dim3(64), 0, st, p, v); }
 
 void launch_mixed_start(const StripGeom &g, const PcgSlots &D, const PcgState<float> &I, const MixedState &M, int n,
                         hipStream_t st) {

@@ -24,16 +24,21 @@ void launch_setup(const StripGeom &g, const StripMat &m, const PcgSlots &S, int 
                   hipStream_t st);
 // one lock-step PCG iteration over the groups of a device descriptor array
 // (nblocks = sum of sweep tiles x slots, resp. chunks x slots)
-// (cs: the groups' FP64 angle data holds (cos 2theta, sin 2theta) pairs)
+// (cs: the groups' FP64 angle data holds (cos 2theta, sin 2theta) pairs).
+// The iteration index is `it`, or *itb + it when itb is not null (graph
+// replay: the captured launches carry offsets, the base lives on the device).
 template <typename T>
 void launch_pcg_pass1(const PcgGroup<T> *groups, int ng, int nblocks, const StripMat &m, int it, int cs,
-                      hipStream_t st);
+                      const int *itb, hipStream_t st);
 template <typename T>
-void launch_pcg_pass2(const PcgGroup<T> *groups, int ng, int nblocks, int it, hipStream_t st);
+void launch_pcg_pass2(const PcgGroup<T> *groups, int ng, int nblocks, int it, const int *itb, hipStream_t st);
 void launch_resid64(const StripGeom &g, const StripMat &m, const PcgSlots &D, const PcgState<float> &I,
-                    const MixedState &M, int n, int it, int every, hipStream_t st);
+                    const MixedState &M, int n, int it, int every, const int *itb, hipStream_t st);
 void launch_ru_apply(const StripGeom &g, const PcgSlots &D, const PcgState<float> &I, const MixedState &M, int n,
-                     int it, int every, hipStream_t st);
+                     int it, int every, const int *itb, hipStream_t st);
+// *p = v and *p += v by one thread (kernel nodes, so they can be captured)
+void launch_set_int(int *p, int v, hipStream_t st);
+void launch_add_int(int *p, int v, hipStream_t st);
 void launch_mixed_start(const StripGeom &g, const PcgSlots &D, const PcgState<float> &I, const MixedState &M, int n,
                         hipStream_t st);
 void launch_mixed_flush(const StripGeom &g, const PcgSlots &D, const PcgState<float> &I, int n, hipStream_t st);

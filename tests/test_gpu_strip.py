@@ -289,3 +289,31 @@ def test_angle_storage_gives_identical_bits(engine):
         c.close()
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
     assert np.array_equal(out[0][2], out[1][2])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_matches_direct_launches(precision):
+    """Iteration blocks replayed from captured graphs give the same bits as
+    direct launches, across consecutive solves of different sizes (graph cache
+    hits and re-captures), and the iteration limit still holds."""
+    import paper_1907_10271_amd as pk
+    name = "strip_c2"
+    cfg = mi.load_config(name)
+    lock = {"64x16": {"engine": "lockstep"}, "128x32": {"engine": "lockstep"}}
+    a = pk.Context(dict(cfg, graphs=True, level_options=lock))
+    b = pk.Context(dict(cfg, graphs=False, level_options=lock))
+    for n, level in ((5, 2), (3, 2), (7, 1), (2, 3)):
+        xi = dev(_rows(name, level, n))
+        reqs = [(k, level, k % 2 == 0) for k in range(n)]
+        qa, qca, ia = a.solve_batch(reqs, xi, precision=precision)
+        qb, qcb, ib = b.solve_batch(reqs, xi, precision=precision)
+        assert np.array_equal(qa.cpu().numpy(), qb.cpu().numpy()), (n, level)
+        assert np.array_equal(qca.cpu().numpy(), qcb.cpu().numpy()), (n, level)
+        assert np.array_equal(ia["iters_f"], ib["iters_f"]) and np.all(ia["status_f"] == 0)
+    c = pk.Context(dict(cfg, graphs=True, max_iter=5, level_options=lock))
+    _, _, info = c.solve_batch([(0, 2, False)], dev(_rows(name, 2, 1)), precision=precision)
+    assert info[0]["status_f"] == 1
+    if precision == 0:
+        assert info[0]["iters_f"] == 5
+    for x in (a, b, c):
+        x.close()
