@@ -85,7 +85,7 @@ struct mlmc_ctx {
   PcgGroup<float> *d_grp32 = nullptr, *h_grp32 = nullptr;
   // graph replay of iteration blocks: capture stream, device iteration base,
   // and instantiated graphs keyed by the launch configuration they captured
-  bool graphs = true;
+  bool graphs = false;      // measured: no gain on MI355X (iterations are GPU-bound), so off by default
   hipStream_t cap_stream = nullptr;
   int *d_itb = nullptr;
   struct CachedGraph {

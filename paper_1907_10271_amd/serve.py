@@ -274,8 +274,8 @@ def serve_sweep(serve_cfg: dict, precision: int = FP64, rates=None, duration_s: 
     """The request stream of a serving configuration at each arrival rate: Poisson
     arrivals, kinds and levels drawn from the configured mix."""
     import mlmc_inputs as mi
-    strip_cfg = mi.load_config(serve_cfg["strip_config"])
-    plate_cfg = mi.load_config(serve_cfg["plate_config"])
+    strip_cfg = dict(mi.load_config(serve_cfg["strip_config"]), **serve_cfg.get("strip_overrides", {}))
+    plate_cfg = dict(mi.load_config(serve_cfg["plate_config"]), **serve_cfg.get("plate_overrides", {}))
     rates = rates or serve_cfg["rates"]
     dur = duration_s or serve_cfg["duration_s"]
     out = []
