@@ -503,12 +503,22 @@ __global__ __launch_bounds__(64) void k_pass1(const PcgGroup<T> *__restrict__ G,
   T f2u = 0, f2v = 0, f3u = 0, f3v = 0;  // previous element row: f2 of the left lane, own f3
   double part = 0.0;
   const int nk = row_end - j0;
+  // FP64 angles of the next element row are loaded one row ahead (not the
+  // pairs: they would cost the fourth wave per SIMD; not the FP32 solver's
+  // BF16 angles: measured slower)
+  constexpr bool ahead = CSM == 0 && sizeof(T) == 8;
+  Angles<T, CSM> nth;
+  if (ahead) nth.load(S.theta, eb, g, i, elv, j0 - 1, S.theta_fp32);
   for (int k = 0; k <= nk; ++k) {
     const int ey = j0 - 1 + k;
     const RowVals<T> hi = nhi;
     Angles<T, CSM> th;
-    th.load(S.theta, eb, g, i, elv, ey, S.theta_fp32);
-    if (k < nk) nhi = load_row(g, S, vb, i, colv, ey + 2, wp);
+    if (ahead) th = nth;
+    else th.load(S.theta, eb, g, i, elv, ey, S.theta_fp32);
+    if (k < nk) {
+      nhi = load_row(g, S, vb, i, colv, ey + 2, wp);
+      if (ahead) nth.load(S.theta, eb, g, i, elv, ey + 1, S.theta_fp32);
+    }
     const T phu = fma(beta, hi.qu, hi.zu), phv = fma(beta, hi.qv, hi.zv);
     const T rlu = __shfl_down(plu, 1, 64), rlv = __shfl_down(plv, 1, 64);
     const T rhu = __shfl_down(phu, 1, 64), rhv = __shfl_down(phv, 1, 64);
