@@ -9,9 +9,13 @@ of both models, as many request slots as its share of the budget holds
 (``mlmc_footprint`` bytes per request, ``mlmc_reserve``), so that serving
 itself allocates nothing.  A free worker takes the queue whose head has
 waited longest and admits as many of its requests as it has slots for that
-level.  Batches of different workers overlap on the GPU, and requests that
-arrive meanwhile join the next batch of their queue, so the GPU never waits
-for a batch to fill.  Mode tables, level geometry and the solver pools stay
+level.  Classes whose solves take long (fine strip levels, large panels:
+``long_from`` gives the first long level per model) go only to the last
+``long_workers`` workers, which also take short work when no long work
+waits; a multi-second panel batch therefore never holds up a short request.
+Batches of different workers overlap on the GPU, and requests that arrive
+meanwhile join the next batch of their queue, so the GPU never waits for a
+batch to fill.  Mode tables, level geometry and the solver pools stay
 resident in the contexts; only a request's parameter row travels to the
 device, where its field is synthesised.
 
@@ -70,7 +74,8 @@ class Server:
 
     def __init__(self, strip_cfg: dict, plate_cfg: dict, precision: int = FP64, workers: int = 4,
                  max_batch: int = 512, mem_budget_bytes: int = 64 << 30,
-                 n_levels: Optional[Dict[int, int]] = None):
+                 n_levels: Optional[Dict[int, int]] = None, long_from: Optional[Dict[int, int]] = None,
+                 long_workers: int = 0):
         import torch
         import mlmc_inputs
         self.torch, self.inputs = torch, mlmc_inputs
@@ -88,6 +93,9 @@ class Server:
         self.n_batches = 0
         self.stop = False
         self.errors: List[BaseException] = []
+        self.long_from = dict(long_from or {})
+        self.n_long_workers = min(max(long_workers, 0), workers - 1) if self.long_from else 0
+        self.workers = workers
         # the budget is split evenly over workers, the two models and their
         # levels; every pool is allocated now, so serving allocates nothing
         per_ctx = mem_budget_bytes // max(workers, 1) // 2
@@ -121,13 +129,24 @@ class Server:
                 self.queues.setdefault((r.kind, r.level), deque()).append(r)
             self.cv.notify_all()
 
-    def _take(self) -> Optional[List[Request]]:
-        """Head-of-line oldest queue; as many of its requests as the worker's
-        reserved slots of that level hold."""
+    def is_long(self, key: Tuple[int, int]) -> bool:
+        first = self.long_from.get(key[0])
+        return first is not None and key[1] >= first
+
+    def _take(self, w: int) -> Optional[List[Request]]:
+        """For worker w: the queue whose head waited longest among the classes
+        the worker serves (long-class workers prefer long classes); as many of
+        its requests as the worker's reserved slots of that level hold."""
+        long_worker = w >= self.workers - self.n_long_workers
         best, t_best = None, None
-        for key, q in self.queues.items():
-            if q and (t_best is None or q[0].t_arrive < t_best):
-                best, t_best = key, q[0].t_arrive
+        for want_long in ((True, False) if long_worker else (False,)):
+            for key, q in self.queues.items():
+                if not q or (self.n_long_workers and self.is_long(key) != want_long):
+                    continue
+                if t_best is None or q[0].t_arrive < t_best:
+                    best, t_best = key, q[0].t_arrive
+            if best is not None:
+                break
         if best is None:
             return None
         q = self.queues[best]
@@ -145,10 +164,10 @@ class Server:
         self.torch.cuda.set_device(0)
         while True:
             with self.cv:
-                batch = self._take()
+                batch = self._take(w)
                 while batch is None and not self.stop:
                     self.cv.wait()
-                    batch = self._take()
+                    batch = self._take(w)
                 if batch is None:
                     return
             key = (batch[0].kind, batch[0].level)
@@ -279,8 +298,11 @@ def serve_sweep(serve_cfg: dict, precision: int = FP64, rates=None, duration_s: 
     rates = rates or serve_cfg["rates"]
     dur = duration_s or serve_cfg["duration_s"]
     out = []
+    long_from = {STRIP: serve_cfg["long_from"]["strip"], PLATE: serve_cfg["long_from"]["plate"]} \
+        if "long_from" in serve_cfg else None
     with Server(strip_cfg, plate_cfg, precision, serve_cfg["workers"], serve_cfg["max_batch"],
-                int(serve_cfg["mem_budget_gib"] * (1 << 30))) as srv:
+                int(serve_cfg["mem_budget_gib"] * (1 << 30)), long_from=long_from,
+                long_workers=serve_cfg.get("long_workers", 0)) as srv:
         first: Dict[Tuple[int, int], int] = {}
         # warm every class once so the pools are allocated outside the measurement
         warm_cls = np.array([(k, l) for k in (STRIP, PLATE) for l in range(srv.n_levels[k])])

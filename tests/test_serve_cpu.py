@@ -45,3 +45,48 @@ def test_summarize_percentiles():
     # warm-up exclusion
     st2 = summarize(reqs, 10.0, 0.5, 0, rate=100.0)
     assert st2.requests == 50
+
+
+def _policy_server(workers=4, long_workers=1):
+    """A server object with only the queueing state (no contexts), to test the policy."""
+    import threading
+    from collections import deque
+    from paper_1907_10271_amd.serve import Server
+    s = Server.__new__(Server)
+    s.queues, s.cv = {}, threading.Condition()
+    s.inflight = s.max_inflight = s.n_batches = 0
+    s.long_from = {STRIP: 4, PLATE: 2}
+    s.workers, s.n_long_workers = workers, long_workers
+    s.footprint = {(k, l): 1 for k in (STRIP, PLATE) for l in range(5)}
+    s.cap = {(k, l): 3 for k in (STRIP, PLATE) for l in range(5)}
+    s.queues = {}
+    for key, times in {(STRIP, 0): [2.0, 3.0, 4.0, 5.0], (PLATE, 3): [1.0], (STRIP, 4): [1.5]}.items():
+        s.queues[key] = deque(Request(i, key[0], key[1], i, t_arrive=t) for i, t in enumerate(times))
+    return s
+
+
+def test_short_workers_never_take_long_classes():
+    s = _policy_server()
+    b = s._take(0)                                   # a short worker: oldest short queue, capped at 3
+    assert [(r.kind, r.level) for r in b] == [(STRIP, 0)] * 3
+    b = s._take(1)
+    assert [(r.kind, r.level) for r in b] == [(STRIP, 0)]
+    assert s._take(2) is None                        # only long work is left
+    b = s._take(3)                                   # the long worker: oldest long queue first
+    assert [(r.kind, r.level) for r in b] == [(PLATE, 3)]
+    b = s._take(3)
+    assert [(r.kind, r.level) for r in b] == [(STRIP, 4)]
+    assert s._take(3) is None
+
+
+def test_long_worker_takes_short_work_when_no_long_work_waits():
+    s = _policy_server()
+    s.queues[(PLATE, 3)].clear()
+    s.queues[(STRIP, 4)].clear()
+    b = s._take(3)
+    assert [(r.kind, r.level) for r in b] == [(STRIP, 0)] * 3
+    # without long workers every worker takes the oldest queue of any class
+    s = _policy_server(long_workers=0)
+    s.n_long_workers = 0
+    b = s._take(0)
+    assert [(r.kind, r.level) for r in b] == [(PLATE, 3)]
