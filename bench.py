@@ -300,7 +300,8 @@ def main():
                           "pcg_iters_mean": round(float(its_f.mean()), 1), "all_converged": bool(ok)})
     p1 = ctx.profile_read(0 if prec == pk.FP64 else 2)
     p2 = ctx.profile_read(1 if prec == pk.FP64 else 3)
-    achieved = p1["bytes"] / (p1["ms"] / 1e3) / 1e9
+    # (no lock-step operator launches when only whole-solve levels ran)
+    achieved = p1["bytes"] / (p1["ms"] / 1e3) / 1e9 if p1["ms"] > 0 else 0.0
     default_run = (mix == DEFAULT_MIX and prec == pk.FP64 and not args.mixed and not args.set
                    and len(levels) == len(mix))
     traffic = profiled_traffic() if default_run else None
@@ -326,10 +327,12 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
-                     "launches": p1["launches"], "avg_launch_us": round(p1["ms"] * 1e3 / p1["launches"], 3),
-                     "alg_bytes_per_launch": round(p1["bytes"] / p1["launches"], 1)},
-        "vector_pass": {"kernel": "k_pass2", "achieved_GBs": round(p2["bytes"] / (p2["ms"] / 1e3) / 1e9, 1),
-                        "avg_launch_us": round(p2["ms"] * 1e3 / p2["launches"], 3)},
+                     "launches": p1["launches"],
+                     "avg_launch_us": round(p1["ms"] * 1e3 / p1["launches"], 3) if p1["launches"] else None,
+                     "alg_bytes_per_launch": round(p1["bytes"] / p1["launches"], 1) if p1["launches"] else None},
+        "vector_pass": {"kernel": "k_pass2",
+                        "achieved_GBs": round(p2["bytes"] / (p2["ms"] / 1e3) / 1e9, 1) if p2["ms"] > 0 else None,
+                        "avg_launch_us": round(p2["ms"] * 1e3 / p2["launches"], 3) if p2["launches"] else None},
         "cpu_baseline": None if cpu is None else {k: v for k, v in cpu.items() if k != "per_level_s_per_sample"},
     }
     if args.plate:

@@ -50,9 +50,13 @@ struct PlateWork {
   double *band;    // [S][nfree][bw+1] FP64 factor (FP64 solves)
   float *bandf;    // [S][nfree][bw+1] FP32 factor (mixed)
   double *vec;     // [S][NVEC][nfree]
+  double *kel;     // [S][KEL] element matrices K_e, K_G,e (factorisation spread over work-groups)
+  int *flag;       // [S] non-positive pivot met
   int nvec;
   size_t band_stride, vec_stride;
 };
+
+constexpr int KEL = 800;   // K_e (400) and K_G,e (400) of one sample
 
 enum { V_X = 0, V_W = NB, V_P = 2 * NB, V_KX = 3 * NB, V_KW = 4 * NB, V_KP = 5 * NB, V_GX = 6 * NB, V_GW = 7 * NB,
        V_GP = 8 * NB, V_R = 9 * NB, V_T = 10 * NB, NVEC = 11 * NB };
@@ -161,11 +165,12 @@ __device__ void plate_apply(const PlateGeom &g, const double *Ke, const double *
 }
 
 // lower band of K on the free unknowns: band[r][d] = K[r][r - d], d = 0..bw
+// (rows r0 .. r1 - 1, entries shared out over `nthreads` threads from thread t)
 template <typename B>
-__device__ void assemble_band(const PlateGeom &g, const double *Ke, B *band) {
+__device__ void assemble_band(const PlateGeom &g, const double *Ke, B *band, int r0, int r1, int t, int nthreads) {
   const int w = g.bw + 1;
-  for (int idx = threadIdx.x; idx < g.nfree * w; idx += PT) {
-    const int r = idx / w, d = idx % w;
+  for (long long idx = (long long)r0 * w + t; idx < (long long)r1 * w; idx += nthreads) {
+    const int r = (int)(idx / w), d = (int)(idx % w);
     double v = 0.0;
     const int cfree = r - d;
     if (cfree >= 0) {
@@ -480,21 +485,9 @@ struct PlateJob {
   int n;
 };
 
-template <typename B>
-__global__ __launch_bounds__(PT) void k_buckle(PlateGeom g, PlateMat m, PlateWork W, PlateJob J, double tol,
-                                               int max_iter) {
-  __shared__ double Ke[400], KGe[400], Dmb[36];
-  __shared__ double red[4];
-  __shared__ double gram[2 * NS * NS];
-  __shared__ double coef[NS * NB], mu[NB], resn[NB];
-  __shared__ int mk_sh, done_sh;
-  __shared__ B panel[(NBK + MAXBW) * NBK];
-  const int s = blockIdx.x;
-  if (s >= J.n) return;
-  const int n = g.nfree;
-  double *vec = W.vec + (size_t)s * W.vec_stride;
-  auto V = [&](int k) { return vec + (size_t)k * n; };
-  // ---- laminate (Eq. CLTABD) and element matrices
+// laminate (Eq. CLTABD) of sample s and its uniform element matrices
+__device__ void sample_elements(const PlateGeom &g, const PlateMat &m, const PlateJob &J, int s, double *Dmb,
+                                double *Ke, double *KGe) {
   if (threadIdx.x == 0) {
     const double *off = J.offsets + (size_t)J.rows[s] * m.nply;
     double A[6] = {0, 0, 0, 0, 0, 0}, Bm[6] = {0, 0, 0, 0, 0, 0}, D[6] = {0, 0, 0, 0, 0, 0};
@@ -523,20 +516,34 @@ __global__ __launch_bounds__(PT) void k_buckle(PlateGeom g, PlateMat m, PlateWor
   __syncthreads();
   element_matrices(g, m, Dmb, Ke, KGe);
   __syncthreads();
-  // ---- preconditioner: banded Cholesky factor of K
-  B *band = sizeof(B) == 8 ? (B *)(W.band + (size_t)s * W.band_stride) : (B *)(W.bandf + (size_t)s * W.band_stride);
-  assemble_band<B>(g, Ke, band);
-  __syncthreads();
-  const bool ok = band_cholesky<B>(g, band, panel);
-  if (!ok) {
-    if (threadIdx.x == 0) {
-      const int o = J.out_idx[s];
-      J.lam[o] = NAN;
-      if (J.coarse) { J.info[o].status_c = 3; J.info[o].iters_c = 0; }
-      else { J.info[o].status_f = 3; J.info[o].iters_f = 0; }
-    }
-    return;
+}
+
+// lambda, iteration count and status of sample s
+__device__ void write_result(const PlateJob &J, int s, double lam, int it, double res, int st) {
+  const int o = J.out_idx[s];
+  J.lam[o] = lam;
+  if (J.coarse) {
+    J.info[o].iters_c = it;
+    J.info[o].relres_c = res;
+    J.info[o].status_c = st;
+  } else {
+    J.info[o].iters_f = it;
+    J.info[o].relres_f = res;
+    J.info[o].status_f = st;
   }
+}
+
+// LOBPCG (block NB) for the largest mu of K_G x = mu K x with the factored
+// band as preconditioner; writes lambda = 1/mu of sample s
+template <typename B>
+__device__ void lobpcg(const PlateGeom &g, const double *Ke, const double *KGe, const B *band, double *vec,
+                       const PlateJob &J, int s, double tol, int max_iter) {
+  __shared__ double red[4];
+  __shared__ double gram[2 * NS * NS];
+  __shared__ double coef[NS * NB], mu[NB], resn[NB];
+  __shared__ int mk_sh;
+  const int n = g.nfree;
+  auto V = [&](int k) { return vec + (size_t)k * n; };
   // ---- initial block: smooth mode shapes w = sin(p pi x/a) sin(q pi y/b), theta = grad w
   for (int r = threadIdx.x; r < n; r += PT) {
     const int full = g.full_of_free[r], node = full / 5, c = full % 5;
@@ -641,20 +648,180 @@ __global__ __launch_bounds__(PT) void k_buckle(PlateGeom g, PlateMat m, PlateWor
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const int o = J.out_idx[s];
     const bool good = isfinite(mu0) && mu0 > 0.0 && isfinite(res0);
-    J.lam[o] = good ? 1.0 / mu0 : NAN;
     const int st = !isfinite(res0) ? 2 : !(mu0 > 0.0) ? 3 : (res0 > tol) ? 1 : 0;
-    if (J.coarse) {
-      J.info[o].iters_c = it;
-      J.info[o].relres_c = res0;
-      J.info[o].status_c = st;
-    } else {
-      J.info[o].iters_f = it;
-      J.info[o].relres_f = res0;
-      J.info[o].status_f = st;
-    }
+    write_result(J, s, good ? 1.0 / mu0 : NAN, it, res0, st);
   }
+}
+
+// one work-group per sample from start to finish
+template <typename B>
+__global__ __launch_bounds__(PT) void k_buckle(PlateGeom g, PlateMat m, PlateWork W, PlateJob J, double tol,
+                                               int max_iter) {
+  __shared__ double Ke[400], KGe[400], Dmb[36];
+  __shared__ B panel[(NBK + MAXBW) * NBK];
+  const int s = blockIdx.x;
+  if (s >= J.n) return;
+  sample_elements(g, m, J, s, Dmb, Ke, KGe);
+  // ---- preconditioner: banded Cholesky factor of K
+  B *band = sizeof(B) == 8 ? (B *)(W.band + (size_t)s * W.band_stride) : (B *)(W.bandf + (size_t)s * W.band_stride);
+  assemble_band<B>(g, Ke, band, 0, g.nfree, threadIdx.x, PT);
+  __syncthreads();
+  const bool ok = band_cholesky<B>(g, band, panel);
+  if (!ok) {
+    if (threadIdx.x == 0) write_result(J, s, NAN, 0, 0.0, 3);
+    return;
+  }
+  lobpcg<B>(g, Ke, KGe, band, W.vec + (size_t)s * W.vec_stride, J, s, tol, max_iter);
+}
+
+// ---------------------------------------------------------------- wide factorisation
+// Levels with a wide band spread one sample's factorisation over several
+// work-groups, one launch per panel of NBK columns (the launch order takes the
+// place of a grid-wide barrier).  In the launch of panel k0 every work-group
+// loads the previous panel's factor columns on the rows of its trailing
+// window; work-group 0 subtracts their product from the panel's own columns,
+// factors the panel in LDS and writes it back, while the other work-groups
+// subtract it from the rest of the window.  Every band entry receives the same
+// updates, in the same order and with the same arithmetic, as in the
+// one-work-group factorisation, so the factor is bit-identical.
+
+// laminate and element matrices of each sample into W.kel; clears the pivot flag
+__global__ __launch_bounds__(PT) void k_plate_prep(PlateGeom g, PlateMat m, PlateWork W, PlateJob J) {
+  __shared__ double Ke[400], KGe[400], Dmb[36];
+  const int s = blockIdx.x;
+  if (s >= J.n) return;
+  sample_elements(g, m, J, s, Dmb, Ke, KGe);
+  double *kel = W.kel + (size_t)s * KEL;
+  for (int k = threadIdx.x; k < 400; k += PT) {
+    kel[k] = Ke[k];
+    kel[400 + k] = KGe[k];
+  }
+  if (threadIdx.x == 0) W.flag[s] = 0;
+}
+
+template <typename B>
+__device__ __forceinline__ B *sample_band(const PlateWork &W, int s) {
+  return sizeof(B) == 8 ? (B *)(W.band + (size_t)s * W.band_stride) : (B *)(W.bandf + (size_t)s * W.band_stride);
+}
+
+// band rows [blockIdx.x * rows_per_wg, ...) of sample blockIdx.y
+template <typename B>
+__global__ __launch_bounds__(PT) void k_plate_assemble(PlateGeom g, PlateWork W, int n, int rows_per_wg) {
+  __shared__ double Ke[400];
+  const int s = blockIdx.y;
+  if (s >= n) return;
+  for (int k = threadIdx.x; k < 400; k += PT) Ke[k] = W.kel[(size_t)s * KEL + k];
+  __syncthreads();
+  const int r0 = blockIdx.x * rows_per_wg, r1 = min(g.nfree, r0 + rows_per_wg);
+  if (r0 < r1) assemble_band<B>(g, Ke, sample_band<B>(W, s), r0, r1, threadIdx.x, PT);
+}
+
+template <typename B>
+__global__ __launch_bounds__(PT) void k_band_step(PlateGeom g, PlateWork W, int n, int k0) {
+  __shared__ B Lp[MAXBW * NBK];               // previous panel's columns, rows k0 .. k0 + m - 1
+  __shared__ B P[(NBK + MAXBW) * NBK];        // this panel (work-group 0)
+  const int s = blockIdx.y, wg = blockIdx.x, nwg = gridDim.x;
+  if (s >= n) return;
+  if (__builtin_amdgcn_readfirstlane(W.flag[s])) return;
+  const int w = g.bw + 1, nf = g.nfree;
+  B *band = sample_band<B>(W, s);
+  // trailing window of the previous panel (columns k0 - NBK .. k0 - 1): rows and
+  // columns k0 .. k0 + m - 1
+  const int m = (k0 > 0) ? min(g.bw, nf - k0) : 0;
+  for (int idx = threadIdx.x; idx < m * NBK; idx += PT) {
+    const int r = idx / NBK, j = idx % NBK;
+    const int d = r + NBK - j;
+    Lp[idx] = (d <= g.bw) ? band[(size_t)(k0 + r) * w + d] : B(0);
+  }
+  __syncthreads();
+  if (wg == 0) {
+    if (k0 >= nf) return;
+    const int nb = min(NBK, nf - k0);
+    const int rows = min(nb + g.bw, nf - k0);
+    for (int idx = threadIdx.x; idx < rows * NBK; idx += PT) {
+      const int i = idx / NBK, j = idx % NBK;
+      B v = B(0);
+      if (j < nb && i >= j && i - j <= g.bw) v = band[(size_t)(k0 + i) * w + (i - j)];
+      // the previous panel's update of this entry (columns of this panel)
+      if (j < nb && i >= j && i < m) {
+        B acc = B(0);
+        for (int jj = 0; jj < NBK; ++jj) acc += Lp[i * NBK + jj] * Lp[j * NBK + jj];
+        v -= acc;
+      }
+      P[idx] = v;
+    }
+    // panel factorisation (unblocked, in LDS), as in the one-work-group form
+    for (int j = 0; j < nb; ++j) {
+      __syncthreads();
+      const B piv2 = P[j * NBK + j];
+      if (!(piv2 > B(0))) {
+        if (threadIdx.x == 0) W.flag[s] = 1;
+        return;
+      }
+      const B piv = sqrt(piv2);
+      __syncthreads();
+      for (int i = j + threadIdx.x; i < rows; i += PT) P[i * NBK + j] = (i == j) ? piv : P[i * NBK + j] / piv;
+      __syncthreads();
+      const int ncols = nb - 1 - j;
+      for (int idx = threadIdx.x; idx < (rows - j - 1) * ncols; idx += PT) {
+        const int i = j + 1 + idx / ncols, jj = j + 1 + idx % ncols;
+        if (i >= jj) P[i * NBK + jj] -= P[i * NBK + j] * P[jj * NBK + j];
+      }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < rows * NBK; idx += PT) {
+      const int i = idx / NBK, j = idx % NBK;
+      if (j < nb && i >= j && i - j <= g.bw) band[(size_t)(k0 + i) * w + (i - j)] = P[idx];
+    }
+    return;
+  }
+  // the rest of the previous panel's trailing window: 4 x 4 tiles of column offset >= NBK
+  if (m <= 0 || nwg < 2) return;
+  const int mt = (m + 3) / 4, ntile = mt * (mt + 1) / 2;
+  for (int tix = (wg - 1) * PT + threadIdx.x; tix < ntile; tix += (nwg - 1) * PT) {
+    int ti = (int)((sqrt(8.0 * tix + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= tix) ++ti;
+    while (ti * (ti + 1) / 2 > tix) --ti;
+    const int tj = tix - ti * (ti + 1) / 2;
+    if (tj < NBK / 4) continue;                 // columns of panel k0: work-group 0
+    const int r0 = 4 * ti, c0 = 4 * tj;
+    B acc[4][4];
+    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 4; ++c) acc[a][c] = B(0);
+    for (int j = 0; j < NBK; ++j) {
+      B pr[4], pc[4];
+      for (int a = 0; a < 4; ++a) {
+        pr[a] = (r0 + a < m) ? Lp[(r0 + a) * NBK + j] : B(0);
+        pc[a] = (c0 + a < m) ? Lp[(c0 + a) * NBK + j] : B(0);
+      }
+      for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 4; ++c) acc[a][c] += pr[a] * pc[c];
+    }
+    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 4; ++c) {
+        const int r = r0 + a, cc = c0 + c;
+        if (r < m && cc <= r) band[(size_t)(k0 + r) * w + (r - cc)] -= acc[a][c];
+      }
+  }
+}
+
+// LOBPCG of each sample on its factored band (element matrices from W.kel)
+template <typename B>
+__global__ __launch_bounds__(PT) void k_plate_lobpcg(PlateGeom g, PlateWork W, PlateJob J, double tol, int max_iter) {
+  __shared__ double Ke[400], KGe[400];
+  const int s = blockIdx.x;
+  if (s >= J.n) return;
+  for (int k = threadIdx.x; k < 400; k += PT) {
+    Ke[k] = W.kel[(size_t)s * KEL + k];
+    KGe[k] = W.kel[(size_t)s * KEL + 400 + k];
+  }
+  __syncthreads();
+  if (__builtin_amdgcn_readfirstlane(W.flag[s])) {
+    if (threadIdx.x == 0) write_result(J, s, NAN, 0, 0.0, 3);
+    return;
+  }
+  lobpcg<B>(g, Ke, KGe, sample_band<B>(W, s), W.vec + (size_t)s * W.vec_stride, J, s, tol, max_iter);
 }
 
 // diagnostic: y = K x or K_G x on full-dof vectors (constrained unknowns: y = 0)
@@ -708,10 +875,10 @@ struct PlateLevelH {
   // batch workspace
   int cap = 0;
   size_t bytes = 0;
-  double *band = nullptr, *vec = nullptr;
+  double *band = nullptr, *vec = nullptr, *kel = nullptr;
   float *bandf = nullptr;
   int64_t *rows = nullptr;
-  int *outidx = nullptr;
+  int *outidx = nullptr, *flag = nullptr;
 };
 
 struct PlateCtx {
@@ -723,7 +890,27 @@ struct PlateCtx {
   double *d_xf = nullptr, *d_yf = nullptr;
   size_t xf_cap = 0;
   size_t budget = 0;               // bound on the batch workspaces of all levels
+  int wide_min_bw = 200;           // factorise over several work-groups from this band width on (0: never)
 };
+
+// the factorisation spread over work-groups: element matrices, band assembly
+// (256 rows per work-group), one launch per panel, then LOBPCG per sample
+template <typename B>
+static void launch_wide(const PlateGeom &g, const PlateMat &m, const PlateWork &W, const PlateJob &J, int n,
+                        double tol, int max_iter, hipStream_t st) {
+  hipLaunchKernelGGL(k_plate_prep, dim3(n), dim3(PT), 0, st, g, m, W, J);
+  const int rows_per_wg = 256;
+  hipLaunchKernelGGL(k_plate_assemble<B>, dim3((g.nfree + rows_per_wg - 1) / rows_per_wg, n), dim3(PT), 0, st, g, W,
+                     n, rows_per_wg);
+  // work-groups per sample: work-group 0 plus enough for the window's 4 x 4
+  // tiles (one per thread), fewer when many samples share the launch
+  const int mt = (g.bw + 3) / 4, ntile = mt * (mt + 1) / 2;
+  const int need = 1 + (ntile + PT - 1) / PT;
+  const int nwg = std::max(2, std::min(need, std::max(2, 2048 / std::max(n, 1))));
+  for (int k0 = 0; k0 < g.nfree; k0 += NBK)
+    hipLaunchKernelGGL(k_band_step<B>, dim3(nwg, n), dim3(PT), 0, st, g, W, n, k0);
+  hipLaunchKernelGGL(k_plate_lobpcg<B>, dim3(n), dim3(PT), 0, st, g, W, J, tol, max_iter);
+}
 
 static PlateGeom plate_geom(const Json &cfg, int level) {
   PlateGeom g{};
@@ -775,6 +962,8 @@ PlateCtx *plate_create(const Json &cfg, std::string &err) {
     p->mat.N0 = cfg.number_or("N0", 1.0);
     p->tol = cfg.number_or("eig_tol", 1e-8);
     p->max_iter = (int)cfg.number_or("eig_max_iter", 500);
+    // band width from which one sample's factorisation is spread over work-groups
+    p->wide_min_bw = (int)cfg.number_or("wide_factor_min_bw", 200);
     p->lv.resize(p->nlev);
     for (int l = 0; l < p->nlev; ++l) {
       PlateLevelH &L = p->lv[l];
@@ -824,6 +1013,10 @@ static void free_work(PlateLevelH &L) {
   if (L.vec) (void)hipFree(L.vec);
   if (L.rows) (void)hipFree(L.rows);
   if (L.outidx) (void)hipFree(L.outidx);
+  if (L.kel) (void)hipFree(L.kel);
+  if (L.flag) (void)hipFree(L.flag);
+  L.kel = nullptr;
+  L.flag = nullptr;
   L.band = L.vec = nullptr;
   L.bandf = nullptr;
   L.rows = nullptr;
@@ -838,7 +1031,7 @@ static void free_work(PlateLevelH &L) {
 static size_t work_bytes(const PlateLevelH &L) {
   const size_t bs = (size_t)L.g.nfree * (L.g.bw + 1);
   return bs * (sizeof(double) + sizeof(float)) + (size_t)NVEC * L.g.nfree * sizeof(double) + sizeof(int64_t) +
-         sizeof(int);
+         2 * sizeof(int) + KEL * sizeof(double);
 }
 
 // grow the workspace of level l to at least n samples within the budget
@@ -858,7 +1051,8 @@ static int ensure_work(PlateCtx *p, std::string &err, int l, int n) {
   if (hipMalloc(&L.band, bs * sizeof(double) * n) != hipSuccess ||
       hipMalloc(&L.bandf, bs * sizeof(float) * n) != hipSuccess ||
       hipMalloc(&L.vec, (size_t)NVEC * L.g.nfree * sizeof(double) * n) != hipSuccess ||
-      hipMalloc(&L.rows, sizeof(int64_t) * n) != hipSuccess || hipMalloc(&L.outidx, sizeof(int) * n) != hipSuccess) {
+      hipMalloc(&L.rows, sizeof(int64_t) * n) != hipSuccess || hipMalloc(&L.outidx, sizeof(int) * n) != hipSuccess ||
+      hipMalloc(&L.kel, sizeof(double) * KEL * n) != hipSuccess || hipMalloc(&L.flag, sizeof(int) * n) != hipSuccess) {
     free_work(L);
     err = "plate workspace allocation failed";
     return MLMC_ENOMEM;
@@ -953,6 +1147,8 @@ int plate_buckle_batch(PlateCtx *p, std::string &err, int n_req, const mlmc_requ
       Wk.band = L.band;
       Wk.bandf = L.bandf;
       Wk.vec = L.vec;
+      Wk.kel = L.kel;
+      Wk.flag = L.flag;
       Wk.band_stride = (size_t)L.g.nfree * (L.g.bw + 1);
       Wk.vec_stride = (size_t)NVEC * L.g.nfree;
       for (int off = 0; off < total; off += cap) {
@@ -963,10 +1159,14 @@ int plate_buckle_batch(PlateCtx *p, std::string &err, int n_req, const mlmc_requ
           return MLMC_EHIP;
         }
         PlateJob J{offsets, L.rows, L.outidx, coarse ? lam_coarse : lam_fine, info, coarse, n};
-        if (mixed)
+        if (p->wide_min_bw > 0 && L.g.bw >= p->wide_min_bw) {
+          if (mixed) launch_wide<float>(L.g, p->mat, Wk, J, n, tl, p->max_iter, st);
+          else launch_wide<double>(L.g, p->mat, Wk, J, n, tl, p->max_iter, st);
+        } else if (mixed) {
           hipLaunchKernelGGL(k_buckle<float>, dim3(n), dim3(PT), 0, st, L.g, p->mat, Wk, J, tl, p->max_iter);
-        else
+        } else {
           hipLaunchKernelGGL(k_buckle<double>, dim3(n), dim3(PT), 0, st, L.g, p->mat, Wk, J, tl, p->max_iter);
+        }
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) {

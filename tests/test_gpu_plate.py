@@ -116,3 +116,27 @@ def test_selective_refinement_chain_matches_oracle():
         np.testing.assert_allclose(lam[k, :j + 1], ref[k, :j + 1], rtol=1e-10)
         assert np.all(np.isnan(lam[k, j + 1:]))
     assert ex[0] == 2
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_wide_factorisation_gives_identical_bits(precision):
+    """Spreading a sample's band factorisation over work-groups (one launch per
+    panel) applies the same updates in the same order: buckling loads,
+    iteration counts and residuals are bit-identical to the one-work-group
+    form, on the 32^2 and 64^2 meshes, for coupled requests."""
+    import paper_1907_10271_amd as pk
+    cfg = mi.load_config("plate_c4")
+    one = pk.Context(dict(cfg, wide_factor_min_bw=0))
+    wide = pk.Context(dict(cfg, wide_factor_min_bw=1))
+    for level, n in ((1, 5), (2, 3)):
+        off = dev(mi.plate_offsets(cfg, level, 0, n))
+        reqs = [(k, level, True) for k in range(n)]
+        a = one.buckle_batch(reqs, off, precision=precision)
+        b = wide.buckle_batch(reqs, off, precision=precision)
+        assert np.array_equal(a[0].cpu().numpy(), b[0].cpu().numpy()), level
+        assert np.array_equal(a[1].cpu().numpy(), b[1].cpu().numpy()), level
+        for f in ("iters_f", "iters_c", "relres_f", "relres_c", "status_f", "status_c"):
+            assert np.array_equal(a[2][f], b[2][f]), (level, f)
+        assert np.all(a[2]["status_f"] == 0)
+    one.close()
+    wide.close()
