@@ -47,11 +47,13 @@ def test_plate_operators_parity(level):
         assert np.abs(yg[k] - ref_g).max() <= 1e-13 * np.abs(ref_g).max()
 
 
-@pytest.mark.parametrize("level", [0, 1])
+@pytest.mark.parametrize("level", [0, 1, 2])
 def test_buckling_load_parity_fp64(level):
+    """Levels 0-1: one work-group per sample; level 2 (64^2): the factorisation
+    spread over work-groups."""
     ctx = context("plate_c4")
     om = oracle_plate(level)
-    n = 4
+    n = 4 if level < 2 else 1
     off = mi.plate_offsets(C4, level, 0, n)
     lf, lc, info = ctx.buckle_batch([(k, level, False) for k in range(n)], dev(off))
     lf = lf.cpu().numpy()

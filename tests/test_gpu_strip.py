@@ -317,3 +317,26 @@ def test_graph_replay_matches_direct_launches(precision):
         assert info[0]["iters_f"] == 5
     for x in (a, b, c):
         x.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_sampled_parity(precision):
+    """The benchmark's launch configuration (64 coupled 512x128 / 256x64 pairs in
+    one batch, lock-step engine, tuned angle storage): sampled fine and coarse
+    results against the oracle's direct solve.  Tight rtol on the GPU makes the
+    comparison independent of the PCG stopping point; the bar is 1e-10 relative
+    in FP64 and 1e-6 in mixed precision."""
+    import paper_1907_10271_amd as pk
+    name, level, n = "strip_c2", 3, 64
+    ctx = context(name)
+    xi = _rows(name, level, n)
+    qf, qc, info = ctx.solve_batch([(k, level, True) for k in range(n)], dev(xi), precision=precision,
+                                   rtol=1e-13 if precision == pk.FP64 else 0.0)
+    qf, qc = qf.cpu().numpy(), qc.cpu().numpy()
+    assert np.all(info["status_f"] == 0) and np.all(info["status_c"] == 0)
+    bar = 1e-10 if precision == pk.FP64 else 1e-6
+    for k in (0, 37):
+        rf = oracle_strip(name, level).solve(xi[k], method="direct").q
+        rc = oracle_strip(name, level - 1).solve(xi[k], method="direct").q
+        assert abs(qf[k] - rf) <= bar * abs(rf), (k, qf[k], rf)
+        assert abs(qc[k] - rc) <= bar * abs(rc), (k, qc[k], rc)
