@@ -110,6 +110,13 @@ int fail(mlmc_ctx *c, int code, const std::string &msg) {
       return fail(ctx, MLMC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));            \
   } while (0)
 
+// tile height of the operator pass (a multiple of SWEEP_RB)
+void set_sweep_rows(StripGeom &g, int ty) {
+  g.sw_ty = ty;
+  g.sw_nty = (g.nny + ty - 1) / ty;
+  g.sw_ntiles = g.sw_ntx * g.sw_nty;
+}
+
 StripGeom make_geom(const Json &cfg, int level) {
   StripGeom g{};
   g.nx = (int)cfg.number("nx0") << level;
@@ -123,9 +130,8 @@ StripGeom make_geom(const Json &cfg, int level) {
   g.ntiles = g.tiles_x * g.tiles_y;
   g.sw_ntx = (g.nnx + SWEEP_MAXW - 1) / SWEEP_MAXW;
   g.sw_tw = (g.nnx + g.sw_ntx - 1) / g.sw_ntx;
-  g.sw_nty = (g.nny + SWEEP_MAXTY - 1) / SWEEP_MAXTY;
-  g.sw_ty = (g.nny + g.sw_nty - 1) / g.sw_nty;
-  g.sw_ntiles = g.sw_ntx * g.sw_nty;
+  set_sweep_rows(g, SWEEP_MAXTY);
+  g.sw_npart = ((g.nny + SWEEP_RB - 1) / SWEEP_RB) * g.sw_ntx;
   g.nchunks = (g.nnode + CHUNK - 1) / CHUNK;
   g.Lx = cfg.number("Lx");
   g.Ly = cfg.number("Ly");
@@ -181,14 +187,14 @@ size_t strip_mixed_slot_bytes(const StripGeom &g) {
   return n2 * sizeof(double)                               // b
          + (size_t)4 * g.nelem * sizeof(float)             // inner angles (BF16 or FP32)
          + 5 * n2 * sizeof(float)                          // FP32 x, r, p, Ap, dinv
-         + (size_t)(2 * g.sw_ntiles + 4 * g.nchunks) * sizeof(double) + 16 * sizeof(double);
+         + (size_t)(2 * g.sw_npart + 4 * g.nchunks) * sizeof(double) + 16 * sizeof(double);
 }
 
 size_t strip_slot_bytes(const StripGeom &g) {
   const size_t vec = (size_t)2 * g.nnode * sizeof(double);
   return 5 * vec                                      // x, r, p, Ap, dinv
          + (size_t)8 * g.nelem * sizeof(double)       // (cos 2theta, sin 2theta) per Gauss point
-         + (size_t)(g.sw_ntiles + 4 * g.nchunks) * sizeof(double)  // partials
+         + (size_t)(g.sw_npart + 4 * g.nchunks) * sizeof(double)   // partials
          + (size_t)qoi_parts(g) * sizeof(double)      // QoI partial maxima
          + 8 * sizeof(double) + 8 * sizeof(int) + sizeof(int64_t);
 }
@@ -232,7 +238,7 @@ int ensure_pool(mlmc_ctx *c, int level, int n, bool mixed = false) {
   HIPCHK(c, dalloc(&p.Ap, vec));
   HIPCHK(c, dalloc(&p.dinv, vec));
   HIPCHK(c, dalloc(&p.theta, (size_t)8 * g.nelem * n));
-  HIPCHK(c, dalloc(&p.part_pap, (size_t)g.sw_ntiles * n));
+  HIPCHK(c, dalloc(&p.part_pap, (size_t)g.sw_npart * n));
   HIPCHK(c, dalloc(&p.part_rz, (size_t)2 * g.nchunks * n));
   HIPCHK(c, dalloc(&p.part_rr, (size_t)2 * g.nchunks * n));
   HIPCHK(c, dalloc(&p.rzs, (size_t)2 * n));
@@ -269,7 +275,7 @@ int alloc_mixed(mlmc_ctx *c, int level) {
     return fail(c, MLMC_ENOMEM, "level " + std::to_string(level) + ": mixed-precision buffers exceed the budget");
   const size_t n2 = (size_t)2 * g.nnode * n;
   HIPCHK(c, dalloc(&p.b64, n2));
-  HIPCHK(c, dalloc(&p.m_part_rr, (size_t)g.sw_ntiles * n));
+  HIPCHK(c, dalloc(&p.m_part_rr, (size_t)g.sw_npart * n));
   HIPCHK(c, dalloc(&p.m_relres, (size_t)n));
   HIPCHK(c, dalloc(&p.f_rr_ref, (size_t)n));
   HIPCHK(c, dalloc(&p.m_updates, (size_t)n));
@@ -280,7 +286,7 @@ int alloc_mixed(mlmc_ctx *c, int level) {
   HIPCHK(c, dalloc(&p.fp, n2));
   HIPCHK(c, dalloc(&p.fAp, n2));
   HIPCHK(c, dalloc(&p.fdinv, n2));
-  HIPCHK(c, dalloc(&p.f_pap, (size_t)g.sw_ntiles * n));
+  HIPCHK(c, dalloc(&p.f_pap, (size_t)g.sw_npart * n));
   HIPCHK(c, dalloc(&p.f_rz, (size_t)2 * g.nchunks * n));
   HIPCHK(c, dalloc(&p.f_rr, (size_t)2 * g.nchunks * n));
   HIPCHK(c, dalloc(&p.f_rzs, (size_t)2 * n));
@@ -455,10 +461,25 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
     ng = nb2 = 0;
     for (int mode = 0; mode < 2; ++mode) {
       ngm[mode] = nb1m[mode] = 0;
+      // tile height of this operator-pass launch: the tallest tiles that still
+      // give the launch a few waves per SIMD across the chip (short tiles
+      // shorten the row walk of small batches); the sums do not depend on it
+      int ty = SWEEP_MAXTY;
+      for (; ty > SWEEP_RB; ty /= 2) {
+        long waves = 0;
+        for (int k = 0; k < ng_all; ++k) {
+          if (!alive[k] || (grp[k].S.cs != 0) != (mode == 1)) continue;
+          StripGeom gg = c->lv[grp[k].level].g;
+          set_sweep_rows(gg, ty);
+          waves += (long)gg.sw_ntiles * grp[k].n;
+        }
+        if (waves >= 4096) break;
+      }
       for (int k = 0; k < ng_all; ++k) {
         if (!alive[k] || (grp[k].S.cs != 0) != (mode == 1)) continue;
         PcgGroup<T> &D = hg[ng++];
         D.g = c->lv[grp[k].level].g;
+        set_sweep_rows(D.g, ty);
         D.S = grp[k].S;
         D.n = grp[k].n;
         D.blk0 = nb1m[mode];

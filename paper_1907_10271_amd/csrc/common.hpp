@@ -25,6 +25,10 @@ constexpr int TILE_WAVES = TILE_THREADS / 64;
 // column on each side and walks up the element rows
 constexpr int SWEEP_MAXW = 62;
 constexpr int SWEEP_MAXTY = 16;
+// dot-product partials of the operator pass are kept per block of SWEEP_RB node
+// rows (and column tile), so any tile height that is a multiple of SWEEP_RB
+// gives the same sums: the height can follow the batch size
+constexpr int SWEEP_RB = 4;
 // vector pass: CHUNK consecutive nodes per 256-thread block
 constexpr int CHUNK = 1024;
 
@@ -40,6 +44,7 @@ struct StripGeom {
   int nnode, nelem;
   int tiles_x, tiles_y, ntiles;    // 2-D LDS tiles (set-up and the stand-alone operator)
   int sw_tw, sw_ty, sw_ntx, sw_nty, sw_ntiles;  // column-sweep tiles of the PCG operator pass
+  int sw_npart;                    // operator-pass partials per sample: row blocks x column tiles
   int nchunks;                     // contiguous node chunks of the PCG vector pass
   int qx0, qx1, qy0, qy1;  // QoI element index ranges [q*0, q*1)
   double hx, hy, ihx, ihy, wdet;  // wdet = Gauss weight x det J = hx hy / 4

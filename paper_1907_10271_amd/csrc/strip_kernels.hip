@@ -537,6 +537,12 @@ __global__ __launch_bounds__(64) void k_pass1(const PcgGroup<T> *__restrict__ G,
       st2(S.Ap + vb + 2 * ((size_t)ey * g.nnx + i), yu, yv);
       part += (double)plu * (double)yu + (double)plv * (double)yv;
     }
+    // close a block of SWEEP_RB node rows: one partial per (row block, column tile)
+    if (k >= 1 && ((ey + 1) % SWEEP_RB == 0 || ey + 1 == row_end)) {
+      const double ps = wave_sum(part);
+      if (lane == 0) S.part_pap[(size_t)s * g.sw_npart + (ey / SWEEP_RB) * g.sw_ntx + tx] = ps;
+      part = 0.0;
+    }
     f2u = __shfl_up(fu[2], 1, 64);
     f2v = __shfl_up(fv[2], 1, 64);
     f3u = fu[3];
@@ -544,8 +550,6 @@ __global__ __launch_bounds__(64) void k_pass1(const PcgGroup<T> *__restrict__ G,
     plu = phu;
     plv = phv;
   }
-  part = wave_sum(part);
-  if (lane == 0) S.part_pap[(size_t)s * g.sw_ntiles + t] = part;
 }
 
 // ---------------------------------------------------------------- PCG pass 2
@@ -571,7 +575,7 @@ __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G
   const int par = it & 1;
   if (threadIdx.x == 0) flag = S.active[s];
   double ppap = 0.0;
-  for (int k = threadIdx.x; k < g.sw_ntiles; k += 256) ppap += S.part_pap[(size_t)s * g.sw_ntiles + k];
+  for (int k = threadIdx.x; k < g.sw_npart; k += 256) ppap += S.part_pap[(size_t)s * g.sw_npart + k];
   const double rz = S.rzs[(size_t)par * S.S + s];
   const double rz_prev = (it > 0) ? S.rzs[(size_t)(par ^ 1) * S.S + s] : 1.0;
   const size_t vb = (size_t)s * 2 * g.nnode;
@@ -695,6 +699,11 @@ __global__ __launch_bounds__(64) void k_resid64(StripGeom g, StripMat m, PcgSlot
       *reinterpret_cast<double2 *>(D.r + o) = make_double2(ru, rv);
       part += ru * ru + rv * rv;
     }
+    if (k >= 1 && ((ey + 1) % SWEEP_RB == 0 || ey + 1 == row_end)) {
+      const double ps = wave_sum(part);
+      if (lane == 0) M.part_rr[(size_t)s * g.sw_npart + (ey / SWEEP_RB) * g.sw_ntx + tx] = ps;
+      part = 0.0;
+    }
     f2u = __shfl_up(fu[2], 1, 64);
     f2v = __shfl_up(fv[2], 1, 64);
     f3u = fu[3];
@@ -702,8 +711,6 @@ __global__ __launch_bounds__(64) void k_resid64(StripGeom g, StripMat m, PcgSlot
     plu = phu;
     plv = phv;
   }
-  part = wave_sum(part);
-  if (lane == 0) M.part_rr[(size_t)s * g.sw_ntiles + t] = part;
 }
 
 // Second half of a reliable update: x64 += x32, x32 = 0, r32 = r64; the FP64
@@ -720,7 +727,7 @@ __global__ __launch_bounds__(256) void k_ru_apply(StripGeom g, PcgSlots D, PcgSt
     flag = ask >= it + 2 - every && ask <= it + 1;
   }
   double prr = 0.0, pbb = 0.0;
-  for (int k = threadIdx.x; k < g.sw_ntiles; k += 256) prr += M.part_rr[(size_t)s * g.sw_ntiles + k];
+  for (int k = threadIdx.x; k < g.sw_npart; k += 256) prr += M.part_rr[(size_t)s * g.sw_npart + k];
   for (int k = threadIdx.x; k < g.nchunks; k += 256) pbb += M.part_bb[(size_t)s * g.nchunks + k];
   const double rr = block_sum(prr, red4);
   if (!flag) return;

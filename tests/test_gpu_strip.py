@@ -340,3 +340,19 @@ def test_full_size_sampled_parity(precision):
         rc = oracle_strip(name, level - 1).solve(xi[k], method="direct").q
         assert abs(qf[k] - rf) <= bar * abs(rf), (k, qf[k], rf)
         assert abs(qc[k] - rc) <= bar * abs(rc), (k, qc[k], rc)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tile_height_follows_batch_without_changing_bits(precision):
+    """A batch of 56 512x128 samples runs the operator pass with 16-row tiles, a
+    lone sample with 4-row tiles; the partial sums are kept per 4-row block, so
+    the results are bit-identical."""
+    name, level, n = "strip_c2", 3, 56
+    ctx = context(name)
+    xi = dev(_rows(name, level, n))
+    qa, _, ia = ctx.solve_batch([(k, level, False) for k in range(n)], xi, precision=precision)
+    qa = qa.cpu().numpy()
+    for k in (0, n - 1):
+        qs, _, is_ = ctx.solve_batch([(k, level, False)], xi, precision=precision)
+        assert qs.cpu().numpy()[0] == qa[k], (k, qs.cpu().numpy()[0], qa[k])
+        assert is_[0]["iters_f"] == ia[k]["iters_f"]
