@@ -48,9 +48,9 @@ def parse():
     ap.add_argument("--levels", type=str, default="",
                     help="run only these levels (comma list; profiling runs, the line is then not the benchmark)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
-                    help="mixed: FP32 operator on BF16 angles inside FP64 refinement")
+                    help="mixed: FP32 operator on FP32 angles inside FP64 refinement")
     ap.add_argument("--mixed", type=str, default="",
-                    help="overrides of the mixed-precision settings, e.g. update_factor=0.1,theta_storage=fp32")
+                    help="overrides of the mixed-precision settings, e.g. update_factor=0.1,theta_storage=bf16")
     ap.add_argument("--plate", type=str, default="",
                     help="also time the buckling solver: samples per plate level, e.g. 1024,256,32,4")
     ap.add_argument("--serve", type=str, default="",
@@ -317,7 +317,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == pk.FP64 else "f32+bf16 inner, f64 refinement",
+        "dtype": "f64" if prec == pk.FP64 else "f32 inner, f64 refinement",
         "data": "synthetic (seeded KL parameters and wrinkles)",
         "config": {"workload": "waviness strip 20x5 mm, 4 levels 64x16..512x128, Matern-3/2 20 modes + wrinkle, "
                                "Jacobi-PCG rtol 1e-10, FP64",

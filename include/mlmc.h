@@ -222,8 +222,9 @@ int mlmc_level_stats(mlmc_ctx *ctx, int level, int n, const double *q_fine, cons
  * host-side cost per launch; results are unchanged. */
 int mlmc_profile_enable(mlmc_ctx *ctx, int on);
 /* kernel: 0 / 1 = FP64 operator / vector pass, 2 / 3 = the FP32 passes of the
- * mixed-precision inner solver (4 vectors of 8 B/node + 8 B/element of BF16
- * angles, and 8 vectors of 8 B/node). */
+ * mixed-precision inner solver (4 vectors of 8 B/node + 16 B/element of FP32
+ * angles, or 8 B/element with "theta_storage": "bf16", and 8 vectors of
+ * 8 B/node). */
 int mlmc_profile_read(mlmc_ctx *ctx, int kernel, double *total_ms, int64_t *launches, double *alg_bytes);
 
 #ifdef __cplusplus

@@ -33,7 +33,7 @@ struct StripPool {
   int *it_a = nullptr, *it_b = nullptr, *status = nullptr, *active = nullptr, *outidx = nullptr;
   int64_t *rows = nullptr;
   size_t bytes = 0;
-  // mixed precision (allocated on first use): FP64 rhs, BF16 angles, FP32 inner solver
+  // mixed precision (allocated on first use): FP64 rhs, FP32 or BF16 angles, FP32 inner solver
   bool has_mixed = false;
   double *b64 = nullptr, *m_part_rr = nullptr, *m_relres = nullptr, *f_rr_ref = nullptr;
   int *m_updates = nullptr, *f_ru = nullptr;
@@ -66,7 +66,7 @@ struct mlmc_ctx {
   int max_iter = 100000;
   double ru_factor = 0.1;   // reliable update when the FP32 residual fell by this factor
   int ru_every = 4;         // FP64 residual checks every ru_every iterations
-  int theta_fp32 = 0;       // mixed: angles stored as FP32 instead of bfloat16
+  int theta_fp32 = 1;       // mixed: angles stored as FP32 (1) or bfloat16 (0)
   std::vector<StripLevel> lv;
   size_t budget = 0, used = 0;
   int *h_active = nullptr;
@@ -604,7 +604,7 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
       double its = 0;
       for (int k = 0; k < gr.n; ++k) its += c->h_iters[k];
       const double w = sizeof(T);
-      const double wt = (sizeof(T) == 8) ? (gr.S.cs ? 64.0 : 32.0) : 8.0;  // angle data bytes per element
+      const double wt = (sizeof(T) == 8) ? (gr.S.cs ? 64.0 : 32.0) : (c->theta_fp32 ? 16.0 : 8.0);  // angle bytes/element
       c->prof_bytes[prof_k] += its * (4.0 * 2 * w * g.nnode + wt * g.nelem);
       c->prof_bytes[prof_k + 1] += its * (8.0 * 2 * w * g.nnode);
     }
@@ -638,7 +638,7 @@ int run_small(mlmc_ctx *c, int level, const PcgSlots &S, int n, hipStream_t st) 
   return MLMC_OK;
 }
 
-// mixed precision: FP32 PCG (BF16 angles) with reliable updates in FP64 (the
+// mixed precision: FP32 PCG (FP32 or BF16 angles) with reliable updates in FP64 (the
 // residual b - A x recomputed with the FP64 angles whenever the FP32 residual
 // fell by the update factor, and as the only stopping test); x accumulates in
 // FP64.  On return the FP64 pool state of every group holds x.
@@ -707,7 +707,7 @@ int build_strip(mlmc_ctx *c) {
     const Json &mx = cfg.at("mixed");
     c->ru_factor = mx.number_or("update_factor", c->ru_factor);
     c->ru_every = (int)mx.number_or("update_every", c->ru_every);
-    const std::string ts = mx.string_or("theta_storage", "bf16");
+    const std::string ts = mx.string_or("theta_storage", "fp32");
     if (ts != "bf16" && ts != "fp32") throw std::runtime_error("mixed.theta_storage must be bf16 or fp32");
     c->theta_fp32 = ts == "fp32";
   }

@@ -233,11 +233,33 @@ def test_mixed_precision_qoi_and_fp64_residual(name, level):
         ref = om.solve_theta(thetas[k].reshape(-1, 4), method="direct").q
         err = abs(q[k] - ref) / abs(ref)
         assert err <= 1e-6, err
-    # through the sample path as well (BF16 angles synthesised on the GPU)
+    # through the sample path as well (the inner solver's angles synthesised on the GPU)
     qf, qc, inf2 = ctx.solve_batch([(k, level, level > 0) for k in range(4)], dev(xi), precision=pk.MIXED)
     q64, qc64, _ = ctx.solve_batch([(k, level, level > 0) for k in range(4)], dev(xi))
     assert np.all(inf2["status_f"] == 0)
     assert np.max(np.abs(qf.cpu().numpy() - q64.cpu().numpy()) / np.abs(q64.cpu().numpy())) <= 1e-6
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp32"])
+def test_mixed_angle_storage(storage):
+    """Either storage of the inner solver's angles (BF16 or FP32) changes only
+    the approximate inner operator: the FP64 refinement still brings the QoI
+    to within 1e-6 of the FP64 solve, on a lock-step level, for coupled
+    requests."""
+    import paper_1907_10271_amd as pk
+    name, level, n = "strip_c2", 2, 6
+    cfg = dict(mi.load_config(name), small_solver="off")
+    cfg["mixed"] = dict(cfg.get("mixed", {}), theta_storage=storage)
+    ctx = pk.Context(cfg)
+    xi = dev(_rows(name, level, n))
+    reqs = [(k, level, True) for k in range(n)]
+    qf, qc, info = ctx.solve_batch(reqs, xi, precision=pk.MIXED)
+    ref = context(name, "lockstep").solve_batch(reqs, xi)
+    assert np.all(info["status_f"] == 0) and np.all(info["status_c"] == 0)
+    for got, want in ((qf, ref[0]), (qc, ref[1])):
+        got, want = got.cpu().numpy(), want.cpu().numpy()
+        assert np.max(np.abs(got - want) / np.abs(want)) <= 1e-6
+    ctx.close()
 
 
 @pytest.mark.parametrize("name,level", [("strip_c1", 0), ("strip_c1", 1), ("strip_c2", 0), ("strip_c2", 1)])
