@@ -17,6 +17,45 @@ using Qb = QbT<double>;
 // sin and cos from their Taylor series (Horner in x^2): for |x| <= 1 the first
 // omitted terms are below x^19/19! < 1e-17 and x^20/20! < 1e-18, so the result
 // is within a few ulp.
+// Loads and stores through the global address space.  Generic (flat) accesses
+// also count against the LDS/scalar counter, so the wait for a lane shuffle or
+// a work-group sum would also wait for every row prefetch still in flight.
+#define MLMC_GLOBAL __attribute__((address_space(1)))
+// clang vector types for the accesses (HIP's vector structs copy through a
+// generic reference, which would turn the access back into a flat one)
+template <typename V>
+struct NativeOf;
+template <>
+struct NativeOf<double2> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ double2 from(type n) { return make_double2(n.x, n.y); }
+  static __device__ __forceinline__ type to(const double2 &v) { return type{v.x, v.y}; }
+};
+template <>
+struct NativeOf<float2> {
+  typedef float type __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ float2 from(type n) { return make_float2(n.x, n.y); }
+  static __device__ __forceinline__ type to(const float2 &v) { return type{v.x, v.y}; }
+};
+template <>
+struct NativeOf<float4> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ float4 from(type n) { return make_float4(n.x, n.y, n.z, n.w); }
+};
+template <>
+struct NativeOf<uint2> {
+  typedef unsigned int type __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ uint2 from(type n) { return make_uint2(n.x, n.y); }
+};
+template <typename V>
+__device__ __forceinline__ V gload(const void *p) {
+  return NativeOf<V>::from(*(const MLMC_GLOBAL typename NativeOf<V>::type *)p);
+}
+template <typename V>
+__device__ __forceinline__ void gstore(void *p, const V &v) {
+  *(MLMC_GLOBAL typename NativeOf<V>::type *)p = NativeOf<V>::to(v);
+}
+
 __device__ __forceinline__ void sincos_poly(double x, double *s, double *c) {
   const double z = x * x;
   double ps = -1.0 / 355687428096000.0;  // -1/17!
@@ -105,10 +144,10 @@ __device__ __forceinline__ void elem_cs(const double *__restrict__ ang, int cs, 
   if (cs) {
     const double2 *cp = reinterpret_cast<const double2 *>(ang) + 4 * e;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) out[q] = cp[q];
+    for (int q = 0; q < 4; ++q) out[q] = gload<double2>(cp + q);
   } else {
-    const double2 a = *reinterpret_cast<const double2 *>(ang + 4 * e);
-    const double2 b = *reinterpret_cast<const double2 *>(ang + 4 * e + 2);
+    const double2 a = gload<double2>(ang + 4 * e);
+    const double2 b = gload<double2>(ang + 4 * e + 2);
     const double t[4] = {a.x, a.y, b.x, b.y};
 #pragma unroll
     for (int q = 0; q < 4; ++q) sincos_small(2.0 * t[q], &out[q].y, &out[q].x);

@@ -313,32 +313,39 @@ struct PairOf<float> {
 
 template <typename T>
 __device__ __forceinline__ typename PairOf<T>::type ld2(const T *p) {
-  return *reinterpret_cast<const typename PairOf<T>::type *>(p);
+  return gload<typename PairOf<T>::type>(p);
 }
 template <typename T>
 __device__ __forceinline__ void st2(T *p, T a, T b) {
   typename PairOf<T>::type v;
   v.x = a;
   v.y = b;
-  *reinterpret_cast<typename PairOf<T>::type *>(p) = v;
+  gstore(p, v);
 }
 
+// r, dinv and p_old of node (i, jr) (zero outside the mesh or the window).
+// z = dinv r is formed where the row is used, not here: arithmetic on the
+// loaded values would make the prefetch of the next row wait for its loads.
 template <typename T>
 struct RowVals {
-  T zu, zv, qu, qv;
+  T ru, rv, du, dv, qu, qv;
+  // p = z + beta p_old
+  __device__ __forceinline__ T pu(T beta) const { return fma(beta, qu, du * ru); }
+  __device__ __forceinline__ T pv(T beta) const { return fma(beta, qv, dv * rv); }
 };
 
-// z = dinv r and p_old of node (i, jr) (zero outside the mesh or the window)
 template <typename T>
 __device__ __forceinline__ RowVals<T> load_row(const StripGeom &g, const PcgState<T> &S, size_t vb, int i, bool colv,
                                                int jr, bool with_p) {
-  RowVals<T> v = {T(0), T(0), T(0), T(0)};
+  RowVals<T> v = {T(0), T(0), T(0), T(0), T(0), T(0)};
   if (colv && jr >= 0 && jr < g.nny) {
     const size_t o = vb + 2 * ((size_t)jr * g.nnx + i);
     const auto rv = ld2(S.r + o);
     const auto dv = ld2(S.dinv + o);
-    v.zu = dv.x * rv.x;
-    v.zv = dv.y * rv.y;
+    v.ru = rv.x;
+    v.rv = rv.y;
+    v.du = dv.x;
+    v.dv = dv.y;
     if (with_p) {
       const auto po = ld2(S.p + o);
       v.qu = po.x;
@@ -362,7 +369,7 @@ struct Angles<double, 1> {
     if (ok && ey >= 0 && ey < g.ny) {
       const double2 *cp = (const double2 *)theta + 4 * (eb + (size_t)ey * g.nx + i);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) cs[q] = cp[q];
+      for (int q = 0; q < 4; ++q) cs[q] = gload<double2>(cp + q);
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q) cs[q] = make_double2(1.0, 0.0);
@@ -378,8 +385,8 @@ struct Angles<double, 0> {
     t[0] = t[1] = t[2] = t[3] = 0.0;
     if (ok && ey >= 0 && ey < g.ny) {
       const double *tp = (const double *)theta + 4 * (eb + (size_t)ey * g.nx + i);
-      const double2 a = *reinterpret_cast<const double2 *>(tp);
-      const double2 b = *reinterpret_cast<const double2 *>(tp + 2);
+      const double2 a = gload<double2>(tp);
+      const double2 b = gload<double2>(tp + 2);
       t[0] = a.x; t[1] = a.y; t[2] = b.x; t[3] = b.y;
     }
   }
@@ -399,10 +406,10 @@ struct Angles<float, 0> {
     if (ok && ey >= 0 && ey < g.ny) {
       const size_t e = 4 * (eb + (size_t)ey * g.nx + i);
       if (theta_fp32) {
-        const float4 w = *reinterpret_cast<const float4 *>((const float *)theta + e);
+        const float4 w = gload<float4>((const float *)theta + e);
         t[0] = w.x; t[1] = w.y; t[2] = w.z; t[3] = w.w;
       } else {
-        const uint2 w = *reinterpret_cast<const uint2 *>((const uint16_t *)theta + e);
+        const uint2 w = gload<uint2>((const uint16_t *)theta + e);
         t[0] = __uint_as_float(w.x << 16);
         t[1] = __uint_as_float(w.x & 0xFFFF0000u);
         t[2] = __uint_as_float(w.y << 16);
@@ -499,7 +506,7 @@ __global__ __launch_bounds__(64) void k_pass1(const PcgGroup<T> *__restrict__ G,
   if (verdict >= 0 || upd) return;
   const double beta_d = (it == 0) ? 0.0 : rz / rz_prev;
   const T beta = (T)beta_d;
-  T plu = fma(beta, lo.qu, lo.zu), plv = fma(beta, lo.qv, lo.zv);
+  T plu = lo.pu(beta), plv = lo.pv(beta);
   T f2u = 0, f2v = 0, f3u = 0, f3v = 0;  // previous element row: f2 of the left lane, own f3
   double part = 0.0;
   const int nk = row_end - j0;
@@ -519,7 +526,7 @@ __global__ __launch_bounds__(64) void k_pass1(const PcgGroup<T> *__restrict__ G,
       nhi = load_row(g, S, vb, i, colv, ey + 2, wp);
       if (ahead) nth.load(S.theta, eb, g, i, elv, ey + 1, S.theta_fp32);
     }
-    const T phu = fma(beta, hi.qu, hi.zu), phv = fma(beta, hi.qv, hi.zv);
+    const T phu = hi.pu(beta), phv = hi.pv(beta);
     const T rlu = __shfl_down(plu, 1, 64), rlv = __shfl_down(plv, 1, 64);
     const T rhu = __shfl_down(phu, 1, 64), rhv = __shfl_down(phv, 1, 64);
     T fu[4] = {0, 0, 0, 0}, fv[4] = {0, 0, 0, 0};
