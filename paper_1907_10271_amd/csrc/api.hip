@@ -329,6 +329,7 @@ PcgState<float> inner_of(mlmc_ctx *c, int level) {
   I.max_iter = c->max_iter;
   I.mixed = 1;
   I.theta_fp32 = c->theta_fp32;
+  I.cs = c->theta_fp32;  // selects the FP32-angle form of the operator pass
   I.ru2 = c->ru_factor * c->ru_factor;
   I.rr_ref = p.f_rr_ref;
   I.ru = p.f_ru;
@@ -376,12 +377,12 @@ PcgSlots slots_of(mlmc_ctx *c, int level, double rtol) {
   return S;
 }
 
-// caller angles [n][4 nelem] into the pool's angle data (copied, or as pairs)
+// caller angles [n][4 nelem] into the pool's angle data (as codes tan theta, or as pairs)
 int stage_angles(mlmc_ctx *c, int level, const double *theta, int n, hipStream_t st) {
   StripLevel &L = c->lv[level];
   const size_t ngp = (size_t)n * 4 * L.g.nelem;
   if (L.cs) launch_theta_cs(theta, L.pool.theta, ngp, st);
-  else HIPCHK(c, hipMemcpyAsync(L.pool.theta, theta, ngp * sizeof(double), hipMemcpyDeviceToDevice, st));
+  else launch_theta_code(theta, L.pool.theta, ngp, st);
   HIPCHK(c, hipGetLastError());
   return MLMC_OK;
 }
@@ -959,7 +960,7 @@ int mlmc_sample_field(mlmc_ctx *c, int level, int n, const double *xi, int ld_xi
   if (!xi || !theta) return fail(c, MLMC_EINVAL, "null pointer");
   const StripGeom &g = c->lv[level].g;
   launch_kl_synth(c->lv[level].modes, c->K, g, xi, ld_xi, nullptr, n, dtype == 0 ? (double *)theta : nullptr,
-                  dtype == 1 ? theta : nullptr, 0, 4 * g.nelem, nullptr, (hipStream_t)stream);
+                  dtype == 1 ? theta : nullptr, 0, 4 * g.nelem, nullptr, 0, (hipStream_t)stream);
   HIPCHK(c, hipGetLastError());
   return MLMC_OK;
 }
@@ -1090,7 +1091,7 @@ int mlmc_solve_batch(mlmc_ctx *c, int n_req, const mlmc_request *req, const doub
       HIPCHK(c, hipMemcpyAsync(L.pool.outidx, outs[l].data() + done[l], sizeof(int) * n, hipMemcpyHostToDevice, st));
       launch_kl_synth(L.modes, c->K, L.g, xi, ld_xi, L.pool.rows, n, L.cs ? nullptr : L.pool.theta,
                       mixed ? L.pool.theta16 : nullptr, c->theta_fp32, 4 * L.g.nelem, L.cs ? L.pool.theta : nullptr,
-                      st);
+                      1, st);
       PcgSlots S = slots_of(c, l, rt);
       if (L.small) {
         if (int rc = run_small(c, l, S, n, st)) return rc;

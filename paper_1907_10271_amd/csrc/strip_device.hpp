@@ -43,6 +43,17 @@ struct NativeOf<float4> {
   static __device__ __forceinline__ float4 from(type n) { return make_float4(n.x, n.y, n.z, n.w); }
 };
 template <>
+struct NativeOf<double> {
+  typedef double type;
+  static __device__ __forceinline__ double from(type n) { return n; }
+  static __device__ __forceinline__ type to(double v) { return v; }
+};
+template <>
+struct NativeOf<uint4> {
+  typedef unsigned int type __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ uint4 from(type n) { return make_uint4(n.x, n.y, n.z, n.w); }
+};
+template <>
 struct NativeOf<uint2> {
   typedef unsigned int type __attribute__((ext_vector_type(2)));
   static __device__ __forceinline__ uint2 from(type n) { return make_uint2(n.x, n.y); }
@@ -103,6 +114,31 @@ __device__ __forceinline__ void sincos_small(double x, double *s, double *c) {
   *c = ((q + 1) & 2) ? -cc : cc;
 }
 
+// Angles are kept by the solver as their tangent t = tan theta (clamped to
+// +-1e150, so that t^2 stays finite; for every double angle |cos theta| is far
+// above 1e-150; NaN stays NaN).  The rotation then needs no trigonometric series and no
+// stored constants:
+//   cos 2theta = (1 - t^2) / (1 + t^2),  sin 2theta = 2 t / (1 + t^2),
+// with 1/(1 + t^2) from the hardware reciprocal and two Newton steps (each
+// doubles the number of correct bits of the initial estimate).
+__device__ __forceinline__ double angle_code(double th) {
+  double s, c;
+  sincos_small(th, &s, &c);
+  const double t = s / c;
+  return fabs(t) > 1e150 ? copysign(1e150, t) : t;  // a NaN angle stays NaN
+}
+__device__ __forceinline__ void cs_of_code(double t, double *s2, double *c2) {
+  const double den = fma(t, t, 1.0);
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(fma(-den, r, 1.0), r, r);
+  r = fma(fma(-den, r, 1.0), r, r);
+  *c2 = fma(-t, t, 1.0) * r;
+  *s2 = (t + t) * r;
+}
+// (cos 2theta, sin 2theta) of an angle, through its code (every path of the
+// library evaluates the rotation this way, so they agree bit for bit)
+__device__ __forceinline__ void cs_of_angle(double th, double *s2, double *c2) { cs_of_code(angle_code(th), s2, c2); }
+
 // Qbar from c2 = cos 2theta and s2 = sin 2theta (rotation invariants: the
 // fibre axes are turned by +theta from x; entries are linear in cos 2theta,
 // sin 2theta, cos 4theta, sin 4theta)
@@ -123,7 +159,7 @@ __device__ __forceinline__ Qb qbar_cs(const StripMat &m, double s2, double c2) {
 // Qbar(theta): the same from the angle itself
 __device__ __forceinline__ Qb qbar_of(const StripMat &m, double th) {
   double s2, c2;
-  sincos_small(2.0 * th, &s2, &c2);
+  cs_of_angle(th, &s2, &c2);
   const double c4 = 2.0 * c2 * c2 - 1.0;
   const double s4 = 2.0 * s2 * c2;
   Qb q;
@@ -139,7 +175,7 @@ __device__ __forceinline__ Qb qbar_of(const StripMat &m, double th) {
 
 // (cos 2theta, sin 2theta) at the four Gauss points of element e (index within
 // the sample's data `ang`), read as stored pairs (cs != 0) or evaluated from
-// the stored angles
+// the stored angle codes
 __device__ __forceinline__ void elem_cs(const double *__restrict__ ang, int cs, size_t e, double2 out[4]) {
   if (cs) {
     const double2 *cp = reinterpret_cast<const double2 *>(ang) + 4 * e;
@@ -150,7 +186,7 @@ __device__ __forceinline__ void elem_cs(const double *__restrict__ ang, int cs, 
     const double2 b = gload<double2>(ang + 4 * e + 2);
     const double t[4] = {a.x, a.y, b.x, b.y};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) sincos_small(2.0 * t[q], &out[q].y, &out[q].x);
+    for (int q = 0; q < 4; ++q) cs_of_code(t[q], &out[q].y, &out[q].x);
   }
 }
 

@@ -11,9 +11,11 @@
 // bit-reproducible.  Dot products use fixed-order wave butterflies and a
 // fixed-order sum over tiles.
 #include "strip_kernels.hpp"
+
 #include "strip_device.hpp"
 
 #include <cmath>
+#include <type_traits>
 
 namespace mlmc {
 
@@ -88,7 +90,7 @@ __global__ __launch_bounds__(256) void k_kl_synth(const double *__restrict__ mod
                                                   const double *__restrict__ xi, int ld_xi,
                                                   const int64_t *__restrict__ rows, int n,
                                                   double *__restrict__ th64, void *__restrict__ thlo,
-                                                  int lo_fp32, int ld_out, double *__restrict__ cs) {
+                                                  int lo_fp32, int ld_out, double *__restrict__ cs, int code) {
   const int ngp = 4 * g.nelem;
   const int gp = blockIdx.x * 256 + threadIdx.x;
   if (gp >= ngp) return;
@@ -112,10 +114,10 @@ __global__ __launch_bounds__(256) void k_kl_synth(const double *__restrict__ mod
       const double c = cosh((x - xr[K + 1]) / xr[K + 2]);
       th += A / (c * c);
     }
-    if (th64) th64[(size_t)s * ld_out + gp] = th;
+    if (th64) th64[(size_t)s * ld_out + gp] = code ? angle_code(th) : th;
     if (cs) {
       double s2, c2;
-      sincos_small(2.0 * th, &s2, &c2);
+      cs_of_angle(th, &s2, &c2);
       *reinterpret_cast<double2 *>(cs + (size_t)s * 2 * ngp + 2 * (size_t)gp) = make_double2(c2, s2);
     }
     if (thlo) {
@@ -323,101 +325,91 @@ __device__ __forceinline__ void st2(T *p, T a, T b) {
   gstore(p, v);
 }
 
-// r, dinv and p_old of node (i, jr) (zero outside the mesh or the window).
-// z = dinv r is formed where the row is used, not here: arithmetic on the
-// loaded values would make the prefetch of the next row wait for its loads.
+// r, dinv and p_old of node (i, jr).  The loads are issued for every lane,
+// from the nearest node inside the mesh, with no branch: the wait for the
+// current row then covers exactly the loads issued before it and leaves the
+// next row's in flight.  Values of nodes outside the mesh or the window are
+// never used (their elements are skipped and their nodes not owned).  z = dinv r
+// is formed where the row is used, not here, for the same reason.
 template <typename T>
 struct RowVals {
   T ru, rv, du, dv, qu, qv;
-  // p = z + beta p_old
-  __device__ __forceinline__ T pu(T beta) const { return fma(beta, qu, du * ru); }
-  __device__ __forceinline__ T pv(T beta) const { return fma(beta, qv, dv * rv); }
+  // p = z + beta p_old (p_old = 0 before the first iteration, wp false)
+  __device__ __forceinline__ T pu(T beta, bool wp) const { return fma(beta, wp ? qu : T(0), du * ru); }
+  __device__ __forceinline__ T pv(T beta, bool wp) const { return fma(beta, wp ? qv : T(0), dv * rv); }
 };
 
+__device__ __forceinline__ int clampi(int v, int hi) { return min(max(v, 0), hi); }
+
 template <typename T>
-__device__ __forceinline__ RowVals<T> load_row(const StripGeom &g, const PcgState<T> &S, size_t vb, int i, bool colv,
-                                               int jr, bool with_p) {
-  RowVals<T> v = {T(0), T(0), T(0), T(0), T(0), T(0)};
-  if (colv && jr >= 0 && jr < g.nny) {
-    const size_t o = vb + 2 * ((size_t)jr * g.nnx + i);
-    const auto rv = ld2(S.r + o);
-    const auto dv = ld2(S.dinv + o);
-    v.ru = rv.x;
-    v.rv = rv.y;
-    v.du = dv.x;
-    v.dv = dv.y;
-    if (with_p) {
-      const auto po = ld2(S.p + o);
-      v.qu = po.x;
-      v.qv = po.y;
-    }
-  }
+__device__ __forceinline__ RowVals<T> load_row(const StripGeom &g, const PcgState<T> &S, size_t vb, int ic, int jr) {
+  const size_t o = vb + 2 * ((size_t)clampi(jr, g.nny - 1) * g.nnx + ic);
+  const auto rv = ld2(S.r + o);
+  const auto dv = ld2(S.dinv + o);
+  const auto po = ld2(S.p + o);  // not written before the first iteration: not used there
+  RowVals<T> v;
+  v.ru = rv.x;
+  v.rv = rv.y;
+  v.du = dv.x;
+  v.dv = dv.y;
+  v.qu = po.x;
+  v.qv = po.y;
   return v;
 }
 
-// the four Gauss-point angles of element (i, ey) and the rotated stiffness at
+// the four Gauss-point angles of element (ic, ey) and the rotated stiffness at
 // one of them.  FP64: CSM = 1 reads stored (cos 2theta, sin 2theta) pairs
-// (64 B per element), CSM = 0 reads the angles (32 B) and evaluates the pairs
-// one Gauss point at a time; both give the same bits.
+// (64 B per element), CSM = 0 reads the angle codes tan theta (32 B) and
+// evaluates the pairs one Gauss point at a time; both give the same bits.  As for the rows, the
+// loads are unconditional (ic is clamped by the caller, ey here) and the values
+// of elements outside the mesh are never used.
 template <typename T, int CSM = 0>
 struct Angles;
 template <>
 struct Angles<double, 1> {
   double2 cs[4];
-  __device__ __forceinline__ void load(const void *theta, size_t eb, const StripGeom &g, int i, bool ok, int ey,
-                                       int = 0) {
-    if (ok && ey >= 0 && ey < g.ny) {
-      const double2 *cp = (const double2 *)theta + 4 * (eb + (size_t)ey * g.nx + i);
+  __device__ __forceinline__ void load(const void *theta, size_t eb, const StripGeom &g, int ic, int ey, int = 0) {
+    const double2 *cp = (const double2 *)theta + 4 * (eb + (size_t)clampi(ey, g.ny - 1) * g.nx + ic);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) cs[q] = gload<double2>(cp + q);
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) cs[q] = make_double2(1.0, 0.0);
-    }
+    for (int q = 0; q < 4; ++q) cs[q] = gload<double2>(cp + q);
   }
   __device__ __forceinline__ QbT<double> qb(const StripMat &m, int q) const { return qbar_cs(m, cs[q].y, cs[q].x); }
 };
 template <>
 struct Angles<double, 0> {
   double t[4];
-  __device__ __forceinline__ void load(const void *theta, size_t eb, const StripGeom &g, int i, bool ok, int ey,
-                                       int = 0) {
-    t[0] = t[1] = t[2] = t[3] = 0.0;
-    if (ok && ey >= 0 && ey < g.ny) {
-      const double *tp = (const double *)theta + 4 * (eb + (size_t)ey * g.nx + i);
-      const double2 a = gload<double2>(tp);
-      const double2 b = gload<double2>(tp + 2);
-      t[0] = a.x; t[1] = a.y; t[2] = b.x; t[3] = b.y;
-    }
+  __device__ __forceinline__ void load(const void *theta, size_t eb, const StripGeom &g, int ic, int ey, int = 0) {
+    const double *tp = (const double *)theta + 4 * (eb + (size_t)clampi(ey, g.ny - 1) * g.nx + ic);
+    const double2 a = gload<double2>(tp);
+    const double2 b = gload<double2>(tp + 2);
+    t[0] = a.x; t[1] = a.y; t[2] = b.x; t[3] = b.y;
   }
   __device__ __forceinline__ QbT<double> qb(const StripMat &m, int q) const {
     double s2, c2;
-    sincos_small(2.0 * t[q], &s2, &c2);
+    cs_of_code(t[q], &s2, &c2);
     return qbar_cs(m, s2, c2);
   }
 };
 template <>
 struct Angles<float, 0> {
-  float t[4];
-  // angles stored as bfloat16 (theta_fp32 == 0) or FP32
-  __device__ __forceinline__ void load(const void *theta, size_t eb, const StripGeom &g, int i, bool ok, int ey,
-                                       int theta_fp32) {
-    t[0] = t[1] = t[2] = t[3] = 0.0f;
-    if (ok && ey >= 0 && ey < g.ny) {
-      const size_t e = 4 * (eb + (size_t)ey * g.nx + i);
-      if (theta_fp32) {
-        const float4 w = gload<float4>((const float *)theta + e);
-        t[0] = w.x; t[1] = w.y; t[2] = w.z; t[3] = w.w;
-      } else {
-        const uint2 w = gload<uint2>((const uint16_t *)theta + e);
-        t[0] = __uint_as_float(w.x << 16);
-        t[1] = __uint_as_float(w.x & 0xFFFF0000u);
-        t[2] = __uint_as_float(w.y << 16);
-        t[3] = __uint_as_float(w.y & 0xFFFF0000u);
-      }
-    }
+  uint2 w;  // two bfloat16 angles per word, decoded at use
+  __device__ __forceinline__ void load(const void *theta, size_t eb, const StripGeom &g, int ic, int ey, int = 0) {
+    w = gload<uint2>((const uint16_t *)theta + 4 * (eb + (size_t)clampi(ey, g.ny - 1) * g.nx + ic));
   }
-  __device__ __forceinline__ QbT<float> qb(const StripMat &m, int q) const { return qbar_f32(m, t[q]); }
+  __device__ __forceinline__ QbT<float> qb(const StripMat &m, int q) const {
+    const uint32_t h = (q >> 1) ? w.y : w.x;
+    return qbar_f32(m, __uint_as_float((q & 1) ? (h & 0xFFFF0000u) : (h << 16)));
+  }
+};
+template <>
+struct Angles<float, 1> {
+  float4 t;  // FP32 angles
+  __device__ __forceinline__ void load(const void *theta, size_t eb, const StripGeom &g, int ic, int ey, int = 0) {
+    t = gload<float4>((const float *)theta + 4 * (eb + (size_t)clampi(ey, g.ny - 1) * g.nx + ic));
+  }
+  __device__ __forceinline__ QbT<float> qb(const StripMat &m, int q) const {
+    return qbar_f32(m, q == 0 ? t.x : q == 1 ? t.y : q == 2 ? t.z : t.w);
+  }
 };
 
 // ---------------------------------------------------------------- PCG pass 1
@@ -435,7 +427,7 @@ struct Angles<float, 0> {
 // The next node row is loaded while the current row is computed.  Dot
 // products are accumulated in FP64 for both precisions.
 template <typename T, int CSM>
-__global__ __launch_bounds__(64) void k_pass1(const PcgGroup<T> *__restrict__ G, int ng, StripMat m, int it_off,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_pass1(const PcgGroup<T> *__restrict__ G, int ng, StripMat m, int it_off,
                                              int nblocks, const int *__restrict__ itb) {
   const int it = itb ? __builtin_amdgcn_readfirstlane(*itb) + it_off : it_off;
   const int lb = xcd_remap(blockIdx.x, nblocks);
@@ -464,13 +456,13 @@ __global__ __launch_bounds__(64) void k_pass1(const PcgGroup<T> *__restrict__ G,
   const int tx = t % g.sw_ntx, ty = t / g.sw_ntx;
   const int i0 = tx * g.sw_tw, j0 = ty * g.sw_ty;
   const int i = i0 - 1 + lane;
-  const bool colv = lane <= g.sw_tw + 1 && i >= 0 && i < g.nnx;
   const bool elv = lane <= g.sw_tw && i >= 0 && i < g.nx;
   const bool own = lane >= 1 && lane <= g.sw_tw && i < g.nnx;
   const int row_end = min(j0 + g.sw_ty, g.nny);
   const bool wp = it > 0;
-  RowVals<T> lo = load_row(g, S, vb, i, colv, j0 - 1, wp);
-  RowVals<T> nhi = load_row(g, S, vb, i, colv, j0, wp);
+  const int ic = clampi(i, g.nnx - 1), ice = clampi(i, g.nx - 1);  // nearest node / element column
+  RowVals<T> lo = load_row(g, S, vb, ic, j0 - 1);
+  RowVals<T> nhi = load_row(g, S, vb, ic, j0);
   const double rz = wave_sum(prz);
   if (!active) return;
   const double rr = wave_sum(prr);
@@ -506,27 +498,38 @@ __global__ __launch_bounds__(64) void k_pass1(const PcgGroup<T> *__restrict__ G,
   if (verdict >= 0 || upd) return;
   const double beta_d = (it == 0) ? 0.0 : rz / rz_prev;
   const T beta = (T)beta_d;
-  T plu = lo.pu(beta), plv = lo.pv(beta);
+  T plu = lo.pu(beta, wp), plv = lo.pv(beta, wp);
   T f2u = 0, f2v = 0, f3u = 0, f3v = 0;  // previous element row: f2 of the left lane, own f3
+  T yu = 0, yv = 0;                      // A p of the last node row, stored one row late
   double part = 0.0;
   const int nk = row_end - j0;
-  // FP64 angles of the next element row are loaded one row ahead (not the
-  // pairs: they would cost the fourth wave per SIMD; not the FP32 solver's
-  // BF16 angles: measured slower)
+  // the next element row's angle codes are loaded one row ahead (not the
+  // pairs: they would cost the fourth wave per SIMD)
   constexpr bool ahead = CSM == 0 && sizeof(T) == 8;
   Angles<T, CSM> nth;
-  if (ahead) nth.load(S.theta, eb, g, i, elv, j0 - 1, S.theta_fp32);
-  for (int k = 0; k <= nk; ++k) {
+  if (ahead) nth.load(S.theta, eb, g, ice, j0 - 1);
+  // One node row per step.  Memory operations are issued in a fixed order and
+  // without branches around them: the store of the previous row, this row's
+  // angles, the next row's values.  Each wait then covers exactly what it
+  // needs; the last step, which prefetches nothing, is a separate copy.
+  auto step = [&](const int k, auto prefetch) {
     const int ey = j0 - 1 + k;
+    // everything issued by the previous step has arrived: its prefetch and the
+    // store before it (vmcnt 0; expcnt and lgkmcnt not waited for)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    if (k >= 2 && own) st2(S.Ap + vb + 2 * ((size_t)(ey - 1) * g.nnx + i), yu, yv);
     const RowVals<T> hi = nhi;
     Angles<T, CSM> th;
-    if (ahead) th = nth;
-    else th.load(S.theta, eb, g, i, elv, ey, S.theta_fp32);
-    if (k < nk) {
-      nhi = load_row(g, S, vb, i, colv, ey + 2, wp);
-      if (ahead) nth.load(S.theta, eb, g, i, elv, ey + 1, S.theta_fp32);
+    if constexpr (ahead) th = nth;
+    else th.load(S.theta, eb, g, ice, ey);
+    // keep this row's angle loads ahead of the prefetch, so that waiting for
+    // them does not wait for the next row
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (decltype(prefetch)::value) {
+      nhi = load_row(g, S, vb, ic, ey + 2);
+      if constexpr (ahead) nth.load(S.theta, eb, g, ice, ey + 1);
     }
-    const T phu = hi.pu(beta), phv = hi.pv(beta);
+    const T phu = hi.pu(beta, wp), phv = hi.pv(beta, wp);
     const T rlu = __shfl_down(plu, 1, 64), rlv = __shfl_down(plv, 1, 64);
     const T rhu = __shfl_down(phu, 1, 64), rhv = __shfl_down(phv, 1, 64);
     T fu[4] = {0, 0, 0, 0}, fv[4] = {0, 0, 0, 0};
@@ -537,17 +540,16 @@ __global__ __launch_bounds__(64) void k_pass1(const PcgGroup<T> *__restrict__ G,
     }
     const T f1lu = __shfl_up(fu[1], 1, 64), f1lv = __shfl_up(fv[1], 1, 64);
     if (k >= 1 && own) {
-      T yu = ((f2u + f3u) + f1lu) + fu[0];
-      T yv = ((f2v + f3v) + f1lv) + fv[0];
+      yu = ((f2u + f3u) + f1lu) + fu[0];
+      yv = ((f2v + f3v) + f1lv) + fv[0];
       if (i == 0) { yu = plu; yv = plv; }
       if (i == g.nx) yu = plu;
-      st2(S.Ap + vb + 2 * ((size_t)ey * g.nnx + i), yu, yv);
       part += (double)plu * (double)yu + (double)plv * (double)yv;
     }
     // close a block of SWEEP_RB node rows: one partial per (row block, column tile)
     if (k >= 1 && ((ey + 1) % SWEEP_RB == 0 || ey + 1 == row_end)) {
       const double ps = wave_sum(part);
-      if (lane == 0) S.part_pap[(size_t)s * g.sw_npart + (ey / SWEEP_RB) * g.sw_ntx + tx] = ps;
+      if (lane == 0) gstore(S.part_pap + (size_t)s * g.sw_npart + (ey / SWEEP_RB) * g.sw_ntx + tx, ps);
       part = 0.0;
     }
     f2u = __shfl_up(fu[2], 1, 64);
@@ -556,7 +558,10 @@ __global__ __launch_bounds__(64) void k_pass1(const PcgGroup<T> *__restrict__ G,
     f3v = fv[3];
     plu = phu;
     plv = phv;
-  }
+  };
+  for (int k = 0; k < nk; ++k) step(k, std::true_type{});
+  step(nk, std::false_type{});
+  if (nk >= 1 && own) st2(S.Ap + vb + 2 * ((size_t)(row_end - 1) * g.nnx + i), yu, yv);
 }
 
 // ---------------------------------------------------------------- PCG pass 2
@@ -986,11 +991,11 @@ static inline dim3 tile_grid(const StripGeom &g, int n) { return dim3(g.ntiles, 
 
 void launch_kl_synth(const double *modes, int K, const StripGeom &g, const double *xi, int ld_xi,
                      const int64_t *rows, int n, double *th64, void *thlo, int lo_fp32, int ld_out, double *cs,
-                     hipStream_t st) {
+                     int code, hipStream_t st) {
   if (n <= 0) return;
   dim3 grid((4 * g.nelem + 255) / 256, (n + SYN_SAMPLES - 1) / SYN_SAMPLES);
   hipLaunchKernelGGL(k_kl_synth, grid, dim3(256), 0, st, modes, K, g, xi, ld_xi, rows, n, th64, thlo, lo_fp32, ld_out,
-                     cs);
+                     cs, code);
 }
 
 // (cos 2theta, sin 2theta) per Gauss point from given angles
@@ -998,8 +1003,19 @@ __global__ void k_theta_cs(const double *__restrict__ th, double *__restrict__ c
   const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   double s2, c2;
-  sincos_small(2.0 * th[k], &s2, &c2);
+  cs_of_angle(th[k], &s2, &c2);
   *reinterpret_cast<double2 *>(cs + 2 * k) = make_double2(c2, s2);
+}
+
+// angle codes (tan theta) per Gauss point from given angles
+__global__ void k_theta_code(const double *__restrict__ th, double *__restrict__ t, size_t n) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) t[k] = angle_code(th[k]);
+}
+
+void launch_theta_code(const double *theta, double *code, size_t n, hipStream_t st) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_theta_code, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, theta, code, n);
 }
 
 void launch_theta_cs(const double *theta, double *cs, size_t n, hipStream_t st) {
@@ -1029,13 +1045,11 @@ void launch_setup(const StripGeom &g, const StripMat &m, const PcgSlots &S, int 
 template <typename T>
 void launch_pcg_pass1(const PcgGroup<T> *groups, int ng, int nblocks, const StripMat &m, int it, int cs,
                       const int *itb, hipStream_t st) {
-  if constexpr (sizeof(T) == 8) {
-    if (cs) {
-      hipLaunchKernelGGL((k_pass1<T, 1>), dim3(nblocks), dim3(64), 0, st, groups, ng, m, it, nblocks, itb);
-      return;
-    }
-  }
-  hipLaunchKernelGGL((k_pass1<T, 0>), dim3(nblocks), dim3(64), 0, st, groups, ng, m, it, nblocks, itb);
+  // cs: stored (cos 2theta, sin 2theta) pairs (FP64), FP32 angles (FP32 solver)
+  if (cs)
+    hipLaunchKernelGGL((k_pass1<T, 1>), dim3(nblocks), dim3(64), 0, st, groups, ng, m, it, nblocks, itb);
+  else
+    hipLaunchKernelGGL((k_pass1<T, 0>), dim3(nblocks), dim3(64), 0, st, groups, ng, m, it, nblocks, itb);
 }
 
 template <typename T>

@@ -9,13 +9,16 @@ namespace mlmc {
 using mlmc_info_dev = ::mlmc_info;
 
 // KL synthesis of n samples (parameter rows rows[s], or s); optional outputs:
-// th64 [n][ld_out] FP64 angles, thlo [n][ld_out] bfloat16/FP32 angles, cs
-// [n][4 nelem][2] (cos 2theta, sin 2theta)
+// th64 [n][ld_out] FP64 angles (code != 0: their codes tan theta, the solver's
+// storage), thlo [n][ld_out] bfloat16/FP32 angles, cs [n][4 nelem][2]
+// (cos 2theta, sin 2theta)
 void launch_kl_synth(const double *modes, int K, const StripGeom &g, const double *xi, int ld_xi,
                      const int64_t *rows, int n, double *th64, void *thlo, int lo_fp32, int ld_out, double *cs,
-                     hipStream_t st);
+                     int code, hipStream_t st);
 // (cos 2theta, sin 2theta) of n angles
 void launch_theta_cs(const double *theta, double *cs, size_t n, hipStream_t st);
+// angle codes tan theta of n angles
+void launch_theta_code(const double *theta, double *code, size_t n, hipStream_t st);
 void launch_modes_nystrom(const double *gx, const double *gy, const double *coef, int ngrid, int K, double var,
                           double kappa, const StripGeom &g, double *modes, hipStream_t st);
 void launch_apply(const StripGeom &g, const StripMat &m, const double *theta, const double *x, double *y, int raw,
