@@ -86,6 +86,7 @@ struct mlmc_ctx {
   // graph replay of iteration blocks: capture stream, device iteration base,
   // and instantiated graphs keyed by the launch configuration they captured
   bool graphs = false;      // measured: no gain on MI355X (iterations are GPU-bound), so off by default
+  int sweep_rows = 0;       // operator-pass tile height: 0 = chosen per launch, else 4, 8 or 16
   hipStream_t cap_stream = nullptr;
   int *d_itb = nullptr;
   struct CachedGraph {
@@ -462,11 +463,14 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
     ng = nb2 = 0;
     for (int mode = 0; mode < 2; ++mode) {
       ngm[mode] = nb1m[mode] = 0;
-      // tile height of this operator-pass launch: the tallest tiles that still
-      // give the launch a few waves per SIMD across the chip (short tiles
-      // shorten the row walk of small batches); the sums do not depend on it
-      int ty = SWEEP_MAXTY;
-      for (; ty > SWEEP_RB; ty /= 2) {
+      // tile height of this operator-pass launch: 8 element rows, or 4 when 8
+      // leaves the device with fewer waves than it holds at once (small
+      // batches, single requests).  Measured on the 4-level benchmark, 8
+      // beats 16 and 4 at every lock-step level (16-row tiles leave a large,
+      // partly filled last round of waves).  The sums do not depend on it.
+      const long resident = pass1_resident_waves<T>(mode);
+      int ty = 2 * SWEEP_RB;
+      {
         long waves = 0;
         for (int k = 0; k < ng_all; ++k) {
           if (!alive[k] || (grp[k].S.cs != 0) != (mode == 1)) continue;
@@ -474,8 +478,9 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
           set_sweep_rows(gg, ty);
           waves += (long)gg.sw_ntiles * grp[k].n;
         }
-        if (waves >= 4096) break;
+        if (waves < resident) ty = SWEEP_RB;
       }
+      if (c->sweep_rows) ty = c->sweep_rows;
       for (int k = 0; k < ng_all; ++k) {
         if (!alive[k] || (grp[k].S.cs != 0) != (mode == 1)) continue;
         PcgGroup<T> &D = hg[ng++];
@@ -729,6 +734,9 @@ int build_strip(mlmc_ctx *c) {
     if (cfg.at("graphs").type != Json::Bool) throw std::runtime_error("graphs must be true or false");
     c->graphs = cfg.at("graphs").b;
   }
+  c->sweep_rows = (int)cfg.number_or("sweep_rows", 0);
+  if (c->sweep_rows != 0 && c->sweep_rows != SWEEP_RB && c->sweep_rows != 2 * SWEEP_RB && c->sweep_rows != SWEEP_MAXTY)
+    throw std::runtime_error("sweep_rows must be 0 (automatic), 4, 8 or 16");
   const std::string sm = cfg.string_or("small_solver", "auto");
   if (sm != "auto" && sm != "off") throw std::runtime_error("small_solver must be auto or off");
   int lds = 0;

@@ -14,6 +14,8 @@
 
 #include "strip_device.hpp"
 
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <type_traits>
 
@@ -1053,6 +1055,22 @@ void launch_pcg_pass1(const PcgGroup<T> *groups, int ng, int nblocks, const Stri
 }
 
 template <typename T>
+int pass1_resident_waves(int cs) {
+  static std::atomic<int> cached[2];
+  std::atomic<int> &v = cached[cs ? 1 : 0];
+  if (v.load() == 0) {
+    int dev = 0, ncu = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const void *f = cs ? (const void *)k_pass1<T, 1> : (const void *)k_pass1<T, 0>;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 64, 0);
+    (void)hipGetLastError();
+    v.store(std::max(1, per_cu) * std::max(1, ncu));
+  }
+  return v.load();
+}
+
+template <typename T>
 void launch_pcg_pass2(const PcgGroup<T> *groups, int ng, int nblocks, int it, const int *itb, hipStream_t st) {
   hipLaunchKernelGGL(k_pass2<T>, dim3(nblocks), dim3(256), 0, st, groups, ng, it, itb);
 }
@@ -1061,6 +1079,8 @@ template void launch_pcg_pass1<double>(const PcgGroup<double> *, int, int, const
                                        hipStream_t);
 template void launch_pcg_pass1<float>(const PcgGroup<float> *, int, int, const StripMat &, int, int, const int *,
                                       hipStream_t);
+template int pass1_resident_waves<double>(int);
+template int pass1_resident_waves<float>(int);
 template void launch_pcg_pass2<double>(const PcgGroup<double> *, int, int, int, const int *, hipStream_t);
 template void launch_pcg_pass2<float>(const PcgGroup<float> *, int, int, int, const int *, hipStream_t);
 

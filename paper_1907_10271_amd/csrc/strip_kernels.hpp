@@ -27,12 +27,16 @@ void launch_setup(const StripGeom &g, const StripMat &m, const PcgSlots &S, int 
                   hipStream_t st);
 // one lock-step PCG iteration over the groups of a device descriptor array
 // (nblocks = sum of sweep tiles x slots, resp. chunks x slots)
-// (cs: the groups' FP64 angle data holds (cos 2theta, sin 2theta) pairs).
+// (cs: the groups' FP64 angle data holds (cos 2theta, sin 2theta) pairs, or,
+// for the FP32 solver, FP32 angles instead of bfloat16 ones).
 // The iteration index is `it`, or *itb + it when itb is not null (graph
 // replay: the captured launches carry offsets, the base lives on the device).
 template <typename T>
 void launch_pcg_pass1(const PcgGroup<T> *groups, int ng, int nblocks, const StripMat &m, int it, int cs,
                       const int *itb, hipStream_t st);
+// operator-pass waves (one per work-group) the device keeps resident at once
+template <typename T>
+int pass1_resident_waves(int cs);
 template <typename T>
 void launch_pcg_pass2(const PcgGroup<T> *groups, int ng, int nblocks, int it, const int *itb, hipStream_t st);
 void launch_resid64(const StripGeom &g, const StripMat &m, const PcgSlots &D, const PcgState<float> &I,

@@ -366,14 +366,23 @@ def test_full_size_sampled_parity(precision):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_tile_height_follows_batch_without_changing_bits(precision):
-    """A batch of 56 512x128 samples runs the operator pass with 16-row tiles, a
-    lone sample with 4-row tiles; the partial sums are kept per 4-row block, so
-    the results are bit-identical."""
+    """The operator pass keeps its partial sums per 4-row block, so 16-, 8- and
+    4-row tiles (forced with sweep_rows) give the same bits as the automatic
+    choice, which follows the batch (8 rows for 56 samples of 512x128, 4 for a
+    lone sample)."""
+    import paper_1907_10271_amd as pk
     name, level, n = "strip_c2", 3, 56
     ctx = context(name)
     xi = dev(_rows(name, level, n))
-    qa, _, ia = ctx.solve_batch([(k, level, False) for k in range(n)], xi, precision=precision)
+    reqs = [(k, level, False) for k in range(n)]
+    qa, _, ia = ctx.solve_batch(reqs, xi, precision=precision)
     qa = qa.cpu().numpy()
+    for rows in (16, 8, 4):
+        c = pk.Context(dict(mi.load_config(name), sweep_rows=rows))
+        qr, _, ir = c.solve_batch(reqs, xi, precision=precision)
+        assert np.array_equal(qr.cpu().numpy(), qa), rows
+        assert np.array_equal(ir["iters_f"], ia["iters_f"]), rows
+        c.close()
     for k in (0, n - 1):
         qs, _, is_ = ctx.solve_batch([(k, level, False)], xi, precision=precision)
         assert qs.cpu().numpy()[0] == qa[k], (k, qs.cpu().numpy()[0], qa[k])
