@@ -212,17 +212,18 @@ int mlmc_level_stats(mlmc_ctx *ctx, int level, int n, const double *q_fine, cons
 
 /* Kernel timing for roofline measurement.  While enabled, every launch of the
  * two PCG passes (kernel 0: operator pass, fused p-update + A p + p.Ap;
- * kernel 1: vector pass, x/r update + r.z, r.r) is bracketed by HIP events on
+ * kernel 1: vector pass, x/z update + r.z, r.r) is bracketed by HIP events on
  * the stream of the solve.  mlmc_profile_read returns the summed event time
  * (ms), the number of launches and the algorithmic HBM bytes of those
  * launches (bytes each active sample must move per iteration times the
- * iterations it ran: operator pass reads r, dinv, p and writes A p, 4 vectors
- * of 16 B/node, plus 32 B/element of angles; vector pass reads x, r, p, A p,
- * dinv and writes x, r, p, 8 vectors of 16 B/node).  Timing adds a small
- * host-side cost per launch; results are unchanged. */
+ * iterations it ran; the residual is kept preconditioned, z = r / diag(A):
+ * operator pass reads z, p and writes A p, 3 vectors of 16 B/node, plus
+ * 32 B/element of angle codes or 64 B/element of pairs; vector pass reads x,
+ * z, p, A p, diag(A) and writes x, z, p, 8 vectors of 16 B/node).  Timing adds
+ * a small host-side cost per launch; results are unchanged. */
 int mlmc_profile_enable(mlmc_ctx *ctx, int on);
 /* kernel: 0 / 1 = FP64 operator / vector pass, 2 / 3 = the FP32 passes of the
- * mixed-precision inner solver (4 vectors of 8 B/node + 16 B/element of FP32
+ * mixed-precision inner solver (3 vectors of 8 B/node + 16 B/element of FP32
  * angles, or 8 B/element with "theta_storage": "bf16", and 8 vectors of
  * 8 B/node). */
 int mlmc_profile_read(mlmc_ctx *ctx, int kernel, double *total_ms, int64_t *launches, double *alg_bytes);

@@ -27,7 +27,7 @@ thread_local std::string g_create_error;
 
 struct StripPool {
   int cap = 0;
-  double *x = nullptr, *r = nullptr, *p = nullptr, *Ap = nullptr, *dinv = nullptr, *theta = nullptr;
+  double *x = nullptr, *z = nullptr, *p = nullptr, *Ap = nullptr, *dg = nullptr, *theta = nullptr;
   double *part_pap = nullptr, *part_rz = nullptr, *part_rr = nullptr, *rzs = nullptr;
   double *tol2 = nullptr, *bb = nullptr, *relres = nullptr, *qpart = nullptr;
   int *it_a = nullptr, *it_b = nullptr, *status = nullptr, *active = nullptr, *outidx = nullptr;
@@ -38,7 +38,7 @@ struct StripPool {
   double *b64 = nullptr, *m_part_rr = nullptr, *m_relres = nullptr, *f_rr_ref = nullptr;
   int *m_updates = nullptr, *f_ru = nullptr;
   void *theta16 = nullptr;  // inner-solver angles: bfloat16 or FP32
-  float *fx = nullptr, *fr = nullptr, *fp = nullptr, *fAp = nullptr, *fdinv = nullptr;
+  float *fx = nullptr, *fz = nullptr, *fp = nullptr, *fAp = nullptr, *fdg = nullptr;
   double *f_pap = nullptr, *f_rz = nullptr, *f_rr = nullptr, *f_rzs = nullptr, *f_tol2 = nullptr, *f_bb = nullptr,
          *f_relres = nullptr;
   int *f_it_a = nullptr, *f_it_b = nullptr, *f_status = nullptr, *f_active = nullptr;
@@ -201,10 +201,10 @@ size_t strip_slot_bytes(const StripGeom &g) {
 }
 
 void free_pool(mlmc_ctx *c, StripPool &p) {
-  void *bufs[] = {p.x, p.r, p.p, p.Ap, p.dinv, p.theta, p.part_pap, p.part_rz, p.part_rr, p.rzs, p.tol2, p.bb,
+  void *bufs[] = {p.x, p.z, p.p, p.Ap, p.dg, p.theta, p.part_pap, p.part_rz, p.part_rr, p.rzs, p.tol2, p.bb,
                   p.relres, p.qpart, p.it_a, p.it_b, p.status, p.active, p.outidx, p.rows,
                   p.b64, p.m_part_rr, p.m_relres, p.f_rr_ref, p.m_updates, p.f_ru,
-                  p.theta16, p.fx, p.fr, p.fp, p.fAp, p.fdinv, p.f_pap, p.f_rz, p.f_rr, p.f_rzs, p.f_tol2, p.f_bb,
+                  p.theta16, p.fx, p.fz, p.fp, p.fAp, p.fdg, p.f_pap, p.f_rz, p.f_rr, p.f_rzs, p.f_tol2, p.f_bb,
                   p.f_relres, p.f_it_a, p.f_it_b, p.f_status, p.f_active};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
@@ -234,10 +234,10 @@ int ensure_pool(mlmc_ctx *c, int level, int n, bool mixed = false) {
   StripPool &p = L.pool;
   const size_t vec = (size_t)2 * g.nnode * n;
   HIPCHK(c, dalloc(&p.x, vec));
-  HIPCHK(c, dalloc(&p.r, vec));
+  HIPCHK(c, dalloc(&p.z, vec));
   HIPCHK(c, dalloc(&p.p, vec));
   HIPCHK(c, dalloc(&p.Ap, vec));
-  HIPCHK(c, dalloc(&p.dinv, vec));
+  HIPCHK(c, dalloc(&p.dg, vec));
   HIPCHK(c, dalloc(&p.theta, (size_t)8 * g.nelem * n));
   HIPCHK(c, dalloc(&p.part_pap, (size_t)g.sw_npart * n));
   HIPCHK(c, dalloc(&p.part_rz, (size_t)2 * g.nchunks * n));
@@ -283,10 +283,10 @@ int alloc_mixed(mlmc_ctx *c, int level) {
   HIPCHK(c, dalloc(&p.f_ru, (size_t)n));
   HIPCHK(c, hipMalloc(&p.theta16, (size_t)4 * g.nelem * n * (c->theta_fp32 ? 4 : 2)));
   HIPCHK(c, dalloc(&p.fx, n2));
-  HIPCHK(c, dalloc(&p.fr, n2));
+  HIPCHK(c, dalloc(&p.fz, n2));
   HIPCHK(c, dalloc(&p.fp, n2));
   HIPCHK(c, dalloc(&p.fAp, n2));
-  HIPCHK(c, dalloc(&p.fdinv, n2));
+  HIPCHK(c, dalloc(&p.fdg, n2));
   HIPCHK(c, dalloc(&p.f_pap, (size_t)g.sw_npart * n));
   HIPCHK(c, dalloc(&p.f_rz, (size_t)2 * g.nchunks * n));
   HIPCHK(c, dalloc(&p.f_rr, (size_t)2 * g.nchunks * n));
@@ -310,10 +310,10 @@ PcgState<float> inner_of(mlmc_ctx *c, int level) {
   StripPool &p = c->lv[level].pool;
   PcgState<float> I{};
   I.x = p.fx;
-  I.r = p.fr;
+  I.z = p.fz;
   I.p = p.fp;
   I.Ap = p.fAp;
-  I.dinv = p.fdinv;
+  I.dg = p.fdg;
   I.theta = p.theta16;
   I.part_pap = p.f_pap;
   I.part_rz = p.f_rz;
@@ -355,10 +355,10 @@ PcgSlots slots_of(mlmc_ctx *c, int level, double rtol) {
   StripPool &p = c->lv[level].pool;
   PcgSlots S{};
   S.x = p.x;
-  S.r = p.r;
+  S.z = p.z;
   S.p = p.p;
   S.Ap = p.Ap;
-  S.dinv = p.dinv;
+  S.dg = p.dg;
   S.theta = p.theta;
   S.cs = c->lv[level].cs ? 1 : 0;
   S.part_pap = p.part_pap;
@@ -611,8 +611,8 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
       for (int k = 0; k < gr.n; ++k) its += c->h_iters[k];
       const double w = sizeof(T);
       const double wt = (sizeof(T) == 8) ? (gr.S.cs ? 64.0 : 32.0) : (c->theta_fp32 ? 16.0 : 8.0);  // angle bytes/element
-      c->prof_bytes[prof_k] += its * (4.0 * 2 * w * g.nnode + wt * g.nelem);
-      c->prof_bytes[prof_k + 1] += its * (8.0 * 2 * w * g.nnode);
+      c->prof_bytes[prof_k] += its * (3.0 * 2 * w * g.nnode + wt * g.nelem);  // z, p_old in; A p out
+      c->prof_bytes[prof_k + 1] += its * (8.0 * 2 * w * g.nnode);  // x, z, p_old, A p, dg in; x, z, p out
     }
   }
   return MLMC_OK;

@@ -65,9 +65,12 @@ struct StripMat {
 
 // per-slot PCG state of a level pool (device pointers); T = double for the
 // FP64 solver, float for the inner solver of the mixed-precision form
+// The residual is kept preconditioned: z = dinv r with dinv = 1/dg, dg the
+// Jacobi diagonal (1 on prescribed unknowns); r is recovered as dg z where it
+// is needed.  The operator pass then reads one vector less per node.
 template <typename T>
 struct PcgState {
-  T *x, *r, *p, *Ap, *dinv;        // [S][2 nnode]; all slots iterate in lock-step
+  T *x, *z, *p, *Ap, *dg;          // [S][2 nnode]; all slots iterate in lock-step
   const void *theta;               // [S][4 nelem]: double (FP64) or bfloat16 bits (float solver)
   double *part_pap;                // [S][sw_ntiles]
   double *part_rz, *part_rr;       // [2][S][nchunks]

@@ -114,6 +114,18 @@ __device__ __forceinline__ void sincos_small(double x, double *s, double *c) {
   *c = ((q + 1) & 2) ? -cc : cc;
 }
 
+// 1/d from the hardware reciprocal and Newton steps (two for FP64, one for
+// FP32: each doubles the correct bits of the estimate)
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  return fma(fma(-d, r, 1.0), r, r);
+}
+__device__ __forceinline__ float rcp_nr(float d) {
+  const float r = __builtin_amdgcn_rcpf(d);
+  return fmaf(fmaf(-d, r, 1.0f), r, r);
+}
+
 // Angles are kept by the solver as their tangent t = tan theta (clamped to
 // +-1e150, so that t^2 stays finite; for every double angle |cos theta| is far
 // above 1e-150; NaN stays NaN).  The rotation then needs no trigonometric series and no
@@ -128,10 +140,7 @@ __device__ __forceinline__ double angle_code(double th) {
   return fabs(t) > 1e150 ? copysign(1e150, t) : t;  // a NaN angle stays NaN
 }
 __device__ __forceinline__ void cs_of_code(double t, double *s2, double *c2) {
-  const double den = fma(t, t, 1.0);
-  double r = __builtin_amdgcn_rcp(den);
-  r = fma(fma(-den, r, 1.0), r, r);
-  r = fma(fma(-den, r, 1.0), r, r);
+  const double r = rcp_nr(fma(t, t, 1.0));
   *c2 = fma(-t, t, 1.0) * r;
   *s2 = (t + t) * r;
 }

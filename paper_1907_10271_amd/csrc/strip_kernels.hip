@@ -207,8 +207,9 @@ __global__ __launch_bounds__(TILE_THREADS) void k_apply(StripGeom g, StripMat m,
 }
 
 // ---------------------------------------------------------------- PCG set-up
-// b = -P K g and dinv = 1/diag(P K P + I - P); x = 0, r = b; partial sums of
-// r.z and r.r into parity buffer 0; slot marked active at iteration 0.
+// b = -P K g and dg = diag(P K P + I - P); x = 0, z = dinv b (dinv = 1/dg);
+// b and dinv also to b_out / dinv_out when given; slot marked active at
+// iteration 0.
 __global__ __launch_bounds__(TILE_THREADS) void k_setup(StripGeom g, StripMat m, PcgSlots S,
                                                         double *__restrict__ b_out, double *__restrict__ dinv_out) {
   __shared__ double eo[16][TILE_ELEMS];
@@ -255,12 +256,13 @@ __global__ __launch_bounds__(TILE_THREADS) void k_setup(StripGeom g, StripMat m,
     double diu, div, kgu, kgv;
     gather_node(eo, li, lj, 0, diu, div);
     gather_node(eo, li, lj, 8, kgu, kgv);
-    double bu = -kgu, bv = -kgv, du = 1.0 / diu, dv = 1.0 / div;
-    if (i == 0) { bu = 0.0; bv = 0.0; du = 1.0; dv = 1.0; }
-    if (i == g.nx) { bu = 0.0; du = 1.0; }
+    double bu = -kgu, bv = -kgv, gu = diu, gv = div;
+    if (i == 0) { bu = 0.0; bv = 0.0; gu = 1.0; gv = 1.0; }
+    if (i == g.nx) { bu = 0.0; gu = 1.0; }
+    const double du = 1.0 / gu, dv = 1.0 / gv;
     const size_t o = (size_t)s * 2 * g.nnode + 2 * ((size_t)j * g.nnx + i);
-    *reinterpret_cast<double2 *>(S.dinv + o) = make_double2(du, dv);
-    *reinterpret_cast<double2 *>(S.r + o) = make_double2(bu, bv);
+    *reinterpret_cast<double2 *>(S.dg + o) = make_double2(gu, gv);
+    *reinterpret_cast<double2 *>(S.z + o) = make_double2(du * bu, dv * bv);
     *reinterpret_cast<double2 *>(S.x + o) = make_double2(0.0, 0.0);
     if (b_out) *reinterpret_cast<double2 *>(b_out + o) = make_double2(bu, bv);
     if (dinv_out) *reinterpret_cast<double2 *>(dinv_out + o) = make_double2(du, dv);
@@ -272,8 +274,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_setup(StripGeom g, StripMat m,
   }
 }
 
-// initial partial sums of r.z and r.r (z = dinv r) per vector-pass chunk,
-// into parity buffer 0
+// initial partial sums of r.z and r.r (r = dg z) per vector-pass chunk, into
+// parity buffer 0
 __global__ __launch_bounds__(256) void k_init_partials(StripGeom g, PcgSlots S) {
   __shared__ double red4[4];
   const int s = blockIdx.y, c = blockIdx.x;
@@ -282,10 +284,11 @@ __global__ __launch_bounds__(256) void k_init_partials(StripGeom g, PcgSlots S) 
   for (int k = 0; k < CHUNK / 256; ++k) {
     const int node = c * CHUNK + k * 256 + threadIdx.x;
     if (node < g.nnode) {
-      const double2 rv = *reinterpret_cast<const double2 *>(S.r + vb + 2 * (size_t)node);
-      const double2 dv = *reinterpret_cast<const double2 *>(S.dinv + vb + 2 * (size_t)node);
-      prz += rv.x * (dv.x * rv.x) + rv.y * (dv.y * rv.y);
-      prr += rv.x * rv.x + rv.y * rv.y;
+      const double2 zv = *reinterpret_cast<const double2 *>(S.z + vb + 2 * (size_t)node);
+      const double2 gv = *reinterpret_cast<const double2 *>(S.dg + vb + 2 * (size_t)node);
+      const double ru = gv.x * zv.x, rv = gv.y * zv.y;
+      prz += ru * zv.x + rv * zv.y;
+      prr += ru * ru + rv * rv;
     }
   }
   prz = block_sum(prz, red4);
@@ -327,18 +330,18 @@ __device__ __forceinline__ void st2(T *p, T a, T b) {
   gstore(p, v);
 }
 
-// r, dinv and p_old of node (i, jr).  The loads are issued for every lane,
-// from the nearest node inside the mesh, with no branch: the wait for the
-// current row then covers exactly the loads issued before it and leaves the
-// next row's in flight.  Values of nodes outside the mesh or the window are
-// never used (their elements are skipped and their nodes not owned).  z = dinv r
-// is formed where the row is used, not here, for the same reason.
+// z and p_old of node (i, jr).  The loads are issued for every lane, from the
+// nearest node inside the mesh, with no branch: the wait for the current row
+// then covers exactly the loads issued before it and leaves the next row's in
+// flight.  Values of nodes outside the mesh or the window are never used
+// (their elements are skipped and their nodes not owned).  p is formed where
+// the row is used, not here, for the same reason.
 template <typename T>
 struct RowVals {
-  T ru, rv, du, dv, qu, qv;
+  T zu, zv, qu, qv;
   // p = z + beta p_old (p_old = 0 before the first iteration, wp false)
-  __device__ __forceinline__ T pu(T beta, bool wp) const { return fma(beta, wp ? qu : T(0), du * ru); }
-  __device__ __forceinline__ T pv(T beta, bool wp) const { return fma(beta, wp ? qv : T(0), dv * rv); }
+  __device__ __forceinline__ T pu(T beta, bool wp) const { return fma(beta, wp ? qu : T(0), zu); }
+  __device__ __forceinline__ T pv(T beta, bool wp) const { return fma(beta, wp ? qv : T(0), zv); }
 };
 
 __device__ __forceinline__ int clampi(int v, int hi) { return min(max(v, 0), hi); }
@@ -346,14 +349,11 @@ __device__ __forceinline__ int clampi(int v, int hi) { return min(max(v, 0), hi)
 template <typename T>
 __device__ __forceinline__ RowVals<T> load_row(const StripGeom &g, const PcgState<T> &S, size_t vb, int ic, int jr) {
   const size_t o = vb + 2 * ((size_t)clampi(jr, g.nny - 1) * g.nnx + ic);
-  const auto rv = ld2(S.r + o);
-  const auto dv = ld2(S.dinv + o);
+  const auto zv = ld2(S.z + o);
   const auto po = ld2(S.p + o);  // not written before the first iteration: not used there
   RowVals<T> v;
-  v.ru = rv.x;
-  v.rv = rv.y;
-  v.du = dv.x;
-  v.dv = dv.y;
+  v.zu = zv.x;
+  v.zv = zv.y;
   v.qu = po.x;
   v.qv = po.y;
   return v;
@@ -568,8 +568,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
 // ---------------------------------------------------------------- PCG pass 2
 // alpha = rz / p.Ap; p = z + beta p_old (bit-identical to pass 1); x += alpha p;
-// r -= alpha Ap; store p; partial r.z (z = dinv r) and r.r per chunk of CHUNK
-// consecutive nodes (all loads issued before the reduction of p.Ap)
+// r = dg z - alpha Ap; z = r / dg; store p, x, z; partial r.z and r.r per
+// chunk of CHUNK consecutive nodes (all loads issued before the reduction of
+// p.Ap)
 template <typename T>
 __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G, int ng, int it_off,
                                               const int *__restrict__ itb) {
@@ -593,18 +594,19 @@ __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G
   const double rz = S.rzs[(size_t)par * S.S + s];
   const double rz_prev = (it > 0) ? S.rzs[(size_t)(par ^ 1) * S.S + s] : 1.0;
   const size_t vb = (size_t)s * 2 * g.nnode;
-  P2 pv[PER], av[PER], xv[PER], rv[PER], dv[PER];
+  P2 pv[PER], av[PER], xv[PER], zv[PER], gv[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int node = c * CHUNK + k * 256 + threadIdx.x;
-    pv[k].x = pv[k].y = av[k].x = av[k].y = xv[k].x = xv[k].y = rv[k].x = rv[k].y = dv[k].x = dv[k].y = T(0);
+    pv[k].x = pv[k].y = av[k].x = av[k].y = xv[k].x = xv[k].y = zv[k].x = zv[k].y = T(0);
+    gv[k].x = gv[k].y = T(1);
     if (node < g.nnode) {
       const size_t o = vb + 2 * (size_t)node;
       if (it > 0) pv[k] = ld2(S.p + o);
       av[k] = ld2(S.Ap + o);
       xv[k] = ld2(S.x + o);
-      rv[k] = ld2(S.r + o);
-      dv[k] = ld2(S.dinv + o);
+      zv[k] = ld2(S.z + o);
+      gv[k] = ld2(S.dg + o);
     }
   }
   const double pap = block_sum(ppap, red4);  // publishes flag
@@ -624,15 +626,16 @@ __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G
     const int node = c * CHUNK + k * 256 + threadIdx.x;
     if (node < g.nnode) {
       const size_t o = vb + 2 * (size_t)node;
-      const T pnx = fma(beta, pv[k].x, dv[k].x * rv[k].x);
-      const T pny = fma(beta, pv[k].y, dv[k].y * rv[k].y);
+      const T pnx = fma(beta, pv[k].x, zv[k].x);
+      const T pny = fma(beta, pv[k].y, zv[k].y);
       const T xx = fma(alpha, pnx, xv[k].x), xy = fma(alpha, pny, xv[k].y);
-      const T rx = fma(-alpha, av[k].x, rv[k].x), ry = fma(-alpha, av[k].y, rv[k].y);
+      const T rx = fma(-alpha, av[k].x, gv[k].x * zv[k].x), ry = fma(-alpha, av[k].y, gv[k].y * zv[k].y);
+      const T znx = rx * rcp_nr(gv[k].x), zny = ry * rcp_nr(gv[k].y);
       st2(S.p + o, pnx, pny);
       st2(S.x + o, xx, xy);
-      st2(S.r + o, rx, ry);
+      st2(S.z + o, znx, zny);
       const double drx = rx, dry = ry;
-      prz += drx * ((double)dv[k].x * drx) + dry * ((double)dv[k].y * dry);
+      prz += drx * (double)znx + dry * (double)zny;
       prr += drx * drx + dry * dry;
     }
   }
@@ -649,7 +652,8 @@ __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G
 // ---------------------------------------------------------------- mixed precision
 // Reliable update of slot s (requested by pass 1 of iteration it): the FP64
 // residual r = b - A (x64 + x32) with the FP64 angles (column sweep as in
-// pass 1, node values = x), partial ||r||^2 per sweep tile.
+// pass 1, node values = x), stored preconditioned (z64 = r / dg); partial
+// ||r||^2 per sweep tile.
 __global__ __launch_bounds__(64) void k_resid64(StripGeom g, StripMat m, PcgSlots D, PcgState<float> I, MixedState M,
                                                 int it_off, int every, int nblocks, const int *__restrict__ itb) {
   const int it = itb ? __builtin_amdgcn_readfirstlane(*itb) + it_off : it_off;
@@ -709,8 +713,9 @@ __global__ __launch_bounds__(64) void k_resid64(StripGeom g, StripMat m, PcgSlot
       if (i == g.nx) yu = plu;
       const size_t o = vb + 2 * ((size_t)ey * g.nnx + i);
       const double2 bv = *reinterpret_cast<const double2 *>(M.b + o);
+      const double2 gv = *reinterpret_cast<const double2 *>(D.dg + o);
       const double ru = bv.x - yu, rv = bv.y - yv;
-      *reinterpret_cast<double2 *>(D.r + o) = make_double2(ru, rv);
+      *reinterpret_cast<double2 *>(D.z + o) = make_double2(ru * rcp_nr(gv.x), rv * rcp_nr(gv.y));
       part += ru * ru + rv * rv;
     }
     if (k >= 1 && ((ey + 1) % SWEEP_RB == 0 || ey + 1 == row_end)) {
@@ -727,7 +732,7 @@ __global__ __launch_bounds__(64) void k_resid64(StripGeom g, StripMat m, PcgSlot
   }
 }
 
-// Second half of a reliable update: x64 += x32, x32 = 0, r32 = r64; the FP64
+// Second half of a reliable update: x64 += x32, x32 = 0, z32 = z64; the FP64
 // stopping test ||r|| <= rtol ||b||; the inner partial sums for the next
 // iteration (parity of it + 1) and the slot's restart.
 __global__ __launch_bounds__(256) void k_ru_apply(StripGeom g, PcgSlots D, PcgState<float> I, MixedState M, int it_off,
@@ -759,12 +764,12 @@ __global__ __launch_bounds__(256) void k_ru_apply(StripGeom g, PcgSlots D, PcgSt
       x.y += (double)d.y;
       *reinterpret_cast<double2 *>(D.x + o) = x;
       *reinterpret_cast<float2 *>(I.x + o) = make_float2(0.0f, 0.0f);
-      const double2 rv = *reinterpret_cast<const double2 *>(D.r + o);
-      const float2 r32 = make_float2((float)rv.x, (float)rv.y);
-      *reinterpret_cast<float2 *>(I.r + o) = r32;
-      const float2 d32 = *reinterpret_cast<const float2 *>(I.dinv + o);
-      const double a = r32.x, b = r32.y;
-      prz += a * ((double)d32.x * a) + b * ((double)d32.y * b);
+      const double2 zv = *reinterpret_cast<const double2 *>(D.z + o);
+      const float2 z32 = make_float2((float)zv.x, (float)zv.y);
+      *reinterpret_cast<float2 *>(I.z + o) = z32;
+      const float2 g32 = *reinterpret_cast<const float2 *>(I.dg + o);
+      const double a = g32.x * z32.x, b = g32.y * z32.y;  // r as the inner vector pass forms it
+      prz += a * (double)z32.x + b * (double)z32.y;
       pr2 += a * a + b * b;
     }
   }
@@ -786,7 +791,7 @@ __global__ __launch_bounds__(256) void k_ru_apply(StripGeom g, PcgSlots D, PcgSt
 }
 
 // start of a mixed-precision solve (after the FP64 set-up): FP32 copies of
-// r = b and dinv, x32 = 0, initial inner partial sums; slot flags
+// z = dinv b and dg, x32 = 0, initial inner partial sums; slot flags
 __global__ __launch_bounds__(256) void k_mixed_start(StripGeom g, PcgSlots D, PcgState<float> I, MixedState M) {
   __shared__ double red4[4];
   const int s = blockIdx.y, c = blockIdx.x;
@@ -796,15 +801,15 @@ __global__ __launch_bounds__(256) void k_mixed_start(StripGeom g, PcgSlots D, Pc
     const int node = c * CHUNK + k * 256 + threadIdx.x;
     if (node < g.nnode) {
       const size_t o = vb + 2 * (size_t)node;
-      const double2 rv = *reinterpret_cast<const double2 *>(D.r + o);
-      const double2 dv = *reinterpret_cast<const double2 *>(D.dinv + o);
-      const float2 d32 = make_float2((float)dv.x, (float)dv.y);
-      const float2 r32 = make_float2((float)rv.x, (float)rv.y);
-      *reinterpret_cast<float2 *>(I.dinv + o) = d32;
-      *reinterpret_cast<float2 *>(I.r + o) = r32;
+      const double2 zv = *reinterpret_cast<const double2 *>(D.z + o);
+      const double2 gv = *reinterpret_cast<const double2 *>(D.dg + o);
+      const float2 g32 = make_float2((float)gv.x, (float)gv.y);
+      const float2 z32 = make_float2((float)zv.x, (float)zv.y);
+      *reinterpret_cast<float2 *>(I.dg + o) = g32;
+      *reinterpret_cast<float2 *>(I.z + o) = z32;
       *reinterpret_cast<float2 *>(I.x + o) = make_float2(0.0f, 0.0f);
-      const double a = r32.x, b = r32.y;
-      prz += a * ((double)d32.x * a) + b * ((double)d32.y * b);
+      const double a = g32.x * z32.x, b = g32.y * z32.y;  // r as the inner vector pass forms it
+      prz += a * (double)z32.x + b * (double)z32.y;
       pr2 += a * a + b * b;
     }
   }

@@ -49,22 +49,24 @@ __global__ __launch_bounds__(SMALL_MAX_THREADS) void k_small_solve(StripGeom g, 
   const double *th_s = (const double *)S.theta + (size_t)s * (S.cs ? 8 : 4) * g.nelem;
   const int hx = g.nx / 2, ncol = hx * (g.ny / 2);  // elements per colour
 
-  // set-up state from the lifting kernel: r = b, dinv, x = 0
-  const double *rs = S.r + (size_t)s * 2 * g.nnode, *ds = S.dinv + (size_t)s * 2 * g.nnode;
-  double x[MAXN][2], r[MAXN][2], dg[MAXN][2];
+  // set-up state from the lifting kernel: z = dinv b and dg; here r = dg z, dinv = 1/dg
+  const double *rs = S.z + (size_t)s * 2 * g.nnode, *ds = S.dg + (size_t)s * 2 * g.nnode;
+  double x[MAXN][2], r[MAXN][2], dinv[MAXN][2];
   double prz = 0.0, prr = 0.0;
 #pragma unroll
   for (int j = 0; j < MAXN; ++j) {
     const int k = tid + j * nt;
     x[j][0] = x[j][1] = r[j][0] = r[j][1] = 0.0;
-    dg[j][0] = dg[j][1] = 1.0;
+    dinv[j][0] = dinv[j][1] = 1.0;
     if (k < g.nnode) {
-      const double2 bv = *reinterpret_cast<const double2 *>(rs + 2 * (size_t)k);
-      const double2 dv = *reinterpret_cast<const double2 *>(ds + 2 * (size_t)k);
+      const double2 zv = *reinterpret_cast<const double2 *>(rs + 2 * (size_t)k);
+      const double2 gv = *reinterpret_cast<const double2 *>(ds + 2 * (size_t)k);
+      const double2 bv = make_double2(gv.x * zv.x, gv.y * zv.y);
+      const double2 dv = make_double2(1.0 / gv.x, 1.0 / gv.y);
       r[j][0] = bv.x;
       r[j][1] = bv.y;
-      dg[j][0] = dv.x;
-      dg[j][1] = dv.y;
+      dinv[j][0] = dv.x;
+      dinv[j][1] = dv.y;
       prz += bv.x * (dv.x * bv.x) + bv.y * (dv.y * bv.y);
       prr += bv.x * bv.x + bv.y * bv.y;
     }
@@ -87,8 +89,8 @@ __global__ __launch_bounds__(SMALL_MAX_THREADS) void k_small_solve(StripGeom g, 
       const int k = tid + j * nt;
       if (k < g.nnode) {
         const double pu = (it == 0) ? 0.0 : pl[2 * k], pv = (it == 0) ? 0.0 : pl[2 * k + 1];
-        pl[2 * k] = fma(beta, pu, dg[j][0] * r[j][0]);
-        pl[2 * k + 1] = fma(beta, pv, dg[j][1] * r[j][1]);
+        pl[2 * k] = fma(beta, pu, dinv[j][0] * r[j][0]);
+        pl[2 * k + 1] = fma(beta, pv, dinv[j][1] * r[j][1]);
         al[2 * k] = 0.0;
         al[2 * k + 1] = 0.0;
       }
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(SMALL_MAX_THREADS) void k_small_solve(StripGeom g, 
         x[j][1] = fma(alpha, pv, x[j][1]);
         r[j][0] = fma(-alpha, yu, r[j][0]);
         r[j][1] = fma(-alpha, yv, r[j][1]);
-        prz += r[j][0] * (dg[j][0] * r[j][0]) + r[j][1] * (dg[j][1] * r[j][1]);
+        prz += r[j][0] * (dinv[j][0] * r[j][0]) + r[j][1] * (dinv[j][1] * r[j][1]);
         prr += r[j][0] * r[j][0] + r[j][1] * r[j][1];
       }
     }
