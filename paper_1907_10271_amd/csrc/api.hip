@@ -29,8 +29,8 @@ struct StripPool {
   int cap = 0;
   double *x = nullptr, *z = nullptr, *p = nullptr, *Ap = nullptr, *dg = nullptr, *theta = nullptr;
   double *part_pap = nullptr, *part_rz = nullptr, *part_rr = nullptr, *rzs = nullptr;
-  double *tol2 = nullptr, *bb = nullptr, *relres = nullptr, *qpart = nullptr;
-  int *it_a = nullptr, *it_b = nullptr, *status = nullptr, *active = nullptr, *outidx = nullptr;
+  double *tol2 = nullptr, *bb = nullptr, *relres = nullptr, *qpart = nullptr, *alpha = nullptr;
+  int *it_a = nullptr, *it_b = nullptr, *status = nullptr, *active = nullptr, *outidx = nullptr, *xpend = nullptr;
   int64_t *rows = nullptr;
   size_t bytes = 0;
   // mixed precision (allocated on first use): FP64 rhs, FP32 or BF16 angles, FP32 inner solver
@@ -193,7 +193,7 @@ size_t strip_mixed_slot_bytes(const StripGeom &g) {
 
 size_t strip_slot_bytes(const StripGeom &g) {
   const size_t vec = (size_t)2 * g.nnode * sizeof(double);
-  return 5 * vec                                      // x, r, p, Ap, dinv
+  return 5 * vec                                      // x, z, p, Ap, dg
          + (size_t)8 * g.nelem * sizeof(double)       // (cos 2theta, sin 2theta) per Gauss point
          + (size_t)(g.sw_npart + 4 * g.nchunks) * sizeof(double)   // partials
          + (size_t)qoi_parts(g) * sizeof(double)      // QoI partial maxima
@@ -202,7 +202,7 @@ size_t strip_slot_bytes(const StripGeom &g) {
 
 void free_pool(mlmc_ctx *c, StripPool &p) {
   void *bufs[] = {p.x, p.z, p.p, p.Ap, p.dg, p.theta, p.part_pap, p.part_rz, p.part_rr, p.rzs, p.tol2, p.bb,
-                  p.relres, p.qpart, p.it_a, p.it_b, p.status, p.active, p.outidx, p.rows,
+                  p.relres, p.qpart, p.alpha, p.it_a, p.it_b, p.status, p.active, p.outidx, p.xpend, p.rows,
                   p.b64, p.m_part_rr, p.m_relres, p.f_rr_ref, p.m_updates, p.f_ru,
                   p.theta16, p.fx, p.fz, p.fp, p.fAp, p.fdg, p.f_pap, p.f_rz, p.f_rr, p.f_rzs, p.f_tol2, p.f_bb,
                   p.f_relres, p.f_it_a, p.f_it_b, p.f_status, p.f_active};
@@ -246,12 +246,15 @@ int ensure_pool(mlmc_ctx *c, int level, int n, bool mixed = false) {
   HIPCHK(c, dalloc(&p.tol2, (size_t)n));
   HIPCHK(c, dalloc(&p.bb, (size_t)n));
   HIPCHK(c, dalloc(&p.relres, (size_t)n));
+  HIPCHK(c, dalloc(&p.alpha, (size_t)2 * n));
   HIPCHK(c, dalloc(&p.qpart, (size_t)qoi_parts(g) * n));
   HIPCHK(c, dalloc(&p.it_a, (size_t)n));
   HIPCHK(c, dalloc(&p.it_b, (size_t)n));
   HIPCHK(c, dalloc(&p.status, (size_t)n));
   HIPCHK(c, dalloc(&p.active, (size_t)n));
   HIPCHK(c, dalloc(&p.outidx, (size_t)n));
+  HIPCHK(c, dalloc(&p.xpend, (size_t)n));
+  HIPCHK(c, hipMemset(p.xpend, 0, sizeof(int) * n));
   HIPCHK(c, dalloc(&p.rows, (size_t)n));
   HIPCHK(c, hipMemset(p.active, 0, sizeof(int) * n));
   p.cap = n;
@@ -368,6 +371,8 @@ PcgSlots slots_of(mlmc_ctx *c, int level, double rtol) {
   S.tol2 = p.tol2;
   S.bb = p.bb;
   S.relres = p.relres;
+  S.alpha = p.alpha;
+  S.xpend = p.xpend;
   S.it_a = p.it_a;
   S.it_b = p.it_b;
   S.status = p.status;
@@ -612,7 +617,16 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
       const double w = sizeof(T);
       const double wt = (sizeof(T) == 8) ? (gr.S.cs ? 64.0 : 32.0) : (c->theta_fp32 ? 16.0 : 8.0);  // angle bytes/element
       c->prof_bytes[prof_k] += its * (3.0 * 2 * w * g.nnode + wt * g.nelem);  // z, p_old in; A p out
-      c->prof_bytes[prof_k + 1] += its * (8.0 * 2 * w * g.nnode);  // x, z, p_old, A p, dg in; x, z, p out
+      // x, z, p_old, A p, dg in; x, z, p out (FP64: x only every second iteration)
+      double vec = 8.0 * its;
+      if (sizeof(T) == 8) {
+        vec = 0.0;
+        for (int k = 0; k < gr.n; ++k) {
+          const int ik = c->h_iters[k];
+          vec += 6.0 * ((ik + 1) / 2) + 8.0 * (ik / 2);
+        }
+      }
+      c->prof_bytes[prof_k + 1] += vec * 2 * w * g.nnode;
     }
   }
   return MLMC_OK;
@@ -633,7 +647,11 @@ int run_pcg(mlmc_ctx *c, const std::vector<SolveGroup> &sg, hipStream_t st) {
     ig.push_back({x.level, x.S, x.n});
   }
   HIPCHK(c, hipGetLastError());
-  return pcg_iterate<double>(c, ig, st, 0, [](int, const std::vector<char> &, const int *, hipStream_t) {});
+  if (int rc = pcg_iterate<double>(c, ig, st, 0, [](int, const std::vector<char> &, const int *, hipStream_t) {}))
+    return rc;
+  for (const auto &x : sg) launch_x_flush(c->lv[x.level].g, x.S, x.n, st);
+  HIPCHK(c, hipGetLastError());
+  return MLMC_OK;
 }
 
 // coarse level: set-up + PCG to completion by one work-group per sample, FP64

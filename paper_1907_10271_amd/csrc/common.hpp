@@ -90,6 +90,12 @@ struct PcgState {
   double ru2;
   double *rr_ref;                  // [S] ||r||^2 at the last FP64 residual
   int *ru;                         // [S]
+  // FP64 solver: x takes two steps at once, at odd iterations (the even
+  // iteration's p is the next one's p_old, already loaded there).  alpha of
+  // the last step [2][S] (by parity); xpend[s] = it + 1 when the step of
+  // iteration it is still to be added to x (set-up clears it), else 0
+  double *alpha;
+  int *xpend;
 };
 using PcgSlots = PcgState<double>;
 

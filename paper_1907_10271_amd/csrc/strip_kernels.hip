@@ -271,6 +271,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_setup(StripGeom g, StripMat m,
     S.it_a[s] = 0;
     S.status[s] = S_OK;
     S.active[s] = 1;
+    if (S.xpend) S.xpend[s] = 0;
   }
 }
 
@@ -570,7 +571,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // alpha = rz / p.Ap; p = z + beta p_old (bit-identical to pass 1); x += alpha p;
 // r = dg z - alpha Ap; z = r / dg; store p, x, z; partial r.z and r.r per
 // chunk of CHUNK consecutive nodes (all loads issued before the reduction of
-// p.Ap)
+// p.Ap).  FP64: x moves at odd iterations only, by both steps in the order of
+// one step at a time (the even step's p is this iteration's p_old), so x is
+// read and written every second iteration with the same bits.
 template <typename T>
 __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G, int ng, int it_off,
                                               const int *__restrict__ itb) {
@@ -593,6 +596,9 @@ __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G
   for (int k = threadIdx.x; k < g.sw_npart; k += 256) ppap += S.part_pap[(size_t)s * g.sw_npart + k];
   const double rz = S.rzs[(size_t)par * S.S + s];
   const double rz_prev = (it > 0) ? S.rzs[(size_t)(par ^ 1) * S.S + s] : 1.0;
+  constexpr bool lazy = sizeof(T) == 8;
+  const bool xstep = !lazy || (it & 1);
+  const T alpha_prev = (lazy && xstep) ? (T)S.alpha[(size_t)(par ^ 1) * S.S + s] : T(0);
   const size_t vb = (size_t)s * 2 * g.nnode;
   P2 pv[PER], av[PER], xv[PER], zv[PER], gv[PER];
 #pragma unroll
@@ -604,7 +610,7 @@ __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G
       const size_t o = vb + 2 * (size_t)node;
       if (it > 0) pv[k] = ld2(S.p + o);
       av[k] = ld2(S.Ap + o);
-      xv[k] = ld2(S.x + o);
+      if (xstep) xv[k] = ld2(S.x + o);
       zv[k] = ld2(S.z + o);
       gv[k] = ld2(S.dg + o);
     }
@@ -628,11 +634,17 @@ __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G
       const size_t o = vb + 2 * (size_t)node;
       const T pnx = fma(beta, pv[k].x, zv[k].x);
       const T pny = fma(beta, pv[k].y, zv[k].y);
-      const T xx = fma(alpha, pnx, xv[k].x), xy = fma(alpha, pny, xv[k].y);
       const T rx = fma(-alpha, av[k].x, gv[k].x * zv[k].x), ry = fma(-alpha, av[k].y, gv[k].y * zv[k].y);
       const T znx = rx * rcp_nr(gv[k].x), zny = ry * rcp_nr(gv[k].y);
       st2(S.p + o, pnx, pny);
-      st2(S.x + o, xx, xy);
+      if (xstep) {
+        T xx = xv[k].x, xy = xv[k].y;
+        if (lazy) {
+          xx = fma(alpha_prev, pv[k].x, xx);
+          xy = fma(alpha_prev, pv[k].y, xy);
+        }
+        st2(S.x + o, fma(alpha, pnx, xx), fma(alpha, pny, xy));
+      }
       st2(S.z + o, znx, zny);
       const double drx = rx, dry = ry;
       prz += drx * (double)znx + dry * (double)zny;
@@ -645,7 +657,34 @@ __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G
     const size_t pb = ((size_t)(par ^ 1) * S.S + s) * g.nchunks + c;
     S.part_rz[pb] = prz;
     S.part_rr[pb] = prr;
-    if (c == 0) S.it_a[s] = it + 1;
+    if (c == 0) {
+      S.it_a[s] = it + 1;
+      if (lazy) {
+        S.alpha[(size_t)par * S.S + s] = (double)alpha;
+        S.xpend[s] = xstep ? 0 : it + 1;
+      }
+    }
+  }
+}
+
+// x += alpha p for slots whose last completed vector pass left its step
+// pending (FP64 solver, after the iterations)
+__global__ __launch_bounds__(256) void k_x_flush(StripGeom g, PcgSlots S) {
+  const int s = blockIdx.y, c = blockIdx.x;
+  const int pend = S.xpend[s];
+  if (!pend) return;
+  const double alpha = S.alpha[(size_t)((pend - 1) & 1) * S.S + s];
+  const size_t vb = (size_t)s * 2 * g.nnode;
+  for (int k = 0; k < CHUNK / 256; ++k) {
+    const int node = c * CHUNK + k * 256 + threadIdx.x;
+    if (node < g.nnode) {
+      const size_t o = vb + 2 * (size_t)node;
+      const double2 pv = *reinterpret_cast<const double2 *>(S.p + o);
+      double2 xv = *reinterpret_cast<const double2 *>(S.x + o);
+      xv.x = fma(alpha, pv.x, xv.x);
+      xv.y = fma(alpha, pv.y, xv.y);
+      *reinterpret_cast<double2 *>(S.x + o) = xv;
+    }
   }
 }
 
@@ -1114,6 +1153,11 @@ void launch_add_int(int *p, int v, hipStream_t st) { hipLaunchKernelGGL(k_add_in
 void launch_mixed_start(const StripGeom &g, const PcgSlots &D, const PcgState<float> &I, const MixedState &M, int n,
                         hipStream_t st) {
   hipLaunchKernelGGL(k_mixed_start, dim3(g.nchunks, n), dim3(256), 0, st, g, D, I, M);
+}
+
+void launch_x_flush(const StripGeom &g, const PcgSlots &S, int n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_x_flush, dim3(g.nchunks, n), dim3(256), 0, st, g, S);
 }
 
 void launch_mixed_flush(const StripGeom &g, const PcgSlots &D, const PcgState<float> &I, int n, hipStream_t st) {

@@ -48,6 +48,8 @@ void launch_set_int(int *p, int v, hipStream_t st);
 void launch_add_int(int *p, int v, hipStream_t st);
 void launch_mixed_start(const StripGeom &g, const PcgSlots &D, const PcgState<float> &I, const MixedState &M, int n,
                         hipStream_t st);
+// after the FP64 iterations: add the pending step of slots 0..n-1 to x
+void launch_x_flush(const StripGeom &g, const PcgSlots &S, int n, hipStream_t st);
 void launch_mixed_flush(const StripGeom &g, const PcgSlots &D, const PcgState<float> &I, int n, hipStream_t st);
 int qoi_parts(const StripGeom &g);
 // QoI of n slots, written through out_idx: entries below coarse_base go to
