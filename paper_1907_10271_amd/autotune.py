@@ -6,8 +6,8 @@ combination of
 * engine: ``small`` (one work-group solves a whole sample, PCG state on chip;
   only where it fits) or ``lockstep`` (all samples of a batch iterate together
   through the column-sweep operator pass and the vector pass), and
-* angle storage: ``theta`` (angles, cos/sin 2theta evaluated every
-  iteration) or ``cs`` (stored cos/sin 2theta pairs, twice the bytes),
+* angle storage: ``theta`` (angle codes tan theta, cos/sin 2theta formed
+  every iteration) or ``cs`` (stored cos/sin 2theta pairs, twice the bytes),
 
 on a batch of uncoupled samples sized to fill the GPU, and keeps the fastest.
 The result, keyed by mesh (``"NXxNY"``), is written as JSON; contexts created
