@@ -327,7 +327,8 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
-                     "launches": p1["launches"],
+                     "timed_launches": p1["launches"],
+                     "timing": "HIP events around the passes of one iteration in the middle of every 32",
                      "avg_launch_us": round(p1["ms"] * 1e3 / p1["launches"], 3) if p1["launches"] else None,
                      "alg_bytes_per_launch": round(p1["bytes"] / p1["launches"], 1) if p1["launches"] else None},
         "vector_pass": {"kernel": "k_pass2",

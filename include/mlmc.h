@@ -210,17 +210,19 @@ int mlmc_level_stats(mlmc_ctx *ctx, int level, int n, const double *q_fine, cons
 
 /* ------------------------------------------------------------ diagnostics */
 
-/* Kernel timing for roofline measurement.  While enabled, every launch of the
+/* Kernel timing for roofline measurement.  While enabled, the launches of the
  * two PCG passes (kernel 0: operator pass, fused p-update + A p + p.Ap;
- * kernel 1: vector pass, x/z update + r.z, r.r) is bracketed by HIP events on
- * the stream of the solve.  mlmc_profile_read returns the summed event time
- * (ms), the number of launches and the algorithmic HBM bytes of those
- * launches (bytes each active sample must move per iteration times the
- * iterations it ran; the residual is kept preconditioned, z = r / diag(A):
+ * kernel 1: vector pass, x/z update + r.z, r.r) of one iteration in the
+ * middle of every block of 32 iterations are bracketed by HIP events on the
+ * stream of the solve (timing every launch would slow the solve by about 7%).
+ * mlmc_profile_read returns the summed event time (ms) and the number of
+ * those timed launches, and the algorithmic HBM bytes of exactly those
+ * launches (the bytes each sample active in the timed iteration must move;
+ * the residual is kept preconditioned, z = r / diag(A):
  * operator pass reads z, p and writes A p, 3 vectors of 16 B/node, plus
  * 32 B/element of angle codes or 64 B/element of pairs; vector pass reads x,
- * z, p, A p, diag(A) and writes x, z, p, 8 vectors of 16 B/node).  Timing adds
- * a small host-side cost per launch; results are unchanged. */
+ * z, p, A p, diag(A) and writes x, z, p, 8 vectors of 16 B/node, x only at
+ * odd iterations).  Results are unchanged. */
 int mlmc_profile_enable(mlmc_ctx *ctx, int on);
 /* kernel: 0 / 1 = FP64 operator / vector pass, 2 / 3 = the FP32 passes of the
  * mixed-precision inner solver (3 vectors of 8 B/node + 16 B/element of FP32

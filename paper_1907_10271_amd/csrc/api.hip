@@ -449,8 +449,12 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
   if (ng_all == 0) return MLMC_OK;
   if (ng_all > MAX_GROUPS) return fail(c, MLMC_EINVAL, "too many level groups in one lock-step solve");
   const int block = 32;
-  if (c->prof && c->ev.size() < 3 * block) {
-    c->ev.resize(3 * block);
+  // profiling times one iteration per block, the middle one (the queue is
+  // full there), and counts the algorithmic bytes of exactly those launches
+  const int timed_b = block / 2;
+  std::vector<long> timed_its;
+  if (c->prof && c->ev.size() < 3) {
+    c->ev.resize(3);
     for (auto &e : c->ev) HIPCHK(c, hipEventCreate(&e));
   }
   int tot = 0;
@@ -509,12 +513,13 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
   auto launch_block = [&](int base, const int *itb, hipStream_t s, bool timed) -> int {
     for (int b = 0; b < block; ++b) {
       const int k = base + b;
-      if (timed) HIPCHK(c, hipEventRecord(c->ev[3 * b], s));
+      const bool ev = timed && b == timed_b;
+      if (ev) HIPCHK(c, hipEventRecord(c->ev[0], s));
       if (ngm[0]) launch_pcg_pass1<T>(dg, ngm[0], nb1m[0], c->mat, k, 0, itb, s);
       if (ngm[1]) launch_pcg_pass1<T>(dg + ngm[0], ngm[1], nb1m[1], c->mat, k, 1, itb, s);
-      if (timed) HIPCHK(c, hipEventRecord(c->ev[3 * b + 1], s));
+      if (ev) HIPCHK(c, hipEventRecord(c->ev[1], s));
       launch_pcg_pass2<T>(dg, ng, nb2, k, itb, s);
-      if (timed) HIPCHK(c, hipEventRecord(c->ev[3 * b + 2], s));
+      if (ev) HIPCHK(c, hipEventRecord(c->ev[2], s));
       extra(k, alive, itb, s);
     }
     return MLMC_OK;
@@ -574,15 +579,14 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
     }
     HIPCHK(c, hipStreamSynchronize(st));
     if (c->prof) {
-      for (int b = 0; b < block; ++b) {
-        float t1 = 0, t2 = 0;
-        HIPCHK(c, hipEventElapsedTime(&t1, c->ev[3 * b], c->ev[3 * b + 1]));
-        HIPCHK(c, hipEventElapsedTime(&t2, c->ev[3 * b + 1], c->ev[3 * b + 2]));
-        c->prof_ms[prof_k] += t1;
-        c->prof_ms[prof_k + 1] += t2;
-      }
-      c->prof_launches[prof_k] += block;
-      c->prof_launches[prof_k + 1] += block;
+      float t1 = 0, t2 = 0;
+      HIPCHK(c, hipEventElapsedTime(&t1, c->ev[0], c->ev[1]));
+      HIPCHK(c, hipEventElapsedTime(&t2, c->ev[1], c->ev[2]));
+      c->prof_ms[prof_k] += t1;
+      c->prof_ms[prof_k + 1] += t2;
+      c->prof_launches[prof_k] += 1;
+      c->prof_launches[prof_k + 1] += 1;
+      timed_its.push_back(it + timed_b);
     }
     bool changed = false, any = false;
     off = 0;
@@ -612,21 +616,17 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
       c->h_iters.resize(gr.n);
       HIPCHK(c, hipMemcpyAsync(c->h_iters.data(), gr.S.it_b, sizeof(int) * gr.n, hipMemcpyDeviceToHost, st));
       HIPCHK(c, hipStreamSynchronize(st));
-      double its = 0;
-      for (int k = 0; k < gr.n; ++k) its += c->h_iters[k];
+      // a slot with final iteration count K is active in iterations 0..K-1
       const double w = sizeof(T);
       const double wt = (sizeof(T) == 8) ? (gr.S.cs ? 64.0 : 32.0) : (c->theta_fp32 ? 16.0 : 8.0);  // angle bytes/element
-      c->prof_bytes[prof_k] += its * (3.0 * 2 * w * g.nnode + wt * g.nelem);  // z, p_old in; A p out
-      // x, z, p_old, A p, dg in; x, z, p out (FP64: x only every second iteration)
-      double vec = 8.0 * its;
-      if (sizeof(T) == 8) {
-        vec = 0.0;
-        for (int k = 0; k < gr.n; ++k) {
-          const int ik = c->h_iters[k];
-          vec += 6.0 * ((ik + 1) / 2) + 8.0 * (ik / 2);
-        }
+      for (long ti : timed_its) {
+        double act = 0;
+        for (int k = 0; k < gr.n; ++k) act += c->h_iters[k] > ti ? 1.0 : 0.0;
+        c->prof_bytes[prof_k] += act * (3.0 * 2 * w * g.nnode + wt * g.nelem);  // z, p_old in; A p out
+        // x, z, p_old, A p, dg in; x, z, p out (FP64: x only at odd iterations)
+        const double vec = (sizeof(T) == 8 && !(ti & 1)) ? 6.0 : 8.0;
+        c->prof_bytes[prof_k + 1] += act * vec * 2 * w * g.nnode;
       }
-      c->prof_bytes[prof_k + 1] += vec * 2 * w * g.nnode;
     }
   }
   return MLMC_OK;
