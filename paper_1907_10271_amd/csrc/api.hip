@@ -112,9 +112,13 @@ int fail(mlmc_ctx *c, int code, const std::string &msg) {
   } while (0)
 
 // tile height of the operator pass (a multiple of SWEEP_RB)
+// tiles of `ty` node rows; a remainder of at most half a tile joins the last
+// tile instead of making a row of near-empty tiles (a mesh of 2^k element rows
+// has 2^k + 1 node rows)
 void set_sweep_rows(StripGeom &g, int ty) {
   g.sw_ty = ty;
-  g.sw_nty = (g.nny + ty - 1) / ty;
+  const int full = g.nny / ty, rem = g.nny - full * ty;
+  g.sw_nty = (full == 0) ? 1 : (rem <= ty / 2 ? full : full + 1);
   g.sw_ntiles = g.sw_ntx * g.sw_nty;
 }
 
@@ -753,8 +757,8 @@ int build_strip(mlmc_ctx *c) {
     c->graphs = cfg.at("graphs").b;
   }
   c->sweep_rows = (int)cfg.number_or("sweep_rows", 0);
-  if (c->sweep_rows != 0 && c->sweep_rows != SWEEP_RB && c->sweep_rows != 2 * SWEEP_RB && c->sweep_rows != SWEEP_MAXTY)
-    throw std::runtime_error("sweep_rows must be 0 (automatic), 4, 8 or 16");
+  if (c->sweep_rows < 0 || c->sweep_rows > SWEEP_MAXTY || c->sweep_rows % SWEEP_RB != 0)
+    throw std::runtime_error("sweep_rows must be 0 (automatic), 4, 8, 12 or 16");
   const std::string sm = cfg.string_or("small_solver", "auto");
   if (sm != "auto" && sm != "off") throw std::runtime_error("small_solver must be auto or off");
   int lds = 0;

@@ -461,7 +461,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   const int i = i0 - 1 + lane;
   const bool elv = lane <= g.sw_tw && i >= 0 && i < g.nx;
   const bool own = lane >= 1 && lane <= g.sw_tw && i < g.nnx;
-  const int row_end = min(j0 + g.sw_ty, g.nny);
+  const int row_end = (ty == g.sw_nty - 1) ? g.nny : j0 + g.sw_ty;  // the last tile takes the remainder
   const bool wp = it > 0;
   const int ic = clampi(i, g.nnx - 1), ice = clampi(i, g.nx - 1);  // nearest node / element column
   RowVals<T> lo = load_row(g, S, vb, ic, j0 - 1);
@@ -710,7 +710,7 @@ __global__ __launch_bounds__(64) void k_resid64(StripGeom g, StripMat m, PcgSlot
   const bool colv = lane <= g.sw_tw + 1 && i >= 0 && i < g.nnx;
   const bool elv = lane <= g.sw_tw && i >= 0 && i < g.nx;
   const bool own = lane >= 1 && lane <= g.sw_tw && i < g.nnx;
-  const int row_end = min(j0 + g.sw_ty, g.nny);
+  const int row_end = (ty == g.sw_nty - 1) ? g.nny : j0 + g.sw_ty;  // the last tile takes the remainder
   auto xrow = [&](int jr, double &a, double &b) {
     a = b = 0.0;
     if (colv && jr >= 0 && jr < g.nny) {
