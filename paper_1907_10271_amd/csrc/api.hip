@@ -29,8 +29,8 @@ struct StripPool {
   int cap = 0;
   double *x = nullptr, *z = nullptr, *p = nullptr, *Ap = nullptr, *dg = nullptr, *theta = nullptr;
   double *part_pap = nullptr, *part_rz = nullptr, *part_rr = nullptr, *rzs = nullptr;
-  double *tol2 = nullptr, *bb = nullptr, *relres = nullptr, *qpart = nullptr, *alpha = nullptr;
-  int *it_a = nullptr, *it_b = nullptr, *status = nullptr, *active = nullptr, *outidx = nullptr, *xpend = nullptr;
+  double *tol2 = nullptr, *bb = nullptr, *relres = nullptr, *qpart = nullptr, *xa = nullptr;
+  int *it_a = nullptr, *it_b = nullptr, *status = nullptr, *active = nullptr, *outidx = nullptr, *xs = nullptr;
   int64_t *rows = nullptr;
   size_t bytes = 0;
   // mixed precision (allocated on first use): FP64 rhs, FP32 or BF16 angles, FP32 inner solver
@@ -40,8 +40,8 @@ struct StripPool {
   void *theta16 = nullptr;  // inner-solver angles: bfloat16 or FP32
   float *fx = nullptr, *fz = nullptr, *fp = nullptr, *fAp = nullptr, *fdg = nullptr;
   double *f_pap = nullptr, *f_rz = nullptr, *f_rr = nullptr, *f_rzs = nullptr, *f_tol2 = nullptr, *f_bb = nullptr,
-         *f_relres = nullptr;
-  int *f_it_a = nullptr, *f_it_b = nullptr, *f_status = nullptr, *f_active = nullptr;
+         *f_relres = nullptr, *f_xa = nullptr;
+  int *f_it_a = nullptr, *f_it_b = nullptr, *f_status = nullptr, *f_active = nullptr, *f_xs = nullptr;
   size_t mixed_bytes = 0;
 };
 
@@ -191,8 +191,8 @@ size_t strip_mixed_slot_bytes(const StripGeom &g) {
   const size_t n2 = (size_t)2 * g.nnode;
   return n2 * sizeof(double)                               // b
          + (size_t)4 * g.nelem * sizeof(float)             // inner angles (BF16 or FP32)
-         + 5 * n2 * sizeof(float)                          // FP32 x, r, p, Ap, dinv
-         + (size_t)(2 * g.sw_npart + 4 * g.nchunks) * sizeof(double) + 16 * sizeof(double);
+         + 5 * n2 * sizeof(float)                          // FP32 x, z, p, Ap, dg
+         + (size_t)(2 * g.sw_npart + 4 * g.nchunks) * sizeof(double) + 16 * sizeof(double);  // and scalars
 }
 
 size_t strip_slot_bytes(const StripGeom &g) {
@@ -206,10 +206,10 @@ size_t strip_slot_bytes(const StripGeom &g) {
 
 void free_pool(mlmc_ctx *c, StripPool &p) {
   void *bufs[] = {p.x, p.z, p.p, p.Ap, p.dg, p.theta, p.part_pap, p.part_rz, p.part_rr, p.rzs, p.tol2, p.bb,
-                  p.relres, p.qpart, p.alpha, p.it_a, p.it_b, p.status, p.active, p.outidx, p.xpend, p.rows,
+                  p.relres, p.qpart, p.xa, p.it_a, p.it_b, p.status, p.active, p.outidx, p.xs, p.rows,
                   p.b64, p.m_part_rr, p.m_relres, p.f_rr_ref, p.m_updates, p.f_ru,
                   p.theta16, p.fx, p.fz, p.fp, p.fAp, p.fdg, p.f_pap, p.f_rz, p.f_rr, p.f_rzs, p.f_tol2, p.f_bb,
-                  p.f_relres, p.f_it_a, p.f_it_b, p.f_status, p.f_active};
+                  p.f_relres, p.f_xa, p.f_it_a, p.f_it_b, p.f_status, p.f_active, p.f_xs};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   c->used -= p.bytes + p.mixed_bytes;
@@ -250,15 +250,15 @@ int ensure_pool(mlmc_ctx *c, int level, int n, bool mixed = false) {
   HIPCHK(c, dalloc(&p.tol2, (size_t)n));
   HIPCHK(c, dalloc(&p.bb, (size_t)n));
   HIPCHK(c, dalloc(&p.relres, (size_t)n));
-  HIPCHK(c, dalloc(&p.alpha, (size_t)2 * n));
+  HIPCHK(c, dalloc(&p.xa, (size_t)2 * n));
   HIPCHK(c, dalloc(&p.qpart, (size_t)qoi_parts(g) * n));
   HIPCHK(c, dalloc(&p.it_a, (size_t)n));
   HIPCHK(c, dalloc(&p.it_b, (size_t)n));
   HIPCHK(c, dalloc(&p.status, (size_t)n));
   HIPCHK(c, dalloc(&p.active, (size_t)n));
   HIPCHK(c, dalloc(&p.outidx, (size_t)n));
-  HIPCHK(c, dalloc(&p.xpend, (size_t)n));
-  HIPCHK(c, hipMemset(p.xpend, 0, sizeof(int) * n));
+  HIPCHK(c, dalloc(&p.xs, (size_t)2 * n));
+  HIPCHK(c, hipMemset(p.xs, 0, sizeof(int) * 2 * n));
   HIPCHK(c, dalloc(&p.rows, (size_t)n));
   HIPCHK(c, hipMemset(p.active, 0, sizeof(int) * n));
   p.cap = n;
@@ -301,6 +301,9 @@ int alloc_mixed(mlmc_ctx *c, int level) {
   HIPCHK(c, dalloc(&p.f_tol2, (size_t)n));
   HIPCHK(c, dalloc(&p.f_bb, (size_t)n));
   HIPCHK(c, dalloc(&p.f_relres, (size_t)n));
+  HIPCHK(c, dalloc(&p.f_xa, (size_t)2 * n));
+  HIPCHK(c, dalloc(&p.f_xs, (size_t)2 * n));
+  HIPCHK(c, hipMemset(p.f_xs, 0, sizeof(int) * 2 * n));
   HIPCHK(c, dalloc(&p.f_it_a, (size_t)n));
   HIPCHK(c, dalloc(&p.f_it_b, (size_t)n));
   HIPCHK(c, dalloc(&p.f_status, (size_t)n));
@@ -333,6 +336,8 @@ PcgState<float> inner_of(mlmc_ctx *c, int level) {
   I.it_b = p.f_it_b;
   I.status = p.f_status;
   I.active = p.f_active;
+  I.xa = p.f_xa;
+  I.xs = p.f_xs;
   I.S = p.cap;
   I.max_iter = c->max_iter;
   I.mixed = 1;
@@ -375,8 +380,8 @@ PcgSlots slots_of(mlmc_ctx *c, int level, double rtol) {
   S.tol2 = p.tol2;
   S.bb = p.bb;
   S.relres = p.relres;
-  S.alpha = p.alpha;
-  S.xpend = p.xpend;
+  S.xa = p.xa;
+  S.xs = p.xs;
   S.it_a = p.it_a;
   S.it_b = p.it_b;
   S.status = p.status;
@@ -627,8 +632,9 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
         double act = 0;
         for (int k = 0; k < gr.n; ++k) act += c->h_iters[k] > ti ? 1.0 : 0.0;
         c->prof_bytes[prof_k] += act * (3.0 * 2 * w * g.nnode + wt * g.nelem);  // z, p_old in; A p out
-        // x, z, p_old, A p, dg in; x, z, p out (FP64: x only at odd iterations)
-        const double vec = (sizeof(T) == 8 && !(ti & 1)) ? 6.0 : 8.0;
+        // x, z, p_old, A p, dg in; x, z, p out, x every second pass (odd
+        // iterations; in mixed mode a reliable update can shift the parity)
+        const double vec = (ti & 1) ? 8.0 : 6.0;
         c->prof_bytes[prof_k + 1] += act * vec * 2 * w * g.nnode;
       }
     }

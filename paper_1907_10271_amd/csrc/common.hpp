@@ -90,12 +90,15 @@ struct PcgState {
   double ru2;
   double *rr_ref;                  // [S] ||r||^2 at the last FP64 residual
   int *ru;                         // [S]
-  // FP64 solver: x takes two steps at once, at odd iterations (the even
-  // iteration's p is the next one's p_old, already loaded there).  alpha of
-  // the last step [2][S] (by parity); xpend[s] = it + 1 when the step of
-  // iteration it is still to be added to x (set-up clears it), else 0
-  double *alpha;
-  int *xpend;
+  // x takes two steps at once, every second completed vector pass (the
+  // deferred step's p is the next pass's p_old, already loaded there).
+  // xs[1][s]: whether the last completed vector pass left its step pending
+  // (set-up clears it).  FP32 inner solver: xa[1][s] is that step's alpha,
+  // and xs[0] / xa[0] the same copied by the operator pass for the vector pass
+  // of its iteration (so no launch reads what it writes).  FP64 solver: steps
+  // are deferred at even iterations, whose alpha is xa[0][s].
+  double *xa;                      // [2][S]
+  int *xs;                         // [2][S]
 };
 using PcgSlots = PcgState<double>;
 

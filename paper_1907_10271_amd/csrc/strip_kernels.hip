@@ -271,7 +271,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_setup(StripGeom g, StripMat m,
     S.it_a[s] = 0;
     S.status[s] = S_OK;
     S.active[s] = 1;
-    if (S.xpend) S.xpend[s] = 0;
+    S.xs[S.S + s] = 0;
   }
 }
 
@@ -497,6 +497,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       S.ru[s] = it + 1;
       S.active[s] = 0;
     }
+    if (sizeof(T) == 4 && verdict < 0 && !upd) {  // FP32 inner solver: state for this vector pass
+      S.xs[s] = S.xs[S.S + s];
+      S.xa[s] = S.xa[S.S + s];
+    }
   }
   if (verdict >= 0 || upd) return;
   const double beta_d = (it == 0) ? 0.0 : rz / rz_prev;
@@ -571,9 +575,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // alpha = rz / p.Ap; p = z + beta p_old (bit-identical to pass 1); x += alpha p;
 // r = dg z - alpha Ap; z = r / dg; store p, x, z; partial r.z and r.r per
 // chunk of CHUNK consecutive nodes (all loads issued before the reduction of
-// p.Ap).  FP64: x moves at odd iterations only, by both steps in the order of
-// one step at a time (the even step's p is this iteration's p_old), so x is
-// read and written every second iteration with the same bits.
+// p.Ap).  x moves at every second pass only, by both steps in the order of one
+// step at a time (the deferred step's p is this pass's p_old), so x is read
+// and written half as often with the same bits.
 template <typename T>
 __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G, int ng, int it_off,
                                               const int *__restrict__ itb) {
@@ -596,9 +600,12 @@ __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G
   for (int k = threadIdx.x; k < g.sw_npart; k += 256) ppap += S.part_pap[(size_t)s * g.sw_npart + k];
   const double rz = S.rzs[(size_t)par * S.S + s];
   const double rz_prev = (it > 0) ? S.rzs[(size_t)(par ^ 1) * S.S + s] : 1.0;
-  constexpr bool lazy = sizeof(T) == 8;
-  const bool xstep = !lazy || (it & 1);
-  const T alpha_prev = (lazy && xstep) ? (T)S.alpha[(size_t)(par ^ 1) * S.S + s] : T(0);
+  // a step is pending: this pass moves x by both.  The FP64 solver never
+  // pauses: it defers at even iterations and keeps that step's alpha in
+  // xa[0][s], so the pattern is known without a load.  The FP32 inner
+  // solver's reliable updates can shift it: there pass 1 copies the state.
+  const bool xstep = (sizeof(T) == 8) ? (it & 1) != 0 : S.xs[s] != 0;
+  const T alpha_prev = xstep ? (T)S.xa[s] : T(0);
   const size_t vb = (size_t)s * 2 * g.nnode;
   P2 pv[PER], av[PER], xv[PER], zv[PER], gv[PER];
 #pragma unroll
@@ -638,11 +645,7 @@ __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G
       const T znx = rx * rcp_nr(gv[k].x), zny = ry * rcp_nr(gv[k].y);
       st2(S.p + o, pnx, pny);
       if (xstep) {
-        T xx = xv[k].x, xy = xv[k].y;
-        if (lazy) {
-          xx = fma(alpha_prev, pv[k].x, xx);
-          xy = fma(alpha_prev, pv[k].y, xy);
-        }
+        const T xx = fma(alpha_prev, pv[k].x, xv[k].x), xy = fma(alpha_prev, pv[k].y, xv[k].y);
         st2(S.x + o, fma(alpha, pnx, xx), fma(alpha, pny, xy));
       }
       st2(S.z + o, znx, zny);
@@ -659,10 +662,9 @@ __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G
     S.part_rr[pb] = prr;
     if (c == 0) {
       S.it_a[s] = it + 1;
-      if (lazy) {
-        S.alpha[(size_t)par * S.S + s] = (double)alpha;
-        S.xpend[s] = xstep ? 0 : it + 1;
-      }
+      S.xs[S.S + s] = xstep ? 0 : 1;
+      if (sizeof(T) == 4) S.xa[S.S + s] = (double)alpha;
+      else if (!xstep) S.xa[s] = (double)alpha;  // read by the next (odd) pass only
     }
   }
 }
@@ -671,9 +673,8 @@ __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G
 // pending (FP64 solver, after the iterations)
 __global__ __launch_bounds__(256) void k_x_flush(StripGeom g, PcgSlots S) {
   const int s = blockIdx.y, c = blockIdx.x;
-  const int pend = S.xpend[s];
-  if (!pend) return;
-  const double alpha = S.alpha[(size_t)((pend - 1) & 1) * S.S + s];
+  if (!S.xs[S.S + s]) return;
+  const double alpha = S.xa[s];  // FP64: the deferred step's alpha
   const size_t vb = (size_t)s * 2 * g.nnode;
   for (int k = 0; k < CHUNK / 256; ++k) {
     const int node = c * CHUNK + k * 256 + threadIdx.x;
@@ -711,12 +712,25 @@ __global__ __launch_bounds__(64) void k_resid64(StripGeom g, StripMat m, PcgSlot
   const bool elv = lane <= g.sw_tw && i >= 0 && i < g.nx;
   const bool own = lane >= 1 && lane <= g.sw_tw && i < g.nnx;
   const int row_end = (ty == g.sw_nty - 1) ? g.nny : j0 + g.sw_ty;  // the last tile takes the remainder
+  // x = x64 + x32, with the inner solver's pending step (if any) added to x32
+  // as the next vector pass would add it
+  const bool pend = I.xs[I.S + s] != 0;
+  const float xa = (float)I.xa[I.S + s];
+  if (t == 0 && lane == 0) {  // for the fold-in that follows (it must not read what it writes)
+    I.xs[s] = pend ? 1 : 0;
+    I.xa[s] = I.xa[I.S + s];
+  }
   auto xrow = [&](int jr, double &a, double &b) {
     a = b = 0.0;
     if (colv && jr >= 0 && jr < g.nny) {
       const size_t o = vb + 2 * ((size_t)jr * g.nnx + i);
       const double2 v = *reinterpret_cast<const double2 *>(D.x + o);
-      const float2 d = *reinterpret_cast<const float2 *>(I.x + o);
+      float2 d = *reinterpret_cast<const float2 *>(I.x + o);
+      if (pend) {
+        const float2 pp = *reinterpret_cast<const float2 *>(I.p + o);
+        d.x = fmaf(xa, pp.x, d.x);
+        d.y = fmaf(xa, pp.y, d.y);
+      }
       a = v.x + (double)d.x;
       b = v.y + (double)d.y;
     }
@@ -771,7 +785,8 @@ __global__ __launch_bounds__(64) void k_resid64(StripGeom g, StripMat m, PcgSlot
   }
 }
 
-// Second half of a reliable update: x64 += x32, x32 = 0, z32 = z64; the FP64
+// Second half of a reliable update: x64 += x32 (with a pending inner step),
+// x32 = 0, z32 = z64; the FP64
 // stopping test ||r|| <= rtol ||b||; the inner partial sums for the next
 // iteration (parity of it + 1) and the slot's restart.
 __global__ __launch_bounds__(256) void k_ru_apply(StripGeom g, PcgSlots D, PcgState<float> I, MixedState M, int it_off,
@@ -792,12 +807,19 @@ __global__ __launch_bounds__(256) void k_ru_apply(StripGeom g, PcgSlots D, PcgSt
   const double bb = block_sum(pbb, red4);
   const bool done = !(rr > M.rtol2 * bb);
   const size_t vb = (size_t)s * 2 * g.nnode;
+  const bool pend = I.xs[s] != 0;  // pending inner step, as the residual kernel saw it
+  const float xa = (float)I.xa[s];
   double prz = 0.0, pr2 = 0.0;
   for (int k = 0; k < CHUNK / 256; ++k) {
     const int node = c * CHUNK + k * 256 + threadIdx.x;
     if (node < g.nnode) {
       const size_t o = vb + 2 * (size_t)node;
-      const float2 d = *reinterpret_cast<const float2 *>(I.x + o);
+      float2 d = *reinterpret_cast<const float2 *>(I.x + o);
+      if (pend) {
+        const float2 pp = *reinterpret_cast<const float2 *>(I.p + o);
+        d.x = fmaf(xa, pp.x, d.x);
+        d.y = fmaf(xa, pp.y, d.y);
+      }
       double2 x = *reinterpret_cast<const double2 *>(D.x + o);
       x.x += (double)d.x;
       x.y += (double)d.y;
@@ -819,6 +841,7 @@ __global__ __launch_bounds__(256) void k_ru_apply(StripGeom g, PcgSlots D, PcgSt
     I.part_rz[pb] = prz;
     I.part_rr[pb] = pr2;
     if (c == 0) {
+      I.xs[I.S + s] = 0;  // the pending step is in x64 now
       M.relres[s] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
       M.updates[s] += 1;
       I.rr_ref[s] = rr;
@@ -861,6 +884,7 @@ __global__ __launch_bounds__(256) void k_mixed_start(StripGeom g, PcgSlots D, Pc
       I.active[s] = 1;
       I.status[s] = S_OK;
       I.ru[s] = 0;
+      I.xs[I.S + s] = 0;
       M.updates[s] = 0;
       M.relres[s] = 1.0;
     }
@@ -871,11 +895,18 @@ __global__ __launch_bounds__(256) void k_mixed_start(StripGeom g, PcgSlots D, Pc
 __global__ __launch_bounds__(256) void k_mixed_flush(StripGeom g, PcgSlots D, PcgState<float> I) {
   const int s = blockIdx.y, c = blockIdx.x;
   const size_t vb = (size_t)s * 2 * g.nnode;
+  const bool pend = I.xs[I.S + s] != 0;
+  const float xa = (float)I.xa[I.S + s];
   for (int k = 0; k < CHUNK / 256; ++k) {
     const int node = c * CHUNK + k * 256 + threadIdx.x;
     if (node < g.nnode) {
       const size_t o = vb + 2 * (size_t)node;
       float2 d = *reinterpret_cast<const float2 *>(I.x + o);
+      if (pend) {
+        const float2 pp = *reinterpret_cast<const float2 *>(I.p + o);
+        d.x = fmaf(xa, pp.x, d.x);
+        d.y = fmaf(xa, pp.y, d.y);
+      }
       double2 x = *reinterpret_cast<const double2 *>(D.x + o);
       x.x += (double)d.x;
       x.y += (double)d.y;
