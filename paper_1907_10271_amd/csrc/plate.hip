@@ -272,93 +272,132 @@ __device__ bool band_cholesky(const PlateGeom &g, B *band, B *P /* LDS [(NBK + b
   return bad == 0;
 }
 
-// z = (L L^T)^-1 r for NB right-hand sides, blocked by NBK rows: the small
-// diagonal triangle is solved by one thread, the band part of the block's
-// columns is applied by all threads
+// value of lane `l` (uniform) to every lane
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// z = (L L^T)^-1 r for NB right-hand sides, in steps of PS rows: one wave
+// solves the step's diagonal triangle (lane = right-hand side x row, the
+// solved value passed by lane reads), then all threads apply the band part
+// of the step's columns.  Fewer, larger steps: the solve is a chain of
+// n / PS dependent steps, each about one memory round trip long.
+constexpr int PS = 32;
+static_assert(NB * PS == 64, "one lane per right-hand side and row of a step");
 template <typename B>
 __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, double *z, int ld, B *tmp) {
   const int w = g.bw + 1, n = g.nfree;
-  __shared__ B Lb[NBK * NBK], yb[NB * NBK];
+  __shared__ B Lb[PS * PS], yb[NB * PS];
   for (int v = 0; v < NB; ++v)
     for (int i = threadIdx.x; i < n; i += PT) tmp[(size_t)v * n + i] = (B)r[(size_t)v * ld + i];
+  // stage the step's diagonal triangle, Lb[i PS + j] = L(k0 + i, k0 + j), j <= i
+  auto stage = [&](int k0, int nb) {
+#pragma unroll
+    for (int idx = threadIdx.x; idx < PS * PS; idx += PT) {
+      const int i = idx / PS, j = idx % PS;
+      Lb[idx] = (i < nb && j <= i) ? band[(size_t)(k0 + i) * w + (i - j)] : B(i == j ? 1 : 0);
+    }
+    for (int idx = threadIdx.x; idx < NB * PS; idx += PT) {
+      const int v = idx / PS, i = idx % PS;
+      yb[idx] = (i < nb) ? tmp[(size_t)v * n + k0 + i] : B(0);
+    }
+  };
   // forward: L y = r
-  for (int k0 = 0; k0 < n; k0 += NBK) {
-    const int nb = min(NBK, n - k0);
+  for (int k0 = 0; k0 < n; k0 += PS) {
+    const int nb = min(PS, n - k0);
     __syncthreads();
-    // stage the diagonal triangle and the right-hand sides of the block in LDS
-    for (int idx = threadIdx.x; idx < NBK * NBK; idx += PT) {
-      const int j = idx / NBK, jj = idx % NBK;
-      Lb[idx] = (j < nb && jj <= j) ? band[(size_t)(k0 + j) * w + (j - jj)] : B(1);
-    }
-    for (int idx = threadIdx.x; idx < NB * NBK; idx += PT) {
-      const int v = idx / NBK, j = idx % NBK;
-      yb[idx] = (j < nb) ? tmp[(size_t)v * n + k0 + j] : B(0);
-    }
+    stage(k0, nb);
     __syncthreads();
-    if (threadIdx.x < NB) {
-      const int v = threadIdx.x;
+    if (threadIdx.x < 64) {
+      const int v = threadIdx.x / PS, i = threadIdx.x % PS;
+      B y = yb[v * PS + i];
+      const B dinv = B(1) / Lb[i * PS + i];
       for (int j = 0; j < nb; ++j) {
-        B s = yb[v * NBK + j];
-        for (int jj = 0; jj < j; ++jj) s -= Lb[j * NBK + jj] * yb[v * NBK + jj];
-        yb[v * NBK + j] = s / Lb[j * NBK + j];
+        if (i == j) y *= dinv;
+        const B y0 = lane_value(y, j), y1 = lane_value(y, PS + j);
+        if (i > j) y -= Lb[i * PS + j] * (v ? y1 : y0);
       }
+      yb[v * PS + i] = y;
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < NB * nb; idx += PT) {
       const int v = idx / nb, j = idx % nb;
-      tmp[(size_t)v * n + k0 + j] = yb[v * NBK + j];
+      tmp[(size_t)v * n + k0 + j] = yb[v * PS + j];
     }
+    // the step's PS columns of row rr: row rr's entries for columns k0 + j sit
+    // at p[-j], contiguous; away from the band's end all PS loads are issued
+    // at once from one address
     const int hi = min(n, k0 + nb + g.bw);
     for (int rr = k0 + nb + threadIdx.x; rr < hi; rr += PT) {
+      const int d0 = rr - k0;
+      const B *p = band + (size_t)rr * w + d0;
       B acc[NB];
       for (int v = 0; v < NB; ++v) acc[v] = B(0);
-      for (int j = 0; j < nb; ++j) {
-        const int d = rr - (k0 + j);
-        if (d <= g.bw) {
-          const B l = band[(size_t)rr * w + d];
-          for (int v = 0; v < NB; ++v) acc[v] += l * yb[v * NBK + j];
+      if (nb == PS && d0 <= g.bw) {
+#pragma unroll
+        for (int j16 = 0; j16 < PS; j16 += 16) {
+          B l[16];
+#pragma unroll
+          for (int j = 0; j < 16; ++j) l[j] = p[-(j16 + j)];
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            for (int v = 0; v < NB; ++v) acc[v] += l[j] * yb[v * PS + j16 + j];
         }
+      } else {
+        for (int j = max(0, d0 - g.bw); j < nb; ++j)
+          for (int v = 0; v < NB; ++v) acc[v] += p[-j] * yb[v * PS + j];
       }
       for (int v = 0; v < NB; ++v) tmp[(size_t)v * n + rr] -= acc[v];
     }
   }
   // backward: L^T z = y
-  const int last = ((n - 1) / NBK) * NBK;
-  for (int k0 = last; k0 >= 0; k0 -= NBK) {
-    const int nb = min(NBK, n - k0);
+  const int last = ((n - 1) / PS) * PS;
+  for (int k0 = last; k0 >= 0; k0 -= PS) {
+    const int nb = min(PS, n - k0);
     __syncthreads();
-    for (int idx = threadIdx.x; idx < NBK * NBK; idx += PT) {
-      const int j = idx / NBK, jj = idx % NBK;
-      Lb[idx] = (j < nb && jj <= j) ? band[(size_t)(k0 + j) * w + (j - jj)] : B(1);
-    }
-    for (int idx = threadIdx.x; idx < NB * NBK; idx += PT) {
-      const int v = idx / NBK, j = idx % NBK;
-      yb[idx] = (j < nb) ? tmp[(size_t)v * n + k0 + j] : B(0);
-    }
+    stage(k0, nb);
     __syncthreads();
-    if (threadIdx.x < NB) {
-      const int v = threadIdx.x;
+    if (threadIdx.x < 64) {
+      const int v = threadIdx.x / PS, i = threadIdx.x % PS;
+      B y = yb[v * PS + i];
+      const B dinv = B(1) / Lb[i * PS + i];
       for (int j = nb - 1; j >= 0; --j) {
-        B s = yb[v * NBK + j];
-        for (int jj = j + 1; jj < nb; ++jj) s -= Lb[jj * NBK + j] * yb[v * NBK + jj];
-        yb[v * NBK + j] = s / Lb[j * NBK + j];
+        if (i == j) y *= dinv;
+        const B y0 = lane_value(y, j), y1 = lane_value(y, PS + j);
+        if (i < j) y -= Lb[j * PS + i] * (v ? y1 : y0);
       }
+      yb[v * PS + i] = y;
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < NB * nb; idx += PT) {
       const int v = idx / nb, j = idx % nb;
-      tmp[(size_t)v * n + k0 + j] = yb[v * NBK + j];
+      tmp[(size_t)v * n + k0 + j] = yb[v * PS + j];
     }
+    // column c's entries in rows k0 + j sit at p[j (w + 1)]; loads in groups of 8
     const int lo = max(0, k0 - g.bw);
     for (int c = lo + threadIdx.x; c < k0; c += PT) {
+      const B *p = band + (size_t)k0 * w + (k0 - c);
       B acc[NB];
       for (int v = 0; v < NB; ++v) acc[v] = B(0);
-      for (int j = 0; j < nb; ++j) {
-        const int d = k0 + j - c;
-        if (d <= g.bw) {
-          const B l = band[(size_t)(k0 + j) * w + d];
-          for (int v = 0; v < NB; ++v) acc[v] += l * yb[v * NBK + j];
+      if (nb == PS && k0 + PS - 1 - c <= g.bw) {
+#pragma unroll
+        for (int j8 = 0; j8 < PS; j8 += 8) {
+          B l[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) l[j] = p[(size_t)(j8 + j) * (w + 1)];
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            for (int v = 0; v < NB; ++v) acc[v] += l[j] * yb[v * PS + j8 + j];
         }
+      } else {
+        const int j1 = min(nb, c + g.bw + 1 - k0);  // rows within the band of column c
+        for (int j = 0; j < j1; ++j)
+          for (int v = 0; v < NB; ++v) acc[v] += p[(size_t)j * (w + 1)] * yb[v * PS + j];
       }
       for (int v = 0; v < NB; ++v) tmp[(size_t)v * n + c] -= acc[v];
     }
@@ -541,7 +580,6 @@ __device__ void lobpcg(const PlateGeom &g, const double *Ke, const double *KGe, 
   __shared__ double red[4];
   __shared__ double gram[2 * NS * NS];
   __shared__ double coef[NS * NB], mu[NB], resn[NB];
-  __shared__ int mk_sh;
   const int n = g.nfree;
   auto V = [&](int k) { return vec + (size_t)k * n; };
   // ---- initial block: smooth mode shapes w = sin(p pi x/a) sin(q pi y/b), theta = grad w
@@ -622,7 +660,7 @@ __device__ void lobpcg(const PlateGeom &g, const double *Ke, const double *KGe, 
         }
       }
     __syncthreads();
-    if (threadIdx.x == 0) mk_sh = rayleigh_ritz(gram, gram + NS * NS, ms, coef, mu);
+    if (threadIdx.x == 0) (void)rayleigh_ritz(gram, gram + NS * NS, ms, coef, mu);
     __syncthreads();
     // new X = S c, new P = [W, P] c_{W,P}; images follow by linear combination
     for (int r = threadIdx.x; r < n; r += PT) {
@@ -656,8 +694,11 @@ __device__ void lobpcg(const PlateGeom &g, const double *Ke, const double *KGe, 
 
 // one work-group per sample from start to finish
 template <typename B>
-__global__ __launch_bounds__(PT) void k_buckle(PlateGeom g, PlateMat m, PlateWork W, PlateJob J, double tol,
-                                               int max_iter) {
+// two waves per SIMD (a few registers spill): batches of small panels need the
+// occupancy more than the solve's wide loads need registers
+__global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(2))) void k_buckle(PlateGeom g, PlateMat m,
+                                                                                       PlateWork W, PlateJob J,
+                                                                                       double tol, int max_iter) {
   __shared__ double Ke[400], KGe[400], Dmb[36];
   __shared__ B panel[(NBK + MAXBW) * NBK];
   const int s = blockIdx.x;
