@@ -191,6 +191,10 @@ def test_error_paths():
     assert e.value.code == -4
     with pytest.raises(pk.MLMCError):
         pk.Context('{"kind": "strip"}')
+    for bad in ({"sweep_rows": 6}, {"sweep_rows": 20}, {"mixed": {"theta_storage": "fp16"}},
+                {"mixed": {"update_every": 3}}):
+        with pytest.raises(pk.MLMCError):
+            pk.Context(dict(mi.load_config("strip_c1"), **bad))
 
 
 @pytest.mark.parametrize("engine", ["auto", "lockstep"])
