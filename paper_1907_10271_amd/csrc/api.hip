@@ -88,6 +88,10 @@ struct mlmc_ctx {
   bool graphs = false;      // measured: no gain on MI355X (iterations are GPU-bound), so off by default
   int sweep_rows = 0;       // operator-pass tile height: 0 = chosen per launch, else 4, 8 or 16
   hipStream_t cap_stream = nullptr;
+  // whole-solve levels of a batch run on side_stream, next to the lock-step
+  // launches on the caller's stream (fork after the set-up, join before the end)
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int *d_itb = nullptr;
   struct CachedGraph {
     std::vector<char> key;
@@ -879,7 +883,10 @@ int mlmc_create(const char *config_json, size_t mem_budget_bytes, mlmc_ctx **out
         hipMalloc((void **)&c->d_grp32, MAX_GROUPS * sizeof(PcgGroup<float>)) != hipSuccess ||
         hipHostMalloc((void **)&c->h_grp32, MAX_GROUPS * sizeof(PcgGroup<float>)) != hipSuccess ||
         hipMalloc((void **)&c->d_itb, sizeof(int)) != hipSuccess ||
-        hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
       throw std::runtime_error("allocation of the stats buffers failed");
     if (kind == "strip") {
       c->kind = 0;
@@ -928,6 +935,9 @@ void mlmc_destroy(mlmc_ctx *c) {
   }
   if (c->d_itb) (void)hipFree(c->d_itb);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->plate) plate_destroy(c->plate);
   for (auto &e : c->ev) (void)hipEventDestroy(e);
   delete c;
@@ -1119,6 +1129,7 @@ int mlmc_solve_batch(mlmc_ctx *c, int n_req, const mlmc_request *req, const doub
       if (done[l] < (int)rows[l].size()) lvls.push_back(l);
     if (lvls.empty()) break;
     std::vector<SolveGroup> lock;
+    bool any_small = false;
     for (int l : lvls) {
       StripLevel &L = c->lv[l];
       const int n = std::min(cap[l], (int)rows[l].size() - done[l]);
@@ -1128,13 +1139,25 @@ int mlmc_solve_batch(mlmc_ctx *c, int n_req, const mlmc_request *req, const doub
       launch_kl_synth(L.modes, c->K, L.g, xi, ld_xi, L.pool.rows, n, L.cs ? nullptr : L.pool.theta,
                       mixed ? L.pool.theta16 : nullptr, c->theta_fp32, 4 * L.g.nelem, L.cs ? L.pool.theta : nullptr,
                       1, st);
-      PcgSlots S = slots_of(c, l, rt);
-      if (L.small) {
-        if (int rc = run_small(c, l, S, n, st)) return rc;
-      } else {
-        lock.push_back({l, S, n});
-      }
+      if (L.small) any_small = true;
+      else lock.push_back({l, slots_of(c, l, rt), n});
       cnt.push_back(n);
+    }
+    // whole-solve levels (one work-group per sample, few waves per CU) run on
+    // the side stream while the lock-step launches run on the caller's
+    hipStream_t side = lock.empty() ? st : c->side_stream;
+    if (any_small && side != st) {
+      HIPCHK(c, hipEventRecord(c->ev_fork, st));
+      HIPCHK(c, hipStreamWaitEvent(side, c->ev_fork, 0));
+    }
+    for (size_t k = 0; k < lvls.size(); ++k) {
+      const int l = lvls[k];
+      StripLevel &L = c->lv[l];
+      if (!L.small) continue;
+      PcgSlots S = slots_of(c, l, rt);
+      if (int rc = run_small(c, l, S, cnt[k], side)) return rc;
+      launch_qoi(L.g, c->mat, report_view(c, l, S, MLMC_FP64), cnt[k], L.pool.qpart, L.pool.outidx, q_fine, q_coarse,
+                 info, n_req, side);
     }
     for (size_t k0 = 0; k0 < lock.size(); k0 += MAX_GROUPS) {
       std::vector<SolveGroup> part(lock.begin() + k0, lock.begin() + std::min(lock.size(), k0 + MAX_GROUPS));
@@ -1144,12 +1167,17 @@ int mlmc_solve_batch(mlmc_ctx *c, int n_req, const mlmc_request *req, const doub
     for (size_t k = 0; k < lvls.size(); ++k) {
       const int l = lvls[k];
       StripLevel &L = c->lv[l];
-      const bool mixed = precision == MLMC_MIXED && !L.small;
+      if (L.small) continue;
+      const bool mixed = precision == MLMC_MIXED;
       PcgSlots S = slots_of(c, l, rt);
       launch_qoi(L.g, c->mat, report_view(c, l, S, mixed ? MLMC_MIXED : MLMC_FP64), cnt[k], L.pool.qpart,
                  L.pool.outidx, q_fine, q_coarse, info, n_req, st);
-      done[l] += cnt[k];
     }
+    if (any_small && side != st) {
+      HIPCHK(c, hipEventRecord(c->ev_join, side));
+      HIPCHK(c, hipStreamWaitEvent(st, c->ev_join, 0));
+    }
+    for (size_t k = 0; k < lvls.size(); ++k) done[lvls[k]] += cnt[k];
     HIPCHK(c, hipGetLastError());
     // the row/index buffers are reused by the next round
     HIPCHK(c, hipStreamSynchronize(st));
