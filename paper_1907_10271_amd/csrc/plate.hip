@@ -208,11 +208,13 @@ __device__ bool band_cholesky(const PlateGeom &g, B *band, B *P /* LDS [(NBK + b
     const int nb = min(NBK, n - k0);
     const int rows = min(nb + g.bw, n - k0);  // panel rows k0 .. k0 + rows - 1
     __syncthreads();
-    for (int idx = threadIdx.x; idx < rows * NBK; idx += PT) {
-      const int i = idx / NBK, j = idx % NBK;
-      B v = B(0);
-      if (j < nb && i >= j && i - j <= g.bw) v = band[(size_t)(k0 + i) * w + (i - j)];
-      P[idx] = v;
+    for (int i = threadIdx.x; i < rows; i += PT) {  // a row's entries at once (see k_band_step)
+      const B *row = band + (size_t)(k0 + i) * w;
+      B e[NBK];
+#pragma unroll
+      for (int j = 0; j < NBK; ++j) e[j] = row[min(max(i - j, 0), g.bw)];
+#pragma unroll
+      for (int j = 0; j < NBK; ++j) P[i * NBK + j] = (j < nb && i >= j && i - j <= g.bw) ? e[j] : B(0);
     }
     // panel factorisation (unblocked, in LDS)
     for (int j = 0; j < nb; ++j) {
@@ -769,28 +771,39 @@ __global__ __launch_bounds__(PT) void k_band_step(PlateGeom g, PlateWork W, int 
   B *band = sample_band<B>(W, s);
   // trailing window of the previous panel (columns k0 - NBK .. k0 - 1): rows and
   // columns k0 .. k0 + m - 1
+  // (one thread per band row: a row's NBK entries are contiguous, and all its
+  // loads are issued at once; entries outside the band read an in-range entry
+  // of the row and are replaced by zero)
   const int m = (k0 > 0) ? min(g.bw, nf - k0) : 0;
-  for (int idx = threadIdx.x; idx < m * NBK; idx += PT) {
-    const int r = idx / NBK, j = idx % NBK;
-    const int d = r + NBK - j;
-    Lp[idx] = (d <= g.bw) ? band[(size_t)(k0 + r) * w + d] : B(0);
+  for (int r = threadIdx.x; r < m; r += PT) {
+    const B *row = band + (size_t)(k0 + r) * w;
+    B v[NBK];
+#pragma unroll
+    for (int j = 0; j < NBK; ++j) v[j] = row[min(r + NBK - j, g.bw)];
+#pragma unroll
+    for (int j = 0; j < NBK; ++j) Lp[r * NBK + j] = (r + NBK - j <= g.bw) ? v[j] : B(0);
   }
   __syncthreads();
   if (wg == 0) {
     if (k0 >= nf) return;
     const int nb = min(NBK, nf - k0);
     const int rows = min(nb + g.bw, nf - k0);
-    for (int idx = threadIdx.x; idx < rows * NBK; idx += PT) {
-      const int i = idx / NBK, j = idx % NBK;
-      B v = B(0);
-      if (j < nb && i >= j && i - j <= g.bw) v = band[(size_t)(k0 + i) * w + (i - j)];
-      // the previous panel's update of this entry (columns of this panel)
-      if (j < nb && i >= j && i < m) {
-        B acc = B(0);
-        for (int jj = 0; jj < NBK; ++jj) acc += Lp[i * NBK + jj] * Lp[j * NBK + jj];
-        v -= acc;
+    for (int i = threadIdx.x; i < rows; i += PT) {
+      const B *row = band + (size_t)(k0 + i) * w;
+      B e[NBK];
+#pragma unroll
+      for (int j = 0; j < NBK; ++j) e[j] = row[min(max(i - j, 0), g.bw)];
+#pragma unroll
+      for (int j = 0; j < NBK; ++j) {
+        B v = (j < nb && i >= j && i - j <= g.bw) ? e[j] : B(0);
+        // the previous panel's update of this entry (columns of this panel)
+        if (j < nb && i >= j && i < m) {
+          B acc = B(0);
+          for (int jj = 0; jj < NBK; ++jj) acc += Lp[i * NBK + jj] * Lp[j * NBK + jj];
+          v -= acc;
+        }
+        P[i * NBK + j] = v;
       }
-      P[idx] = v;
     }
     // panel factorisation (unblocked, in LDS), as in the one-work-group form
     for (int j = 0; j < nb; ++j) {
