@@ -87,6 +87,10 @@ struct mlmc_ctx {
   // and instantiated graphs keyed by the launch configuration they captured
   bool graphs = false;      // measured: no gain on MI355X (iterations are GPU-bound), so off by default
   int sweep_rows = 0;       // operator-pass tile height: 0 = chosen per launch, else 4, 8 or 16
+  // lock-step launches whose vectors and angles exceed this many bytes use
+  // streaming accesses for the vectors that pass through once (the default is
+  // the size of MI355X's Infinity Cache)
+  double streaming_min_bytes = 256.0 * 1048576.0;
   hipStream_t cap_stream = nullptr;
   // whole-solve levels of a batch run on side_stream, next to the lock-step
   // launches on the caller's stream (fork after the set-up, join before the end)
@@ -477,6 +481,7 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
   PcgGroup<T> *hg = host_groups<T>(c), *dg = dev_groups<T>(c);
   int ng = 0, nb2 = 0;
   int ngm[2] = {0, 0}, nb1m[2] = {0, 0};   // operator-pass groups and blocks per angle mode
+  int nt = 0;                             // streaming accesses in both passes
   // compact the live groups into the descriptor array, groups with stored
   // angles first, then those with stored (cos, sin) pairs (each mode has its
   // own operator-pass kernel; the vector pass takes all groups).  The staging
@@ -517,6 +522,14 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
         ngm[mode]++;
       }
     }
+    // bytes one iteration touches: x, z, p, Ap, dg and the angles (FP64:
+    // codes 32 B or pairs 64 B per element; FP32: bfloat16 8 B or FP32 16 B)
+    double ws = 0;
+    for (int k = 0; k < ng; ++k) {
+      const double ab = sizeof(T) == 8 ? (hg[k].S.cs ? 64.0 : 32.0) : (hg[k].S.cs ? 16.0 : 8.0);
+      ws += (double)hg[k].n * (10.0 * sizeof(T) * hg[k].g.nnode + ab * hg[k].g.nelem);
+    }
+    nt = ws > c->streaming_min_bytes;
     HIPCHK(c, hipMemcpyAsync(dg, hg, sizeof(PcgGroup<T>) * ng, hipMemcpyHostToDevice, st));
     return MLMC_OK;
   };
@@ -528,10 +541,10 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
       const int k = base + b;
       const bool ev = timed && b == timed_b;
       if (ev) HIPCHK(c, hipEventRecord(c->ev[0], s));
-      if (ngm[0]) launch_pcg_pass1<T>(dg, ngm[0], nb1m[0], c->mat, k, 0, itb, s);
-      if (ngm[1]) launch_pcg_pass1<T>(dg + ngm[0], ngm[1], nb1m[1], c->mat, k, 1, itb, s);
+      if (ngm[0]) launch_pcg_pass1<T>(dg, ngm[0], nb1m[0], c->mat, k, 0, itb, s, nt);
+      if (ngm[1]) launch_pcg_pass1<T>(dg + ngm[0], ngm[1], nb1m[1], c->mat, k, 1, itb, s, nt);
       if (ev) HIPCHK(c, hipEventRecord(c->ev[1], s));
-      launch_pcg_pass2<T>(dg, ng, nb2, k, itb, s);
+      launch_pcg_pass2<T>(dg, ng, nb2, k, itb, s, nt);
       if (ev) HIPCHK(c, hipEventRecord(c->ev[2], s));
       extra(k, alive, itb, s);
     }
@@ -548,6 +561,7 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
     put(ngm, sizeof ngm);
     put(nb1m, sizeof nb1m);
     put(&nb2, sizeof nb2);
+    put(&nt, sizeof nt);
     for (char a : alive) key.push_back(a);
     for (auto &e : c->gcache)
       if (e.key == key) {
@@ -769,6 +783,11 @@ int build_strip(mlmc_ctx *c) {
   c->sweep_rows = (int)cfg.number_or("sweep_rows", 0);
   if (c->sweep_rows < 0 || c->sweep_rows > SWEEP_MAXTY || c->sweep_rows % SWEEP_RB != 0)
     throw std::runtime_error("sweep_rows must be 0 (automatic), 4, 8, 12 or 16");
+  {
+    const double mb = cfg.number_or("streaming_min_mb", 256.0);
+    if (!(mb >= 0.0)) throw std::runtime_error("streaming_min_mb must be a number >= 0");
+    c->streaming_min_bytes = mb * 1048576.0;
+  }
   const std::string sm = cfg.string_or("small_solver", "auto");
   if (sm != "auto" && sm != "off") throw std::runtime_error("small_solver must be auto or off");
   int lds = 0;

@@ -330,6 +330,25 @@ __device__ __forceinline__ void st2(T *p, T a, T b) {
   v.y = b;
   gstore(p, v);
 }
+// Streaming forms (NT): nontemporal accesses, which do not displace what the
+// caches hold.  Used when a launch's working set is larger than the Infinity
+// Cache, so that the angles and the node rows the operator pass has just read
+// stay cached while the vectors stream past them.
+template <bool NT, typename T>
+__device__ __forceinline__ typename PairOf<T>::type ld2s(const T *p) {
+  using V = typename PairOf<T>::type;
+  if constexpr (NT) return NativeOf<V>::from(__builtin_nontemporal_load((const MLMC_GLOBAL typename NativeOf<V>::type *)p));
+  else return gload<V>(p);
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st2s(T *p, T a, T b) {
+  using V = typename PairOf<T>::type;
+  V v;
+  v.x = a;
+  v.y = b;
+  if constexpr (NT) __builtin_nontemporal_store(NativeOf<V>::to(v), (MLMC_GLOBAL typename NativeOf<V>::type *)p);
+  else gstore(p, v);
+}
 
 // z and p_old of node (i, jr).  The loads are issued for every lane, from the
 // nearest node inside the mesh, with no branch: the wait for the current row
@@ -428,8 +447,9 @@ struct Angles<float, 1> {
 // p = z + beta p_old (not stored: pass 2 recomputes it bit-identically, so
 // neighbours read p_old in their halos), Ap = A p, partial p.Ap per tile.
 // The next node row is loaded while the current row is computed.  Dot
-// products are accumulated in FP64 for both precisions.
-template <typename T, int CSM>
+// products are accumulated in FP64 for both precisions.  NT: Ap is stored
+// with streaming stores.
+template <typename T, int CSM, bool NT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_pass1(const PcgGroup<T> *__restrict__ G, int ng, StripMat m, int it_off,
                                              int nblocks, const int *__restrict__ itb) {
   const int it = itb ? __builtin_amdgcn_readfirstlane(*itb) + it_off : it_off;
@@ -524,7 +544,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     // everything issued by the previous step has arrived: its prefetch and the
     // store before it (vmcnt 0; expcnt and lgkmcnt not waited for)
     __builtin_amdgcn_s_waitcnt(0x0F70);
-    if (k >= 2 && own) st2(S.Ap + vb + 2 * ((size_t)(ey - 1) * g.nnx + i), yu, yv);
+    if (k >= 2 && own) st2s<NT>(S.Ap + vb + 2 * ((size_t)(ey - 1) * g.nnx + i), yu, yv);
     const RowVals<T> hi = nhi;
     Angles<T, CSM> th;
     if constexpr (ahead) th = nth;
@@ -568,7 +588,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   };
   for (int k = 0; k < nk; ++k) step(k, std::true_type{});
   step(nk, std::false_type{});
-  if (nk >= 1 && own) st2(S.Ap + vb + 2 * ((size_t)(row_end - 1) * g.nnx + i), yu, yv);
+  if (nk >= 1 && own) st2s<NT>(S.Ap + vb + 2 * ((size_t)(row_end - 1) * g.nnx + i), yu, yv);
 }
 
 // ---------------------------------------------------------------- PCG pass 2
@@ -577,8 +597,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // chunk of CHUNK consecutive nodes (all loads issued before the reduction of
 // p.Ap).  x moves at every second pass only, by both steps in the order of one
 // step at a time (the deferred step's p is this pass's p_old), so x is read
-// and written half as often with the same bits.
-template <typename T>
+// and written half as often with the same bits.  NT: streaming loads of Ap,
+// x and dg and streaming stores; z and p_old, which pass 1 has just read,
+// are loaded as cached data.
+template <typename T, bool NT>
 __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G, int ng, int it_off,
                                               const int *__restrict__ itb) {
   const int it = itb ? __builtin_amdgcn_readfirstlane(*itb) + it_off : it_off;
@@ -616,10 +638,10 @@ __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G
     if (node < g.nnode) {
       const size_t o = vb + 2 * (size_t)node;
       if (it > 0) pv[k] = ld2(S.p + o);
-      av[k] = ld2(S.Ap + o);
-      if (xstep) xv[k] = ld2(S.x + o);
+      av[k] = ld2s<NT>(S.Ap + o);
+      if (xstep) xv[k] = ld2s<NT>(S.x + o);
       zv[k] = ld2(S.z + o);
-      gv[k] = ld2(S.dg + o);
+      gv[k] = ld2s<NT>(S.dg + o);
     }
   }
   const double pap = block_sum(ppap, red4);  // publishes flag
@@ -643,12 +665,12 @@ __global__ __launch_bounds__(256) void k_pass2(const PcgGroup<T> *__restrict__ G
       const T pny = fma(beta, pv[k].y, zv[k].y);
       const T rx = fma(-alpha, av[k].x, gv[k].x * zv[k].x), ry = fma(-alpha, av[k].y, gv[k].y * zv[k].y);
       const T znx = rx * rcp_nr(gv[k].x), zny = ry * rcp_nr(gv[k].y);
-      st2(S.p + o, pnx, pny);
+      st2s<NT>(S.p + o, pnx, pny);
       if (xstep) {
         const T xx = fma(alpha_prev, pv[k].x, xv[k].x), xy = fma(alpha_prev, pv[k].y, xv[k].y);
-        st2(S.x + o, fma(alpha, pnx, xx), fma(alpha, pny, xy));
+        st2s<NT>(S.x + o, fma(alpha, pnx, xx), fma(alpha, pny, xy));
       }
-      st2(S.z + o, znx, zny);
+      st2s<NT>(S.z + o, znx, zny);
       const double drx = rx, dry = ry;
       prz += drx * (double)znx + dry * (double)zny;
       prr += drx * drx + dry * dry;
@@ -1121,12 +1143,11 @@ void launch_setup(const StripGeom &g, const StripMat &m, const PcgSlots &S, int 
 
 template <typename T>
 void launch_pcg_pass1(const PcgGroup<T> *groups, int ng, int nblocks, const StripMat &m, int it, int cs,
-                      const int *itb, hipStream_t st) {
+                      const int *itb, hipStream_t st, bool nt) {
   // cs: stored (cos 2theta, sin 2theta) pairs (FP64), FP32 angles (FP32 solver)
-  if (cs)
-    hipLaunchKernelGGL((k_pass1<T, 1>), dim3(nblocks), dim3(64), 0, st, groups, ng, m, it, nblocks, itb);
-  else
-    hipLaunchKernelGGL((k_pass1<T, 0>), dim3(nblocks), dim3(64), 0, st, groups, ng, m, it, nblocks, itb);
+  void (*f)(const PcgGroup<T> *, int, StripMat, int, int, const int *) =
+      cs ? (nt ? k_pass1<T, 1, true> : k_pass1<T, 1, false>) : (nt ? k_pass1<T, 0, true> : k_pass1<T, 0, false>);
+  hipLaunchKernelGGL(f, dim3(nblocks), dim3(64), 0, st, groups, ng, m, it, nblocks, itb);
 }
 
 template <typename T>
@@ -1137,7 +1158,7 @@ int pass1_resident_waves(int cs) {
     int dev = 0, ncu = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const void *f = cs ? (const void *)k_pass1<T, 1> : (const void *)k_pass1<T, 0>;
+    const void *f = cs ? (const void *)k_pass1<T, 1, false> : (const void *)k_pass1<T, 0, false>;
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 64, 0);
     (void)hipGetLastError();
     v.store(std::max(1, per_cu) * std::max(1, ncu));
@@ -1146,18 +1167,20 @@ int pass1_resident_waves(int cs) {
 }
 
 template <typename T>
-void launch_pcg_pass2(const PcgGroup<T> *groups, int ng, int nblocks, int it, const int *itb, hipStream_t st) {
-  hipLaunchKernelGGL(k_pass2<T>, dim3(nblocks), dim3(256), 0, st, groups, ng, it, itb);
+void launch_pcg_pass2(const PcgGroup<T> *groups, int ng, int nblocks, int it, const int *itb, hipStream_t st,
+                      bool nt) {
+  void (*f)(const PcgGroup<T> *, int, int, const int *) = nt ? k_pass2<T, true> : k_pass2<T, false>;
+  hipLaunchKernelGGL(f, dim3(nblocks), dim3(256), 0, st, groups, ng, it, itb);
 }
 
 template void launch_pcg_pass1<double>(const PcgGroup<double> *, int, int, const StripMat &, int, int, const int *,
-                                       hipStream_t);
+                                       hipStream_t, bool);
 template void launch_pcg_pass1<float>(const PcgGroup<float> *, int, int, const StripMat &, int, int, const int *,
-                                      hipStream_t);
+                                      hipStream_t, bool);
 template int pass1_resident_waves<double>(int);
 template int pass1_resident_waves<float>(int);
-template void launch_pcg_pass2<double>(const PcgGroup<double> *, int, int, int, const int *, hipStream_t);
-template void launch_pcg_pass2<float>(const PcgGroup<float> *, int, int, int, const int *, hipStream_t);
+template void launch_pcg_pass2<double>(const PcgGroup<double> *, int, int, int, const int *, hipStream_t, bool);
+template void launch_pcg_pass2<float>(const PcgGroup<float> *, int, int, int, const int *, hipStream_t, bool);
 
 void launch_resid64(const StripGeom &g, const StripMat &m, const PcgSlots &D, const PcgState<float> &I,
                     const MixedState &M, int n, int it, int every, const int *itb, hipStream_t st) {

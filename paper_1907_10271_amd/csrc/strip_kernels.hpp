@@ -31,14 +31,18 @@ void launch_setup(const StripGeom &g, const StripMat &m, const PcgSlots &S, int 
 // for the FP32 solver, FP32 angles instead of bfloat16 ones).
 // The iteration index is `it`, or *itb + it when itb is not null (graph
 // replay: the captured launches carry offsets, the base lives on the device).
+// nt: streaming (nontemporal) accesses for the vectors that pass through
+// once, for launches whose working set is larger than the Infinity Cache;
+// the results do not depend on it.
 template <typename T>
 void launch_pcg_pass1(const PcgGroup<T> *groups, int ng, int nblocks, const StripMat &m, int it, int cs,
-                      const int *itb, hipStream_t st);
+                      const int *itb, hipStream_t st, bool nt);
 // operator-pass waves (one per work-group) the device keeps resident at once
 template <typename T>
 int pass1_resident_waves(int cs);
 template <typename T>
-void launch_pcg_pass2(const PcgGroup<T> *groups, int ng, int nblocks, int it, const int *itb, hipStream_t st);
+void launch_pcg_pass2(const PcgGroup<T> *groups, int ng, int nblocks, int it, const int *itb, hipStream_t st,
+                      bool nt);
 void launch_resid64(const StripGeom &g, const StripMat &m, const PcgSlots &D, const PcgState<float> &I,
                     const MixedState &M, int n, int it, int every, const int *itb, hipStream_t st);
 void launch_ru_apply(const StripGeom &g, const PcgSlots &D, const PcgState<float> &I, const MixedState &M, int n,

@@ -192,7 +192,7 @@ def test_error_paths():
     with pytest.raises(pk.MLMCError):
         pk.Context('{"kind": "strip"}')
     for bad in ({"sweep_rows": 6}, {"sweep_rows": 20}, {"mixed": {"theta_storage": "fp16"}},
-                {"mixed": {"update_every": 3}}):
+                {"mixed": {"update_every": 3}}, {"streaming_min_mb": -1}, {"streaming_min_mb": "big"}):
         with pytest.raises(pk.MLMCError):
             pk.Context(dict(mi.load_config("strip_c1"), **bad))
 
@@ -391,3 +391,23 @@ def test_tile_height_follows_batch_without_changing_bits(precision):
         qs, _, is_ = ctx.solve_batch([(k, level, False)], xi, precision=precision)
         assert qs.cpu().numpy()[0] == qa[k], (k, qs.cpu().numpy()[0], qa[k])
         assert is_[0]["iters_f"] == ia[k]["iters_f"]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_streaming_accesses_do_not_change_bits(precision):
+    """Launches whose working set exceeds streaming_min_mb use nontemporal
+    accesses for the vectors; forcing them on (0 MiB) or off gives the same
+    bits, for a coupled batch and for a whole-solve level beside it."""
+    import paper_1907_10271_amd as pk
+    name = "strip_c2"
+    xi = dev(_rows(name, 3, 12))
+    reqs = [(k, 3, True) for k in range(6)] + [(k, 2, False) for k in range(6, 12)]
+    res = []
+    for mb in (0, 1e9):
+        c = pk.Context(dict(mi.load_config(name), streaming_min_mb=mb))
+        qf, qc, info = c.solve_batch(reqs, xi, precision=precision)
+        res.append((qf.cpu().numpy(), qc.cpu().numpy(), info["iters_f"].copy(), info["iters_c"].copy()))
+        c.close()
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1], equal_nan=True)
+    assert np.array_equal(res[0][2], res[1][2]) and np.array_equal(res[0][3], res[1][3])
