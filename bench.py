@@ -65,6 +65,10 @@ def parse():
     ap.add_argument("--set", action="append", default=[], metavar="KEY=JSON",
                     help="override a key of the strip workload definition (tuning runs; the line is then "
                          "not the default benchmark), e.g. --set angle_storage='\"cs\"'")
+    ap.add_argument("--calls", choices=["auto", "level", "round"], default="auto",
+                    help="solve calls per step: one per level (per-level times inside the timed region), one "
+                         "for the whole batch round, or auto (measured: per level for FP64, one call for "
+                         "mixed precision)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
@@ -260,7 +264,8 @@ def main():
         del src, dst
     stream = torch.cuda.current_stream()
 
-    def step(s, events=None):
+    def step_levels(s, events=None):
+        """The batch round as one solve call per level."""
         accs = []
         for l, n in enumerate(mix):
             if l not in levels:
@@ -276,6 +281,38 @@ def main():
             accs.append((acc, info))
         return accs
 
+    # the batch round as one call: every level's requests together (the
+    # library runs the whole-solve levels beside the lock-step ones and puts
+    # the lock-step levels in shared launches); parameter rows of all levels
+    # are gathered per step before the timed region
+    offs, o = {}, 0
+    for l, n in enumerate(mix):
+        if l in levels:
+            offs[l] = o
+            o += n
+    all_reqs = [(offs[l] + k, l, l > 0) for l, n in enumerate(mix) if l in levels for k in range(n)]
+    xi_round = [torch.cat([xi[l][s * n:(s + 1) * n] for l, n in enumerate(mix) if l in levels]).contiguous()
+                for s in range(nsteps)]
+    torch.cuda.synchronize()
+
+    def step_round(s, events=None):
+        qf, qc, info = ctx.solve_batch(all_reqs, xi_round[s], precision=prec)
+        accs = []
+        for l, n in enumerate(mix):
+            if l not in levels:
+                accs.append(None)
+                continue
+            a, b = offs[l], offs[l] + n
+            acc = ctx.level_stats(l, qf[a:b], qc[a:b] if l > 0 else None)
+            accs.append((acc, info[a:b]))
+        return accs
+
+    # measured on this benchmark: FP64 631 ms per step with one call per level
+    # against 648 ms with one call (sharing the operator-pass launches gives
+    # level 2 the streaming accesses of the large launch, and the whole-solve
+    # levels beside them gain nothing); mixed precision 546 against 517 ms
+    per_level_calls = args.calls == "level" or (args.calls == "auto" and prec == pk.FP64)
+    step = step_levels if per_level_calls else step_round
     for s in range(args.warmup):
         step(s)
     torch.cuda.synchronize()
@@ -290,19 +327,28 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    p1 = ctx.profile_read(0 if prec == pk.FP64 else 2)
+    p2 = ctx.profile_read(1 if prec == pk.FP64 else 3)
+    ctx.profile(False)
+    if not per_level_calls:
+        # per-level times (outside the timed region): each level alone, on the
+        # parameter rows of the last timed step
+        step_levels(args.warmup + args.steps - 1, ev[-1])
+        torch.cuda.synchronize()
     per_level = []
     for l, n in enumerate(mix):
         if l not in levels:
             continue
-        ms = np.mean([ev[s][l][0].elapsed_time(ev[s][l][1]) for s in range(args.steps)])
+        if per_level_calls:
+            ms = np.mean([ev[s][l][0].elapsed_time(ev[s][l][1]) for s in range(args.steps)])
+        else:
+            ms = ev[-1][l][0].elapsed_time(ev[-1][l][1])
         its_f = np.concatenate([r[l][1]["iters_f"] for r in results])
         ok = all(np.all(r[l][1]["status_f"] == 0) for r in results)
         per_level.append({"level": l, "mesh": f"{cfg['nx0'] << l}x{cfg['ny0'] << l}", "samples": n,
-                          "coupled": l > 0, "ms": round(float(ms), 3),
+                          "coupled": l > 0, ("ms" if per_level_calls else "ms_alone"): round(float(ms), 3),
                           "samples_per_s": round(n / (ms / 1e3), 1),
                           "pcg_iters_mean": round(float(its_f.mean()), 1), "all_converged": bool(ok)})
-    p1 = ctx.profile_read(0 if prec == pk.FP64 else 2)
-    p2 = ctx.profile_read(1 if prec == pk.FP64 else 3)
     # (no lock-step operator launches when only whole-solve levels ran)
     achieved = p1["bytes"] / (p1["ms"] / 1e3) / 1e9 if p1["ms"] > 0 else 0.0
     default_run = (mix == DEFAULT_MIX and prec == pk.FP64 and not args.mixed and not args.set
@@ -324,7 +370,8 @@ def main():
         "data": "synthetic (seeded KL parameters and wrinkles)",
         "config": {"workload": "waviness strip 20x5 mm, 4 levels 64x16..512x128, Matern-3/2 20 modes + wrinkle, "
                                "Jacobi-PCG rtol 1e-10, FP64",
-                   "batch_per_level": mix, "parallelism": "single GPU, data-parallel over samples"},
+                   "batch_per_level": mix, "parallelism": "single GPU, data-parallel over samples",
+                   "solve_calls_per_step": "one per level" if per_level_calls else "one for all levels"},
         "per_level": per_level,
         "roofline": {"bound": "hbm", "kernel": "k_pass1 (PCG operator pass)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
