@@ -142,3 +142,25 @@ def test_wide_factorisation_gives_identical_bits(precision):
         assert np.all(a[2]["status_f"] == 0)
     one.close()
     wide.close()
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_load_128(k):
+    return oracle_plate(3).buckling_load(mi.plate_offsets(C4, 3, 0, 4)[k])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_sampled_parity(precision):
+    """The largest panel mesh (128^2, about 83k unknowns, band width 650) in the
+    plate benchmark's launch of four samples: the wide factorisation and the
+    eigensolver's banded solves at full size.  Samples 0 and 3 are computed by
+    the oracle one by one (about 15 s each); all four must converge."""
+    ctx = context("plate_c4")
+    off = mi.plate_offsets(C4, 3, 0, 4)
+    lf, _, info = ctx.buckle_batch([(k, 3, False) for k in range(4)], dev(off), precision=precision)
+    lf = lf.cpu().numpy()
+    bar = 1e-10 if precision == 0 else 1e-6
+    assert np.all(info["status_f"] == 0), info
+    for k in (0, 3):
+        ref = _oracle_load_128(k)
+        assert abs(lf[k] - ref) <= bar * ref, (k, lf[k], ref)
