@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -668,13 +669,18 @@ struct SolveGroup {
 };
 
 // FP64: set-up + lock-step PCG to completion for the groups
-int run_pcg(mlmc_ctx *c, const std::vector<SolveGroup> &sg, hipStream_t st) {
+// (after_setup, when given, runs once the set-up kernels are queued and before
+// the iterations)
+int run_pcg(mlmc_ctx *c, const std::vector<SolveGroup> &sg, hipStream_t st,
+            const std::function<int()> &after_setup = {}) {
   std::vector<IterGroup<double>> ig;
   for (const auto &x : sg) {
     launch_setup(c->lv[x.level].g, c->mat, x.S, x.n, nullptr, nullptr, st);
     ig.push_back({x.level, x.S, x.n});
   }
   HIPCHK(c, hipGetLastError());
+  if (after_setup)
+    if (int rc = after_setup()) return rc;
   if (int rc = pcg_iterate<double>(c, ig, st, 0, [](int, const std::vector<char> &, const int *, hipStream_t) {}))
     return rc;
   for (const auto &x : sg) launch_x_flush(c->lv[x.level].g, x.S, x.n, st);
@@ -694,7 +700,8 @@ int run_small(mlmc_ctx *c, int level, const PcgSlots &S, int n, hipStream_t st) 
 // residual b - A x recomputed with the FP64 angles whenever the FP32 residual
 // fell by the update factor, and as the only stopping test); x accumulates in
 // FP64.  On return the FP64 pool state of every group holds x.
-int run_mixed(mlmc_ctx *c, const std::vector<SolveGroup> &sg, hipStream_t st) {
+int run_mixed(mlmc_ctx *c, const std::vector<SolveGroup> &sg, hipStream_t st,
+              const std::function<int()> &after_setup = {}) {
   std::vector<IterGroup<float>> ig;
   std::vector<MixedState> ms;
   for (const auto &x : sg) {
@@ -708,6 +715,8 @@ int run_mixed(mlmc_ctx *c, const std::vector<SolveGroup> &sg, hipStream_t st) {
     ms.push_back(M);
   }
   HIPCHK(c, hipGetLastError());
+  if (after_setup)
+    if (int rc = after_setup()) return rc;
   const int every = c->ru_every;
   // the graph key covers the per-group arguments the reliable-update launches bake in
   std::vector<char> sig;
@@ -1163,24 +1172,35 @@ int mlmc_solve_batch(mlmc_ctx *c, int n_req, const mlmc_request *req, const doub
       cnt.push_back(n);
     }
     // whole-solve levels (one work-group per sample, few waves per CU) run on
-    // the side stream while the lock-step launches run on the caller's
+    // the side stream while the lock-step launches run on the caller's.  They
+    // start after the lock-step set-up kernels: their work-groups live for a
+    // whole solve, and the set-up's last work-groups would otherwise wait for
+    // them to leave the CUs before the first iteration could start.
     hipStream_t side = lock.empty() ? st : c->side_stream;
-    if (any_small && side != st) {
-      HIPCHK(c, hipEventRecord(c->ev_fork, st));
-      HIPCHK(c, hipStreamWaitEvent(side, c->ev_fork, 0));
-    }
-    for (size_t k = 0; k < lvls.size(); ++k) {
-      const int l = lvls[k];
-      StripLevel &L = c->lv[l];
-      if (!L.small) continue;
-      PcgSlots S = slots_of(c, l, rt);
-      if (int rc = run_small(c, l, S, cnt[k], side)) return rc;
-      launch_qoi(L.g, c->mat, report_view(c, l, S, MLMC_FP64), cnt[k], L.pool.qpart, L.pool.outidx, q_fine, q_coarse,
-                 info, n_req, side);
-    }
+    bool side_started = false;
+    auto start_side = [&]() -> int {
+      if (side_started) return MLMC_OK;
+      side_started = true;
+      if (any_small && side != st) {
+        HIPCHK(c, hipEventRecord(c->ev_fork, st));
+        HIPCHK(c, hipStreamWaitEvent(side, c->ev_fork, 0));
+      }
+      for (size_t k = 0; k < lvls.size(); ++k) {
+        const int l = lvls[k];
+        StripLevel &L = c->lv[l];
+        if (!L.small) continue;
+        PcgSlots S = slots_of(c, l, rt);
+        if (int rc = run_small(c, l, S, cnt[k], side)) return rc;
+        launch_qoi(L.g, c->mat, report_view(c, l, S, MLMC_FP64), cnt[k], L.pool.qpart, L.pool.outidx, q_fine,
+                   q_coarse, info, n_req, side);
+      }
+      return MLMC_OK;
+    };
+    if (lock.empty())
+      if (int rc = start_side()) return rc;
     for (size_t k0 = 0; k0 < lock.size(); k0 += MAX_GROUPS) {
       std::vector<SolveGroup> part(lock.begin() + k0, lock.begin() + std::min(lock.size(), k0 + MAX_GROUPS));
-      const int rc = precision == MLMC_MIXED ? run_mixed(c, part, st) : run_pcg(c, part, st);
+      const int rc = precision == MLMC_MIXED ? run_mixed(c, part, st, start_side) : run_pcg(c, part, st, start_side);
       if (rc) return rc;
     }
     for (size_t k = 0; k < lvls.size(); ++k) {
