@@ -45,6 +45,7 @@ CONFIG_FILES = {
     "strip_c3": "strip_c3.json",
     "plate_c4": "plate_c4.json",
     "serve_c5": "serve_c5.json",
+    "plate_t2": "plate_t2.json",
 }
 
 

@@ -12,7 +12,18 @@
   stiffness ``k G t`` with ``k = 5/6``).
 * Bilinear Q4 elements with selective reduced integration: membrane,
   coupling and bending terms with 2x2 Gauss points, the shear term with
-  the single centre point.
+  the single centre point (``"shear": "sri"``, the default).  For thick
+  panels that one-point shear term leaves a checkerboard ``w`` mode with
+  almost no energy, which becomes a spurious buckling mode; ``"shear":
+  "mitc4"`` uses the assumed transverse shear strain of Bathe and Dvorkin's
+  MITC4 element instead (``gamma_x`` sampled at the midpoints of the two
+  edges along x and interpolated linearly across, ``gamma_y`` likewise
+  between the midpoints of the edges along y; 2x2 Gauss points).
+* ``"condensed": true`` is the decoupled model of Section 4.1: in-plane
+  stress from ``A`` and moments from ``D* = D - B^T A^-1 B``, i.e. the
+  element is built with ``(A, 0, D*)``; with a prescribed membrane load the
+  in-plane unknowns then carry no geometric stiffness, so the buckling load
+  equals that of the 3-unknown plate ``(w, theta_x, theta_y)`` with ``D*``.
 * Geometric stiffness of a unit compressive edge load ``N0 = 1`` along x:
   ``K_G = int w_x w_x`` (2x2 Gauss).  The printed weak form uses
   ``sigma = diag(-1, 0)`` on the right-hand side, which would make the
@@ -59,7 +70,20 @@ def laminate_abd(Q: np.ndarray, angles_rad, t_ply: float):
     return A, B, D
 
 
-def plate_element(mesh: Mesh, A, B, D, As):
+def _shear_rows(mesh: Mesh, xi: float, eta: float) -> np.ndarray:
+    """Rows of ``gamma = grad w - theta`` (2 x 20) at a reference point."""
+    N, dxi, deta = shape_q1(xi, eta)
+    dNx, dNy = dxi / (0.5 * mesh.hx), deta / (0.5 * mesh.hy)
+    Bs = np.zeros((2, 20))
+    for a in range(4):
+        Bs[0, 5 * a + 2] = dNx[a]
+        Bs[0, 5 * a + 3] = -N[a]
+        Bs[1, 5 * a + 2] = dNy[a]
+        Bs[1, 5 * a + 4] = -N[a]
+    return Bs
+
+
+def plate_element(mesh: Mesh, A, B, D, As, shear: str = "sri"):
     """Element stiffness (20 x 20) and geometric stiffness (20 x 20) of one Q4 RM element."""
     jx, jy = 0.5 * mesh.hx, 0.5 * mesh.hy
     det = jx * jy
@@ -85,23 +109,27 @@ def plate_element(mesh: Mesh, A, B, D, As):
         for a in range(4):
             g[5 * a + 2] = dNx[a]
         KG += det * np.outer(g, g)
-    # transverse shear, one-point rule (weight 4)
-    N, dxi, deta = shape_q1(0.0, 0.0)
-    dNx, dNy = dxi / jx, deta / jy
-    Bs = np.zeros((2, 20))
-    for a in range(4):
-        Bs[0, 5 * a + 2] = dNx[a]
-        Bs[0, 5 * a + 3] = -N[a]
-        Bs[1, 5 * a + 2] = dNy[a]
-        Bs[1, 5 * a + 4] = -N[a]
-    Ke += 4.0 * det * Bs.T @ As @ Bs
+    if shear == "sri":
+        # transverse shear, one-point rule (weight 4)
+        Bs = _shear_rows(mesh, 0.0, 0.0)
+        Ke += 4.0 * det * Bs.T @ As @ Bs
+    elif shear == "mitc4":
+        # assumed shear strain: gamma_x tied at (0, -1), (0, 1), gamma_y at (-1, 0), (1, 0)
+        gx_lo, gx_hi = _shear_rows(mesh, 0.0, -1.0)[0], _shear_rows(mesh, 0.0, 1.0)[0]
+        gy_lo, gy_hi = _shear_rows(mesh, -1.0, 0.0)[1], _shear_rows(mesh, 1.0, 0.0)[1]
+        for xi, eta in GP_REF:
+            Bs = np.vstack([0.5 * (1 - eta) * gx_lo + 0.5 * (1 + eta) * gx_hi,
+                            0.5 * (1 - xi) * gy_lo + 0.5 * (1 + xi) * gy_hi])
+            Ke += det * Bs.T @ As @ Bs
+    else:
+        raise ValueError(f"unknown shear treatment {shear!r}")
     return Ke, KG
 
 
-def plate_element_bending_only(mesh: Mesh, D, As):
+def plate_element_bending_only(mesh: Mesh, D, As, shear: str = "sri"):
     """3-dof element (w, theta_x, theta_y) with bending ``D`` only: the decoupled
-    model of Section 4.1 with ``D* = D`` (exact when ``B = 0``)."""
-    Ke5, KG5 = plate_element(mesh, np.eye(3), np.zeros((3, 3)), D, As)
+    model of Section 4.1 (pass ``D*`` for the condensed laminate)."""
+    Ke5, KG5 = plate_element(mesh, np.eye(3), np.zeros((3, 3)), D, As, shear)
     keep = [5 * a + c for a in range(4) for c in (2, 3, 4)]
     return Ke5[np.ix_(keep, keep)], KG5[np.ix_(keep, keep)]
 
@@ -134,6 +162,11 @@ def ss_constrained_dofs(mesh: Mesh, ndof: int = 5) -> np.ndarray:
     return np.unique(np.concatenate(c))
 
 
+def condensed_bending(A, B, D):
+    """``D* = D - B^T A^-1 B`` (Section 4.1, the decoupled model)."""
+    return D - B.T @ np.linalg.solve(A, B)
+
+
 @dataclass
 class PlateSystem:
     K: sp.csr_matrix      # constrained stiffness (free dofs only)
@@ -160,10 +193,13 @@ class PlateModel:
 
     def system(self, offsets_rad, ndof: int = 5) -> PlateSystem:
         A, B, D = self.abd(offsets_rad)
+        shear = self.cfg.get("shear", "sri")
+        if self.cfg.get("condensed", False):
+            D, B = condensed_bending(A, B, D), np.zeros((3, 3))
         if ndof == 5:
-            Ke, KGe = plate_element(self.mesh, A, B, D, self.As)
+            Ke, KGe = plate_element(self.mesh, A, B, D, self.As, shear)
         else:
-            Ke, KGe = plate_element_bending_only(self.mesh, D, self.As)
+            Ke, KGe = plate_element_bending_only(self.mesh, D, self.As, shear)
         K = _assemble_uniform(self.mesh, Ke, ndof)
         KG = _assemble_uniform(self.mesh, self.cfg.get("N0", 1.0) * KGe, ndof)
         con = ss_constrained_dofs(self.mesh, ndof)

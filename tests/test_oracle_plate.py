@@ -6,7 +6,7 @@ import pytest
 
 import mlmc_inputs as mi
 from oracle.mesh import Mesh
-from oracle.plate import (PlateModel, laminate_abd, navier_orthotropic, plate_element)
+from oracle.plate import (PlateModel, condensed_bending, laminate_abd, navier_orthotropic, plate_element)
 from oracle.sr import indicator, sr_chain, sr_pair
 
 C4 = mi.load_config("plate_c4")
@@ -110,3 +110,72 @@ def test_sr_close_sample_refines():
     lam, j, _ = sr_chain(lambda j: lam_vals[j], 3, lam_star=0.885, m=4, alpha=1.0, j_min=1)
     # |0.90-0.885| = 0.015 < 0.05/3 -> refine; |0.887-0.885| < 0.013/3 -> refine; level 3 is the last
     assert j == 3 and lam == 0.8832
+
+
+T2 = mi.load_config("plate_t2")
+
+
+def _null_dim(K):
+    ev = np.linalg.eigvalsh(K)
+    return int(np.sum(np.abs(ev) < 1e-9 * ev.max()))
+
+
+def test_mitc4_element_has_only_the_rigid_zero_modes():
+    """MITC4 transverse shear (Bathe-Dvorkin): the 20x20 element of a coupled
+    laminate has exactly the six rigid motions as zero-energy modes; the
+    one-point shear rule has two more (hourglass modes, among them the
+    checkerboard w that becomes the thick panel's spurious buckling mode)."""
+    m = PlateModel(T2, 0)
+    A, B, D = m.abd(np.radians([2.0, -1.0, 3.0, 0.0, -2.0, 1.0, 0.5, -3.0]))
+    Km, _ = plate_element(m.mesh, A, B, D, m.As, "mitc4")
+    Ks, _ = plate_element(m.mesh, A, B, D, m.As, "sri")
+    assert np.abs(Km - Km.T).max() <= 1e-12 * np.abs(Km).max()
+    assert _null_dim(Km) == 6 and _null_dim(Ks) == 8
+    # the rigid motions: u, v translations, in-plane rotation, w = 1, and the
+    # tilts w = x, theta_x = 1 and w = y, theta_y = 1
+    xs = np.array([-1.0, 1.0, 1.0, -1.0]) * 0.5 * m.mesh.hx
+    ys = np.array([-1.0, -1.0, 1.0, 1.0]) * 0.5 * m.mesh.hy
+    rig = np.zeros((6, 20))
+    for a in range(4):
+        rig[0, 5 * a] = 1.0
+        rig[1, 5 * a + 1] = 1.0
+        rig[2, 5 * a], rig[2, 5 * a + 1] = -ys[a], xs[a]
+        rig[3, 5 * a + 2] = 1.0
+        rig[4, 5 * a + 2], rig[4, 5 * a + 3] = xs[a], 1.0
+        rig[5, 5 * a + 2], rig[5, 5 * a + 4] = ys[a], 1.0
+    assert np.abs(Km @ rig.T).max() <= 1e-9 * np.abs(Km).max()
+
+
+def test_condensed_bending_is_the_schur_complement():
+    """D* = D - B^T A^-1 B is the inverse of the bending block of the inverse
+    laminate matrix [[A, B], [B, D]]^-1; it equals D for the pristine Winckler
+    stacking, whose B vanishes."""
+    m = PlateModel(T2, 0)
+    A, B, D = m.abd(np.radians([2.0, -1.0, 3.0, 0.0, -2.0, 1.0, 0.5, -3.0]))
+    assert np.abs(B).max() > 1.0
+    inv = np.linalg.inv(np.block([[A, B], [B, D]]))
+    np.testing.assert_allclose(np.linalg.inv(inv[3:, 3:]), condensed_bending(A, B, D), rtol=1e-10, atol=1e-6)
+    A0, B0, D0 = m.abd(np.zeros(8))
+    assert np.abs(B0).max() <= 1e-12 * np.abs(D0).max()
+    np.testing.assert_allclose(condensed_bending(A0, B0, D0), D0, rtol=1e-12, atol=1e-12 * np.abs(D0).max())
+
+
+def test_condensed_five_unknown_model_equals_the_three_unknown_plate():
+    m = PlateModel(T2, 0)
+    off = mi.plate_offsets(T2, 0, 0, 1)[0]
+    l5, l3 = m.buckling_load(off, ndof=5), m.buckling_load(off, ndof=3)
+    assert abs(l5 - l3) <= 1e-10 * l3
+
+
+def test_panel_load_converges_to_the_printed_value():
+    """Test Problem II pristine panel with 0.8 mm plies: the load converges
+    from above under refinement (with MITC4; the one-point shear rule drops
+    to a checkerboard mode at 64x64), and the total edge force lambda L_y is
+    within 0.5% of the 278.59 kN the paper prints for its pristine panel
+    (the figure caption of Section 4)."""
+    lam = [PlateModel(T2, lv).buckling_load(np.zeros(8)) for lv in (0, 1)]
+    assert lam[0] > lam[1] and (lam[0] - lam[1]) < 1e-2 * lam[1]
+    force_kn = lam[1] * T2["b"] / 1000.0
+    assert abs(force_kn - 278.59) <= 5e-3 * 278.59, force_kn
+    sri = PlateModel(dict(T2, shear="sri"), 1).buckling_load(np.zeros(8))
+    assert sri < 0.5 * lam[1]
