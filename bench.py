@@ -53,6 +53,9 @@ def parse():
                     help="overrides of the mixed-precision settings, e.g. update_factor=0.1,theta_storage=bf16")
     ap.add_argument("--plate", type=str, default="",
                     help="also time the buckling solver: samples per plate level, e.g. 1024,256,32,4")
+    ap.add_argument("--plate-config", type=str, default="plate_c4",
+                    help="panel workload of the plate leg: plate_c4 (500 mm panel) or plate_t2 (the 636 x 212 mm "
+                         "Test Problem II panel)")
     ap.add_argument("--serve", type=str, default="",
                     help="also run the serving loop over the mixed request stream at these arrival rates "
                          "(requests/s, comma list)")
@@ -157,10 +160,10 @@ def profiled_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
-def plate_leg(pk, torch, counts, prec):
-    """Buckling loads per level of the panel workload (one timed batch per level)."""
-    pcfg = mi.load_config("plate_c4")
-    pctx = pk.Context(mi.config_text("plate_c4"))
+def plate_leg(pk, torch, counts, prec, name="plate_c4"):
+    """Buckling loads per level of a panel workload (one timed batch per level)."""
+    pcfg = mi.load_config(name)
+    pctx = pk.Context(mi.config_text(name))
     res = []
     for l, n in enumerate(counts):
         if n <= 0:
@@ -387,7 +390,8 @@ def main():
         "cpu_baseline": None if cpu is None else {k: v for k, v in cpu.items() if k != "per_level_s_per_sample"},
     }
     if args.plate:
-        out["plate"] = plate_leg(pk, torch, [int(v) for v in args.plate.split(",")], prec)
+        out["plate"] = plate_leg(pk, torch, [int(v) for v in args.plate.split(",")], prec, args.plate_config)
+        out["plate_workload"] = args.plate_config
     if args.serve:
         out["serving"] = serve_leg(pk, [float(v) for v in args.serve.split(",")], args.serve_duration, prec)
     if args.time_to_eps > 0:

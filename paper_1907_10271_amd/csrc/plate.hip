@@ -40,6 +40,8 @@ struct PlateMat {
   double Q11, Q22, Q12, Q66;
   double shear_k_G_t;  // k G t
   double N0;
+  int mitc4;      // transverse shear: 0 one-point rule, 1 MITC4 assumed strain
+  int condensed;  // decoupled laminate (A, 0, D* = D - B^T A^-1 B)
   int nply;
   double t_ply;
   double layup[MAXPLY];
@@ -119,18 +121,45 @@ __device__ void element_matrices(const PlateGeom &g, const PlateMat &m, const do
       kv += det * s;
       if (c == 2 && d == 2) kg += det * m.N0 * dNxa * dNxb;
     }
-    // transverse shear at the centre (weight 4): gamma = (w_x - theta_x, w_y - theta_y)
-    const double Na = 0.25, Nb = 0.25;
-    const double dNxa = 0.25 * xa[a] / jx, dNya = 0.25 * ya[a] / jy;
-    const double dNxb = 0.25 * xa[b2] / jx, dNyb = 0.25 * ya[b2] / jy;
-    double sa[2] = {0, 0}, sb[2] = {0, 0};
-    if (c == 2) { sa[0] = dNxa; sa[1] = dNya; }
-    if (c == 3) sa[0] = -Na;
-    if (c == 4) sa[1] = -Na;
-    if (d == 2) { sb[0] = dNxb; sb[1] = dNyb; }
-    if (d == 3) sb[0] = -Nb;
-    if (d == 4) sb[1] = -Nb;
-    kv += 4.0 * det * m.shear_k_G_t * (sa[0] * sb[0] + sa[1] * sb[1]);
+    if (!m.mitc4) {
+      // transverse shear at the centre (weight 4): gamma = (w_x - theta_x, w_y - theta_y)
+      const double Na = 0.25, Nb = 0.25;
+      const double dNxa = 0.25 * xa[a] / jx, dNya = 0.25 * ya[a] / jy;
+      const double dNxb = 0.25 * xa[b2] / jx, dNyb = 0.25 * ya[b2] / jy;
+      double sa[2] = {0, 0}, sb[2] = {0, 0};
+      if (c == 2) { sa[0] = dNxa; sa[1] = dNya; }
+      if (c == 3) sa[0] = -Na;
+      if (c == 4) sa[1] = -Na;
+      if (d == 2) { sb[0] = dNxb; sb[1] = dNyb; }
+      if (d == 3) sb[0] = -Nb;
+      if (d == 4) sb[1] = -Nb;
+      kv += 4.0 * det * m.shear_k_G_t * (sa[0] * sb[0] + sa[1] * sb[1]);
+    } else {
+      // MITC4 assumed shear strain (Bathe and Dvorkin): gamma_x of unknown
+      // (node, component) tied at the edge midpoints (0, -1), (0, 1) and
+      // interpolated linearly in eta; gamma_y tied at (-1, 0), (1, 0) and
+      // interpolated in xi; 2x2 Gauss points
+      auto tie_x = [&](int n, int cc, double et) {  // gamma_x row at (0, et)
+        const double N = 0.25 * (1 + ya[n] * et);
+        return cc == 2 ? 0.25 * xa[n] * (1 + ya[n] * et) / jx : cc == 3 ? -N : 0.0;
+      };
+      auto tie_y = [&](int n, int cc, double xt) {  // gamma_y row at (xt, 0)
+        const double N = 0.25 * (1 + xa[n] * xt);
+        return cc == 2 ? 0.25 * ya[n] * (1 + xa[n] * xt) / jy : cc == 4 ? -N : 0.0;
+      };
+      const double xa0 = tie_x(a, c, -1), xa1 = tie_x(a, c, 1), ya0 = tie_y(a, c, -1), ya1 = tie_y(a, c, 1);
+      const double xb0 = tie_x(b2, d, -1), xb1 = tie_x(b2, d, 1), yb0 = tie_y(b2, d, -1), yb1 = tie_y(b2, d, 1);
+      double ks = 0.0;
+      for (int q = 0; q < 4; ++q) {
+        const double xi = (q & 1) ? gq : -gq, eta = (q & 2) ? gq : -gq;
+        const double gxa = 0.5 * (1 - eta) * xa0 + 0.5 * (1 + eta) * xa1;
+        const double gya = 0.5 * (1 - xi) * ya0 + 0.5 * (1 + xi) * ya1;
+        const double gxb = 0.5 * (1 - eta) * xb0 + 0.5 * (1 + eta) * xb1;
+        const double gyb = 0.5 * (1 - xi) * yb0 + 0.5 * (1 + xi) * yb1;
+        ks += gxa * gxb + gya * gyb;
+      }
+      kv += det * m.shear_k_G_t * ks;
+    }
     Ke[idx] = kv;
     KGe[idx] = kg;
   }
@@ -526,34 +555,60 @@ struct PlateJob {
   int n;
 };
 
+// laminate matrix Dmb = [[A, B], [B, D]] (6 x 6, Eq. CLTABD) of one sample's
+// ply offsets; for the decoupled model (Section 4.1) [[A, 0], [0, D*]] with
+// D* = D - B^T A^-1 B.  One thread.
+__device__ void laminate_dmb(const PlateMat &m, const double *off, double *Dmb) {
+  double A[6] = {0, 0, 0, 0, 0, 0}, Bm[6] = {0, 0, 0, 0, 0, 0}, D[6] = {0, 0, 0, 0, 0, 0};
+  const double z0 = -0.5 * m.nply * m.t_ply;
+  for (int k = 0; k < m.nply; ++k) {
+    double q[6];
+    qbar_ply(m, m.layup[k] + off[k], q);
+    const double za = z0 + k * m.t_ply, zb = za + m.t_ply;
+    for (int t = 0; t < 6; ++t) {
+      A[t] += q[t] * (zb - za);
+      Bm[t] += q[t] * (zb * zb - za * za) * 0.5;
+      D[t] += q[t] * (zb * zb * zb - za * za * za) / 3.0;
+    }
+  }
+  // 3x3 blocks from (11, 12, 22, 16, 26, 66)
+  auto full3 = [](const double *v, double *M3) {
+    const double f[9] = {v[0], v[1], v[3], v[1], v[2], v[4], v[3], v[4], v[5]};
+    for (int i = 0; i < 9; ++i) M3[i] = f[i];
+  };
+  double A3[9], B3[9], D3[9];
+  full3(A, A3);
+  full3(Bm, B3);
+  full3(D, D3);
+  if (m.condensed) {
+    // A^-1 by cofactors (A symmetric positive definite), then D - B A^-1 B
+    const double c00 = A3[4] * A3[8] - A3[5] * A3[7], c01 = A3[5] * A3[6] - A3[3] * A3[8],
+                 c02 = A3[3] * A3[7] - A3[4] * A3[6];
+    const double det = A3[0] * c00 + A3[1] * c01 + A3[2] * c02;
+    const double Ai[9] = {c00 / det, (A3[2] * A3[7] - A3[1] * A3[8]) / det, (A3[1] * A3[5] - A3[2] * A3[4]) / det,
+                          c01 / det, (A3[0] * A3[8] - A3[2] * A3[6]) / det, (A3[2] * A3[3] - A3[0] * A3[5]) / det,
+                          c02 / det, (A3[1] * A3[6] - A3[0] * A3[7]) / det, (A3[0] * A3[4] - A3[1] * A3[3]) / det};
+    double AiB[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) AiB[3 * i + j] = Ai[3 * i] * B3[j] + Ai[3 * i + 1] * B3[3 + j] + Ai[3 * i + 2] * B3[6 + j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        D3[3 * i + j] -= B3[i] * AiB[j] + B3[3 + i] * AiB[3 + j] + B3[6 + i] * AiB[6 + j];  // (B^T A^-1 B)_ij
+    for (int i = 0; i < 9; ++i) B3[i] = 0.0;
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      Dmb[6 * i + j] = A3[3 * i + j];
+      Dmb[6 * i + 3 + j] = B3[3 * i + j];
+      Dmb[6 * (3 + i) + j] = B3[3 * j + i];
+      Dmb[6 * (3 + i) + 3 + j] = D3[3 * i + j];
+    }
+}
+
 // laminate (Eq. CLTABD) of sample s and its uniform element matrices
 __device__ void sample_elements(const PlateGeom &g, const PlateMat &m, const PlateJob &J, int s, double *Dmb,
                                 double *Ke, double *KGe) {
-  if (threadIdx.x == 0) {
-    const double *off = J.offsets + (size_t)J.rows[s] * m.nply;
-    double A[6] = {0, 0, 0, 0, 0, 0}, Bm[6] = {0, 0, 0, 0, 0, 0}, D[6] = {0, 0, 0, 0, 0, 0};
-    const double z0 = -0.5 * m.nply * m.t_ply;
-    for (int k = 0; k < m.nply; ++k) {
-      double q[6];
-      qbar_ply(m, m.layup[k] + off[k], q);
-      const double za = z0 + k * m.t_ply, zb = za + m.t_ply;
-      for (int t = 0; t < 6; ++t) {
-        A[t] += q[t] * (zb - za);
-        Bm[t] += q[t] * (zb * zb - za * za) * 0.5;
-        D[t] += q[t] * (zb * zb * zb - za * za * za) / 3.0;
-      }
-    }
-    // 3x3 blocks from (11, 12, 22, 16, 26, 66)
-    auto put = [&](const double *v, int r0, int c0) {
-      const double M3[9] = {v[0], v[1], v[3], v[1], v[2], v[4], v[3], v[4], v[5]};
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) Dmb[6 * (r0 + i) + c0 + j] = M3[3 * i + j];
-    };
-    put(A, 0, 0);
-    put(Bm, 0, 3);
-    put(Bm, 3, 0);
-    put(D, 3, 3);
-  }
+  if (threadIdx.x == 0) laminate_dmb(m, J.offsets + (size_t)J.rows[s] * m.nply, Dmb);
   __syncthreads();
   element_matrices(g, m, Dmb, Ke, KGe);
   __syncthreads();
@@ -883,30 +938,7 @@ __global__ __launch_bounds__(PT) void k_plate_apply(PlateGeom g, PlateMat m, con
                                                     const double *x, double *y, double *xf, double *yf) {
   __shared__ double Ke[400], KGe[400], Dmb[36];
   const int s = blockIdx.x;
-  if (threadIdx.x == 0) {
-    const double *off = offsets + (size_t)s * m.nply;
-    double A[6] = {0, 0, 0, 0, 0, 0}, Bm[6] = {0, 0, 0, 0, 0, 0}, D[6] = {0, 0, 0, 0, 0, 0};
-    const double z0 = -0.5 * m.nply * m.t_ply;
-    for (int k = 0; k < m.nply; ++k) {
-      double q[6];
-      qbar_ply(m, m.layup[k] + off[k], q);
-      const double za = z0 + k * m.t_ply, zb = za + m.t_ply;
-      for (int t = 0; t < 6; ++t) {
-        A[t] += q[t] * (zb - za);
-        Bm[t] += q[t] * (zb * zb - za * za) * 0.5;
-        D[t] += q[t] * (zb * zb * zb - za * za * za) / 3.0;
-      }
-    }
-    auto put = [&](const double *v, int r0, int c0) {
-      const double M3[9] = {v[0], v[1], v[3], v[1], v[2], v[4], v[3], v[4], v[5]};
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) Dmb[6 * (r0 + i) + c0 + j] = M3[3 * i + j];
-    };
-    put(A, 0, 0);
-    put(Bm, 0, 3);
-    put(Bm, 3, 0);
-    put(D, 3, 3);
-  }
+  if (threadIdx.x == 0) laminate_dmb(m, offsets + (size_t)s * m.nply, Dmb);
   __syncthreads();
   element_matrices(g, m, Dmb, Ke, KGe);
   __syncthreads();
@@ -1014,6 +1046,14 @@ PlateCtx *plate_create(const Json &cfg, std::string &err) {
     const double t = p->mat.t_ply * p->mat.nply;
     p->mat.shear_k_G_t = cfg.number_or("shear_k", 5.0 / 6.0) * G * t;
     p->mat.N0 = cfg.number_or("N0", 1.0);
+    const std::string shear = cfg.string_or("shear", "sri");
+    if (shear != "sri" && shear != "mitc4") throw std::runtime_error("shear must be sri or mitc4");
+    p->mat.mitc4 = shear == "mitc4";
+    p->mat.condensed = 0;
+    if (cfg.has("condensed")) {
+      if (cfg.at("condensed").type != Json::Bool) throw std::runtime_error("condensed must be true or false");
+      p->mat.condensed = cfg.at("condensed").b;
+    }
     p->tol = cfg.number_or("eig_tol", 1e-8);
     p->max_iter = (int)cfg.number_or("eig_max_iter", 500);
     // band width from which one sample's factorisation is spread over work-groups

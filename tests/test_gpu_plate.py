@@ -164,3 +164,60 @@ def test_full_size_sampled_parity(precision):
     for k in (0, 3):
         ref = _oracle_load_128(k)
         assert abs(lf[k] - ref) <= bar * ref, (k, lf[k], ref)
+
+
+T2 = mi.load_config("plate_t2")
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_t2(level):
+    from oracle.plate import PlateModel
+    return PlateModel(T2, level)
+
+
+@functools.lru_cache(maxsize=None)
+def _t2_load(level, k):
+    return oracle_t2(level).buckling_load(mi.plate_offsets(T2, level, 0, k + 1)[k])
+
+
+def test_panel_t2_operators_parity():
+    """Test Problem II panel: the decoupled laminate (A, 0, D*) and the MITC4
+    shear term of the GPU element against the oracle's assembled K and K_G."""
+    ctx = context("plate_t2")
+    om = oracle_t2(0)
+    off = mi.plate_offsets(T2, 0, 0, 2)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((2, 5 * om.mesh.n_nodes))
+    yk = ctx.plate_apply(0, dev(off), dev(x), geometric=False).cpu().numpy()
+    yg = ctx.plate_apply(0, dev(off), dev(x), geometric=True).cpu().numpy()
+    for k in range(2):
+        s = om.system(off[k])
+        ref_k = full_from_free(s, s.K @ x[k][s.free])
+        ref_g = full_from_free(s, s.KG @ x[k][s.free])
+        assert np.abs(yk[k] - ref_k).max() <= 1e-13 * np.abs(ref_k).max()
+        assert np.abs(yg[k] - ref_g).max() <= 1e-13 * np.abs(ref_g).max()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_panel_t2_buckling_parity(precision):
+    """Test Problem II panel (636 x 212 mm, Winckler stacking, D*, MITC4):
+    buckling loads against the oracle at 32^2 (one work-group per sample),
+    64^2 and the full-size 128^2 (factorisation spread over work-groups), in
+    the plate benchmark's batches for this panel (sampled at 128^2)."""
+    ctx = context("plate_t2")
+    bar = 1e-10 if precision == 0 else 1e-6
+    for level, n, check in ((0, 16, (0, 15)), (1, 8, (0, 7)), (2, 2, (1,))):
+        off = mi.plate_offsets(T2, level, 0, n)
+        lf, _, info = ctx.buckle_batch([(k, level, False) for k in range(n)], dev(off), precision=precision)
+        lf = lf.cpu().numpy()
+        assert np.all(info["status_f"] == 0), (level, info["status_f"])
+        for k in check:
+            ref = _t2_load(level, k)
+            assert abs(lf[k] - ref) <= bar * ref, (level, k, lf[k], ref)
+
+
+def test_panel_t2_bad_settings_rejected():
+    import paper_1907_10271_amd as pk
+    for bad in ({"shear": "mitc9"}, {"condensed": 1}):
+        with pytest.raises(pk.MLMCError):
+            pk.Context(dict(T2, **bad))
