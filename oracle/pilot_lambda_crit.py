@@ -6,9 +6,10 @@ empirical quantile of the level-0 buckling load over a fixed-seed pilot
 sample (the oracle's sparse eigen-solve, one process per core) and scales
 it by the ratio of the pristine loads on the finest and the coarsest level,
 so the threshold refers to the finest discretisation.  The result is written
-to ``tests/golden/lambda_crit.json`` and to the workload definition.
+to ``tests/golden/lambda_crit.json`` (``lambda_crit_<workload>.json`` for a
+panel workload other than the 500 mm one) and to the workload definition.
 
-Run: ``python -m oracle.pilot_lambda_crit [n_samples]`` (oracle only).
+Run: ``python -m oracle.pilot_lambda_crit [n_samples] [workload]`` (oracle only).
 """
 from __future__ import annotations
 
@@ -34,10 +35,10 @@ def _solve(row):
     return _M.buckling_load(row)
 
 
-def main(n: int = 6000) -> dict:
+def main(n: int = 6000, name: str = "plate_c4") -> dict:
     global _M
     os.environ.setdefault("OMP_NUM_THREADS", "1")
-    cfg = mi.load_config("plate_c4")
+    cfg = mi.load_config(name)
     _M = PlateModel(cfg, 0)
     rows = mi.plate_offsets(cfg, 0, 0, n, stream=PILOT_STREAM)
     t0 = time.time()
@@ -51,9 +52,11 @@ def main(n: int = 6000) -> dict:
            "pristine_level0": pristine[0], "pristine_top": pristine[1], "pilot_stream": PILOT_STREAM,
            "level0_mean": float(lam0.mean()), "level0_std": float(lam0.std()), "seconds": time.time() - t0,
            "source": "oracle/pilot_lambda_crit.py"}
-    with open(os.path.join(ROOT, "tests", "golden", "lambda_crit.json"), "w") as f:
+    gold = "lambda_crit.json" if name == "plate_c4" else f"lambda_crit_{name}.json"
+    out["workload"] = name
+    with open(os.path.join(ROOT, "tests", "golden", gold), "w") as f:
         json.dump(out, f, indent=1)
-    path = mi.config_path("plate_c4")
+    path = mi.config_path(name)
     c = json.load(open(path))
     c["lambda_crit"] = lam_crit
     c["lambda_crit_source"] = "oracle/pilot_lambda_crit.py (level-0 quantile x pristine top/level-0 ratio)"
@@ -64,4 +67,5 @@ def main(n: int = 6000) -> dict:
 
 
 if __name__ == "__main__":
-    print(json.dumps(main(int(sys.argv[1]) if len(sys.argv) > 1 else 6000), indent=1))
+    print(json.dumps(main(int(sys.argv[1]) if len(sys.argv) > 1 else 6000,
+                          sys.argv[2] if len(sys.argv) > 2 else "plate_c4"), indent=1))
