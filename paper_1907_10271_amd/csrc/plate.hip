@@ -639,12 +639,15 @@ __device__ void lobpcg(const PlateGeom &g, const double *Ke, const double *KGe, 
   __shared__ double coef[NS * NB], mu[NB], resn[NB];
   const int n = g.nfree;
   auto V = [&](int k) { return vec + (size_t)k * n; };
-  // ---- initial block: smooth mode shapes w = sin(p pi x/a) sin(q pi y/b), theta = grad w
+  // ---- initial block: smooth mode shapes w = sin(p pi x/a) sin(pi y/b), theta = grad w,
+  // for p = p0, p0 + 1 half-waves along x, p0 the integer nearest to a/b (a long
+  // panel buckles in about a/b half-waves; 1 for a square panel)
+  const int p0 = max(1, (int)lround(g.a / g.b));
   for (int r = threadIdx.x; r < n; r += PT) {
     const int full = g.full_of_free[r], node = full / 5, c = full % 5;
     const double x = (node % g.nnx) * g.hx, y = (node / g.nnx) * g.hy;
     for (int v = 0; v < NB; ++v) {
-      const double px = M_PI * (v + 1) / g.a, py = M_PI / g.b;
+      const double px = M_PI * (p0 + v) / g.a, py = M_PI / g.b;
       double val = 0.0;
       if (c == 2) val = sin(px * x) * sin(py * y);
       if (c == 3) val = px * cos(px * x) * sin(py * y);
