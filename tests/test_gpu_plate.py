@@ -203,10 +203,13 @@ def test_panel_t2_buckling_parity(precision):
     """Test Problem II panel (636 x 212 mm, Winckler stacking, D*, MITC4):
     buckling loads against the oracle at 32^2 (one work-group per sample),
     64^2 and the full-size 128^2 (factorisation spread over work-groups), in
-    the plate benchmark's batches for this panel (sampled at 128^2)."""
+    the plate benchmark's batches for this panel (every sample at 32^2,
+    sampled above).  LOBPCG stops at a small residual, which any eigenpair
+    has: checking every sample of a batch guards against convergence to a
+    higher mode (seen with a start of one and two half-waves along x)."""
     ctx = context("plate_t2")
     bar = 1e-10 if precision == 0 else 1e-6
-    for level, n, check in ((0, 16, (0, 15)), (1, 8, (0, 7)), (2, 2, (1,))):
+    for level, n, check in ((0, 16, range(16)), (1, 8, (0, 7)), (2, 2, (1,))):
         off = mi.plate_offsets(T2, level, 0, n)
         lf, _, info = ctx.buckle_batch([(k, level, False) for k in range(n)], dev(off), precision=precision)
         lf = lf.cpu().numpy()
