@@ -179,3 +179,20 @@ def test_panel_load_converges_to_the_printed_value():
     assert abs(force_kn - 278.59) <= 5e-3 * 278.59, force_kn
     sri = PlateModel(dict(T2, shear="sri"), 1).buckling_load(np.zeros(8))
     assert sri < 0.5 * lam[1]
+
+
+@pytest.mark.parametrize("name,fixture", [("plate_c4", "lambda_crit.json"), ("plate_t2", "lambda_crit_plate_t2.json")])
+def test_threshold_fixtures_match_the_workloads(name, fixture):
+    """The failure thresholds in the workload definitions are the ones the
+    oracle-only pilot wrote (its level-0 quantile times the ratio of the
+    pristine loads on the finest and the coarsest level)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", fixture)) as f:
+        gold = json.load(f)
+    cfg = mi.load_config(name)
+    assert cfg["lambda_crit"] == gold["lambda_crit"]
+    assert gold["p_target"] == cfg["p_target"]
+    assert abs(gold["level0_quantile"] * gold["pristine_top"] / gold["pristine_level0"] - gold["lambda_crit"]) \
+        <= 1e-12 * gold["lambda_crit"]
+    assert gold["level0_mean"] - 4 * gold["level0_std"] < gold["level0_quantile"] < gold["level0_mean"]
