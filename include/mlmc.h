@@ -189,8 +189,10 @@ int mlmc_buckle_batch(mlmc_ctx *ctx, int n_req, const mlmc_request *req, const d
 /* Matrix-free plate operators for one sample per row of ply_offsets (dev
  * [n][n_plies], radians): y = P K P x (geometric == 0) or y = P K_G P x
  * (geometric != 0), with P the projector on the unconstrained unknowns
- * (Section 4.1: Reissner-Mindlin Q4, selective reduced integration;
- * K_G = int N0 w_x w_x).  x, y: dev [n][5 n_nodes], unknowns (u, v, w,
+ * (Section 4.1: Reissner-Mindlin Q4, selective reduced integration, or the
+ * MITC4 assumed transverse shear strain when the workload sets
+ * "shear": "mitc4"; laminate [[A, B], [B, D]], or [[A, 0], [0, D*]] with
+ * D* = D - B^T A^-1 B when it sets "condensed": true; K_G = int N0 w_x w_x).  x, y: dev [n][5 n_nodes], unknowns (u, v, w,
  * theta_x, theta_y) per node, node (i, j) at j (nx + 1) + i; y = 0 on
  * constrained unknowns. */
 int mlmc_plate_apply(mlmc_ctx *ctx, int level, int n, const double *ply_offsets, int geometric, const double *x,
