@@ -35,9 +35,12 @@
   y = 0, b); in-plane rigid motions are removed by ``u = 0`` on x = 0 and
   ``v = 0`` on y = 0.
 
-The pristine buckling load of the paper's own panel (278.59 kN) is not
-reproduced: it is a different panel with an ambiguous ply thickness --
-parity unpinned for that number.
+The paper's own panel (Test Problem II: 636 x 212 mm, eight 0.8 mm plies,
+``"condensed": true``, ``"shear": "mitc4"``) reproduces the printed
+pristine load of 278.59 kN to 0.17% at 128 x 128 when 0.8 mm is read as the
+ply thickness and the load as the total edge force ``lambda L_y``; that is
+pinned (tests/test_oracle_plate.py).  The 500 mm panel workload has no
+printed value to pin against.
 """
 from __future__ import annotations
 
