@@ -196,3 +196,15 @@ def test_threshold_fixtures_match_the_workloads(name, fixture):
     assert abs(gold["level0_quantile"] * gold["pristine_top"] / gold["pristine_level0"] - gold["lambda_crit"]) \
         <= 1e-12 * gold["lambda_crit"]
     assert gold["level0_mean"] - 4 * gold["level0_std"] < gold["level0_quantile"] < gold["level0_mean"]
+
+
+def test_panel_load_error_rate_alpha_one():
+    """The paper reports that the FE error of its panel's buckling load falls
+    with order alpha ~ 1 in the number of unknowns M (Section 4, the
+    convergence figure).  M grows four-fold per level, so successive
+    differences of the pristine load shrink about four-fold."""
+    lam = [PlateModel(T2, lv).buckling_load(np.zeros(8)) for lv in (0, 1, 2)]
+    d01, d12 = lam[0] - lam[1], lam[1] - lam[2]
+    assert d01 > 0 and d12 > 0
+    alpha = math.log(d01 / d12) / math.log(4.0)
+    assert 0.8 < alpha < 1.2, alpha
