@@ -7,15 +7,25 @@
 * 2-D separable exponential: the oracle's Nystrom machinery applied to the
   separable kernel reproduces the closed-form products (this pins the
   Nystrom code used for the Matern covariance).
-* Matern: trace identity of the discrete operator, orthonormality in the
-  quadrature inner product, Nystrom interpolation reproduces the grid
-  values, eigen-equation residuals, robust sign convention, and a sample
-  variance check of the synthesised field.
+* 2-D separable exponential, selection and order: the ten largest
+  eigenvalues of a 2-D Nystrom solve of the full covariance operator on the
+  strip (no use of the product structure in the eigensolve, Richardson
+  extrapolated over two grids) equal the oracle's closed-form products in
+  value and order, and its eigenvectors equal the oracle's modes.
+* Matern: the oracle's kernel is the general Matern form
+  ``s^2 2^(1-nu)/Gamma(nu) (sqrt(2 nu) r/l)^nu K_nu(sqrt(2 nu) r/l)`` at
+  ``nu = 3/2`` (modified Bessel function from scipy); trace identity of the
+  discrete operator, orthonormality in the quadrature inner product,
+  Nystrom interpolation reproduces the grid values, eigen-equation
+  residuals, robust sign convention, and a sample variance check of the
+  synthesised field.
 """
 import math
 
 import numpy as np
 import pytest
+from scipy.sparse.linalg import LinearOperator, eigsh
+from scipy.special import gamma, kv
 
 import mlmc_inputs as mi
 from oracle.kl import (KL, exp1d_eigen, exp1d_mode, gauss_legendre_grid, matern32,
@@ -95,6 +105,58 @@ def test_exp_separable_selection_and_gaps():
     # variance fraction captured by 10 modes on the 20 x 5 strip
     frac = kl.mu.sum() / (kl.var * C1["Lx"] * C1["Ly"])
     assert 0.4 < frac < 0.55
+
+
+def _nystrom_2d_separable(Lx, Ly, corr_x, corr_y, var, nqx, nqy, k):
+    """Top-``k`` eigenpairs of the Nystrom discretisation of the 2-D operator
+    with kernel ``var exp(-|dx|/corr_x - |dy|/corr_y)`` on a tensor
+    Gauss-Legendre grid (x fastest).  The matrix is applied as a whole 2-D
+    operator; the eigensolver sees one symmetric matrix of order nqx*nqy."""
+    gx, wx = np.polynomial.legendre.leggauss(nqx)
+    gy, wy = np.polynomial.legendre.leggauss(nqy)
+    x, wx = 0.5 * Lx * (gx + 1.0), 0.5 * Lx * wx
+    y, wy = 0.5 * Ly * (gy + 1.0), 0.5 * Ly * wy
+    sx, sy = np.sqrt(wx), np.sqrt(wy)
+    Ex = sx[:, None] * np.exp(-np.abs(x[:, None] - x[None, :]) / corr_x) * sx[None, :]
+    Ey = sy[:, None] * np.exp(-np.abs(y[:, None] - y[None, :]) / corr_y) * sy[None, :]
+    n = nqx * nqy
+    op = LinearOperator((n, n), dtype=np.float64,
+                        matvec=lambda v: var * (Ey @ v.reshape(nqy, nqx) @ Ex.T).ravel())
+    ev, vec = eigsh(op, k=k, which="LA", tol=1e-13)
+    order = np.argsort(ev)[::-1]
+    X, Y = np.meshgrid(x, y)
+    W = np.outer(wy, wx).ravel()
+    return ev[order], vec[:, order] / np.sqrt(W)[:, None], np.stack([X.ravel(), Y.ravel()], 1), W
+
+
+def test_separable_selection_matches_a_2d_nystrom_solve():
+    # Eqs. covarianceFunction / inftyKL: the truncated expansion keeps the K
+    # largest eigenvalues of the 2-D covariance operator, in decreasing order.
+    kl = KL(C1)
+    kw = dict(Lx=C1["Lx"], Ly=C1["Ly"], corr_x=C1["kl"]["corr_x"], corr_y=C1["kl"]["corr_y"], var=kl.var, k=12)
+    mu_c, _, _, _ = _nystrom_2d_separable(nqx=100, nqy=25, **kw)
+    mu_f, vec, pts, W = _nystrom_2d_separable(nqx=200, nqy=50, **kw)
+    # the kinked kernel makes the Nystrom eigenvalues converge like h^2:
+    # one Richardson step removes that term
+    mu_x = (4.0 * mu_f - mu_c) / 3.0
+    np.testing.assert_allclose(mu_f[:kl.K], kl.mu, rtol=3e-3)
+    np.testing.assert_allclose(mu_x[:kl.K], kl.mu, rtol=1e-4)
+    # the (K+1)-th eigenvalue is the first one left out
+    assert abs(mu_x[kl.K] / kl.mu_next - 1.0) < 1e-4
+    # same modes in the same order: quadrature inner products of +-1
+    F = kl.modes_at(pts)
+    inner = np.abs(np.sum(W[:, None] * F * vec[:, :kl.K], axis=0))
+    assert np.all(inner > 0.9999), inner
+
+
+@pytest.mark.parametrize("length", [1.5, 0.7])
+def test_matern32_is_the_general_matern_form_at_nu_three_halves(length):
+    nu, var = 1.5, 0.0027
+    r = np.array([1e-3, 0.01, 0.1, 0.3, 0.5, 0.9, 1.5, 2.2, 3.0, 4.5, 7.0, 11.0])
+    z = math.sqrt(2.0 * nu) * r / length
+    general = var * 2.0 ** (1.0 - nu) / gamma(nu) * z ** nu * kv(nu, z)
+    np.testing.assert_allclose(matern32(r, var, length), general, rtol=1e-13, atol=0)
+    assert matern32(np.array([0.0]), var, length)[0] == var
 
 
 def test_matern_nystrom_identities():

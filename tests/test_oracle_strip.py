@@ -3,7 +3,9 @@
 Each check is independent of the oracle's own formulas: tensor rotation
 written out from the fibre direction vector, rigid-body modes, exactness of
 bilinear elements on linear fields (patch test), the closed-form off-axis
-uniaxial stress state, and a dense direct solve.
+uniaxial stress state, a dense direct solve, and the QoI region: exactly
+the central half of the element columns and rows at every level, and a
+displacement field whose stress peaks outside the region.
 """
 import math
 
@@ -167,3 +169,41 @@ def test_qoi_converges_under_refinement():
     qs = [StripModel(cfg, l).solve(row, method="direct").q for l in range(4)]
     d = np.abs(np.diff(qs))
     assert d[2] < d[0]
+
+
+@pytest.mark.parametrize("name", ["strip_c1", "strip_c2", "strip_c3"])
+def test_qoi_region_is_the_central_half_of_elements(name):
+    # Section 3.2 takes the maximum over the integration points of a central
+    # sub-region; the workloads use the central half in each direction, which
+    # on these meshes is exactly element columns [nx/4, 3nx/4) and rows
+    # [ny/4, 3ny/4) at every level (element (i, j) has id j nx + i).
+    from oracle.strip import in_region
+    cfg = mi.load_config(name)
+    for level in range(cfg["n_levels"]):
+        mesh = level_mesh(cfg, level)
+        nx, ny = mesh.nx, mesh.ny
+        expect = np.array([j * nx + i for j in range(ny // 4, 3 * ny // 4) for i in range(nx // 4, 3 * nx // 4)])
+        got = np.nonzero(in_region(mesh, cfg["qoi_region"]))[0]
+        np.testing.assert_array_equal(got, expect)
+
+
+def test_qoi_takes_the_maximum_inside_the_region_only():
+    # nodal displacement u = -c x^2, v = 0 at theta = 0: the compressive
+    # fibre stress grows with x, so the QoI comes from the last element
+    # column inside the region, not from the loaded end x = Lx.
+    mesh = level_mesh(CFG, 0)
+    c = 1e-4
+    xy = mesh.node_xy()
+    d = np.zeros(2 * mesh.n_nodes)
+    d[0::2] = -c * xy[:, 0] ** 2
+    theta = np.zeros((mesh.n_elem, 4))
+    q = fibre_stress_qoi(mesh, Q, theta, d, CFG["qoi_region"])
+    i_last = 3 * mesh.nx // 4 - 1
+    # u is linear in x inside an element (bilinear interpolant of a function
+    # of x alone), so eps_xx = (u_b - u_a) / h = -c (x_a + x_b) there
+    xa, xb = i_last * mesh.hx, (i_last + 1) * mesh.hx
+    eps_xx = -c * (xa + xb)
+    assert abs(q - (-Q[0, 0] * eps_xx)) <= 1e-12 * abs(q)
+    # over the whole strip the maximum would be larger (last column at x = Lx)
+    q_all = fibre_stress_qoi(mesh, Q, theta, d, [0.0, CFG["Lx"], 0.0, CFG["Ly"]])
+    assert q_all > 1.3 * q
