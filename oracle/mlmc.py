@@ -113,6 +113,54 @@ def biased_relative_variance(N: int, p: float, k: int) -> float:
     return N * p * (1.0 - p) / (N * p + k) ** 2
 
 
+def indicator_rate(x: int, N: int, k: int = 1, below: int = 10) -> float:
+    """Rate of an event seen ``x`` times in ``N`` samples: the frequency
+    ``x / N``, or, while fewer than ``below`` events have been seen, the biased
+    ``p~ = (x + k) / (N + k)`` of Eq. biased_estimator, which bounds a rare
+    rate from above (Section 2.4; reading: ``k = 1``, switched on below 10
+    events)."""
+    if x < below:
+        return biased_p(x, N, k)
+    return x / N
+
+
+def indicator_variance(n_plus: int, n_minus: int, N: int, k: int = 1, below: int = 10,
+                       two_sided: bool = True) -> float:
+    """Variance estimate of an indicator level from its event counts.
+
+    ``two_sided``: a difference ``Y = Q_f - Q_c`` in {-1, 0, +1}, with the
+    trinomial variance ``p+ + p- - (p+ - p-)^2`` (the printed moments read with
+    consistent signs); otherwise an indicator ``Q`` in {0, 1} with no coarse
+    term, where ``p- = 0`` and the variance is ``p (1 - p)``.  Each rate comes
+    from ``indicator_rate``."""
+    pp = indicator_rate(n_plus, N, k, below)
+    pm = indicator_rate(n_minus, N, k, below) if two_sided else 0.0
+    return pp + pm - (pp - pm) ** 2
+
+
+def two_level_rare_event(q_base, y, k: int = 1, below: int = 10) -> dict:
+    """Two-level estimate ``E[Q] ~ Qhat_j + Yhat_{L,j}``, ``Y_{L,j} = Q_L - Q_j``
+    (Section 4.3).  ``q_base``: indicators of the base level ``j`` on their own
+    samples; ``y``: differences ``Q_L - Q_j`` on an independent set of samples,
+    both terms of one sample from the same selective-refinement chain.  The
+    estimate is the sum of the two sample means (Eq. MLMC_defn with two
+    terms); its mean square sampling error is ``V_j / N_j + V_Y / N_Y`` with
+    each variance from ``indicator_variance`` (Bernoulli for the base,
+    trinomial for the difference)."""
+    q = np.asarray(q_base, dtype=np.float64)
+    d = np.asarray(y, dtype=np.float64)
+    n0, n1 = len(q), len(d)
+    x0 = int(np.sum(q == 1.0))
+    xp, xm = int(np.sum(d == 1.0)), int(np.sum(d == -1.0))
+    assert x0 == int(np.sum(q != 0.0)) and xp + xm == int(np.sum(d != 0.0)), "indicators must be 0/1 and -1/0/1"
+    v0 = indicator_variance(x0, 0, n0, k, below, two_sided=False)
+    vy = indicator_variance(xp, xm, n1, k, below, two_sided=True)
+    est = x0 / n0 + (xp - xm) / n1
+    mse = v0 / n0 + vy / n1
+    return {"estimate": est, "rmse": math.sqrt(mse), "var_base": v0, "var_y": vy, "n0": n0, "n1": n1,
+            "n_base_plus": x0, "n_plus": xp, "n_minus": xm}
+
+
 def trinomial_moments(p_plus: float, p_minus: float):
     """Mean and variance of ``Y`` in {-1, 0, +1} with ``P(+1) = p+``, ``P(-1) = p-``."""
     mean = p_plus - p_minus

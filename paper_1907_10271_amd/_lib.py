@@ -115,6 +115,46 @@ def _ptr(t) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+def _check_dev(*specs) -> None:
+    """Raise ValueError unless every tensor is a contiguous FP64 tensor on a
+    GPU with the given shape.  Each spec is ``(tensor, name, shape)`` or
+    ``(tensor, name, shape, min_cols)``: ``None`` in ``shape`` = any extent,
+    ``min_cols`` bounds the last extent from below.  The library reads these
+    buffers with the row widths the shapes imply, so a mismatch must never
+    reach it.  Layouts are checked for all tensors before their location."""
+    torch = _torch()
+    for spec in specs:
+        t, name, shape = spec[:3]
+        min_cols = spec[3] if len(spec) > 3 else None
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+        if t.dtype != torch.float64:
+            raise ValueError(f"{name}: must be float64, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: must be contiguous")
+        if t.dim() != len(shape):
+            raise ValueError(f"{name}: expected {len(shape)} dimensions, got shape {tuple(t.shape)}")
+        for k, want in enumerate(shape):
+            if want is not None and t.shape[k] != want:
+                raise ValueError(f"{name}: extent {k} is {t.shape[k]}, expected {want} (shape {tuple(t.shape)})")
+        if min_cols is not None and t.shape[-1] < min_cols:
+            raise ValueError(f"{name}: rows of {t.shape[-1]} values, at least {min_cols} needed")
+    for spec in specs:
+        if not spec[0].is_cuda:
+            raise ValueError(f"{spec[1]}: must be a device tensor, got device {spec[0].device}")
+
+
+def _check_requests(requests: Sequence, n_rows: int, n_levels: int) -> None:
+    for k, r in enumerate(requests):
+        if len(r) != 3:
+            raise ValueError(f"request {k}: expected (sample_row, level, coupled), got {r!r}")
+        s, lvl = int(r[0]), int(r[1])
+        if not 0 <= s < n_rows:
+            raise ValueError(f"request {k}: sample row {s} outside [0, {n_rows})")
+        if not 0 <= lvl < n_levels:
+            raise ValueError(f"request {k}: level {lvl} outside [0, {n_levels})")
+
+
 def _stream(stream=None) -> int:
     torch = _torch()
     s = torch.cuda.current_stream() if stream is None else stream
@@ -141,6 +181,12 @@ class Context:
             raise MLMCError(rc, self.lib.mlmc_last_error(None).decode())
         self.h = h
         self.n_levels = self.lib.mlmc_num_levels(self.h)
+        # values per parameter row: K KL coefficients + 3 wrinkle values for a
+        # strip, one offset per ply for a plate
+        if self.cfg.get("kind") == "plate":
+            self.n_params = len(self.cfg["layup_deg"])
+        else:
+            self.n_params = int(self.cfg["kl"]["n_modes"]) + 3
 
     def close(self):
         if getattr(self, "h", None):
@@ -175,6 +221,7 @@ class Context:
     # ------------------------------------------------------------ strip
     def sample_field(self, level: int, xi, dtype: int = 0, stream=None):
         torch = _torch()
+        _check_dev((xi, "xi", (None, None), self.n_params))
         n = xi.shape[0]
         ngp = self.level_info(level)["n_gp"]
         out = torch.empty((n, ngp), dtype=torch.float64 if dtype == 0 else torch.int16, device=xi.device)
@@ -184,6 +231,9 @@ class Context:
 
     def strip_apply(self, level: int, theta, x, raw: bool = False, stream=None):
         torch = _torch()
+        li = self.level_info(level)
+        _check_dev((x, "x", (None, li["n_dofs"])),
+                   (theta, "theta", (x.shape[0] if x.dim() else None, li["n_gp"])))
         y = torch.empty_like(x)
         self._check(self.lib.mlmc_strip_apply(self.h, level, x.shape[0], _ptr(theta), _ptr(x), _ptr(y), int(raw),
                                               _stream(stream)))
@@ -191,8 +241,10 @@ class Context:
 
     def strip_rhs_diag(self, level: int, theta, stream=None):
         torch = _torch()
+        li = self.level_info(level)
+        _check_dev((theta, "theta", (None, li["n_gp"])))
         n = theta.shape[0]
-        nd = self.level_info(level)["n_dofs"]
+        nd = li["n_dofs"]
         b = torch.empty((n, nd), dtype=torch.float64, device=theta.device)
         dinv = torch.empty_like(b)
         self._check(self.lib.mlmc_strip_rhs_diag(self.h, level, n, _ptr(theta), _ptr(b), _ptr(dinv),
@@ -202,6 +254,7 @@ class Context:
     def strip_solve_theta(self, level: int, theta, precision: int = FP64, rtol: float = 0.0,
                           want_d: bool = False, stream=None):
         torch = _torch()
+        _check_dev((theta, "theta", (None, self.level_info(level)["n_gp"])))
         n = theta.shape[0]
         q = torch.empty(n, dtype=torch.float64, device=theta.device)
         info = torch.zeros(n * 32, dtype=torch.uint8, device=theta.device)
@@ -215,6 +268,8 @@ class Context:
     def solve_batch(self, requests: Sequence, xi, precision: int = FP64, rtol: float = 0.0, stream=None):
         """``requests``: sequence of ``(sample_row, level, coupled)``."""
         torch = _torch()
+        _check_dev((xi, "xi", (None, None), self.n_params))
+        _check_requests(requests, xi.shape[0], self.n_levels)
         n = len(requests)
         arr = (Request * max(n, 1))()
         for k, (s, l, c) in enumerate(requests):
@@ -229,6 +284,8 @@ class Context:
     # ------------------------------------------------------------ plate
     def buckle_batch(self, requests: Sequence, offsets, precision: int = FP64, tol: float = 0.0, stream=None):
         torch = _torch()
+        _check_dev((offsets, "offsets", (None, self.n_params)))
+        _check_requests(requests, offsets.shape[0], self.n_levels)
         n = len(requests)
         arr = (Request * max(n, 1))()
         for k, (s, l, c) in enumerate(requests):
@@ -251,6 +308,8 @@ class Context:
 
     def plate_apply(self, level: int, offsets, x, geometric: bool = False, stream=None):
         torch = _torch()
+        _check_dev((offsets, "offsets", (None, self.n_params)),
+                   (x, "x", (offsets.shape[0] if offsets.dim() else None, 5 * self.level_info(level)["n_nodes"])))
         y = torch.empty_like(x)
         self._check(self.lib.mlmc_plate_apply(self.h, level, x.shape[0], _ptr(offsets), int(geometric), _ptr(x),
                                               _ptr(y), _stream(stream)))
@@ -260,6 +319,10 @@ class Context:
     def level_stats(self, level: int, q_fine, q_coarse=None, cost_per_sample: float = 0.0,
                     lambda_star: float = math.nan, acc: Optional[LevelAcc] = None, stream=None) -> LevelAcc:
         acc = LevelAcc() if acc is None else acc
+        specs = [(q_fine, "q_fine", (None,))]
+        if q_coarse is not None:
+            specs.append((q_coarse, "q_coarse", (q_fine.shape[0] if q_fine.dim() else None,)))
+        _check_dev(*specs)
         self._check(self.lib.mlmc_level_stats(self.h, level, q_fine.shape[0], _ptr(q_fine), _ptr(q_coarse),
                                               cost_per_sample, lambda_star, C.byref(acc), _stream(stream)))
         return acc

@@ -242,27 +242,34 @@ def sr_exit_levels(lam: np.ndarray, lam_star: float, m: float, alpha: float, j_m
 
 @dataclass
 class IndicatorSums:
-    """Level accumulator of a failure-indicator difference Y in {-1, 0, 1}."""
+    """Level accumulator of a failure indicator: a difference Y in {-1, 0, 1}
+    (``two_sided``, levels above 0) or, with no coarse term (level 0), an
+    indicator Q in {0, 1}."""
     n: int = 0
     n_plus: int = 0
     n_minus: int = 0
     k: int = 1
     seconds: float = 0.0
     use_biased_below: int = 10
+    two_sided: bool = True
 
     @property
     def mean(self) -> float:
         return (self.n_plus - self.n_minus) / self.n
 
+    def rate(self, x: int) -> float:
+        """Rate of an event seen ``x`` times: the frequency, or, when fewer than
+        ``use_biased_below`` events were seen, the biased p~ = (x + k)/(N + k)
+        of Eq. biased_estimator (an upper bound for rare events)."""
+        return (x + self.k) / (self.n + self.k) if x < self.use_biased_below else x / self.n
+
     @property
     def var(self) -> float:
-        """Variance of the trinomial Y, V = p+ + p- - (p+ - p-)^2, with each rate
-        estimated by the frequency, or, when fewer than ``use_biased_below``
-        events were seen, by the biased p~ = (x + k)/(N + k) of Eq.
-        biased_estimator (an upper bound for rare events)."""
-        def rate(x: int) -> float:
-            return (x + self.k) / (self.n + self.k) if x < self.use_biased_below else x / self.n
-        pp, pm = rate(self.n_plus), rate(self.n_minus)
+        """Variance of Y, V = p+ + p- - (p+ - p-)^2 with each rate from
+        ``rate``; without a coarse term Y = Q cannot be -1, so p- = 0 and
+        V = p (1 - p)."""
+        pp = self.rate(self.n_plus)
+        pm = self.rate(self.n_minus) if self.two_sided else 0.0
         return pp + pm - (pp - pm) ** 2
 
     @property
@@ -344,7 +351,7 @@ class PlateSRSampler:
             lam, ex = self.chains(level, rows)
             idx = np.arange(k)
             lam_f = lam[idx, ex]
-            acc = self._acc.setdefault(level, IndicatorSums(k=self.k_biased))
+            acc = self._acc.setdefault(level, IndicatorSums(k=self.k_biased, two_sided=level > 0))
             if level > 0:
                 lam_c = lam[idx, np.minimum(ex, level - 1)]
                 qd = torch.from_numpy(np.stack([lam_f, lam_c])).to("cuda")
@@ -381,20 +388,35 @@ def run_plate_mlmc_sr(ctx, cfg: Dict, lam_star: Optional[float] = None, tau_rel:
 
 
 def two_level_rare_event(ctx, cfg: Dict, L: int, n0: int, n1: int, lam_star: Optional[float] = None,
-                         precision: int = FP64) -> Dict:
-    """The two-level estimator E[Q] ~ Qhat_0 + Yhat_{L,0}, Y_{L,0} = Q_L - Q_0 with
-    Q_L from the full selective-refinement chain (Section 4.3)."""
+                         precision: int = FP64, j: int = 0, k_biased: int = 1) -> Dict:
+    """The two-level estimator E[Q] ~ Qhat_j + Yhat_{L,j}, Y_{L,j} = Q_L - Q_j
+    (Section 4.3).  The base term takes ``n0`` samples of level ``j`` (rows of
+    stream 100), each a selective-refinement chain truncated at ``j``; the
+    difference takes ``n1`` chains up to ``L`` (rows of stream 101), with Q_L
+    from the whole chain and Q_j from the same chain truncated at ``j``.
+    Variances use the biased rates of Eq. biased_estimator below 10 events
+    (Bernoulli for the base term, trinomial for the difference); the RMSE is
+    the sampling error ``sqrt(V_j / n0 + V_Y / n1)``.  ``rows`` holds the
+    per-sample loads and exit levels behind the counts."""
+    if not 0 <= j < L:
+        raise ValueError(f"need 0 <= j < L, got j={j}, L={L}")
     lam_star = cfg["lambda_crit"] if lam_star is None else lam_star
     s = PlateSRSampler(ctx, cfg, lam_star, precision=precision, stream_offset=100)
     t0 = time.perf_counter()
-    rows0 = s.mi.plate_offsets(cfg, 0, 0, n0, stream=100)
-    lam0, _ = s.chains(0, rows0)
-    q0 = (lam0[:, 0] < lam_star).astype(float)
+    rows0 = s.mi.plate_offsets(cfg, j, 0, n0, stream=100)
+    lam0, ex0 = s.chains(j, rows0)
+    q0 = lam0[np.arange(n0), ex0] < lam_star
     rows1 = s.mi.plate_offsets(cfg, L, 0, n1, stream=101)
-    lam1, ex = s.chains(L, rows1)
-    qL = (lam1[np.arange(n1), ex] < lam_star).astype(float)
-    y = qL - (lam1[:, 0] < lam_star).astype(float)
-    est = q0.mean() + y.mean()
-    var = q0.var() / n0 + y.var() / n1
-    return {"estimate": est, "rmse": math.sqrt(var), "n0": n0, "n1": n1, "L": L, "solves": s.solves.tolist(),
-            "seconds": time.perf_counter() - t0, "p0": q0.mean(), "yhat": y.mean()}
+    lam1, ex1 = s.chains(L, rows1)
+    i1 = np.arange(n1)
+    qL = lam1[i1, ex1] < lam_star
+    qj = lam1[i1, np.minimum(ex1, j)] < lam_star
+    base = IndicatorSums(n=n0, n_plus=int(q0.sum()), k=k_biased, two_sided=False)
+    diff = IndicatorSums(n=n1, n_plus=int(np.sum(qL & ~qj)), n_minus=int(np.sum(qj & ~qL)), k=k_biased)
+    est = base.mean + diff.mean
+    mse = base.var / n0 + diff.var / n1
+    return {"estimate": est, "rmse": math.sqrt(mse), "n0": n0, "n1": n1, "L": L, "j": j,
+            "n_base_plus": base.n_plus, "n_plus": diff.n_plus, "n_minus": diff.n_minus,
+            "var_base": base.var, "var_y": diff.var, "solves": s.solves.tolist(),
+            "seconds": time.perf_counter() - t0, "p_base": base.mean, "yhat": diff.mean,
+            "rows": {"lam_base": lam0, "exit_base": ex0, "lam": lam1, "exit": ex1}}

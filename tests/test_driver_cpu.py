@@ -97,3 +97,46 @@ def test_indicator_sums_biased_variance():
     assert abs(a.var - omlmc.trinomial_moments(pp, pm)[1]) < 1e-15
     b = IndicatorSums(n=1000, n_plus=40, n_minus=12)
     assert abs(b.var - omlmc.trinomial_moments(0.04, 0.012)[1]) < 1e-15
+
+
+def test_level_zero_indicator_variance_has_no_minus_term():
+    # Y_0 = Q_0 in {0, 1}: the variance is p~ (1 - p~) with the biased p+ only,
+    # as the oracle's Bernoulli form gives, and never the trinomial one
+    from paper_1907_10271_amd.driver import IndicatorSums
+    for n, x in [(100, 0), (100, 1), (5000, 7), (300, 40)]:
+        a = IndicatorSums(n=n, n_plus=x, two_sided=False)
+        ref = omlmc.indicator_variance(x, 0, n, two_sided=False)
+        assert abs(a.var - ref) < 1e-15
+        p = omlmc.indicator_rate(x, n)
+        assert abs(a.var - p * (1 - p)) < 1e-15
+        b = IndicatorSums(n=n, n_plus=x, n_minus=0)
+        assert abs(b.var - omlmc.indicator_variance(x, 0, n)) < 1e-15
+
+
+def test_two_level_counts_and_variance_follow_the_oracle():
+    # the driver's two-level bookkeeping (counts from chains, variances from
+    # IndicatorSums) on synthetic chains, against the oracle's estimator
+    from oracle.sr import sr_pair
+    from paper_1907_10271_amd.driver import IndicatorSums, sr_exit_levels
+    rng = np.random.default_rng(21)
+    lam_star, L, j = 0.875, 3, 0
+    n0, n1 = 700, 300
+    lam0 = 0.89 + 0.01 * rng.standard_normal(n0)
+    base = lam0 < lam_star
+    lam = 0.89 + 0.01 * rng.standard_normal((n1, 1)) - 0.004 * (1 - 4.0 ** -np.arange(L + 1)) \
+        + 0.0005 * rng.standard_normal((n1, L + 1))
+    ex = sr_exit_levels(lam, lam_star, 4.0, 1.0, 1)
+    qL = lam[np.arange(n1), ex] < lam_star
+    qj = lam[np.arange(n1), np.minimum(ex, j)] < lam_star
+    y_ref = []
+    for r in lam:
+        qf, _, _, _ = sr_pair(lambda k: r[k], L, lam_star, 4.0, 1.0, 1)
+        y_ref.append(qf - int(r[0] < lam_star))
+    assert np.array_equal(qL.astype(int) - qj.astype(int), np.array(y_ref))
+    b = IndicatorSums(n=n0, n_plus=int(base.sum()), two_sided=False)
+    d = IndicatorSums(n=n1, n_plus=int(np.sum(qL & ~qj)), n_minus=int(np.sum(qj & ~qL)))
+    ref = omlmc.two_level_rare_event(base.astype(float), np.array(y_ref, float))
+    assert d.n_plus == ref["n_plus"] and d.n_minus == ref["n_minus"] and b.n_plus == ref["n_base_plus"]
+    assert abs(b.mean + d.mean - ref["estimate"]) < 1e-15
+    assert abs(math.sqrt(b.var / n0 + d.var / n1) - ref["rmse"]) < 1e-15
+    assert d.n_plus > 0

@@ -224,3 +224,63 @@ def test_panel_t2_bad_settings_rejected():
     for bad in ({"shear": "mitc9"}, {"condensed": 1}):
         with pytest.raises(pk.MLMCError):
             pk.Context(dict(T2, **bad))
+
+
+def _rare_event_threshold(lam_base, lam_chain, fac, margin):
+    """A threshold near the 15% quantile of the finest chain loads such that
+    every stored load, and every selective-refinement test of every chain, is
+    at least ``margin`` (relative) away from a tie, so GPU and oracle loads
+    that agree to the parity tolerance take the same decisions."""
+    vals = np.sort(np.concatenate([lam_base.ravel(), lam_chain.ravel()]))
+    lo, hi = np.quantile(lam_chain[:, -1], [0.1, 0.2])
+    cands = [(vals[i + 1] - vals[i], 0.5 * (vals[i] + vals[i + 1])) for i in range(len(vals) - 1)
+             if lo <= vals[i] <= hi]
+    for _, ls in sorted(cands, reverse=True):
+        if np.min(np.abs(vals - ls)) < margin * ls:
+            continue
+        t = np.abs(np.abs(lam_chain[:, 1:] - ls) - fac * np.abs(lam_chain[:, 1:] - lam_chain[:, :-1]))
+        tb = np.abs(np.abs(lam_base[:, 1:] - ls) - fac * np.abs(lam_base[:, 1:] - lam_base[:, :-1]))
+        if t.min() >= margin * ls and tb.min() >= margin * ls:
+            return ls
+    raise AssertionError("no threshold clear of ties")
+
+
+@pytest.mark.parametrize("precision,j", [(0, 0), (0, 1), (1, 0)])
+def test_two_level_rare_event_matches_oracle(precision, j):
+    """The two-level estimator Qhat_j + Yhat_{2,j} of Section 4.3 on the GPU
+    (selective-refinement chains through the C ABI) against the oracle's
+    estimator on the oracle's loads of the same rows (stored by
+    tests/golden/make_rare_event_lambdas.py): loads, exit levels, event
+    counts, estimate and RMSE (biased rates below 10 events)."""
+    import json
+    import os
+    from oracle import mlmc as omlmc
+    from oracle.sr import sr_chain
+    from paper_1907_10271_amd.driver import two_level_rare_event
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "rare_event_plate_c4.json")))
+    lam_base, lam_chain = np.array(fx["lam_base"]), np.array(fx["lam_chain"])
+    m, alpha = C4["sr"]["m"], C4["sr"]["alpha"]
+    fac = 1.0 / (m ** alpha - 1.0)
+    lam_star = _rare_event_threshold(lam_base, lam_chain, fac, 1e-5)
+    r = two_level_rare_event(context("plate_c4"), C4, L=fx["L"], n0=fx["n0"], n1=fx["n1"], lam_star=lam_star,
+                             precision=precision, j=j)
+    tol = 1e-10 if precision == 0 else 1e-6
+    # oracle chains on the oracle's loads
+    q_base, y = [], []
+    for k, row in enumerate(lam_base):
+        lam_j, ex, _ = sr_chain(lambda l: row[l], j, lam_star, m, alpha, 1)
+        q_base.append(float(lam_j < lam_star))
+        assert r["rows"]["exit_base"][k] == ex
+        np.testing.assert_allclose(r["rows"]["lam_base"][k, :ex + 1], row[:ex + 1], rtol=tol)
+    for k, row in enumerate(lam_chain):
+        lam_L, ex, _ = sr_chain(lambda l: row[l], fx["L"], lam_star, m, alpha, 1)
+        lam_c, _, _ = sr_chain(lambda l: row[l], j, lam_star, m, alpha, 1)
+        y.append(float(lam_L < lam_star) - float(lam_c < lam_star))
+        assert r["rows"]["exit"][k] == ex
+        np.testing.assert_allclose(r["rows"]["lam"][k, :ex + 1], row[:ex + 1], rtol=tol)
+    ref = omlmc.two_level_rare_event(np.array(q_base), np.array(y))
+    assert (r["n_base_plus"], r["n_plus"], r["n_minus"]) == (ref["n_base_plus"], ref["n_plus"], ref["n_minus"])
+    assert abs(r["estimate"] - ref["estimate"]) <= 1e-15
+    assert abs(r["rmse"] - ref["rmse"]) <= 1e-15 * ref["rmse"] + 1e-18
+    # the regime the estimator is built for: few events, some of them below the biased-rate threshold
+    assert 0 < ref["n_plus"] and min(ref["n_base_plus"], ref["n_plus"], ref["n_minus"]) < 10

@@ -139,3 +139,72 @@ def test_algorithm1_stops_at_top_level_uncertified():
     res = mlmc.algorithm1(sampler, lambda l: 4.0 ** l, e=0.01, theta=0.5, n_star=50, m=4, L_max=2,
                           max_new=5000)
     assert res.L == 2 and not res.converged
+
+
+def test_indicator_variance_is_the_sample_variance_when_events_are_common():
+    # with the biased rates switched off (below = 0) the estimate is the plain
+    # population variance of the 0/1 or -1/0/+1 samples (Eq. varianceestim)
+    rng = np.random.default_rng(3)
+    q = (rng.random(500) < 0.3).astype(float)
+    assert abs(mlmc.indicator_variance(int(q.sum()), 0, 500, below=0, two_sided=False) - np.var(q)) < 1e-15
+    y = rng.choice([-1.0, 0.0, 1.0], size=400, p=[0.1, 0.7, 0.2])
+    v = mlmc.indicator_variance(int(np.sum(y == 1)), int(np.sum(y == -1)), 400, below=0)
+    assert abs(v - np.var(y)) < 1e-15
+    # the default threshold (10 events) leaves common events at their frequency
+    assert mlmc.indicator_variance(int(np.sum(y == 1)), int(np.sum(y == -1)), 400) == v
+
+
+def test_bernoulli_level_uses_the_biased_rate_of_its_failures_only():
+    # Q in {0, 1} has no -1 outcome: V = p~ (1 - p~) with p~ = (x + k)/(N + k)
+    for x, N, k in [(0, 100, 1), (3, 1000, 1), (7, 150, 2)]:
+        pt = (x + k) / (N + k)
+        assert mlmc.indicator_variance(x, 0, N, k=k, two_sided=False) == pytest.approx(pt * (1 - pt), rel=1e-15)
+    # the two-sided form adds a biased p- as well, so it is strictly larger
+    assert mlmc.indicator_variance(0, 0, 100) > mlmc.indicator_variance(0, 0, 100, two_sided=False)
+
+
+def test_two_level_estimate_telescopes_on_shared_chains():
+    # base and difference taken on the same samples: Qhat_j + mean(Q_L - Q_j) = mean(Q_L)
+    rng = np.random.default_rng(11)
+    qj = (rng.random(300) < 0.05).astype(float)
+    qL = qj.copy()
+    flip = rng.random(300) < 0.02
+    qL[flip] = 1.0 - qL[flip]
+    r = mlmc.two_level_rare_event(qj, qL - qj)
+    assert abs(r["estimate"] - qL.mean()) < 1e-15
+    assert r["n_plus"] == int(np.sum((qL - qj) == 1)) and r["n_minus"] == int(np.sum((qL - qj) == -1))
+
+
+def test_two_level_variance_against_exact_enumeration():
+    # exact distribution of Qhat_0 + Yhat: X0 ~ Bin(N0, p0) independent of
+    # (X+, X-) ~ Multinomial(N1; p+, p-).  With the biased rates off the
+    # estimator's variance is p0 (1 - p0)/N0 + (p+ + p- - (p+ - p-)^2)/N1, and
+    # the expected plug-in estimate is (N-1)/N of it for each term; with the
+    # biased rates on, rare-event variances are bounded from above
+    from scipy.stats import multinomial
+    N0, N1 = 12, 9
+    for p0, pp, pm in [(0.05, 0.03, 0.01), (0.2, 0.1, 0.0), (0.01, 0.004, 0.002)]:
+        est_m = est_v = 0.0
+        mean_mse_plain = mean_mse_biased = 0.0
+        probs = []
+        for x0 in range(N0 + 1):
+            w0 = binom.pmf(x0, N0, p0)
+            for xp in range(N1 + 1):
+                for xm in range(N1 + 1 - xp):
+                    w = w0 * multinomial.pmf([xp, xm, N1 - xp - xm], N1, [pp, pm, 1 - pp - pm])
+                    q = np.r_[np.ones(x0), np.zeros(N0 - x0)]
+                    y = np.r_[np.ones(xp), -np.ones(xm), np.zeros(N1 - xp - xm)]
+                    r = mlmc.two_level_rare_event(q, y)
+                    rp = mlmc.two_level_rare_event(q, y, below=0)
+                    probs.append(w)
+                    est_m += w * r["estimate"]
+                    est_v += w * r["estimate"] ** 2
+                    mean_mse_plain += w * rp["rmse"] ** 2
+                    mean_mse_biased += w * r["rmse"] ** 2
+        assert abs(sum(probs) - 1.0) < 1e-12
+        var_true = p0 * (1 - p0) / N0 + (pp + pm - (pp - pm) ** 2) / N1
+        assert abs(est_m - (p0 + pp - pm)) < 1e-14
+        assert abs(est_v - est_m ** 2 - var_true) < 1e-14
+        plain = p0 * (1 - p0) * (N0 - 1) / N0 ** 2 + (pp + pm - (pp - pm) ** 2) * (N1 - 1) / N1 ** 2
+        assert abs(mean_mse_plain - plain) < 1e-14
+        assert mean_mse_biased > var_true
