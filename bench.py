@@ -6,14 +6,21 @@ Q1 meshes 64x16, 128x32, 256x64, 512x128; Matern-3/2 KL field with 20 modes
 plus a sech^2 wrinkle; Jacobi-PCG to rtol 1e-10).  One step is one MLMC
 batch round: on every level a batch of coupled samples (Y_0 = Q_0 on level 0,
 fine/coarse pairs with shared parameters above) goes through KL synthesis,
-lifting, PCG, the QoI and the FP64 level sums.  The per-level batch sizes
-follow the shape of the optimal MLMC allocation (more samples on coarse
-levels).  Parameter rows are generated and copied to the GPU before the
-timed region.
+lifting, PCG, the QoI and the FP64 level sums.  The per-level batches are a
+fixed mix, 2048 / 512 / 128 / 64, that gives every level a batch large
+enough to fill the GPU (more samples on the cheaper coarse levels, as MLMC
+allocates them); the allocation the MLMC formula itself chooses is what the
+time-to-epsilon leg runs.  Parameter rows are generated and copied to the GPU
+before the timed region.
 
 Printed: one JSON line with the whole-job rate (coupled samples/s), per-level
-rates, the roofline of the dominant kernel (the PCG operator pass, timed with
-HIP events on the solve stream) and the CPU oracle timed on the host cores.
+rates, the roofline of the dominant kernel (the PCG vector pass) and of the
+operator pass (both timed with HIP events on the solve stream), the CPU
+oracle timed on the host cores, and two further legs of the metric: the
+wall time of adaptive MLMC (Algorithm 1) to a relative RMSE in FP64 and in
+mixed precision on the five-level strip, and the serving loop's p50/p99
+latency over a mixed strip/panel request stream at 1e2, 1e3 and 1e4
+requests/s.
 """
 from __future__ import annotations
 
@@ -56,15 +63,18 @@ def parse():
     ap.add_argument("--plate-config", type=str, default="plate_c4",
                     help="panel workload of the plate leg: plate_c4 (500 mm panel) or plate_t2 (the 636 x 212 mm "
                          "Test Problem II panel)")
-    ap.add_argument("--serve", type=str, default="",
+    ap.add_argument("--serve", type=str, default="100,1000,10000",
                     help="also run the serving loop over the mixed request stream at these arrival rates "
-                         "(requests/s, comma list)")
-    ap.add_argument("--serve-duration", type=float, default=0.0,
-                    help="seconds of arrivals per rate (default: the serving configuration's)")
-    ap.add_argument("--time-to-eps", type=float, default=0.0,
-                    help="also run adaptive MLMC (Algorithm 1) to this relative RMSE, FP64 and mixed precision")
-    ap.add_argument("--tte-config", type=str, default="strip_c2",
+                         "(requests/s, comma list; empty: no serving leg)")
+    ap.add_argument("--serve-duration", type=float, default=3.0,
+                    help="seconds of arrivals per rate (0: the serving configuration's)")
+    ap.add_argument("--time-to-eps", type=str, default="1e-3,1e-4",
+                    help="also run adaptive MLMC (Algorithm 1) to these relative RMSEs, FP64 and mixed precision "
+                         "(comma list; empty: no time-to-epsilon leg)")
+    ap.add_argument("--tte-config", type=str, default="strip_c3",
                     help="strip workload of the time-to-epsilon runs")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="only the batch-round benchmark: no time-to-epsilon and no serving leg (profiling runs)")
     ap.add_argument("--set", action="append", default=[], metavar="KEY=JSON",
                     help="override a key of the strip workload definition (tuning runs; the line is then "
                          "not the default benchmark), e.g. --set angle_storage='\"cs\"'")
@@ -109,7 +119,10 @@ def cpu_baseline(cfg, mix, counts):
         m.modes()
     rows = [mi.strip_xi(cfg, l, 10 ** 6, counts[l]) for l in range(nl)]
     _ORACLE_MODELS = (models, rows)
-    cores = min(len(os.sched_getaffinity(0)), 16)
+    # one worker per host core of this GPU's share of the host: the boxes
+    # this runs on give one GPU 16 cores, whatever the affinity mask shows
+    visible = len(os.sched_getaffinity(0))
+    cores = min(visible, int(os.environ.get("MLMC_HOST_CORES", "16")))
     jobs = [(l, k) for l in reversed(range(nl)) for k in range(counts[l])]
     res = []
     # one BLAS thread per worker process (the forked workers inherit the limit)
@@ -128,26 +141,28 @@ def cpu_baseline(cfg, mix, counts):
     sample = (f"{'+'.join(str(c) for c in counts)} coupled samples on levels 0..{nl - 1} "
               f"({wall:.1f} s wall on {cores} worker processes); per-sample oracle seconds "
               + ", ".join(f"L{l}={t:.3f}" for l, t in enumerate(per_level)))
-    return {"value": value, "unit": "coupled samples/s", "cores": cores, "kind": "oracle", "sample": sample,
-            "per_level_s_per_sample": per_level}
+    return {"value": value, "unit": "coupled samples/s", "cores": cores, "host_cpus_visible": visible,
+            "kind": "oracle", "sample": sample, "per_level_s_per_sample": per_level}
 
 
 # ------------------------------------------------------------------ GPU
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_pass1_strip4lvl_fp64_hbm_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "{kernel}_strip4lvl_fp64_hbm_traffic.md")
 CSRC = os.path.join(ROOT, "paper_1907_10271_amd", "csrc")
 # sources that define the operator pass, its launches and the strip solve around it
 STRIP_SOURCES = ("api.hip", "common.hpp", "strip_device.hpp", "strip_kernels.hip", "strip_kernels.hpp",
                  "strip_small.hip", "strip_small.hpp")
 
 
-def profiled_traffic():
-    """HBM bytes per operator-pass launch from the committed hardware-counter
-    summary of this benchmark, or None when the library sources changed since."""
+def profiled_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` (k_pass1 or k_pass2) from the
+    committed hardware-counter summary of this benchmark, or None when the
+    library sources changed since."""
     import hashlib
-    if not os.path.exists(TRAFFIC_PROFILE):
+    path = TRAFFIC_PROFILE.format(kernel=kernel)
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_PROFILE):
+    for line in open(path):
         if " = " in line:
             k, v = line.split(" = ", 1)
             vals[k.strip()] = v.strip()
@@ -330,8 +345,9 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    p1 = ctx.profile_read(0 if prec == pk.FP64 else 2)
-    p2 = ctx.profile_read(1 if prec == pk.FP64 else 3)
+    k1, k2 = (0, 1) if prec == pk.FP64 else (2, 3)
+    p1, p2 = ctx.profile_read(k1), ctx.profile_read(k2)
+    dofs1, dofs2 = ctx.profile_read(k1 + 4)["bytes"], ctx.profile_read(k2 + 4)["bytes"]
     ctx.profile(False)
     if not per_level_calls:
         # per-level times (outside the timed region): each level alone, on the
@@ -352,11 +368,40 @@ def main():
                           "coupled": l > 0, ("ms" if per_level_calls else "ms_alone"): round(float(ms), 3),
                           "samples_per_s": round(n / (ms / 1e3), 1),
                           "pcg_iters_mean": round(float(its_f.mean()), 1), "all_converged": bool(ok)})
-    # (no lock-step operator launches when only whole-solve levels ran)
-    achieved = p1["bytes"] / (p1["ms"] / 1e3) / 1e9 if p1["ms"] > 0 else 0.0
     default_run = (mix == DEFAULT_MIX and prec == pk.FP64 and not args.mixed and not args.set
                    and len(levels) == len(mix))
-    traffic = profiled_traffic() if default_run else None
+    # Roofline of the two PCG passes, each priced at the algorithmic bytes per
+    # unknown of the plain two-pass FP64 iteration (vector pass: read x, r,
+    # A p, p, diag(A), write x, r = 7 vectors; operator: read x, write y, and
+    # the angles, 4 Gauss points x 8 B per 2 unknowns) times the unknowns of
+    # the samples active in the timed launches, over the event-timed launch
+    # duration; beside it the kernel's own byte model (which keeps z = r /
+    # diag(A), fuses the p-update into the operator pass and moves x every
+    # second iteration).  Mixed precision halves the vector bytes and stores
+    # FP32 angles.
+    w = 8.0 if prec == pk.FP64 else 4.0
+    per_unknown = {"k_pass2": 7 * w, "k_pass1": 2 * w + 2 * w}
+
+    def roof(kernel, p, dofs, what):
+        if not p["launches"] or p["ms"] <= 0:
+            return None
+        sec = p["ms"] / 1e3
+        alg = per_unknown[kernel] * dofs
+        achieved = alg / sec / 1e9
+        traffic = profiled_traffic(kernel) if default_run else None
+        return {"bound": "hbm", "kernel": f"{kernel}<{'double' if prec == pk.FP64 else 'float'}> ({what})",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic),
+                "alg_bytes_per_unknown": per_unknown[kernel],
+                "unknowns_per_launch": round(dofs / p["launches"], 1),
+                "alg_bytes_per_launch": round(alg / p["launches"], 1),
+                "avg_launch_us": round(p["ms"] * 1e3 / p["launches"], 3), "timed_launches": p["launches"],
+                "timing": "HIP events on the solve stream around the passes of iteration 16 (even blocks) or 17 "
+                          "(odd blocks) of every block of 32",
+                "kernel_model_bytes_per_launch": round(p["bytes"] / p["launches"], 1),
+                "kernel_model_GBs": round(p["bytes"] / sec / 1e9, 1)}
+
     total = sum(n for l, n in enumerate(mix) if l in levels)
     out = {
         "metric": "coupled-sample solves/s (4-level FP64 waviness strip, one MLMC batch round per step)",
@@ -376,26 +421,19 @@ def main():
                    "batch_per_level": mix, "parallelism": "single GPU, data-parallel over samples",
                    "solve_calls_per_step": "one per level" if per_level_calls else "one for all levels"},
         "per_level": per_level,
-        "roofline": {"bound": "hbm", "kernel": "k_pass1 (PCG operator pass)",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None if traffic is None else round(traffic),
-                     "timed_launches": p1["launches"],
-                     "timing": "HIP events around the passes of one iteration in the middle of every 32",
-                     "avg_launch_us": round(p1["ms"] * 1e3 / p1["launches"], 3) if p1["launches"] else None,
-                     "alg_bytes_per_launch": round(p1["bytes"] / p1["launches"], 1) if p1["launches"] else None},
-        "vector_pass": {"kernel": "k_pass2",
-                        "achieved_GBs": round(p2["bytes"] / (p2["ms"] / 1e3) / 1e9, 1) if p2["ms"] > 0 else None,
-                        "avg_launch_us": round(p2["ms"] * 1e3 / p2["launches"], 3) if p2["launches"] else None},
+        # the vector pass takes the larger share of the GPU time (kernel trace)
+        "roofline": roof("k_pass2", p2, dofs2, "PCG vector pass, the dominant kernel"),
+        "roofline_operator": roof("k_pass1", p1, dofs1, "PCG operator pass"),
         "cpu_baseline": None if cpu is None else {k: v for k, v in cpu.items() if k != "per_level_s_per_sample"},
     }
     if args.plate:
         out["plate"] = plate_leg(pk, torch, [int(v) for v in args.plate.split(",")], prec, args.plate_config)
         out["plate_workload"] = args.plate_config
-    if args.serve:
+    del ctx
+    if args.time_to_eps and not args.no_legs:
+        out["time_to_eps"] = [tte_leg(pk, torch, args.tte_config, float(e)) for e in args.time_to_eps.split(",")]
+    if args.serve and not args.no_legs:
         out["serving"] = serve_leg(pk, [float(v) for v in args.serve.split(",")], args.serve_duration, prec)
-    if args.time_to_eps > 0:
-        out["time_to_eps"] = tte_leg(pk, torch, args.tte_config, args.time_to_eps)
     if len(levels) != len(mix):
         out["metric"] = "profiling run on levels " + args.levels + " only (not the benchmark)"
     if cpu is not None:

@@ -60,7 +60,9 @@ typedef enum {
   MLMC_S_NOCONV = 1,    /* iteration limit reached */
   MLMC_S_NAN = 2,       /* NaN/Inf met (e.g. non-finite parameters) */
   MLMC_S_BREAKDOWN = 3, /* p^T A p <= 0 or a singular Rayleigh-Ritz step */
-  MLMC_S_SKIPPED = 4    /* not solved (coarse part of a level-0 request) */
+  MLMC_S_SKIPPED = 4,   /* not solved (coarse part of a level-0 request) */
+  MLMC_S_NOTLOWEST = 5  /* buckling: converged, but a lower eigenvalue exists (the
+                           lowest-mode check of mlmc_buckle_batch failed) */
 } mlmc_sample_status;
 
 /* One sample request: row `sample` of the parameter array, mesh level `level`;
@@ -181,7 +183,15 @@ int mlmc_solve_batch(mlmc_ctx *ctx, int n_req, const mlmc_request *req, const do
  * ply_offsets[req[i].sample] (radians, dev [n_rows][n_plies], rows checked as
  * for mlmc_solve_batch); coupled requests
  * also solve level - 1.  lam_fine, lam_coarse: dev [n_req] in N/mm of edge
- * load; tol: relative eigen-residual (<= 0: configured).  Synchronous. */
+ * load; tol: relative eigen-residual (<= 0: configured).  Synchronous.
+ * Lowest-mode check (on unless the workload sets "cert_shift": 0): after a
+ * solve converges, the band of K - sigma K_G with sigma = lambda (1 -
+ * cert_shift) (default 1e-6) is factored in FP64; since K is positive
+ * definite and K_G semi-definite on the free unknowns, a factorisation without
+ * a non-positive pivot shows that no eigenvalue lies below lambda (1 -
+ * cert_shift).  A sample that fails the check keeps its lambda and gets
+ * status MLMC_S_NOTLOWEST.  "eig_start_p0" (default 0: the integer nearest to
+ * a / b) sets the half-waves along x of the first start vector. */
 int mlmc_buckle_batch(mlmc_ctx *ctx, int n_req, const mlmc_request *req, const double *ply_offsets,
                       int64_t n_rows, double *lam_fine, double *lam_coarse, mlmc_info *info, int precision,
                       double tol, void *stream);
@@ -216,7 +226,9 @@ int mlmc_level_stats(mlmc_ctx *ctx, int level, int n, const double *q_fine, cons
  * two PCG passes (kernel 0: operator pass, fused p-update + A p + p.Ap;
  * kernel 1: vector pass, x/z update + r.z, r.r) of one iteration in the
  * middle of every block of 32 iterations are bracketed by HIP events on the
- * stream of the solve (timing every launch would slow the solve by about 7%).
+ * stream of the solve (timing every launch would slow the solve by about 7%):
+ * iteration 16 of even blocks and 17 of odd ones, so that both forms of the
+ * vector pass are sampled.
  * mlmc_profile_read returns the summed event time (ms) and the number of
  * those timed launches, and the algorithmic HBM bytes of exactly those
  * launches (the bytes each sample active in the timed iteration must move;
@@ -229,7 +241,9 @@ int mlmc_profile_enable(mlmc_ctx *ctx, int on);
 /* kernel: 0 / 1 = FP64 operator / vector pass, 2 / 3 = the FP32 passes of the
  * mixed-precision inner solver (3 vectors of 8 B/node + 16 B/element of FP32
  * angles, or 8 B/element with "theta_storage": "bf16", and 8 vectors of
- * 8 B/node). */
+ * 8 B/node).  kernel + 4 (4..7): the same launches, with *alg_bytes set to
+ * the number of unknowns (dofs) the active samples of those launches hold,
+ * the unit of per-unknown byte figures. */
 int mlmc_profile_read(mlmc_ctx *ctx, int kernel, double *total_ms, int64_t *launches, double *alg_bytes);
 
 #ifdef __cplusplus

@@ -46,6 +46,7 @@ CONFIG_FILES = {
     "plate_c4": "plate_c4.json",
     "serve_c5": "serve_c5.json",
     "plate_t2": "plate_t2.json",
+    "cosserat_t1": "cosserat_t1.json",
 }
 
 

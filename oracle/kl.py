@@ -128,7 +128,7 @@ class KL:
         self.Lx, self.Ly = float(cfg["Lx"]), float(cfg["Ly"])
         self.kind = kl["type"]
         self.K = int(kl["n_modes"])
-        s = math.radians(kl["sigma_deg"])
+        s = float(kl["sigma_rad"]) if "sigma_rad" in kl else math.radians(kl["sigma_deg"])
         self.var = s * s
         if self.kind == "exp_separable":
             ax, ay = 0.5 * self.Lx, 0.5 * self.Ly

@@ -223,6 +223,27 @@ class PlateModel:
         return 1.0 / np.max(vals)
 
 
+def eigen_count_below(K: sp.spmatrix, KG: sp.spmatrix, sigma: float) -> int:
+    """Number of eigenvalues ``lambda < sigma`` of ``K phi = lambda K_G phi``
+    (Eq. matrixeig), by Sylvester's law of inertia: with ``K`` positive
+    definite it equals the number of negative eigenvalues of
+    ``K - sigma K_G``, read off the block-diagonal factor of a symmetric
+    indefinite (Bunch-Kaufman) LDL^T factorisation of the dense matrix.  Small
+    meshes only (dense, O(n^3))."""
+    A = (K - sigma * KG).toarray()
+    _, D, _ = sla.ldl(A, lower=True)
+    n = D.shape[0]
+    neg, i = 0, 0
+    while i < n:
+        if i + 1 < n and D[i + 1, i] != 0.0:
+            neg += int(np.sum(np.linalg.eigvalsh(D[i:i + 2, i:i + 2]) < 0.0))
+            i += 2
+        else:
+            neg += int(D[i, i] < 0.0)
+            i += 1
+    return neg
+
+
 def navier_orthotropic(D: np.ndarray, a: float, b: float, m_max: int = 20) -> float:
     """Kirchhoff buckling load of a specially orthotropic simply-supported plate under
     uniaxial ``N_x`` (Navier solution, one half-wave across ``b``):

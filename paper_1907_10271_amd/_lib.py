@@ -22,7 +22,7 @@ TUNING_PATH = os.path.join(_PKG, "tuning", "mi355x.json")
 
 MLMC_OK, MLMC_EINVAL, MLMC_ENOMEM, MLMC_EHIP, MLMC_ESTATE = 0, -1, -2, -3, -4
 FP64, MIXED = 0, 1
-S_OK, S_NOCONV, S_NAN, S_BREAKDOWN, S_SKIPPED = 0, 1, 2, 3, 4
+S_OK, S_NOCONV, S_NAN, S_BREAKDOWN, S_SKIPPED, S_NOTLOWEST = 0, 1, 2, 3, 4, 5
 
 EXPORTS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_level_info", "mlmc_num_levels",
            "mlmc_footprint", "mlmc_sample_field", "mlmc_strip_apply", "mlmc_strip_rhs_diag",

@@ -18,7 +18,7 @@ BUILD = os.path.join(PKG, "_build")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libmlmc.so")
 
-SOURCES = ["api.hip", "strip_kernels.hip", "strip_small.hip", "plate.hip", "kl_setup.cpp"]
+SOURCES = ["api.hip", "strip_kernels.hip", "strip_small.hip", "plate.hip", "cosserat.hip", "kl_setup.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MLMC_OFFLOAD_ARCH", "gfx950")
 

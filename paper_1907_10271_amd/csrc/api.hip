@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "cosserat.hpp"
 #include "json.hpp"
 #include "kl_setup.hpp"
 #include "mlmc.h"
@@ -59,7 +60,7 @@ struct StripLevel {
 struct mlmc_ctx {
   std::string err;
   Json cfg;
-  int kind = 0;  // 0 strip, 1 plate
+  int kind = 0;  // 0 strip, 1 plate, 2 Cosserat strip (Test Problem I)
   int nlev = 0;
   int K = 0;
   StripMat mat{};
@@ -79,11 +80,12 @@ struct mlmc_ctx {
   int h_active_cap = 0;
   double *d_stats = nullptr, *h_stats = nullptr;
   PlateCtx *plate = nullptr;
+  CosCtx *cos = nullptr;
   int device = 0;
   // diagnostics: event timing of the PCG passes
   bool prof = false;
   std::vector<hipEvent_t> ev;
-  double prof_ms[4] = {0, 0, 0, 0}, prof_bytes[4] = {0, 0, 0, 0};
+  double prof_ms[4] = {0, 0, 0, 0}, prof_bytes[4] = {0, 0, 0, 0}, prof_dofs[4] = {0, 0, 0, 0};
   int64_t prof_launches[4] = {0, 0, 0, 0};
   std::vector<int> h_iters;
   // group descriptors of the lock-step launches (device copy + pinned staging)
@@ -472,9 +474,11 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
   if (ng_all == 0) return MLMC_OK;
   if (ng_all > MAX_GROUPS) return fail(c, MLMC_EINVAL, "too many level groups in one lock-step solve");
   const int block = 32;
-  // profiling times one iteration per block, the middle one (the queue is
-  // full there), and counts the algorithmic bytes of exactly those launches
-  const int timed_b = block / 2;
+  // profiling times one iteration per block, in the middle (the queue is
+  // full there): iteration 16 of even blocks and 17 of odd ones, so both
+  // variants of the vector pass (x moves at odd iterations) are sampled; it
+  // counts the algorithmic bytes of exactly those launches
+  auto timed_b = [&](long base) { return block / 2 + (int)((base / block) & 1); };
   std::vector<long> timed_its;
   if (c->prof && c->ev.size() < 3) {
     c->ev.resize(3);
@@ -545,7 +549,7 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
   auto launch_block = [&](int base, const int *itb, hipStream_t s, bool timed) -> int {
     for (int b = 0; b < block; ++b) {
       const int k = base + b;
-      const bool ev = timed && b == timed_b;
+      const bool ev = timed && b == timed_b(base);
       if (ev) HIPCHK(c, hipEventRecord(c->ev[0], s));
       if (ngm[0]) launch_pcg_pass1<T>(dg, ngm[0], nb1m[0], c->mat, k, 0, itb, s, nt);
       if (ngm[1]) launch_pcg_pass1<T>(dg + ngm[0], ngm[1], nb1m[1], c->mat, k, 1, itb, s, nt);
@@ -619,7 +623,7 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
       c->prof_ms[prof_k + 1] += t2;
       c->prof_launches[prof_k] += 1;
       c->prof_launches[prof_k + 1] += 1;
-      timed_its.push_back(it + timed_b);
+      timed_its.push_back(it + timed_b(it));
     }
     bool changed = false, any = false;
     off = 0;
@@ -660,6 +664,8 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
         // iterations; in mixed mode a reliable update can shift the parity)
         const double vec = (ti & 1) ? 8.0 : 6.0;
         c->prof_bytes[prof_k + 1] += act * vec * 2 * w * g.nnode;
+        c->prof_dofs[prof_k] += act * 2.0 * g.nnode;
+        c->prof_dofs[prof_k + 1] += act * 2.0 * g.nnode;
       }
     }
   }
@@ -893,6 +899,7 @@ bool bad_level(const mlmc_ctx *c, int level) { return level < 0 || level >= c->n
 
 }  // namespace
 
+
 // ====================================================================== C ABI
 extern "C" {
 
@@ -924,6 +931,14 @@ int mlmc_create(const char *config_json, size_t mem_budget_bytes, mlmc_ctx **out
     if (kind == "strip") {
       c->kind = 0;
       rc = build_strip(c);
+    } else if (kind == "cosserat") {
+      c->kind = 2;
+      c->cos = cos_create(c->cfg, c->budget, c->err);
+      if (!c->cos) rc = MLMC_EINVAL;
+      else {
+        c->nlev = cos_num_levels(c->cos);
+        c->K = cos_num_params(c->cos) - 3;
+      }
     } else if (kind == "plate") {
       c->kind = 1;
       c->plate = plate_create(c->cfg, c->err);
@@ -934,7 +949,7 @@ int mlmc_create(const char *config_json, size_t mem_budget_bytes, mlmc_ctx **out
         plate_set_budget(c->plate, c->budget);
       }
     } else {
-      throw std::runtime_error("config 'kind' must be \"strip\" or \"plate\"");
+      throw std::runtime_error("config 'kind' must be \"strip\", \"plate\" or \"cosserat\"");
     }
   } catch (const std::exception &e) {
     c->err = e.what();
@@ -972,6 +987,7 @@ void mlmc_destroy(mlmc_ctx *c) {
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->plate) plate_destroy(c->plate);
+  if (c->cos) cos_destroy(c->cos);
   for (auto &e : c->ev) (void)hipEventDestroy(e);
   delete c;
 }
@@ -991,6 +1007,9 @@ int mlmc_level_info(const mlmc_ctx *c, int level, int64_t *n_nodes, int64_t *n_d
     nd = 2 * (int64_t)g.nnode;
     ne = g.nelem;
     ng = 4 * (int64_t)g.nelem;
+  } else if (c->kind == 2) {
+    cos_level_sizes(c->cos, level, &nn, &nd, &ne);
+    ng = 4 * ne;
   } else {
     plate_level_sizes(c->plate, level, &nn, &nd, &ne);
     ng = 4 * ne;
@@ -1011,7 +1030,8 @@ int mlmc_footprint(const mlmc_ctx *c, int kind, int level, int precision, size_t
   *bytes = (kind == 0) ? strip_slot_bytes(c->lv[level].g) +
                              (precision == MLMC_MIXED && !c->lv[level].small ? strip_mixed_slot_bytes(c->lv[level].g)
                                                                             : 0)
-                       : plate_slot_bytes(c->plate, level, precision);
+                       : (kind == 2) ? cos_slot_bytes(c->cos, level)
+                                     : plate_slot_bytes(c->plate, level, precision);
   return MLMC_OK;
 }
 
@@ -1021,6 +1041,7 @@ int mlmc_reserve(mlmc_ctx *c, int level, int n, int precision) {
   if (precision != MLMC_FP64 && precision != MLMC_MIXED) return fail(c, MLMC_EINVAL, "bad precision");
   if (n == 0) return MLMC_OK;
   if (c->kind == 1) return plate_reserve(c->plate, c->err, level, n);
+  if (c->kind == 2) return cos_reserve(c->cos, c->err, level, n);
   const bool mixed = precision == MLMC_MIXED && !c->lv[level].small;
   if (n > max_slots(c, level, mixed))
     return fail(c, MLMC_ENOMEM, "level " + std::to_string(level) + ": " + std::to_string(n) +
@@ -1031,12 +1052,14 @@ int mlmc_reserve(mlmc_ctx *c, int level, int n, int precision) {
 int mlmc_sample_field(mlmc_ctx *c, int level, int n, const double *xi, int ld_xi, void *theta, int dtype,
                       void *stream) {
   if (!c) return MLMC_EINVAL;
-  if (c->kind != 0) return fail(c, MLMC_ESTATE, "sample_field needs a strip context");
+  if (c->kind == 1) return fail(c, MLMC_ESTATE, "sample_field needs a strip or Cosserat context");
   if (bad_level(c, level)) return fail(c, MLMC_EINVAL, "level out of range");
   if (n < 0 || ld_xi < c->K + 3) return fail(c, MLMC_EINVAL, "n < 0 or ld_xi < n_modes + 3");
   if (dtype != 0 && dtype != 1) return fail(c, MLMC_EINVAL, "dtype must be 0 (FP64) or 1 (BF16)");
+  if (c->kind == 2 && dtype != 0) return fail(c, MLMC_EINVAL, "the Cosserat model writes FP64 angles only");
   if (n == 0) return MLMC_OK;
   if (!xi || !theta) return fail(c, MLMC_EINVAL, "null pointer");
+  if (c->kind == 2) return cos_sample_field(c->cos, c->err, level, n, xi, ld_xi, (double *)theta, (hipStream_t)stream);
   const StripGeom &g = c->lv[level].g;
   launch_kl_synth(c->lv[level].modes, c->K, g, xi, ld_xi, nullptr, n, dtype == 0 ? (double *)theta : nullptr,
                   dtype == 1 ? theta : nullptr, 0, 4 * g.nelem, nullptr, 0, (hipStream_t)stream);
@@ -1047,11 +1070,12 @@ int mlmc_sample_field(mlmc_ctx *c, int level, int n, const double *xi, int ld_xi
 int mlmc_strip_apply(mlmc_ctx *c, int level, int n, const double *theta, const double *x, double *y, int raw,
                      void *stream) {
   if (!c) return MLMC_EINVAL;
-  if (c->kind != 0) return fail(c, MLMC_ESTATE, "strip_apply needs a strip context");
+  if (c->kind == 1) return fail(c, MLMC_ESTATE, "strip_apply needs a strip or Cosserat context");
   if (bad_level(c, level) || n < 0) return fail(c, MLMC_EINVAL, "level out of range or n < 0");
   if (n == 0) return MLMC_OK;
   if (!theta || !x || !y) return fail(c, MLMC_EINVAL, "null pointer");
   if (n > 65535) return fail(c, MLMC_EINVAL, "n > 65535");
+  if (c->kind == 2) return cos_apply(c->cos, c->err, level, n, theta, x, y, raw, (hipStream_t)stream);
   launch_apply(c->lv[level].g, c->mat, theta, x, y, raw, n, (hipStream_t)stream);
   HIPCHK(c, hipGetLastError());
   return MLMC_OK;
@@ -1060,10 +1084,11 @@ int mlmc_strip_apply(mlmc_ctx *c, int level, int n, const double *theta, const d
 int mlmc_strip_rhs_diag(mlmc_ctx *c, int level, int n, const double *theta, double *b, double *dinv,
                         void *stream) {
   if (!c) return MLMC_EINVAL;
-  if (c->kind != 0) return fail(c, MLMC_ESTATE, "needs a strip context");
+  if (c->kind == 1) return fail(c, MLMC_ESTATE, "needs a strip or Cosserat context");
   if (bad_level(c, level) || n < 0) return fail(c, MLMC_EINVAL, "level out of range or n < 0");
   if (n == 0) return MLMC_OK;
   if (!theta || !b || !dinv) return fail(c, MLMC_EINVAL, "null pointer");
+  if (c->kind == 2) return cos_rhs_diag(c->cos, c->err, level, n, theta, b, dinv, (hipStream_t)stream);
   if (n > max_slots(c, level)) return fail(c, MLMC_ENOMEM, "batch exceeds the memory budget");
   int rc = ensure_pool(c, level, n);
   if (rc) return rc;
@@ -1077,11 +1102,15 @@ int mlmc_strip_rhs_diag(mlmc_ctx *c, int level, int n, const double *theta, doub
 int mlmc_strip_solve_theta(mlmc_ctx *c, int level, int n, const double *theta, double *q, double *d,
                            mlmc_info *info, int precision, double rtol, void *stream) {
   if (!c) return MLMC_EINVAL;
-  if (c->kind != 0) return fail(c, MLMC_ESTATE, "needs a strip context");
+  if (c->kind == 1) return fail(c, MLMC_ESTATE, "needs a strip or Cosserat context");
   if (bad_level(c, level) || n < 0) return fail(c, MLMC_EINVAL, "level out of range or n < 0");
   if (precision != MLMC_FP64 && precision != MLMC_MIXED) return fail(c, MLMC_EINVAL, "bad precision");
   if (n == 0) return MLMC_OK;
   if (!theta || !q) return fail(c, MLMC_EINVAL, "null pointer");
+  if (c->kind == 2) {
+    if (precision != MLMC_FP64) return fail(c, MLMC_EINVAL, "the Cosserat model is solved in FP64 only");
+    return cos_solve_theta(c->cos, c->err, level, n, theta, q, d, info, rtol, (hipStream_t)stream);
+  }
   const bool small = c->lv[level].small;
   const bool mixed = precision == MLMC_MIXED && !small;
   const int cap = max_slots(c, level, mixed);
@@ -1112,12 +1141,17 @@ int mlmc_strip_solve_theta(mlmc_ctx *c, int level, int n, const double *theta, d
 int mlmc_solve_batch(mlmc_ctx *c, int n_req, const mlmc_request *req, const double *xi, int64_t n_rows, int ld_xi,
                      double *q_fine, double *q_coarse, mlmc_info *info, int precision, double rtol, void *stream) {
   if (!c) return MLMC_EINVAL;
-  if (c->kind != 0) return fail(c, MLMC_ESTATE, "solve_batch needs a strip context");
+  if (c->kind == 1) return fail(c, MLMC_ESTATE, "solve_batch needs a strip or Cosserat context");
   if (n_req < 0) return fail(c, MLMC_EINVAL, "n_req < 0");
   if (n_req == 0) return MLMC_OK;
   if (!req || !xi || !q_fine || !q_coarse || !info) return fail(c, MLMC_EINVAL, "null pointer");
   if (ld_xi < c->K + 3) return fail(c, MLMC_EINVAL, "ld_xi < n_modes + 3");
   if (precision != MLMC_FP64 && precision != MLMC_MIXED) return fail(c, MLMC_EINVAL, "bad precision");
+  if (c->kind == 2) {
+    if (precision != MLMC_FP64) return fail(c, MLMC_EINVAL, "the Cosserat model is solved in FP64 only");
+    return cos_solve_batch(c->cos, c->err, n_req, req, xi, n_rows, ld_xi, q_fine, q_coarse, info, rtol,
+                           (hipStream_t)stream);
+  }
   for (int i = 0; i < n_req; ++i) {
     if (bad_level(c, req[i].level)) return fail(c, MLMC_EINVAL, "request " + std::to_string(i) + ": bad level");
     if (req[i].sample < 0 || req[i].sample >= n_rows)
@@ -1284,6 +1318,7 @@ int mlmc_profile_enable(mlmc_ctx *c, int on) {
   for (int k = 0; k < 4; ++k) {
     c->prof_ms[k] = 0;
     c->prof_bytes[k] = 0;
+    c->prof_dofs[k] = 0;
     c->prof_launches[k] = 0;
   }
   return MLMC_OK;
@@ -1291,10 +1326,11 @@ int mlmc_profile_enable(mlmc_ctx *c, int on) {
 
 int mlmc_profile_read(mlmc_ctx *c, int kernel, double *total_ms, int64_t *launches, double *alg_bytes) {
   if (!c) return MLMC_EINVAL;
-  if (kernel < 0 || kernel > 3) return fail(c, MLMC_EINVAL, "kernel must be 0..3");
-  if (total_ms) *total_ms = c->prof_ms[kernel];
-  if (launches) *launches = c->prof_launches[kernel];
-  if (alg_bytes) *alg_bytes = c->prof_bytes[kernel];
+  if (kernel < 0 || kernel > 7) return fail(c, MLMC_EINVAL, "kernel must be 0..7");
+  const int k = kernel & 3;
+  if (total_ms) *total_ms = c->prof_ms[k];
+  if (launches) *launches = c->prof_launches[k];
+  if (alg_bytes) *alg_bytes = kernel < 4 ? c->prof_bytes[k] : c->prof_dofs[k];
   return MLMC_OK;
 }
 

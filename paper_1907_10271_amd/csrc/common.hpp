@@ -125,6 +125,6 @@ struct MixedState {
   double rtol2;
 };
 
-enum SampleStatus { S_OK = 0, S_NOCONV = 1, S_NAN = 2, S_BREAKDOWN = 3, S_SKIPPED = 4 };
+enum SampleStatus { S_OK = 0, S_NOCONV = 1, S_NAN = 2, S_BREAKDOWN = 3, S_SKIPPED = 4, S_NOTLOWEST = 5 };
 
 }  // namespace mlmc

@@ -32,6 +32,11 @@ constexpr int MAXBW = 664;  // largest band half-width (128 x 128 mesh: 654)
 struct PlateGeom {
   int nx, ny, nnx, nny, nn, nfull, nfree, bw;
   double hx, hy, a, b;
+  // eigensolver settings carried with every level: half-waves along x of the
+  // first start vector (0: the integer nearest to a / b), and the relative
+  // shift of the lowest-mode check (0: no check)
+  int start_p0;
+  double cert_shift;
   const int *free_of_full;  // [nfull] free index or -1
   const int *full_of_free;  // [nfree]
 };
@@ -54,6 +59,7 @@ struct PlateWork {
   double *vec;     // [S][NVEC][nfree]
   double *kel;     // [S][KEL] element matrices K_e, K_G,e (factorisation spread over work-groups)
   int *flag;       // [S] non-positive pivot met
+  double *lam;     // [S] lambda of the last solve (lowest-mode check of the wide path)
   int nvec;
   size_t band_stride, vec_stride;
 };
@@ -629,11 +635,17 @@ __device__ void write_result(const PlateJob &J, int s, double lam, int it, doubl
   }
 }
 
+// result of one eigen-solve (the same in every thread of the work-group)
+struct EigResult {
+  double lam, res;
+  int it, status;
+};
+
 // LOBPCG (block NB) for the largest mu of K_G x = mu K x with the factored
-// band as preconditioner; writes lambda = 1/mu of sample s
+// band as preconditioner; returns lambda = 1/mu
 template <typename B>
-__device__ void lobpcg(const PlateGeom &g, const double *Ke, const double *KGe, const B *band, double *vec,
-                       const PlateJob &J, int s, double tol, int max_iter) {
+__device__ EigResult lobpcg(const PlateGeom &g, const double *Ke, const double *KGe, const B *band, double *vec,
+                            double tol, int max_iter) {
   __shared__ double red[4];
   __shared__ double gram[2 * NS * NS];
   __shared__ double coef[NS * NB], mu[NB], resn[NB];
@@ -642,7 +654,7 @@ __device__ void lobpcg(const PlateGeom &g, const double *Ke, const double *KGe, 
   // ---- initial block: smooth mode shapes w = sin(p pi x/a) sin(pi y/b), theta = grad w,
   // for p = p0, p0 + 1 half-waves along x, p0 the integer nearest to a/b (a long
   // panel buckles in about a/b half-waves; 1 for a square panel)
-  const int p0 = max(1, (int)lround(g.a / g.b));
+  const int p0 = g.start_p0 > 0 ? g.start_p0 : max(1, (int)lround(g.a / g.b));
   for (int r = threadIdx.x; r < n; r += PT) {
     const int full = g.full_of_free[r], node = full / 5, c = full % 5;
     const double x = (node % g.nnx) * g.hx, y = (node / g.nnx) * g.hy;
@@ -745,11 +757,29 @@ __device__ void lobpcg(const PlateGeom &g, const double *Ke, const double *KGe, 
     have_p = 1;
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const bool good = isfinite(mu0) && mu0 > 0.0 && isfinite(res0);
-    const int st = !isfinite(res0) ? 2 : !(mu0 > 0.0) ? 3 : (res0 > tol) ? 1 : 0;
-    write_result(J, s, good ? 1.0 / mu0 : NAN, it, res0, st);
-  }
+  const bool good = isfinite(mu0) && mu0 > 0.0 && isfinite(res0);
+  const int st = !isfinite(res0) ? S_NAN : !(mu0 > 0.0) ? S_BREAKDOWN : (res0 > tol) ? S_NOCONV : S_OK;
+  return EigResult{good ? 1.0 / mu0 : NAN, res0, it, st};
+}
+
+// Lowest-mode check (Eq. matrixeig asks for the smallest lambda, and LOBPCG
+// stops at any eigenpair with a small residual).  K is positive definite and
+// K_G semi-definite on the free unknowns, so K - sigma K_G is positive
+// definite exactly when sigma is below the smallest eigenvalue lambda_1.  With
+// sigma = lambda (1 - cert_shift) a Cholesky factorisation of the band of
+// K - sigma K_G that meets no non-positive pivot shows lambda < lambda_1 /
+// (1 - cert_shift): no eigenvalue lies below the computed one by more than
+// the shift.  The band is assembled from the element matrix Ke - sigma KGe
+// (Ke is overwritten) into `band` and factored in FP64.
+__device__ bool lowest_mode_holds(const PlateGeom &g, double lam, double *Ke, const double *KGe, double *band,
+                                  double *panel) {
+  const double sigma = lam * (1.0 - g.cert_shift);
+  __syncthreads();
+  for (int k = threadIdx.x; k < 400; k += PT) Ke[k] -= sigma * KGe[k];
+  __syncthreads();
+  assemble_band<double>(g, Ke, band, 0, g.nfree, threadIdx.x, PT);
+  __syncthreads();
+  return band_cholesky<double>(g, band, panel);
 }
 
 // one work-group per sample from start to finish
@@ -760,7 +790,10 @@ __global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                                                                                        PlateWork W, PlateJob J,
                                                                                        double tol, int max_iter) {
   __shared__ double Ke[400], KGe[400], Dmb[36];
-  __shared__ B panel[(NBK + MAXBW) * NBK];
+  // panel of the factorisation: FP64 room also in the FP32 form, for the FP64
+  // lowest-mode check
+  __shared__ double panel_mem[(NBK + MAXBW) * NBK];
+  B *panel = (B *)panel_mem;
   const int s = blockIdx.x;
   if (s >= J.n) return;
   sample_elements(g, m, J, s, Dmb, Ke, KGe);
@@ -770,10 +803,16 @@ __global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   __syncthreads();
   const bool ok = band_cholesky<B>(g, band, panel);
   if (!ok) {
-    if (threadIdx.x == 0) write_result(J, s, NAN, 0, 0.0, 3);
+    if (threadIdx.x == 0) write_result(J, s, NAN, 0, 0.0, S_BREAKDOWN);
     return;
   }
-  lobpcg<B>(g, Ke, KGe, band, W.vec + (size_t)s * W.vec_stride, J, s, tol, max_iter);
+  EigResult r = lobpcg<B>(g, Ke, KGe, band, W.vec + (size_t)s * W.vec_stride, tol, max_iter);
+  // the FP64 band is free now (FP64: LOBPCG is done with the factor of K;
+  // mixed: the factor lives in the FP32 band)
+  if (r.status == S_OK && g.cert_shift > 0.0 &&
+      !lowest_mode_holds(g, r.lam, Ke, KGe, W.band + (size_t)s * W.band_stride, panel_mem))
+    r.status = S_NOTLOWEST;
+  if (threadIdx.x == 0) write_result(J, s, r.lam, r.it, r.res, r.status);
 }
 
 // ---------------------------------------------------------------- wide factorisation
@@ -930,10 +969,41 @@ __global__ __launch_bounds__(PT) void k_plate_lobpcg(PlateGeom g, PlateWork W, P
   }
   __syncthreads();
   if (__builtin_amdgcn_readfirstlane(W.flag[s])) {
-    if (threadIdx.x == 0) write_result(J, s, NAN, 0, 0.0, 3);
+    if (threadIdx.x == 0) write_result(J, s, NAN, 0, 0.0, S_BREAKDOWN);
     return;
   }
-  lobpcg<B>(g, Ke, KGe, sample_band<B>(W, s), W.vec + (size_t)s * W.vec_stride, J, s, tol, max_iter);
+  const EigResult r = lobpcg<B>(g, Ke, KGe, sample_band<B>(W, s), W.vec + (size_t)s * W.vec_stride, tol, max_iter);
+  if (threadIdx.x == 0) {
+    write_result(J, s, r.lam, r.it, r.res, r.status);
+    W.lam[s] = r.lam;
+    // samples the lowest-mode check skips stay flagged (2); the check's
+    // factorisation sets 1 at a non-positive pivot
+    W.flag[s] = (r.status == S_OK && g.cert_shift > 0.0) ? 0 : 2;
+  }
+}
+
+// wide lowest-mode check, step 1: band of K - sigma K_G, sigma = lambda (1 -
+// cert_shift), into the FP64 band of each checked sample (rows as in
+// k_plate_assemble); the panel launches of k_band_step<double> then factor it
+__global__ __launch_bounds__(PT) void k_cert_assemble(PlateGeom g, PlateWork W, int n, int rows_per_wg) {
+  __shared__ double Kc[400];
+  const int s = blockIdx.y;
+  if (s >= n || __builtin_amdgcn_readfirstlane(W.flag[s])) return;
+  const double sigma = W.lam[s] * (1.0 - g.cert_shift);
+  for (int k = threadIdx.x; k < 400; k += PT) Kc[k] = W.kel[(size_t)s * KEL + k] - sigma * W.kel[(size_t)s * KEL + 400 + k];
+  __syncthreads();
+  const int r0 = blockIdx.x * rows_per_wg, r1 = min(g.nfree, r0 + rows_per_wg);
+  if (r0 < r1) assemble_band<double>(g, Kc, W.band + (size_t)s * W.band_stride, r0, r1, threadIdx.x, PT);
+}
+
+// wide lowest-mode check, step 3: a sample whose factorisation met a
+// non-positive pivot has a lower eigenvalue
+__global__ void k_cert_finish(PlateWork W, PlateJob J) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= J.n || W.flag[s] != 1) return;
+  const int o = J.out_idx[s];
+  if (J.coarse) J.info[o].status_c = S_NOTLOWEST;
+  else J.info[o].status_f = S_NOTLOWEST;
 }
 
 // diagnostic: y = K x or K_G x on full-dof vectors (constrained unknowns: y = 0)
@@ -968,6 +1038,7 @@ struct PlateLevelH {
   float *bandf = nullptr;
   int64_t *rows = nullptr;
   int *outidx = nullptr, *flag = nullptr;
+  double *lam = nullptr;
 };
 
 struct PlateCtx {
@@ -999,6 +1070,14 @@ static void launch_wide(const PlateGeom &g, const PlateMat &m, const PlateWork &
   for (int k0 = 0; k0 < g.nfree; k0 += NBK)
     hipLaunchKernelGGL(k_band_step<B>, dim3(nwg, n), dim3(PT), 0, st, g, W, n, k0);
   hipLaunchKernelGGL(k_plate_lobpcg<B>, dim3(n), dim3(PT), 0, st, g, W, J, tol, max_iter);
+  if (g.cert_shift > 0.0) {
+    // lowest-mode check: FP64 factorisation of K - sigma K_G, spread as above
+    hipLaunchKernelGGL(k_cert_assemble, dim3((g.nfree + rows_per_wg - 1) / rows_per_wg, n), dim3(PT), 0, st, g, W,
+                       n, rows_per_wg);
+    for (int k0 = 0; k0 < g.nfree; k0 += NBK)
+      hipLaunchKernelGGL(k_band_step<double>, dim3(nwg, n), dim3(PT), 0, st, g, W, n, k0);
+    hipLaunchKernelGGL(k_cert_finish, dim3((n + 255) / 256), dim3(256), 0, st, W, J);
+  }
 }
 
 static PlateGeom plate_geom(const Json &cfg, int level) {
@@ -1061,10 +1140,18 @@ PlateCtx *plate_create(const Json &cfg, std::string &err) {
     p->max_iter = (int)cfg.number_or("eig_max_iter", 500);
     // band width from which one sample's factorisation is spread over work-groups
     p->wide_min_bw = (int)cfg.number_or("wide_factor_min_bw", 200);
+    // half-waves along x of the first LOBPCG start vector (0: nearest to a / b)
+    const int start_p0 = (int)cfg.number_or("eig_start_p0", 0);
+    if (start_p0 < 0 || start_p0 > 64) throw std::runtime_error("eig_start_p0 must be in 0..64");
+    // relative shift of the lowest-mode check (0 turns it off)
+    const double cert_shift = cfg.number_or("cert_shift", 1e-6);
+    if (!(cert_shift >= 0.0 && cert_shift < 0.5)) throw std::runtime_error("cert_shift must be in [0, 0.5)");
     p->lv.resize(p->nlev);
     for (int l = 0; l < p->nlev; ++l) {
       PlateLevelH &L = p->lv[l];
       L.g = plate_geom(cfg, l);
+      L.g.start_p0 = start_p0;
+      L.g.cert_shift = cert_shift;
       std::vector<int> fof(L.g.nfull, -1), fo;
       for (int f = 0; f < L.g.nfull; ++f)
         if (!constrained(L.g, f)) {
@@ -1112,6 +1199,8 @@ static void free_work(PlateLevelH &L) {
   if (L.outidx) (void)hipFree(L.outidx);
   if (L.kel) (void)hipFree(L.kel);
   if (L.flag) (void)hipFree(L.flag);
+  if (L.lam) (void)hipFree(L.lam);
+  L.lam = nullptr;
   L.kel = nullptr;
   L.flag = nullptr;
   L.band = L.vec = nullptr;
@@ -1128,7 +1217,7 @@ static void free_work(PlateLevelH &L) {
 static size_t work_bytes(const PlateLevelH &L) {
   const size_t bs = (size_t)L.g.nfree * (L.g.bw + 1);
   return bs * (sizeof(double) + sizeof(float)) + (size_t)NVEC * L.g.nfree * sizeof(double) + sizeof(int64_t) +
-         2 * sizeof(int) + KEL * sizeof(double);
+         2 * sizeof(int) + (KEL + 1) * sizeof(double);
 }
 
 // grow the workspace of level l to at least n samples within the budget
@@ -1149,7 +1238,8 @@ static int ensure_work(PlateCtx *p, std::string &err, int l, int n) {
       hipMalloc(&L.bandf, bs * sizeof(float) * n) != hipSuccess ||
       hipMalloc(&L.vec, (size_t)NVEC * L.g.nfree * sizeof(double) * n) != hipSuccess ||
       hipMalloc(&L.rows, sizeof(int64_t) * n) != hipSuccess || hipMalloc(&L.outidx, sizeof(int) * n) != hipSuccess ||
-      hipMalloc(&L.kel, sizeof(double) * KEL * n) != hipSuccess || hipMalloc(&L.flag, sizeof(int) * n) != hipSuccess) {
+      hipMalloc(&L.kel, sizeof(double) * KEL * n) != hipSuccess || hipMalloc(&L.flag, sizeof(int) * n) != hipSuccess ||
+      hipMalloc(&L.lam, sizeof(double) * n) != hipSuccess) {
     free_work(L);
     err = "plate workspace allocation failed";
     return MLMC_ENOMEM;
@@ -1246,6 +1336,7 @@ int plate_buckle_batch(PlateCtx *p, std::string &err, int n_req, const mlmc_requ
       Wk.vec = L.vec;
       Wk.kel = L.kel;
       Wk.flag = L.flag;
+      Wk.lam = L.lam;
       Wk.band_stride = (size_t)L.g.nfree * (L.g.bw + 1);
       Wk.vec_stride = (size_t)NVEC * L.g.nfree;
       for (int off = 0; off < total; off += cap) {

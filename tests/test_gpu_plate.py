@@ -93,8 +93,11 @@ def test_plate_error_paths():
     import paper_1907_10271_amd as pk
     ctx = context("plate_c4")
     off = dev(mi.plate_offsets(C4, 0, 0, 2))
-    with pytest.raises(pk.MLMCError):
+    with pytest.raises(ValueError, match="sample row 5"):
         ctx.buckle_batch([(5, 0, False)], off)
+    from tests.gpu_util import raw_batch_call
+    assert raw_batch_call(ctx, "buckle", [(5, 0, False)], off) == -1
+    assert raw_batch_call(ctx, "buckle", [(0, 9, False)], off) == -1
     with pytest.raises(pk.MLMCError) as e:
         ctx.solve_batch([(0, 0, False)], off)
     assert e.value.code == -4
@@ -284,3 +287,74 @@ def test_two_level_rare_event_matches_oracle(precision, j):
     assert abs(r["rmse"] - ref["rmse"]) <= 1e-15 * ref["rmse"] + 1e-18
     # the regime the estimator is built for: few events, some of them below the biased-rate threshold
     assert 0 < ref["n_plus"] and min(ref["n_base_plus"], ref["n_plus"], ref["n_minus"]) < 10
+
+
+# Rows of the Test Problem II panel's level-0 stream on which LOBPCG started
+# from one and two half-waves along x (the start before the aspect-ratio
+# start) stops at a higher buckling mode: found by solving rows 0..19999 with
+# that start and the lowest-mode check (1155 rows flagged, none with the
+# default start); the oracle confirms each of these rows below.
+T2_OLD_START_HIGHER_MODE_ROWS = [11, 13, 29, 30, 35, 60]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lowest_mode_check_flags_higher_modes(precision):
+    """The lowest-mode check (a Cholesky factorisation of K - sigma K_G just
+    below the computed load) flags the samples whose eigen-solve stopped at a
+    higher mode, and passes the same samples once the solver finds the lowest
+    mode, with loads equal to the oracle's (Eq. matrixeig asks for the
+    smallest eigenvalue)."""
+    import paper_1907_10271_amd as pk
+    from oracle.plate import PlateModel
+    T2 = mi.load_config("plate_t2")
+    rows = T2_OLD_START_HIGHER_MODE_ROWS + [0, 1]
+    off = dev(np.concatenate([mi.plate_offsets(T2, 0, r, 1) for r in rows]))
+    reqs = [(k, 0, False) for k in range(len(rows))]
+    model = PlateModel(T2, 0)
+    ref = np.array([model.buckling_load(mi.plate_offsets(T2, 0, r, 1)[0]) for r in rows])
+    old = pk.Context(dict(T2, eig_start_p0=1))
+    lam_old, _, info_old = old.buckle_batch(reqs, off, precision=precision)
+    lam_old = lam_old.cpu().numpy()
+    new = pk.Context(mi.config_text("plate_t2"))
+    lam_new, _, info_new = new.buckle_batch(reqs, off, precision=precision)
+    lam_new = lam_new.cpu().numpy()
+    tol = 1e-10 if precision == 0 else 1e-6
+    nbad = len(T2_OLD_START_HIGHER_MODE_ROWS)
+    # the old start: the check flags exactly the solves that stopped above the
+    # oracle's lowest load (the listed rows in FP64, where they were found; the
+    # FP32 preconditioner of the mixed form takes other paths)
+    higher = lam_old > ref * (1 + 1e-6)
+    assert np.array_equal(info_old["status_f"] == pk.S_NOTLOWEST, higher), (info_old["status_f"], lam_old, ref)
+    assert np.all(info_old["status_f"][~higher] == pk.S_OK)
+    np.testing.assert_allclose(lam_old[~higher], ref[~higher], rtol=tol)
+    if precision == 0:
+        assert np.all(higher[:nbad]) and not np.any(higher[nbad:])
+        assert np.all(lam_old[:nbad] > ref[:nbad] * 1.01)
+    # the default start: every row certified and equal to the oracle
+    assert np.all(info_new["status_f"] == pk.S_OK), info_new["status_f"]
+    np.testing.assert_allclose(lam_new, ref, rtol=tol)
+    # with the check off, higher modes pass unflagged
+    off_check = pk.Context(dict(T2, eig_start_p0=1, cert_shift=0.0))
+    lam_nc, _, info_nc = off_check.buckle_batch(reqs, off, precision=precision)
+    assert np.all(info_nc["status_f"] == pk.S_OK)
+    assert np.array_equal(lam_nc.cpu().numpy(), lam_old)
+
+
+def test_lowest_mode_check_on_the_wide_path():
+    """The check on the wide path (the factorisation spread over work-groups,
+    one launch per band panel; forced here on level 0, whose factor is
+    bit-identical either way) flags the same higher modes and passes the
+    lowest ones."""
+    import paper_1907_10271_amd as pk
+    T2 = mi.load_config("plate_t2")
+    rows = T2_OLD_START_HIGHER_MODE_ROWS[:3] + [0]
+    off = dev(np.concatenate([mi.plate_offsets(T2, 0, r, 1) for r in rows]))
+    reqs = [(k, 0, False) for k in range(len(rows))]
+    outs = {}
+    for wide in (0, 100):
+        ctx = pk.Context(dict(T2, eig_start_p0=1, wide_factor_min_bw=wide))
+        lam, _, info = ctx.buckle_batch(reqs, off)
+        outs[wide] = (lam.cpu().numpy(), info["status_f"].copy())
+    assert np.array_equal(outs[0][0], outs[100][0])
+    assert np.array_equal(outs[100][1], [pk.S_NOTLOWEST] * 3 + [pk.S_OK])
+    assert np.array_equal(outs[0][1], outs[100][1])

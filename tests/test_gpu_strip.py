@@ -69,6 +69,60 @@ def test_operator_parity(name, level):
         assert np.abs(y_bc[k] - ref2).max() <= 1e-13 * np.abs(ref2).max()
 
 
+def _any_angles(n_gp, n, seed):
+    """Angles uniform in [-pi, pi] with the edge values of the GPU's angle
+    code (tan theta) and of its sin/cos range reduction placed at the first
+    Gauss points: +-pi/2 (tan near +-1.6e16), +-pi, +-1 rad and just above
+    (the switch from the series to the Cody-Waite reduction), 0 and -0."""
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(-math.pi, math.pi, size=(n, n_gp))
+    special = [math.pi / 2, -math.pi / 2, math.pi, -math.pi, 1.0, -1.0, math.nextafter(1.0, 2.0),
+               -math.nextafter(1.0, 2.0), 1.0 + 1e-9, 1.5, 3.0, -3.1, 0.0, -0.0,
+               math.nextafter(math.pi / 2, 0.0), math.nextafter(math.pi / 2, 4.0)]
+    for k in range(n):
+        th[k, k:k + len(special)] = special
+    return th
+
+
+@pytest.mark.parametrize("name,level", [("strip_c1", 0), ("strip_c2", 0)])
+def test_operator_rhs_and_diagonal_for_any_angle(name, level):
+    """The operator, the lifting and the Jacobi diagonal for angles anywhere in
+    [-pi, pi] (the rotated stiffness of Section 3.1 at every Gauss point)
+    against the oracle's assembled matrix, 1e-13 relative."""
+    from oracle.strip import assemble, reduce_system
+    ctx = context(name)
+    om = oracle_strip(name, level)
+    n_gp = 4 * om.mesh.n_elem
+    thetas = _any_angles(n_gp, 3, seed=23)
+    x = np.random.default_rng(29).standard_normal((3, 2 * om.mesh.n_nodes))
+    y = ctx.strip_apply(level, dev(thetas), dev(x), raw=True).cpu().numpy()
+    b, dinv = ctx.strip_rhs_diag(level, dev(thetas))
+    b, dinv = b.cpu().numpy(), dinv.cpu().numpy()
+    for k in range(3):
+        K = assemble(om.mesh, om.Q, thetas[k].reshape(-1, 4))
+        ref = K @ x[k]
+        assert np.abs(y[k] - ref).max() <= 1e-13 * np.abs(ref).max(), k
+        free, Kff, bf = reduce_system(K, om.bc)
+        assert np.abs(b[k][free] - bf).max() <= 1e-13 * np.abs(bf).max(), k
+        d = Kff.diagonal()
+        assert np.abs(1.0 / dinv[k][free] - d).max() <= 1e-13 * np.abs(d).max(), k
+
+
+def test_solve_and_qoi_for_any_angle():
+    """Solve and fibre-direction stress QoI with angles anywhere in [-pi, pi]
+    (QoI uses cos and sin of theta itself, not only of 2 theta) against the
+    oracle's direct solve, 1e-10 relative."""
+    ctx = context("strip_c1")
+    om = oracle_strip("strip_c1", 0)
+    thetas = _any_angles(4 * om.mesh.n_elem, 3, seed=31)
+    q, _, info = ctx.strip_solve_theta(0, dev(thetas), rtol=1e-13)
+    q = q.cpu().numpy()
+    for k in range(3):
+        ref = om.solve_theta(thetas[k].reshape(-1, 4), method="direct").q
+        assert info[k]["status_f"] == 0
+        assert abs(q[k] - ref) <= 1e-10 * abs(ref), (k, q[k], ref)
+
+
 @pytest.mark.parametrize("name,level", [("strip_c1", 0), ("strip_c2", 1)])
 def test_rhs_and_diagonal_parity(name, level):
     from oracle.strip import assemble, reduce_system
@@ -181,11 +235,15 @@ def test_error_paths():
     import paper_1907_10271_amd as pk
     ctx = context("strip_c1")
     xi = dev(_rows("strip_c1", 0, 2))
-    with pytest.raises(pk.MLMCError) as e:
+    # the binding refuses a bad level or row before the library is called ...
+    with pytest.raises(ValueError, match="level 5"):
         ctx.solve_batch([(0, 5, False)], xi)
-    assert e.value.code == -1
-    with pytest.raises(pk.MLMCError):
+    with pytest.raises(ValueError, match="sample row 7"):
         ctx.solve_batch([(7, 0, False)], xi)          # row outside the parameter array
+    # ... and so does the library itself, before any device work
+    from tests.gpu_util import raw_batch_call
+    assert raw_batch_call(ctx, "solve", [(0, 5, False)], xi) == -1
+    assert raw_batch_call(ctx, "solve", [(7, 0, False)], xi) == -1
     with pytest.raises(pk.MLMCError) as e:
         ctx.buckle_batch([(0, 0, False)], xi)
     assert e.value.code == -4

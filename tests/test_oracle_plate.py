@@ -208,3 +208,37 @@ def test_panel_load_error_rate_alpha_one():
     assert d01 > 0 and d12 > 0
     alpha = math.log(d01 / d12) / math.log(4.0)
     assert 0.8 < alpha < 1.2, alpha
+
+
+def test_eigen_count_below_matches_the_dense_spectrum():
+    # Sylvester count of K - sigma K_G against a brute-force dense generalised
+    # eigen-decomposition of the 16x16 panel, at shifts between and around the
+    # lowest eigenvalues
+    import scipy.linalg as sla
+    from oracle.plate import PlateModel, eigen_count_below
+    cfg = mi.load_config("plate_c4")
+    off = mi.plate_offsets(cfg, 0, 3, 1)[0]
+    s = PlateModel(cfg, 0).system(off)
+    mu = sla.eigh(s.KG.toarray(), s.K.toarray(), eigvals_only=True)
+    lam = np.sort(1.0 / mu[mu > 1e-12 * mu.max()])
+    shifts = [0.5 * lam[0], lam[0] * (1 - 1e-6), lam[0] * (1 + 1e-6), 0.5 * (lam[1] + lam[2]),
+              0.5 * (lam[3] + lam[4]), lam[6] * (1 + 1e-6)]
+    for sig in shifts:
+        assert eigen_count_below(s.K, s.KG, sig) == int(np.sum(lam < sig)), sig
+
+
+def test_inertia_at_32_marks_the_lowest_buckling_load():
+    # 0 negative pivots just below lambda_1, 1 between lambda_1 and lambda_2:
+    # the check the GPU runs after each eigen-solve, on the oracle's side
+    import scipy.sparse.linalg as spla
+    from oracle.plate import PlateModel, eigen_count_below
+    cfg = mi.load_config("plate_c4")
+    off = mi.plate_offsets(cfg, 1, 0, 1)[0]
+    s = PlateModel(cfg, 1).system(off)
+    lu = spla.splu(s.K.tocsc())
+    vals = spla.eigsh(s.KG, k=3, M=s.K, Minv=spla.LinearOperator(s.K.shape, matvec=lu.solve), which="LA",
+                      tol=1e-14, return_eigenvectors=False)
+    lam = np.sort(1.0 / vals)
+    assert eigen_count_below(s.K, s.KG, lam[0] * (1 - 1e-6)) == 0
+    assert eigen_count_below(s.K, s.KG, 0.5 * (lam[0] + lam[1])) == 1
+    assert eigen_count_below(s.K, s.KG, lam[1] * (1 - 1e-6)) == 1
