@@ -165,6 +165,31 @@ int mlmc_strip_rhs_diag(mlmc_ctx *ctx, int level, int n, const double *theta, do
 int mlmc_strip_solve_theta(mlmc_ctx *ctx, int level, int n, const double *theta, double *q, double *d,
                            mlmc_info *info, int precision, double rtol, void *stream);
 
+/* Size of the fixed per-GPU scratch array of mlmc_strip_solve_theta_noalloc. */
+#define MLMC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * form of mlmc_strip_solve_theta, with every workspace buffer of the solve
+ * carved from one fixed device array of MLMC_SCRATCH_BYTES per GPU (part of
+ * the library's code object, held until the process ends) instead of the
+ * context's pool.  The call allocates nothing: no hipMalloc, hipFree, pinned
+ * host memory, events or graphs (event timing and graph replay are off for
+ * the call).
+ * theta: dev [n][n_gp] FP64 angles; q: dev [n] quantities of interest; info:
+ * dev [n] (fine fields filled; may be NULL); rtol <= 0 uses the configured
+ * tolerance.  Results are bit-identical to mlmc_strip_solve_theta in FP64.
+ * The context's device must be current.  Every call on a GPU shares that
+ * GPU's array, whatever the context: calls that overlap on one GPU (two host
+ * threads, or two streams without ordering between the calls) race and give
+ * wrong results.  The call clears the part of the array it uses before the
+ * solve and synchronises `stream` before returning.
+ * Errors: MLMC_EINVAL (level, n < 0, null pointers), MLMC_ESTATE (plate
+ * context, another device current), MLMC_ENOMEM (n solves of `level` need more
+ * than MLMC_SCRATCH_BYTES, or n > 4096; nothing is queued then), MLMC_EHIP. */
+int mlmc_strip_solve_theta_noalloc(mlmc_ctx *ctx, int level, int n, const double *theta, double *q,
+                                   mlmc_info *info, double rtol, void *stream);
+
 /* Sample solves: for request i, Q at req[i].level from parameter row
  * xi[req[i].sample] (and Q at level - 1 with the same row when coupled and
  * level > 0).  req: host [n_req]; xi: dev [n_rows][ld_xi] (every req[i].sample

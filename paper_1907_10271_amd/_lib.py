@@ -27,7 +27,10 @@ S_OK, S_NOCONV, S_NAN, S_BREAKDOWN, S_SKIPPED, S_NOTLOWEST = 0, 1, 2, 3, 4, 5
 EXPORTS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_level_info", "mlmc_num_levels",
            "mlmc_footprint", "mlmc_sample_field", "mlmc_strip_apply", "mlmc_strip_rhs_diag",
            "mlmc_strip_solve_theta", "mlmc_solve_batch", "mlmc_buckle_batch", "mlmc_level_stats",
-           "mlmc_profile_enable", "mlmc_profile_read", "mlmc_plate_apply", "mlmc_reserve"]
+           "mlmc_profile_enable", "mlmc_profile_read", "mlmc_plate_apply", "mlmc_reserve",
+           "mlmc_strip_solve_theta_noalloc"]
+# bytes of the fixed per-GPU scratch array of mlmc_strip_solve_theta_noalloc
+SCRATCH_BYTES = 64 << 20
 
 
 class Request(C.Structure):
@@ -85,6 +88,7 @@ def load() -> C.CDLL:
     lib.mlmc_strip_apply.argtypes = [vp, i, i, vp, vp, vp, i, vp]
     lib.mlmc_strip_rhs_diag.argtypes = [vp, i, i, vp, vp, vp, vp]
     lib.mlmc_strip_solve_theta.argtypes = [vp, i, i, vp, vp, vp, vp, i, d, vp]
+    lib.mlmc_strip_solve_theta_noalloc.argtypes = [vp, i, i, vp, vp, vp, d, vp]
     lib.mlmc_solve_batch.argtypes = [vp, i, C.POINTER(Request), vp, C.c_int64, i, vp, vp, vp, i, d, vp]
     lib.mlmc_buckle_batch.argtypes = [vp, i, C.POINTER(Request), vp, C.c_int64, vp, vp, vp, i, d, vp]
     lib.mlmc_level_stats.argtypes = [vp, i, i, vp, vp, d, d, C.POINTER(LevelAcc), vp]
@@ -264,6 +268,21 @@ class Context:
         self._check(self.lib.mlmc_strip_solve_theta(self.h, level, n, _ptr(theta), _ptr(q), _ptr(d), _ptr(info),
                                                     precision, rtol, _stream(stream)))
         return q, d, info_to_numpy(info)
+
+    def strip_solve_theta_noalloc(self, level: int, theta, q, info=None, rtol: float = 0.0, stream=None):
+        """FP64 solves of the given fields with the library's fixed scratch
+        array as workspace: the call allocates no device memory.  The caller
+        passes the outputs ``q`` (float64 ``[n]``) and optionally ``info``
+        (uint8 ``[n * 32]``)."""
+        torch = _torch()
+        _check_dev((theta, "theta", (None, self.level_info(level)["n_gp"])), (q, "q", (theta.shape[0],)))
+        if info is not None:
+            if info.dtype != torch.uint8 or not info.is_contiguous() or info.numel() < 32 * theta.shape[0] \
+                    or not info.is_cuda:
+                raise ValueError("info: must be a contiguous uint8 device tensor of at least 32 n bytes")
+        self._check(self.lib.mlmc_strip_solve_theta_noalloc(self.h, level, theta.shape[0], _ptr(theta), _ptr(q),
+                                                            _ptr(info), rtol, _stream(stream)))
+        return q, (None if info is None else info_to_numpy(info)[:theta.shape[0]])
 
     def solve_batch(self, requests: Sequence, xi, precision: int = FP64, rtol: float = 0.0, stream=None):
         """``requests``: sequence of ``(sample_row, level, coupled)``."""

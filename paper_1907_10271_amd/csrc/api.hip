@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -105,6 +106,9 @@ struct mlmc_ctx {
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int *d_itb = nullptr;
+  // device address of this GPU's fixed scratch array (mlmc_strip_solve_theta_noalloc)
+  void *scratch = nullptr;
+  std::string scratch_err;
   struct CachedGraph {
     std::vector<char> key;
     hipGraph_t graph = nullptr;
@@ -899,6 +903,81 @@ bool bad_level(const mlmc_ctx *c, int level) { return level < 0 || level >= c->n
 
 }  // namespace
 
+// ---------------------------------------------------------------- fixed scratch
+// Workspace of mlmc_strip_solve_theta_noalloc: one fixed array per GPU, part of
+// the code object, so that entry point allocates nothing.  In host code the
+// name `scratch` only stands for the symbol; the array's device address comes
+// from hipGetSymbolAddress, once per device, at context creation.
+static __device__ __align__(256) unsigned char scratch[MLMC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_addr;  // by device id
+
+// look up (once per device) the current device's scratch address into c->scratch
+int scratch_address(mlmc_ctx *c) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_addr.size() <= c->device) g_scratch_addr.resize(c->device + 1, nullptr);
+  if (!g_scratch_addr[c->device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(c, MLMC_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_addr[c->device] = p;
+  }
+  c->scratch = g_scratch_addr[c->device];
+  return MLMC_OK;
+}
+
+// Lay the FP64 solver state of n slots of a strip level out from `base` in
+// 256-byte aligned pieces (the same buffers a pool slot holds, angles as codes
+// or pairs as the level stores them).  Returns the bytes used; with base ==
+// nullptr it only sizes the layout.
+size_t carve_slots(const mlmc_ctx *c, int level, int n, double rtol, unsigned char *base, PcgSlots *S,
+                   double **qpart) {
+  const StripLevel &L = c->lv[level];
+  const StripGeom &g = L.g;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void * {
+    void *p = base ? (void *)(base + off) : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  const size_t vec = sizeof(double) * 2 * (size_t)g.nnode * n;
+  *S = PcgSlots{};
+  S->x = (double *)take(vec);
+  S->z = (double *)take(vec);
+  S->p = (double *)take(vec);
+  S->Ap = (double *)take(vec);
+  S->dg = (double *)take(vec);
+  S->theta = take(sizeof(double) * (L.cs ? 8 : 4) * (size_t)g.nelem * n);
+  S->cs = L.cs ? 1 : 0;
+  S->part_pap = (double *)take(sizeof(double) * g.sw_npart * (size_t)n);
+  S->part_rz = (double *)take(sizeof(double) * 2 * g.nchunks * (size_t)n);
+  S->part_rr = (double *)take(sizeof(double) * 2 * g.nchunks * (size_t)n);
+  S->rzs = (double *)take(sizeof(double) * 2 * (size_t)n);
+  S->tol2 = (double *)take(sizeof(double) * n);
+  S->bb = (double *)take(sizeof(double) * n);
+  S->relres = (double *)take(sizeof(double) * n);
+  S->xa = (double *)take(sizeof(double) * 2 * (size_t)n);
+  S->xs = (int *)take(sizeof(int) * 2 * (size_t)n);
+  S->it_a = (int *)take(sizeof(int) * n);
+  S->it_b = (int *)take(sizeof(int) * n);
+  S->status = (int *)take(sizeof(int) * n);
+  S->active = (int *)take(sizeof(int) * n);
+  *qpart = (double *)take(sizeof(double) * qoi_parts(g) * (size_t)n);
+  S->S = n;
+  S->max_iter = c->max_iter;
+  S->rtol2 = rtol * rtol;
+  return off;
+}
+
+// slots the pinned flag buffer holds from creation on (the no-alloc entry
+// point never grows it)
+constexpr int NOALLOC_MAX_SLOTS = 4096;
+
+}  // namespace
 
 // ====================================================================== C ABI
 extern "C" {
@@ -928,6 +1007,11 @@ int mlmc_create(const char *config_json, size_t mem_budget_bytes, mlmc_ctx **out
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
       throw std::runtime_error("allocation of the stats buffers failed");
+    // a failed look-up only disables the allocation-free entry point
+    if (scratch_address(c) != MLMC_OK) c->scratch_err = c->err;
+    if (hipHostMalloc((void **)&c->h_active, sizeof(int) * NOALLOC_MAX_SLOTS) != hipSuccess)
+      throw std::runtime_error("allocation of the slot flag buffer failed");
+    c->h_active_cap = NOALLOC_MAX_SLOTS;
     if (kind == "strip") {
       c->kind = 0;
       rc = build_strip(c);
@@ -1133,6 +1217,52 @@ int mlmc_strip_solve_theta(mlmc_ctx *c, int level, int n, const double *theta, d
   launch_qoi(c->lv[level].g, c->mat, report_view(c, level, S, mixed ? MLMC_MIXED : MLMC_FP64), n,
              c->lv[level].pool.qpart, nullptr, q, nullptr, info, 1 << 30, st);
   if (d) launch_total_disp(c->lv[level].g, S.x, d, n, st);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(st));
+  return MLMC_OK;
+}
+
+int mlmc_strip_solve_theta_noalloc(mlmc_ctx *c, int level, int n, const double *theta, double *q, mlmc_info *info,
+                                   double rtol, void *stream) {
+  if (!c) return MLMC_EINVAL;
+  if (c->kind != 0) return fail(c, MLMC_ESTATE, "needs a strip context");
+  if (bad_level(c, level) || n < 0) return fail(c, MLMC_EINVAL, "level out of range or n < 0");
+  if (n == 0) return MLMC_OK;
+  if (!theta || !q) return fail(c, MLMC_EINVAL, "null pointer");
+  int dev = -1;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (!c->scratch) return fail(c, MLMC_EHIP, "no scratch address on this device: " + c->scratch_err);
+  if (dev != c->device) return fail(c, MLMC_ESTATE, "the context's device must be current");
+  const double rt = rtol > 0 ? rtol : c->rtol;
+  PcgSlots S{};
+  double *qpart = nullptr;
+  const size_t need = carve_slots(c, level, n, rt, nullptr, &S, &qpart);
+  if (need > (size_t)MLMC_SCRATCH_BYTES || n > NOALLOC_MAX_SLOTS)
+    return fail(c, MLMC_ENOMEM, "level " + std::to_string(level) + ": " + std::to_string(n) + " solves need " +
+                                    std::to_string(need) + " bytes of scratch, more than the fixed " +
+                                    std::to_string((size_t)MLMC_SCRATCH_BYTES) + " (or more than " +
+                                    std::to_string(NOALLOC_MAX_SLOTS) + " solves)");
+  carve_slots(c, level, n, rt, (unsigned char *)c->scratch, &S, &qpart);
+  hipStream_t st = (hipStream_t)stream;
+  StripLevel &L = c->lv[level];
+  // the array keeps the last call's contents: flags, counters and pending-step
+  // markers must start at zero
+  launch_zero16(c->scratch, need, st);
+  if (info) launch_info_init(info, nullptr, n, st);
+  const size_t ngp = (size_t)n * 4 * L.g.nelem;
+  double *ang = (double *)S.theta;
+  if (L.cs) launch_theta_cs(theta, ang, ngp, st);
+  else launch_theta_code(theta, ang, ngp, st);
+  HIPCHK(c, hipGetLastError());
+  // neither event timing nor graph capture (each would create runtime objects)
+  const bool prof = c->prof, graphs = c->graphs;
+  c->prof = false;
+  c->graphs = false;
+  const int rc = L.small ? run_small(c, level, S, n, st) : run_pcg(c, {{level, S, n}}, st);
+  c->prof = prof;
+  c->graphs = graphs;
+  if (rc) return rc;
+  launch_qoi(L.g, c->mat, S, n, qpart, nullptr, q, nullptr, info, 1 << 30, st);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(st));
   return MLMC_OK;

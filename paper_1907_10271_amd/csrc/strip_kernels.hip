@@ -1201,6 +1201,20 @@ __global__ void k_add_int(int *p, int v) {
   if (threadIdx.x == 0) *p += v;
 }
 
+// zero `words` 16-byte words at p (a kernel, not a memset node, so callers
+// may capture it in a graph)
+__global__ __launch_bounds__(256) void k_zero16(uint4 *p, size_t words) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < words; k += stride) p[k] = make_uint4(0, 0, 0, 0);
+}
+
+void launch_zero16(void *p, size_t bytes, hipStream_t st) {
+  const size_t words = bytes / 16;
+  if (!words) return;
+  const unsigned blocks = (unsigned)std::min<size_t>((words + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_zero16, dim3(blocks), dim3(256), 0, st, (uint4 *)p, words);
+}
+
 void launch_set_int(int *p, int v, hipStream_t st) { hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, p, v); }
 void launch_add_int(int *p, int v, hipStream_t st) { hipLaunchKernelGGL(k_add_int, dim3(1), dim3(64), 0, st, p, v); }
 

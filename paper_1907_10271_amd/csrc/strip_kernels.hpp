@@ -47,6 +47,8 @@ void launch_resid64(const StripGeom &g, const StripMat &m, const PcgSlots &D, co
                     const MixedState &M, int n, int it, int every, const int *itb, hipStream_t st);
 void launch_ru_apply(const StripGeom &g, const PcgSlots &D, const PcgState<float> &I, const MixedState &M, int n,
                      int it, int every, const int *itb, hipStream_t st);
+// zero `bytes` (a multiple of 16) at a 16-byte aligned device address
+void launch_zero16(void *p, size_t bytes, hipStream_t st);
 // *p = v and *p += v by one thread (kernel nodes, so they can be captured)
 void launch_set_int(int *p, int v, hipStream_t st);
 void launch_add_int(int *p, int v, hipStream_t st);
