@@ -75,6 +75,16 @@ def parse():
                     help="strip workload of the time-to-epsilon runs")
     ap.add_argument("--no-legs", action="store_true",
                     help="only the batch-round benchmark: no time-to-epsilon and no serving leg (profiling runs)")
+    ap.add_argument("--plate-mlmc", type=float, default=0.0,
+                    help="also run MLMC with selective refinement (Algorithms 1 and 2) on the panel workload of "
+                         "--plate-config to this relative tolerance, FP64 and mixed precision")
+    ap.add_argument("--plate-mlmc-precisions", type=str, default="fp64,mixed",
+                    help="precisions of the --plate-mlmc leg (comma list of fp64, mixed)")
+    ap.add_argument("--cosserat", type=str, default="",
+                    help="also time the Cosserat Test I workload: coupled samples per level, e.g. "
+                         "2048,1024,512,128,32,8")
+    ap.add_argument("--cosserat-eps", type=float, default=0.0,
+                    help="also run adaptive MLMC (Algorithm 1) on the Cosserat workload to this relative RMSE")
     ap.add_argument("--set", action="append", default=[], metavar="KEY=JSON",
                     help="override a key of the strip workload definition (tuning runs; the line is then "
                          "not the default benchmark), e.g. --set angle_storage='\"cs\"'")
@@ -213,6 +223,79 @@ def serve_leg(pk, rates, duration, prec):
                        "p50_ms": round(s.p50_ms, 2), "p99_ms": round(s.p99_ms, 2),
                        "mean_batch": round(s.mean_batch, 2), "failed": s.failed,
                        "per_class": s.per_class} for r, s in zip(rates, stats)]}
+
+
+def plate_mlmc_leg(pk, torch, name, tau, precisions=("fp64", "mixed")):
+    """MLMC with selective refinement for the failure probability of a panel
+    workload to a relative tolerance, FP64 and mixed precision."""
+    from paper_1907_10271_amd.driver import run_plate_mlmc_sr
+    cfg = mi.load_config(name)
+    out = {"workload": name, "tau_rel": tau, "lambda_star": cfg["lambda_crit"]}
+    for label, prec in (("fp64", pk.FP64), ("mixed", pk.MIXED)):
+        if label not in precisions:
+            continue
+        ctx = pk.Context(mi.config_text(name))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = run_plate_mlmc_sr(ctx, cfg, tau_rel=tau, precision=prec,
+                                log=lambda m: print(f"plate mlmc {label}: {m}", file=sys.stderr, flush=True))
+        torch.cuda.synchronize()
+        d = res.as_dict()
+        out[label] = {"seconds": round(time.perf_counter() - t0, 2), "estimate": d["estimate"],
+                      "rmse": math.sqrt(d["sampling_err2"] + d["bias_estimate"] ** 2), "e_abs": d["e_abs"],
+                      "L": d["L"], "converged": d["converged"], "bias_estimate": d["bias_estimate"],
+                      "sampling_err2": d["sampling_err2"], "N": [lv["N"] for lv in d["levels"]],
+                      "solves_per_level": res.history[-1]["solves_per_level"]}
+        ctx.close()
+    return out
+
+
+def cosserat_leg(pk, torch, counts, eps_rel):
+    """The Cosserat Test I workload: one timed batch of coupled samples per level
+    (synthesis, PCG, QoI, both solves of a pair), and optionally Algorithm 1 to
+    a relative RMSE.  The bandwidth figure divides the algorithmic bytes of all
+    PCG iterations (117 B per unknown and iteration: 7 FP64 vectors and the
+    angle pairs of the operator pass, 7 of the vector pass) by the batch's wall
+    time, set-up and QoI included."""
+    name = "cosserat_t1"
+    cfg = mi.load_config(name)
+    ctx = pk.Context(mi.config_text(name))
+    out = {"workload": name, "per_level": []}
+    for l, n in enumerate(counts):
+        if n <= 0:
+            continue
+        xi = torch.from_numpy(mi.strip_xi(cfg, l, 0, n)).to("cuda")
+        reqs = [(k, l, l > 0) for k in range(n)]
+        ctx.reserve(l, n)
+        if l > 0:
+            ctx.reserve(l - 1, n)
+        ctx.solve_batch(reqs[:1], xi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        qf, qc, info = ctx.solve_batch(reqs, xi)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        nd = [ctx.level_info(k)["n_dofs"] for k in range(cfg["n_levels"])]
+        work = float(info["iters_f"].sum()) * nd[l] + (float(info["iters_c"].sum()) * nd[l - 1] if l > 0 else 0.0)
+        out["per_level"].append({"level": l, "mesh": f"{cfg['nx0'] << l}x{cfg['ny0'] << l}", "samples": n,
+                                 "coupled": l > 0, "ms": round(dt * 1e3, 3), "samples_per_s": round(n / dt, 1),
+                                 "pcg_iters_mean": round(float(info["iters_f"].mean()), 1),
+                                 "whole_solve_GBs": round(117.0 * work / dt / 1e9, 1),
+                                 "all_converged": bool(np.all(info["status_f"] == 0))})
+    if eps_rel > 0:
+        from paper_1907_10271_amd.driver import run_strip_mlmc
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = run_strip_mlmc(ctx, cfg, precision=pk.FP64, eps_rel=eps_rel,
+                             log=lambda m: print(f"cosserat mlmc: {m}", file=sys.stderr, flush=True))
+        torch.cuda.synchronize()
+        d = res.as_dict()
+        out["mlmc"] = {"eps_rel": eps_rel, "seconds": round(time.perf_counter() - t0, 2), "estimate": d["estimate"],
+                       "L": d["L"], "converged": d["converged"], "e_abs": d["e_abs"],
+                       "bias_estimate": d["bias_estimate"], "sampling_err2": d["sampling_err2"],
+                       "alpha": d.get("alpha"), "levels": d["levels"]}
+    ctx.close()
+    return out
 
 
 def tte_leg(pk, torch, name, eps_rel):
@@ -432,6 +515,12 @@ def main():
     del ctx
     if args.time_to_eps and not args.no_legs:
         out["time_to_eps"] = [tte_leg(pk, torch, args.tte_config, float(e)) for e in args.time_to_eps.split(",")]
+    if args.plate_mlmc > 0:
+        out["plate_mlmc"] = plate_mlmc_leg(pk, torch, args.plate_config, args.plate_mlmc,
+                                           args.plate_mlmc_precisions.split(","))
+    if args.cosserat or args.cosserat_eps > 0:
+        out["cosserat"] = cosserat_leg(pk, torch, [int(v) for v in args.cosserat.split(",")] if args.cosserat else [],
+                                       args.cosserat_eps)
     if args.serve and not args.no_legs:
         out["serving"] = serve_leg(pk, [float(v) for v in args.serve.split(",")], args.serve_duration, prec)
     if len(levels) != len(mix):

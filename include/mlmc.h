@@ -7,7 +7,9 @@
  *
  *   - KL synthesis of a random fibre-angle field (Section 3.1, Eq. inftyKL);
  *   - finite-element solves of an orthotropic strip with that field
- *     (Section 3.1, Eq. matrixinplane) and its quantity of interest;
+ *     (Section 3.1, Eq. matrixinplane) and its quantity of interest, for a
+ *     plane-stress strip (u, v per node) or the paper's Cosserat continuum
+ *     (u, v, theta_3 per node, strength from Eq. failureCriterion);
  *   - smallest buckling load of a laminated plate with random ply angles
  *     (Section 4.1, Eqs. CLTABD, MomentWeakForm, matrixeig);
  *   - FP64 level sums for the estimators of Section 2 (Eqs. MLMC_defn,
@@ -92,8 +94,8 @@ typedef struct {
 /* ---------------------------------------------------------------- lifecycle */
 
 /* Create a context on the current HIP device from a JSON workload definition
- * (strip or plate model, mesh hierarchy, material, covariance, solver
- * settings).  Builds the level hierarchy (Section 2.3: uniform refinement),
+ * ("kind": "strip", "cosserat" or "plate"; mesh hierarchy, material,
+ * covariance, solver settings).  Builds the level hierarchy (Section 2.3: uniform refinement),
  * the KL mode tables of every level (Section 3.1) and, for plates, the
  * laminate data (Section 4.1).  `mem_budget_bytes` bounds the workspaces the
  * context may allocate later (0 = 90% of free device memory).
@@ -129,6 +131,17 @@ int mlmc_footprint(const mlmc_ctx *ctx, int kind, int level, int precision, size
 int mlmc_reserve(mlmc_ctx *ctx, int level, int n, int precision);
 
 /* ----------------------------------------------------------- strip (Test I) */
+/* The strip calls below serve two models.  A "strip" context solves the
+ * plane-stress orthotropic strip: unknowns (u, v) per node.  A "cosserat"
+ * context solves the Cosserat continuum of Section 3.1 (Eqs. VarCosserat,
+ * matrixinplane): unknowns (u, v, theta_3) per node (n_dofs = 3 n_nodes), the
+ * fibre-frame matrices C (4 x 4 on the non-symmetric strains eps_11, eps_22,
+ * eps_12, eps_21) and D (2 x 2 on the curvatures) rotated by the angle field,
+ * u = 0 on x = 0, u = delta on x = L, v = 0 on y = 0 and y = L; its level l
+ * uses the first 50 + 50 l (configurable) KL terms of the parameter row; its
+ * quantity of interest is the compressive strength of Eq. failureCriterion;
+ * it is solved in FP64 only (MLMC_MIXED gives MLMC_EINVAL) and its fields
+ * are written in FP64 only. */
 
 /* KL synthesis (Eq. inftyKL truncated after the configured number of modes,
  * plus the optional wrinkle A sech^2((x - x0)/w)) at the 2x2 Gauss points of

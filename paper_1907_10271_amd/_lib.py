@@ -106,7 +106,8 @@ def with_tuning(cfg: dict) -> dict:
         return cfg
     with open(TUNING_PATH) as f:
         doc = json.load(f)
-    opts = {k: {"engine": v["engine"], "angles": v["angles"]} for k, v in doc.get("choices", {}).items()}
+    opts = {k: {"engine": v["engine"], "angles": v["angles"], "sweep_rows": int(v.get("sweep_rows", 0))}
+            for k, v in doc.get("choices", {}).items()}
     return dict(cfg, level_options=opts)
 
 

@@ -9,7 +9,11 @@ combination of
 * angle storage: ``theta`` (angle codes tan theta, cos/sin 2theta formed
   every iteration) or ``cs`` (stored cos/sin 2theta pairs, twice the bytes),
 
-on a batch of uncoupled samples sized to fill the GPU, and keeps the fastest.
+on a batch of uncoupled samples sized to fill the GPU, and keeps the fastest;
+for lock-step meshes it then times the operator pass's tile height (4, 8, 12
+or 16 node rows against the library's per-launch choice, which follows the
+number of waves in flight) and fixes a height only where one beats the
+per-launch choice by more than 1%.
 The result, keyed by mesh (``"NXxNY"``), is written as JSON; contexts created
 through the Python binding apply it as ``level_options`` unless the workload
 definition has its own.  Every choice is fixed per mesh, never per batch, so a
@@ -74,8 +78,28 @@ def tune(workloads, reps: int = 2, log=print) -> dict:
                     log(f"{key}: {engine}/{angles} {n} samples {best * 1e3:.2f} ms")
             pick = min(times, key=times.get)
             engine, angles = pick.split("/")
-            out[key] = {"engine": engine, "angles": angles, "batch": n, "ms": times}
-            log(f"{key}: chose {pick}")
+            rows, rows_ms = 0, {}
+            if engine == "lockstep":
+                for ty in (0, 4, 8, 12, 16):
+                    ctx = Context(dict(cfg, level_options={key: {"engine": engine, "angles": angles,
+                                                                 "sweep_rows": ty}}))
+                    ctx.solve_batch(reqs, xi)
+                    torch.cuda.synchronize()
+                    best = float("inf")
+                    for _ in range(reps):
+                        t0 = time.perf_counter()
+                        ctx.solve_batch(reqs, xi)
+                        torch.cuda.synchronize()
+                        best = min(best, time.perf_counter() - t0)
+                    ctx.close()
+                    rows_ms[ty] = round(best * 1e3, 3)
+                    log(f"{key}: tile height {ty or 'per launch'} {best * 1e3:.2f} ms")
+                fixed = min((t for t in rows_ms if t), key=rows_ms.get)
+                if rows_ms[fixed] < 0.99 * rows_ms[0]:
+                    rows = fixed
+            out[key] = {"engine": engine, "angles": angles, "batch": n, "ms": times, "sweep_rows": rows,
+                        "sweep_rows_ms": {str(t): v for t, v in rows_ms.items()}}
+            log(f"{key}: chose {pick}, tile height {rows or 'per launch'}")
     return out
 
 

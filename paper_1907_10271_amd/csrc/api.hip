@@ -54,6 +54,7 @@ struct StripLevel {
   StripPool pool;
   bool small = false;       // solved by the one-work-group-per-sample kernel
   bool cs = false;          // FP64 angle data stored as (cos 2theta, sin 2theta) pairs
+  int sweep_rows = 0;       // operator-pass tile height of this mesh (0: chosen per launch)
 };
 
 }  // namespace
@@ -526,7 +527,10 @@ int pcg_iterate(mlmc_ctx *c, const std::vector<IterGroup<T>> &grp, hipStream_t s
         if (!alive[k] || (grp[k].S.cs != 0) != (mode == 1)) continue;
         PcgGroup<T> &D = hg[ng++];
         D.g = c->lv[grp[k].level].g;
-        set_sweep_rows(D.g, ty);
+        // a height tuned for the mesh wins over the per-launch choice (the
+        // sums, hence the results, do not depend on it)
+        const int tyk = c->lv[grp[k].level].sweep_rows;
+        set_sweep_rows(D.g, tyk ? tyk : ty);
         D.S = grp[k].S;
         D.n = grp[k].n;
         D.blk0 = nb1m[mode];
@@ -842,6 +846,10 @@ int build_strip(mlmc_ctx *c) {
       if (an == "cs") L.cs = true;
       else if (an == "theta") L.cs = false;
       else if (!an.empty()) throw std::runtime_error("level_options angles must be cs or theta");
+      const int sr = (int)o.number_or("sweep_rows", 0);
+      if (sr < 0 || sr > SWEEP_MAXTY || sr % SWEEP_RB != 0)
+        throw std::runtime_error("level_options sweep_rows must be 0 (per launch), 4, 8, 12 or 16");
+      L.sweep_rows = sr;
     }
     if (sm == "off") L.small = false;   // an explicit "off" wins over per-level options
   }

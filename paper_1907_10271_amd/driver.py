@@ -286,7 +286,7 @@ class PlateSRSampler:
 
     def __init__(self, ctx, cfg: Dict, lam_star: float, precision: int = FP64, j_min: Optional[int] = None,
                  alpha: Optional[float] = None, m: Optional[float] = None, max_batch: int = 2048, k_biased: int = 1,
-                 stream_offset: int = 0):
+                 stream_offset: int = 0, log=None):
         import torch
         import mlmc_inputs as mi
         self.torch, self.mi, self.ctx, self.cfg = torch, mi, ctx, cfg
@@ -303,6 +303,7 @@ class PlateSRSampler:
         self._acc: Dict[int, IndicatorSums] = {}
         self.solves = np.zeros(cfg["n_levels"], dtype=np.int64)
         self.failures = 0
+        self.log = log
 
     def acc(self, level: int) -> IndicatorSums:
         return self._acc[level]
@@ -366,6 +367,9 @@ class PlateSRSampler:
             acc.seconds += dt
             self.next_row[level] = start + k
             done += k
+            if self.log:
+                self.log({"level": level, "batch": k, "done": done, "of": n, "seconds": round(dt, 3),
+                          "solves": self.solves.tolist()})
 
 
 def run_plate_mlmc_sr(ctx, cfg: Dict, lam_star: Optional[float] = None, tau_rel: Optional[float] = None,
@@ -377,7 +381,7 @@ def run_plate_mlmc_sr(ctx, cfg: Dict, lam_star: Optional[float] = None, tau_rel:
     lam_star = cfg["lambda_crit"] if lam_star is None else lam_star
     tau_rel = ml.get("tau_rel", 0.043) if tau_rel is None else tau_rel
     L_max = cfg["n_levels"] - 1 if L_max is None else L_max
-    sampler = PlateSRSampler(ctx, cfg, lam_star, precision=precision)
+    sampler = PlateSRSampler(ctx, cfg, lam_star, precision=precision, log=log)
     dofs = [ctx.level_info(l)["n_dofs"] for l in range(cfg["n_levels"])]
     res = adaptive_mlmc(sampler, L_max, eps_rel=tau_rel, theta=ml.get("theta", 0.5),
                         n_star=ml.get("n_star", 100) if n_star is None else n_star, m=cfg.get("sr", {}).get("m", 4),

@@ -445,6 +445,11 @@ def test_tile_height_follows_batch_without_changing_bits(precision):
         assert np.array_equal(qr.cpu().numpy(), qa), rows
         assert np.array_equal(ir["iters_f"], ia["iters_f"]), rows
         c.close()
+    # a height fixed per mesh (the autotuner's level option) changes no bit either
+    c = pk.Context(dict(mi.load_config(name), level_options={"512x128": {"sweep_rows": 12}}))
+    qr, _, _ = c.solve_batch(reqs, xi, precision=precision)
+    assert np.array_equal(qr.cpu().numpy(), qa)
+    c.close()
     for k in (0, n - 1):
         qs, _, is_ = ctx.solve_batch([(k, level, False)], xi, precision=precision)
         assert qs.cpu().numpy()[0] == qa[k], (k, qs.cpu().numpy()[0], qa[k])
