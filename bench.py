@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--cosserat", type=str, default="",
                     help="also time the Cosserat Test I workload: coupled samples per level, e.g. "
                          "2048,1024,512,128,32,8")
+    ap.add_argument("--cosserat-single", action="store_true",
+                    help="Cosserat leg: single solves on every level instead of coupled pairs (profiling)")
     ap.add_argument("--cosserat-eps", type=float, default=0.0,
                     help="also run adaptive MLMC (Algorithm 1) on the Cosserat workload to this relative RMSE")
     ap.add_argument("--set", action="append", default=[], metavar="KEY=JSON",
@@ -250,7 +252,7 @@ def plate_mlmc_leg(pk, torch, name, tau, precisions=("fp64", "mixed")):
     return out
 
 
-def cosserat_leg(pk, torch, counts, eps_rel):
+def cosserat_leg(pk, torch, counts, eps_rel, coupled=True):
     """The Cosserat Test I workload: one timed batch of coupled samples per level
     (synthesis, PCG, QoI, both solves of a pair), and optionally Algorithm 1 to
     a relative RMSE.  The bandwidth figure divides the algorithmic bytes of all
@@ -265,9 +267,10 @@ def cosserat_leg(pk, torch, counts, eps_rel):
         if n <= 0:
             continue
         xi = torch.from_numpy(mi.strip_xi(cfg, l, 0, n)).to("cuda")
-        reqs = [(k, l, l > 0) for k in range(n)]
+        pair = coupled and l > 0
+        reqs = [(k, l, pair) for k in range(n)]
         ctx.reserve(l, n)
-        if l > 0:
+        if pair:
             ctx.reserve(l - 1, n)
         ctx.solve_batch(reqs[:1], xi)
         torch.cuda.synchronize()
@@ -276,9 +279,9 @@ def cosserat_leg(pk, torch, counts, eps_rel):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         nd = [ctx.level_info(k)["n_dofs"] for k in range(cfg["n_levels"])]
-        work = float(info["iters_f"].sum()) * nd[l] + (float(info["iters_c"].sum()) * nd[l - 1] if l > 0 else 0.0)
+        work = float(info["iters_f"].sum()) * nd[l] + (float(info["iters_c"].sum()) * nd[l - 1] if pair else 0.0)
         out["per_level"].append({"level": l, "mesh": f"{cfg['nx0'] << l}x{cfg['ny0'] << l}", "samples": n,
-                                 "coupled": l > 0, "ms": round(dt * 1e3, 3), "samples_per_s": round(n / dt, 1),
+                                 "coupled": pair, "ms": round(dt * 1e3, 3), "samples_per_s": round(n / dt, 1),
                                  "pcg_iters_mean": round(float(info["iters_f"].mean()), 1),
                                  "whole_solve_GBs": round(117.0 * work / dt / 1e9, 1),
                                  "all_converged": bool(np.all(info["status_f"] == 0))})
@@ -520,7 +523,7 @@ def main():
                                            args.plate_mlmc_precisions.split(","))
     if args.cosserat or args.cosserat_eps > 0:
         out["cosserat"] = cosserat_leg(pk, torch, [int(v) for v in args.cosserat.split(",")] if args.cosserat else [],
-                                       args.cosserat_eps)
+                                       args.cosserat_eps, coupled=not args.cosserat_single)
     if args.serve and not args.no_legs:
         out["serving"] = serve_leg(pk, [float(v) for v in args.serve.split(",")], args.serve_duration, prec)
     if len(levels) != len(mix):

@@ -12,8 +12,8 @@ combination of
 on a batch of uncoupled samples sized to fill the GPU, and keeps the fastest;
 for lock-step meshes it then times the operator pass's tile height (4, 8, 12
 or 16 node rows against the library's per-launch choice, which follows the
-number of waves in flight) and fixes a height only where one beats the
-per-launch choice by more than 1%.
+number of waves in flight) on that batch and on one twice as large, and fixes
+a height only where one beats the per-launch choice by more than 1% on both.
 The result, keyed by mesh (``"NXxNY"``), is written as JSON; contexts created
 through the Python binding apply it as ``level_options`` unless the workload
 definition has its own.  Every choice is fixed per mesh, never per batch, so a
@@ -80,23 +80,28 @@ def tune(workloads, reps: int = 2, log=print) -> dict:
             engine, angles = pick.split("/")
             rows, rows_ms = 0, {}
             if engine == "lockstep":
-                for ty in (0, 4, 8, 12, 16):
-                    ctx = Context(dict(cfg, level_options={key: {"engine": engine, "angles": angles,
-                                                                 "sweep_rows": ty}}))
-                    ctx.solve_batch(reqs, xi)
-                    torch.cuda.synchronize()
-                    best = float("inf")
-                    for _ in range(reps):
-                        t0 = time.perf_counter()
-                        ctx.solve_batch(reqs, xi)
+                # two batch sizes: a height is fixed for the mesh only if it beats
+                # the per-launch choice (which follows the batch) at both
+                xi2 = torch.from_numpy(mi.strip_xi(cfg, level, 0, 2 * n)).to("cuda")
+                for nb, x in ((n, xi), (2 * n, xi2)):
+                    r2 = [(k, level, False) for k in range(nb)]
+                    for ty in (0, 4, 8, 12, 16):
+                        ctx = Context(dict(cfg, level_options={key: {"engine": engine, "angles": angles,
+                                                                     "sweep_rows": ty}}))
+                        ctx.solve_batch(r2, x)
                         torch.cuda.synchronize()
-                        best = min(best, time.perf_counter() - t0)
-                    ctx.close()
-                    rows_ms[ty] = round(best * 1e3, 3)
-                    log(f"{key}: tile height {ty or 'per launch'} {best * 1e3:.2f} ms")
-                fixed = min((t for t in rows_ms if t), key=rows_ms.get)
-                if rows_ms[fixed] < 0.99 * rows_ms[0]:
-                    rows = fixed
+                        best = float("inf")
+                        for _ in range(reps):
+                            t0 = time.perf_counter()
+                            ctx.solve_batch(r2, x)
+                            torch.cuda.synchronize()
+                            best = min(best, time.perf_counter() - t0)
+                        ctx.close()
+                        rows_ms.setdefault(ty, []).append(round(best * 1e3, 3))
+                        log(f"{key}: {nb} samples, tile height {ty or 'per launch'} {best * 1e3:.2f} ms")
+                wins = [t for t in rows_ms if t and all(a < 0.99 * b for a, b in zip(rows_ms[t], rows_ms[0]))]
+                if wins:
+                    rows = min(wins, key=lambda t: sum(rows_ms[t]))
             out[key] = {"engine": engine, "angles": angles, "batch": n, "ms": times, "sweep_rows": rows,
                         "sweep_rows_ms": {str(t): v for t, v in rows_ms.items()}}
             log(f"{key}: chose {pick}, tile height {rows or 'per launch'}")

@@ -282,10 +282,14 @@ class PlateSRSampler:
     """Samples of Y_l = 1(lam_l < lam*) - 1(lam_{l-1} < lam*) with selective
     refinement (Algorithm 2): the chain of each sample is solved level by level
     on the GPU (the surviving samples of a level form one batch), and both terms
-    come from the same chain, the second truncated at l - 1."""
+    come from the same chain, the second truncated at l - 1.  Batches are
+    large (``max_batch`` rows; the library splits each level's solves into
+    launches that fit its workspace), so that the few survivors that reach the
+    fine levels, whose solves take a work-group each for about a second, are
+    solved together rather than a handful per launch."""
 
     def __init__(self, ctx, cfg: Dict, lam_star: float, precision: int = FP64, j_min: Optional[int] = None,
-                 alpha: Optional[float] = None, m: Optional[float] = None, max_batch: int = 2048, k_biased: int = 1,
+                 alpha: Optional[float] = None, m: Optional[float] = None, max_batch: int = 65536, k_biased: int = 1,
                  stream_offset: int = 0, log=None):
         import torch
         import mlmc_inputs as mi
