@@ -228,6 +228,36 @@ __device__ void assemble_band(const PlateGeom &g, const double *Ke, B *band, int
   }
 }
 
+// A 4 x 4 tile of a trailing window (rows and columns R .. R + m - 1, tile at
+// offsets r0, c0; only entries with column <= row exist).  All sixteen entries
+// are loaded before the tile's product is formed, so their loads are in flight
+// together and overlap it, instead of one load-subtract-store round trip per
+// entry; entries outside the window read the window's first entry and are
+// never stored.
+template <typename B>
+__device__ __forceinline__ void tile_load(const B *band, int w, int R, int m, int r0, int c0, B (&v)[4][4]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int r = r0 + a, cc = c0 + c;
+      const bool in = r < m && cc <= r;
+      v[a][c] = band[(size_t)(R + (in ? r : 0)) * w + (in ? r - cc : 0)];
+    }
+}
+
+template <typename B>
+__device__ __forceinline__ void tile_store(B *band, int w, int R, int m, int r0, int c0, const B (&v)[4][4],
+                                           const B (&acc)[4][4]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int r = r0 + a, cc = c0 + c;
+      if (r < m && cc <= r) band[(size_t)(R + r) * w + (r - cc)] = v[a][c] - acc[a][c];
+    }
+}
+
 // Blocked right-looking banded Cholesky in place (band[r][d] = A[r][r - d]):
 // a panel of NBK columns is factored in LDS, then the trailing band window is
 // updated once by the rank-NBK product of the panel (4 x 4 register tiles per
@@ -285,7 +315,8 @@ __device__ bool band_cholesky(const PlateGeom &g, B *band, B *P /* LDS [(NBK + b
       while (ti * (ti + 1) / 2 > tix) --ti;
       const int tj = tix - ti * (ti + 1) / 2;
       const int r0 = 4 * ti, c0 = 4 * tj;  // offsets from R
-      B acc[4][4];
+      B v[4][4], acc[4][4];
+      tile_load(band, w, R, m, r0, c0, v);
       for (int a = 0; a < 4; ++a)
         for (int c = 0; c < 4; ++c) acc[a][c] = B(0);
       for (int j = 0; j < nb; ++j) {
@@ -298,11 +329,7 @@ __device__ bool band_cholesky(const PlateGeom &g, B *band, B *P /* LDS [(NBK + b
         for (int a = 0; a < 4; ++a)
           for (int c = 0; c < 4; ++c) acc[a][c] += pr[a] * pc[c];
       }
-      for (int a = 0; a < 4; ++a)
-        for (int c = 0; c < 4; ++c) {
-          const int r = r0 + a, cc = c0 + c;
-          if (r < m && cc <= r) band[(size_t)(R + r) * w + (r - cc)] -= acc[a][c];
-        }
+      tile_store(band, w, R, m, r0, c0, v, acc);
     }
   }
   __syncthreads();
@@ -937,7 +964,8 @@ __global__ __launch_bounds__(PT) void k_band_step(PlateGeom g, PlateWork W, int 
     const int tj = tix - ti * (ti + 1) / 2;
     if (tj < NBK / 4) continue;                 // columns of panel k0: work-group 0
     const int r0 = 4 * ti, c0 = 4 * tj;
-    B acc[4][4];
+    B v[4][4], acc[4][4];
+    tile_load(band, w, k0, m, r0, c0, v);
     for (int a = 0; a < 4; ++a)
       for (int c = 0; c < 4; ++c) acc[a][c] = B(0);
     for (int j = 0; j < NBK; ++j) {
@@ -949,11 +977,7 @@ __global__ __launch_bounds__(PT) void k_band_step(PlateGeom g, PlateWork W, int 
       for (int a = 0; a < 4; ++a)
         for (int c = 0; c < 4; ++c) acc[a][c] += pr[a] * pc[c];
     }
-    for (int a = 0; a < 4; ++a)
-      for (int c = 0; c < 4; ++c) {
-        const int r = r0 + a, cc = c0 + c;
-        if (r < m && cc <= r) band[(size_t)(k0 + r) * w + (r - cc)] -= acc[a][c];
-      }
+    tile_store(band, w, k0, m, r0, c0, v, acc);
   }
 }
 
