@@ -28,6 +28,11 @@ constexpr int NB = 2;        // LOBPCG block size
 constexpr int NS = 3 * NB;   // Rayleigh-Ritz basis size [X, W, P]
 constexpr int MAXPLY = 32;
 constexpr int MAXBW = 664;  // largest band half-width (128 x 128 mesh: 654)
+// bands narrower than this are factored and solved by one work-group per
+// sample (k_buckle); wider ones always take the wide form
+constexpr int ONE_MAXBW = 256;
+constexpr int RING_ONE = 512, RING_WIDE = 1024;  // band-solve window rows (>= bw + 3 x 32)
+static_assert(RING_ONE >= ONE_MAXBW + 96 && RING_WIDE >= MAXBW + 96, "band-solve windows");
 
 struct PlateGeom {
   int nx, ny, nnx, nny, nn, nfull, nfree, bw;
@@ -247,93 +252,222 @@ __device__ __forceinline__ void tile_load(const B *band, int w, int R, int m, in
 }
 
 template <typename B>
-__device__ __forceinline__ void tile_store(B *band, int w, int R, int m, int r0, int c0, const B (&v)[4][4],
-                                           const B (&acc)[4][4]) {
+__device__ __forceinline__ void tile_store(B *band, int w, int R, int m, int r0, int c0, const B (&v)[4][4]) {
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int r = r0 + a, cc = c0 + c;
-      if (r < m && cc <= r) band[(size_t)(R + r) * w + (r - cc)] = v[a][c] - acc[a][c];
+      if (r < m && cc <= r) band[(size_t)(R + r) * w + (r - cc)] = v[a][c];
     }
 }
 
-// Blocked right-looking banded Cholesky in place (band[r][d] = A[r][r - d]):
-// a panel of NBK columns is factored in LDS, then the trailing band window is
-// updated once by the rank-NBK product of the panel (4 x 4 register tiles per
-// thread).  On return band[k][0] = L_kk and band[k + d][d] = L_{k+d,k}.
-constexpr int NBK = 8;
+// Blocked right-looking banded Cholesky in place (band[r][d] = A[r][r - d]).
+// On return band[k][0] = L_kk and band[k + d][d] = L_{k+d,k}.  A pass takes a
+// panel of KP = 2 NBK columns in two sub-panels of NBK: the first is factored,
+// its product subtracted from the second's columns, the second factored, and
+// the trailing band window then updated by both (4 x 4 register tiles per
+// thread: the first sub-panel's NBK-term sum subtracted, then the second's).
+// Every entry receives the operations of the NBK-column form in the same
+// order, so the factor is bit-identical to the wide form's (k_band_step), while
+// the trailing window, which does not fit on chip and bounds the pass, is read
+// and written once per 2 NBK columns.  A sub-panel's top NBK x NBK block is
+// factored by one thread in registers and each row below by its own thread
+// (forward substitution with the block's factor).  The panel's rows and the
+// window's tiles are final once the previous pass's stores are done (a
+// work-group barrier), so a pass requests all of them first: the tile entries
+// arrive while the panel is factored.
+constexpr int NBK = 8, KP = 2 * NBK;
+constexpr int LDP = KP + ONE_MAXBW, LDPW = NBK + MAXBW;  // LDS panels (column-major): one-work-group and wide form
+constexpr int TQ = 2;  // trailing tiles per thread in flight (the first TQ issued with the panel's loads)
+static_assert(KP + ONE_MAXBW <= 2 * PT, "panel rows: at most two per thread");
+
+// factors the nbs x nbs block of P at rows and columns c0 .. c0 + nbs - 1 (one
+// thread, unblocked order); false at a non-positive pivot
+template <typename B>
+__device__ bool factor_top(B *P, int c0, int nbs) {
+  B a[NBK][NBK];
+#pragma unroll
+  for (int i = 0; i < NBK; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) a[i][j] = (i < nbs) ? P[(c0 + j) * LDP + c0 + i] : B(0);
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < NBK; ++j) {
+    if (j < nbs && ok) {
+      if (!(a[j][j] > B(0))) {
+        ok = false;
+      } else {
+        const B piv = sqrt(a[j][j]);
+        a[j][j] = piv;
+#pragma unroll
+        for (int i = j + 1; i < NBK; ++i)
+          if (i < nbs) a[i][j] = a[i][j] / piv;
+#pragma unroll
+        for (int jj = j + 1; jj < NBK; ++jj)
+#pragma unroll
+          for (int i = jj; i < NBK; ++i)
+            if (i < nbs) a[i][jj] -= a[i][j] * a[jj][j];
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NBK; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j)
+      if (i < nbs) P[(c0 + j) * LDP + c0 + i] = a[i][j];
+  return ok;
+}
+
+// rows i0 .. rows - 1 of sub-panel columns c0 .. c0 + nbs - 1: forward
+// substitution with the factored top block, one thread per row
+template <typename B>
+__device__ void factor_rows(B *P, int c0, int nbs, int i0, int rows) {
+  for (int i = i0 + threadIdx.x; i < rows; i += PT) {
+    B x[NBK];
+#pragma unroll
+    for (int j = 0; j < NBK; ++j) x[j] = P[(c0 + j) * LDP + i];
+#pragma unroll
+    for (int j = 0; j < NBK; ++j) {
+      if (j < nbs) {
+        x[j] = x[j] / P[(c0 + j) * LDP + c0 + j];
+#pragma unroll
+        for (int jj = j + 1; jj < NBK; ++jj)
+          if (jj < nbs) x[jj] -= x[j] * P[(c0 + j) * LDP + c0 + jj];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NBK; ++j)
+      if (j < nbs) P[(c0 + j) * LDP + i] = x[j];
+  }
+}
 
 template <typename B>
-__device__ bool band_cholesky(const PlateGeom &g, B *band, B *P /* LDS [(NBK + bw) * NBK] */) {
+__device__ __forceinline__ bool band_cholesky(const PlateGeom &g, B *band, B *P /* LDS [KP * LDP] */) {
   const int w = g.bw + 1, n = g.nfree;
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
-  for (int k0 = 0; k0 < n; k0 += NBK) {
-    const int nb = min(NBK, n - k0);
-    const int rows = min(nb + g.bw, n - k0);  // panel rows k0 .. k0 + rows - 1
-    __syncthreads();
-    for (int i = threadIdx.x; i < rows; i += PT) {  // a row's entries at once (see k_band_step)
+  auto tile_of = [](int tix, int &r0, int &c0) {
+    int ti = (int)((sqrt(8.0 * tix + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= tix) ++ti;
+    while (ti * (ti + 1) / 2 > tix) --ti;
+    r0 = 4 * ti;
+    c0 = 4 * (tix - ti * (ti + 1) / 2);
+  };
+  for (int k0 = 0; k0 < n; k0 += KP) {
+    const int nbA = min(NBK, n - k0), nbB = max(0, min(NBK, n - k0 - NBK)), nb = nbA + nbB;
+    const int rows = min(nb + g.bw, n - k0);      // panel rows k0 .. k0 + rows - 1
+    const int R = k0 + nb, m = min(g.bw, n - R);  // trailing window rows/columns R .. R + m - 1
+    const int mt = (m + 3) / 4, ntile = m > 0 ? mt * (mt + 1) / 2 : 0;
+    __syncthreads();  // the previous pass's stores are done and P is free
+    // ---- loads: the panel's rows (one thread per band row: a row's entries are
+    // contiguous) and the first TQ of this thread's trailing tiles
+    auto row_load = [&](int i, B (&pe)[KP]) {
       const B *row = band + (size_t)(k0 + i) * w;
-      B e[NBK];
 #pragma unroll
-      for (int j = 0; j < NBK; ++j) e[j] = row[min(max(i - j, 0), g.bw)];
+      for (int j = 0; j < KP; ++j) pe[j] = row[min(max(i - j, 0), g.bw)];
+    };
+    auto row_stage = [&](int i, const B (&pe)[KP]) {
 #pragma unroll
-      for (int j = 0; j < NBK; ++j) P[i * NBK + j] = (j < nb && i >= j && i - j <= g.bw) ? e[j] : B(0);
+      for (int j = 0; j < KP; ++j) P[j * LDP + i] = (j < nb && i >= j && i - j <= g.bw) ? pe[j] : B(0);
+    };
+    B pe[KP];
+    if ((int)threadIdx.x < rows) row_load(threadIdx.x, pe);
+    B tv[TQ][4][4];
+#pragma unroll
+    for (int q = 0; q < TQ; ++q) {
+      const int tix = threadIdx.x + q * PT;
+      if (tix < ntile) {
+        int r0, c0;
+        tile_of(tix, r0, c0);
+        tile_load(band, w, R, m, r0, c0, tv[q]);
+      }
     }
-    // panel factorisation (unblocked, in LDS)
-    for (int j = 0; j < nb; ++j) {
-      __syncthreads();
-      const B piv2 = P[j * NBK + j];
-      if (!(piv2 > B(0))) {
-        if (threadIdx.x == 0) bad = 1;
-        __syncthreads();
-        return false;
-      }
-      const B piv = sqrt(piv2);
-      __syncthreads();
-      for (int i = j + threadIdx.x; i < rows; i += PT) P[i * NBK + j] = (i == j) ? piv : P[i * NBK + j] / piv;
-      __syncthreads();
-      const int ncols = nb - 1 - j;
-      for (int idx = threadIdx.x; idx < (rows - j - 1) * ncols; idx += PT) {
-        const int i = j + 1 + idx / ncols, jj = j + 1 + idx % ncols;
-        if (i >= jj) P[i * NBK + jj] -= P[i * NBK + j] * P[jj * NBK + j];
-      }
+    if ((int)threadIdx.x < rows) row_stage(threadIdx.x, pe);
+    if ((int)threadIdx.x + PT < rows) {  // panels of more than PT rows
+      row_load(threadIdx.x + PT, pe);
+      row_stage(threadIdx.x + PT, pe);
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < rows * NBK; idx += PT) {
-      const int i = idx / NBK, j = idx % NBK;
-      if (j < nb && i >= j && i - j <= g.bw) band[(size_t)(k0 + i) * w + (i - j)] = P[idx];
+    // ---- sub-panel A (columns 0 .. nbA - 1)
+    if (threadIdx.x == 0 && !factor_top(P, 0, nbA)) bad = 1;
+    __syncthreads();
+    if (bad) return false;
+    factor_rows(P, 0, nbA, nbA, rows);
+    __syncthreads();
+    if (nbB > 0) {
+      // sub-panel A's product subtracted from sub-panel B's columns (rows NBK
+      // on): the NBK-term sum of the NBK-column form's trailing update
+      for (int i = NBK + threadIdx.x; i < rows; i += PT) {
+        B x[NBK];
+#pragma unroll
+        for (int j = 0; j < NBK; ++j) x[j] = P[j * LDP + i];
+#pragma unroll
+        for (int jb = NBK; jb < KP; ++jb) {
+          if (jb < nb && jb <= i) {
+            B acc = B(0);
+#pragma unroll
+            for (int j = 0; j < NBK; ++j) acc += x[j] * P[j * LDP + jb];
+            P[jb * LDP + i] -= acc;
+          }
+        }
+      }
+      __syncthreads();
+      // ---- sub-panel B (columns NBK .. nb - 1)
+      if (threadIdx.x == 0 && !factor_top(P, NBK, nbB)) bad = 1;
+      __syncthreads();
+      if (bad) return false;
+      factor_rows(P, NBK, nbB, nb, rows);
+      __syncthreads();
     }
-    // trailing update of rows/columns R .. R + m - 1 (all inside the band)
-    const int R = k0 + nb, m = min(g.bw, n - R);
-    if (m <= 0) continue;
-    const int mt = (m + 3) / 4, ntile = mt * (mt + 1) / 2;
-    for (int tix = threadIdx.x; tix < ntile; tix += PT) {
-      int ti = (int)((sqrt(8.0 * tix + 1.0) - 1.0) * 0.5);
-      while ((ti + 1) * (ti + 2) / 2 <= tix) ++ti;
-      while (ti * (ti + 1) / 2 > tix) --ti;
-      const int tj = tix - ti * (ti + 1) / 2;
-      const int r0 = 4 * ti, c0 = 4 * tj;  // offsets from R
-      B v[4][4], acc[4][4];
-      tile_load(band, w, R, m, r0, c0, v);
-      for (int a = 0; a < 4; ++a)
-        for (int c = 0; c < 4; ++c) acc[a][c] = B(0);
-      for (int j = 0; j < nb; ++j) {
-        B pr[4], pc[4];
-        for (int a = 0; a < 4; ++a) {
-          const int ir = nb + r0 + a, ic = nb + c0 + a;
-          pr[a] = (r0 + a < m) ? P[ir * NBK + j] : B(0);
-          pc[a] = (c0 + a < m) ? P[ic * NBK + j] : B(0);
+    for (int idx = threadIdx.x; idx < rows * KP; idx += PT) {
+      const int i = idx / KP, j = idx % KP;
+      if (j < nb && i >= j && i - j <= g.bw) band[(size_t)(k0 + i) * w + (i - j)] = P[j * LDP + i];
+    }
+    // ---- trailing update of the window by both sub-panels (all inside the band)
+    auto tile_update = [&](int r0, int c0, B (&v)[4][4]) {
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const int j0 = half * NBK, j1 = half ? nb : nbA;
+        if (j0 >= j1) break;
+        B acc[4][4];
+        for (int a = 0; a < 4; ++a)
+          for (int c = 0; c < 4; ++c) acc[a][c] = B(0);
+        for (int j = j0; j < j1; ++j) {
+          B pr[4], pc[4];
+          for (int a = 0; a < 4; ++a) {
+            const int ir = nb + r0 + a, ic = nb + c0 + a;
+            pr[a] = (r0 + a < m) ? P[j * LDP + ir] : B(0);
+            pc[a] = (c0 + a < m) ? P[j * LDP + ic] : B(0);
+          }
+          for (int a = 0; a < 4; ++a)
+            for (int c = 0; c < 4; ++c) acc[a][c] += pr[a] * pc[c];
         }
         for (int a = 0; a < 4; ++a)
-          for (int c = 0; c < 4; ++c) acc[a][c] += pr[a] * pc[c];
+          for (int c = 0; c < 4; ++c) v[a][c] -= acc[a][c];
       }
-      tile_store(band, w, R, m, r0, c0, v, acc);
+      tile_store(band, w, R, m, r0, c0, v);
+    };
+    // tiles q, q + 1 from tv[0], tv[1]; after each, the loads of the tile TQ on
+    for (int q = 0; threadIdx.x + q * PT < ntile; q += TQ) {
+#pragma unroll
+      for (int u = 0; u < TQ; ++u) {
+        const int tix = threadIdx.x + (q + u) * PT;
+        if (tix < ntile) {
+          int r0, c0;
+          tile_of(tix, r0, c0);
+          tile_update(r0, c0, tv[u]);
+          const int tnx = tix + TQ * PT;
+          if (tnx < ntile) {
+            tile_of(tnx, r0, c0);
+            tile_load(band, w, R, m, r0, c0, tv[u]);
+          }
+        }
+      }
     }
   }
   __syncthreads();
-  return bad == 0;
+  return true;
 }
 
 // value of lane `l` (uniform) to every lane
@@ -346,129 +480,217 @@ __device__ __forceinline__ float lane_value(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-// z = (L L^T)^-1 r for NB right-hand sides, in steps of PS rows: one wave
-// solves the step's diagonal triangle (lane = right-hand side x row, the
-// solved value passed by lane reads), then all threads apply the band part
-// of the step's columns.  Fewer, larger steps: the solve is a chain of
-// n / PS dependent steps, each about one memory round trip long.
+// ---- diagonal-block inverses
+// A band-solve step needs the inverse of one PS x PS diagonal block of L.
+// After the factorisation each such block (rows and columns k0 .. k0 + PS - 1,
+// k0 a multiple of PS) is replaced in the band by its inverse X, lower
+// triangular with the same positions, so that a solve step applies a
+// matrix-vector product instead of a chain of PS dependent substitutions.
+// Only the solve reads these positions.
 constexpr int PS = 32;
-static_assert(NB * PS == 64, "one lane per right-hand side and row of a step");
+static_assert(NB * PS == 64, "one lane per right-hand side and row of a solve step");
+
+// Inverts the diagonal blocks blk0 .. blk0 + nstage - 1 that exist, one per
+// half-wave and without work-group barriers: the block is staged in Ls (nstage
+// PS x PS entries of LDS), inverted in place column by column from the last
+// (lane i forms X_ij = -X_jj sum_{j<k<=i} X_ik L_kj, the columns right of j
+// already holding X and column j still holding L), and written back.
 template <typename B>
+__device__ void invert_blocks(B *band, int w, int n, int blk0, int nstage, B *Ls) {
+  const int h = threadIdx.x / PS, i = threadIdx.x % PS;
+  const int k0 = (blk0 + h) * PS;
+  if (h >= nstage || k0 >= n) return;
+  const int nb = min(PS, n - k0);
+  B *L = Ls + h * PS * PS;
+  for (int rr = 0; rr < nb; ++rr)  // row rr of the block, lane i its column i (contiguous in the band)
+    if (i <= rr) L[rr * PS + i] = band[(size_t)(k0 + rr) * w + (rr - i)];
+  for (int j = nb - 1; j >= 0; --j) {
+    const B xjj = B(1) / L[j * PS + j];
+    B acc = B(0);
+    if (i > j && i < nb)
+      for (int k = j + 1; k <= i; ++k) acc += L[i * PS + k] * L[k * PS + j];
+    // every lane of the half-wave has read column j (one wave, in order)
+    if (i > j && i < nb) L[i * PS + j] = -acc * xjj;
+    if (i == j) L[j * PS + j] = xjj;
+  }
+  for (int rr = 0; rr < nb; ++rr)
+    if (i <= rr) band[(size_t)(k0 + rr) * w + (rr - i)] = L[rr * PS + i];
+}
+
+// z = (L L^T)^-1 r for NB right-hand sides, in steps of PS rows, with the
+// diagonal blocks of the band holding their inverses X.  The solved rows a
+// step needs (fewer than bw + 3 PS) live in an LDS window of RING rows.
+// Forward step (rows k0 .. k0 + PS - 1): t_i = r_i - sum_c L_ic y_c over the
+// band columns c < k0, each row's entries read by 8 lanes in contiguous runs
+// (its band row is contiguous), the partial sums combined by lane shuffles;
+// then y = X t, one wave (lane = right-hand side x row).  The band entries of
+// the next step are requested as soon as this step's are used, so they arrive
+// during its reductions and barriers.  Backward step: z = X^T t, then each
+// thread subtracts L_jc z_j from its rows c < k0 of the window (one column c
+// per thread: neighbouring threads read neighbouring band entries).
+template <typename B, int RING, int MAXB>
 __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, double *z, int ld, B *tmp) {
-  const int w = g.bw + 1, n = g.nfree;
-  __shared__ B Lb[PS * PS], yb[NB * PS];
-  for (int v = 0; v < NB; ++v)
-    for (int i = threadIdx.x; i < n; i += PT) tmp[(size_t)v * n + i] = (B)r[(size_t)v * ld + i];
-  // stage the step's diagonal triangle, Lb[i PS + j] = L(k0 + i, k0 + j), j <= i
-  auto stage = [&](int k0, int nb) {
+  static_assert((RING & (RING - 1)) == 0 && RING >= MAXB + 3 * PS, "window rows: a power of two >= bw + 3 PS");
+  constexpr int CH = 32;  // band entries per lane and chunk: a chunk covers 8 CH columns of a row
+  constexpr int MAXCHUNK = (MAXB + 8 * CH - 1) / (8 * CH);  // chunks of the widest band (bw <= MAXB)
+  const int w = g.bw + 1, n = g.nfree, bw = g.bw;
+  __shared__ B ring[NB * RING], Lb[PS * PS], tb[NB * PS];
+  auto win = [&](int v, int row) -> B & { return ring[v * RING + (row & (RING - 1))]; };
+  const int v2 = threadIdx.x / PS, i2 = threadIdx.x % PS;  // mat-vec lanes (wave 0)
+  const int fi = threadIdx.x / 8, fq = threadIdx.x % 8;     // forward: row fi of the step, part fq
+  B e[PS * PS / PT];
+  auto x_load = [&](int k0) {  // X of the step at k0: Lb[i PS + j] = X_ij (j <= i < nb), identity past the end
+    const int nb = min(PS, n - k0);
 #pragma unroll
-    for (int idx = threadIdx.x; idx < PS * PS; idx += PT) {
-      const int i = idx / PS, j = idx % PS;
-      Lb[idx] = (i < nb && j <= i) ? band[(size_t)(k0 + i) * w + (i - j)] : B(i == j ? 1 : 0);
-    }
-    for (int idx = threadIdx.x; idx < NB * PS; idx += PT) {
-      const int v = idx / PS, i = idx % PS;
-      yb[idx] = (i < nb) ? tmp[(size_t)v * n + k0 + i] : B(0);
+    for (int u = 0; u < PS * PS / PT; ++u) {
+      const int idx = threadIdx.x + u * PT, i = idx / PS, j = idx % PS;
+      const int ii = min(i, nb - 1);
+      const B v = band[(size_t)(k0 + ii) * w + max(ii - j, 0)];
+      e[u] = (i < nb && j <= i) ? v : B(i == j ? 1 : 0);
     }
   };
-  // forward: L y = r
+  auto x_store = [&]() {
+#pragma unroll
+    for (int u = 0; u < PS * PS / PT; ++u) Lb[threadIdx.x + u * PT] = e[u];
+  };
+  // chunk c of row fi's band entries left of the step: column k0 + fi - d, d = fi + 1 + fq + 8 u + 8 CH c
+  // (entries past the row's band are not loaded and not used)
+  auto row_load = [&](int k0, int c, B (&l)[CH]) {
+    const int nb = min(PS, n - k0), d0 = fi + 1 + fq + 8 * CH * c;
+    const B *p = band + (size_t)(k0 + min(fi, nb - 1)) * w + d0;
+#pragma unroll
+    for (int u = 0; u < CH; ++u)
+      if (8 * u <= bw - d0) l[u] = p[8 * u];
+  };
+  auto row_dot = [&](int k0, int c, const B (&l)[CH], B (&acc)[NB]) {
+    const int nb = min(PS, n - k0), d0 = fi + 1 + fq + 8 * CH * c;
+    const int col0 = k0 + fi - d0;                            // column of u = 0
+    const int lim = fi < nb ? min(bw - d0, col0) : -1;        // u is used while 8 u <= lim
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const bool ok = 8 * u <= lim;
+      const int idx = (col0 - 8 * u) & (RING - 1);
+      for (int v = 0; v < NB; ++v) acc[v] += ok ? l[u] * ring[v * RING + idx] : B(0);
+    }
+  };
+  const int nchunk = (bw + 8 * CH - 1) / (8 * CH);
+  // ---- forward: L y = r
+  B l[CH];
+  double rv[NB];
+  row_load(0, 0, l);
+  if (fq == 0 && fi < min(PS, n))
+    for (int v = 0; v < NB; ++v) rv[v] = r[(size_t)v * ld + fi];
+  x_load(0);
+  x_store();
   for (int k0 = 0; k0 < n; k0 += PS) {
     const int nb = min(PS, n - k0);
-    __syncthreads();
-    stage(k0, nb);
-    __syncthreads();
+    const bool next = k0 + PS < n;
+    B acc[NB];
+    for (int v = 0; v < NB; ++v) acc[v] = B(0);
+    row_dot(k0, 0, l, acc);
+    for (int c = 1; c < min(nchunk, MAXCHUNK); ++c) {  // bands wider than 8 CH: further chunks loaded here
+      B lc[CH];
+      row_load(k0, c, lc);
+      row_dot(k0, c, lc, acc);
+    }
+    double rc[NB];
+    for (int v = 0; v < NB; ++v) rc[v] = rv[v];
+    if (next) {
+      // the next step's entries, in flight during this step's reductions and
+      // barriers; X first, since its wait at the end of this step covers all
+      // loads issued before it
+      x_load(k0 + PS);
+      if (fq == 0 && fi < min(PS, n - k0 - PS))
+        for (int v = 0; v < NB; ++v) rv[v] = r[(size_t)v * ld + k0 + PS + fi];
+      row_load(k0 + PS, 0, l);
+    }
+    for (int v = 0; v < NB; ++v) {
+      acc[v] += __shfl_xor(acc[v], 1, 8);
+      acc[v] += __shfl_xor(acc[v], 2, 8);
+      acc[v] += __shfl_xor(acc[v], 4, 8);
+    }
+    if (fq == 0 && fi < nb)
+      for (int v = 0; v < NB; ++v) tb[v * PS + fi] = (B)rc[v] - acc[v];
+    __syncthreads();  // tb holds t, Lb holds X
     if (threadIdx.x < 64) {
-      const int v = threadIdx.x / PS, i = threadIdx.x % PS;
-      B y = yb[v * PS + i];
-      const B dinv = B(1) / Lb[i * PS + i];
-      for (int j = 0; j < nb; ++j) {
-        if (i == j) y *= dinv;
-        const B y0 = lane_value(y, j), y1 = lane_value(y, PS + j);
-        if (i > j) y -= Lb[i * PS + j] * (v ? y1 : y0);
+      B y = B(0);
+      for (int j = 0; j < nb; ++j) y += Lb[i2 * PS + j] * tb[v2 * PS + j];
+      if (i2 < nb) {
+        win(v2, k0 + i2) = y;
+        tmp[(size_t)v2 * n + k0 + i2] = y;
       }
-      yb[v * PS + i] = y;
     }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < NB * nb; idx += PT) {
-      const int v = idx / nb, j = idx % nb;
-      tmp[(size_t)v * n + k0 + j] = yb[v * PS + j];
-    }
-    // the step's PS columns of row rr: row rr's entries for columns k0 + j sit
-    // at p[-j], contiguous; away from the band's end all PS loads are issued
-    // at once from one address
-    const int hi = min(n, k0 + nb + g.bw);
-    for (int rr = k0 + nb + threadIdx.x; rr < hi; rr += PT) {
-      const int d0 = rr - k0;
-      const B *p = band + (size_t)rr * w + d0;
-      B acc[NB];
-      for (int v = 0; v < NB; ++v) acc[v] = B(0);
-      if (nb == PS && d0 <= g.bw) {
-#pragma unroll
-        for (int j16 = 0; j16 < PS; j16 += 16) {
-          B l[16];
-#pragma unroll
-          for (int j = 0; j < 16; ++j) l[j] = p[-(j16 + j)];
-#pragma unroll
-          for (int j = 0; j < 16; ++j)
-            for (int v = 0; v < NB; ++v) acc[v] += l[j] * yb[v * PS + j16 + j];
-        }
-      } else {
-        for (int j = max(0, d0 - g.bw); j < nb; ++j)
-          for (int v = 0; v < NB; ++v) acc[v] += p[-j] * yb[v * PS + j];
-      }
-      for (int v = 0; v < NB; ++v) tmp[(size_t)v * n + rr] -= acc[v];
-    }
+    __syncthreads();  // y of the step in the window; Lb free
+    if (next) x_store();
   }
-  // backward: L^T z = y
+  // ---- backward: L^T z = y.  At the start of step k0 the window holds rows
+  // k0 - PS - bw .. k0 + nb - 1 (y less the later steps' updates).  A step's
+  // column entries and entering rows are requested at the end of the step
+  // before, after the next X (whose wait covers the loads issued before it).
   const int last = ((n - 1) / PS) * PS;
+  for (int i = max(0, last - PS - bw) + threadIdx.x; i < n; i += PT)
+    for (int v = 0; v < NB; ++v) win(v, i) = tmp[(size_t)v * n + i];
+  x_load(last);
+  x_store();
+  // column c of step k0: L(k0 + j, c) = band[(k0 + j) w + k0 + j - c], for k0 + j - c <= bw
+  // (entries outside the band are not loaded and not used)
+  auto col_load = [&](int k0, int c, B (&lv)[PS]) {
+    const int nb = min(PS, n - k0);
+    const B *p = band + (size_t)k0 * w + (k0 - c);  // p[j (w + 1)] = L(k0 + j, c)
+#pragma unroll
+    for (int j = 0; j < PS; ++j)
+      if (j < nb && k0 + j - c <= bw) lv[j] = p[(size_t)j * (w + 1)];
+  };
+  B l0[PS], yin[NB];
+  if (last - 1 - (int)threadIdx.x >= max(0, last - bw)) col_load(last, last - 1 - threadIdx.x, l0);
+  if (threadIdx.x < PS && last - 2 * PS - bw + (int)threadIdx.x >= 0)
+    for (int v = 0; v < NB; ++v) yin[v] = tmp[(size_t)v * n + last - 2 * PS - bw + threadIdx.x];
   for (int k0 = last; k0 >= 0; k0 -= PS) {
     const int nb = min(PS, n - k0);
-    __syncthreads();
-    stage(k0, nb);
-    __syncthreads();
+    const bool next = k0 > 0;
+    const int lo = max(0, k0 - bw), c0 = k0 - 1 - threadIdx.x;
+    const int ent = k0 - 2 * PS - bw + threadIdx.x;  // row entering the window (threads < PS)
+    __syncthreads();  // rows k0 .. k0 + nb - 1 of the window are final, Lb holds X
     if (threadIdx.x < 64) {
-      const int v = threadIdx.x / PS, i = threadIdx.x % PS;
-      B y = yb[v * PS + i];
-      const B dinv = B(1) / Lb[i * PS + i];
-      for (int j = nb - 1; j >= 0; --j) {
-        if (i == j) y *= dinv;
-        const B y0 = lane_value(y, j), y1 = lane_value(y, PS + j);
-        if (i < j) y -= Lb[j * PS + i] * (v ? y1 : y0);
+      B y = B(0);
+      for (int j = 0; j < nb; ++j) y += Lb[j * PS + i2] * win(v2, k0 + j);
+      if (i2 < nb) {
+        win(v2, k0 + i2) = y;  // every lane has read the window rows (one wave)
+        z[(size_t)v2 * ld + k0 + i2] = (double)y;
       }
-      yb[v * PS + i] = y;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < NB * nb; idx += PT) {
-      const int v = idx / nb, j = idx % nb;
-      tmp[(size_t)v * n + k0 + j] = yb[v * PS + j];
-    }
-    // column c's entries in rows k0 + j sit at p[j (w + 1)]; loads in groups of 8
-    const int lo = max(0, k0 - g.bw);
-    for (int c = lo + threadIdx.x; c < k0; c += PT) {
-      const B *p = band + (size_t)k0 * w + (k0 - c);
+    if (next) x_load(k0 - PS);
+    auto col_update = [&](int c, const B (&lv)[PS]) {
       B acc[NB];
       for (int v = 0; v < NB; ++v) acc[v] = B(0);
-      if (nb == PS && k0 + PS - 1 - c <= g.bw) {
 #pragma unroll
-        for (int j8 = 0; j8 < PS; j8 += 8) {
-          B l[8];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) l[j] = p[(size_t)(j8 + j) * (w + 1)];
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            for (int v = 0; v < NB; ++v) acc[v] += l[j] * yb[v * PS + j8 + j];
+      for (int j = 0; j < PS; ++j) {
+        if (j < nb) {
+          const B lj = (k0 + j - c <= bw) ? lv[j] : B(0);
+          for (int v = 0; v < NB; ++v) acc[v] += lj * win(v, k0 + j);
         }
-      } else {
-        const int j1 = min(nb, c + g.bw + 1 - k0);  // rows within the band of column c
-        for (int j = 0; j < j1; ++j)
-          for (int v = 0; v < NB; ++v) acc[v] += p[(size_t)j * (w + 1)] * yb[v * PS + j];
       }
-      for (int v = 0; v < NB; ++v) tmp[(size_t)v * n + c] -= acc[v];
+      for (int v = 0; v < NB; ++v) win(v, c) -= acc[v];
+    };
+    if (c0 >= lo) col_update(c0, l0);
+    if constexpr (MAXB >= PT) {  // bands at least as wide as the work-group: further columns
+      for (int c = c0 - PT; c >= lo; c -= PT) {
+        B lv[PS];
+        col_load(k0, c, lv);
+        col_update(c, lv);
+      }
+    }
+    if (threadIdx.x < PS && ent >= 0)
+      for (int v = 0; v < NB; ++v) win(v, ent) = yin[v];
+    if (next) {
+      const int kn = k0 - PS, cn = kn - 1 - threadIdx.x, en = kn - 2 * PS - bw + threadIdx.x;
+      if (cn >= max(0, kn - bw)) col_load(kn, cn, l0);
+      if (threadIdx.x < PS && en >= 0)
+        for (int v = 0; v < NB; ++v) yin[v] = tmp[(size_t)v * n + en];
+      x_store();
     }
   }
-  __syncthreads();
-  for (int v = 0; v < NB; ++v)
-    for (int i = threadIdx.x; i < n; i += PT) z[(size_t)v * ld + i] = (double)tmp[(size_t)v * n + i];
   __syncthreads();
 }
 
@@ -512,14 +734,18 @@ __device__ void jacobi_small(double *A, double *V, int m) {
 
 // Rayleigh-Ritz on span(S) (m columns): largest NB eigenpairs of GA c = mu GB c.
 // GB = R^T R (Cholesky), C = R^-T GA R^-1.  Returns the usable basis size
-// (columns whose Cholesky pivot is too small are dropped: m_used <= m).
-__device__ int rayleigh_ritz(const double *GA, const double *GB, int m, double *coef /*m x NB*/, double *mu) {
-  double R[NS * NS], Ri[NS * NS], C[NS * NS], V[NS * NS];
-  int keep[NS], mk = 0;
+// (columns whose Cholesky pivot is too small are dropped: m_used <= m).  One
+// thread; its small matrices live in LDS (wk: RR_WORK doubles, iwk: 2 NS
+// ints), where indexed accesses cost an LDS round trip rather than the
+// private-memory round trip of a thread-local array.
+constexpr int RR_WORK = 4 * NS * NS + NS;
+__device__ int rayleigh_ritz(const double *GA, const double *GB, int m, double *coef /*m x NB*/, double *mu,
+                             double *wk, int *iwk) {
+  double *R = wk, *Ri = wk + NS * NS, *C = wk + 2 * NS * NS, *V = wk + 3 * NS * NS, *rj = wk + 4 * NS * NS;
+  int *keep = iwk, *order = iwk + NS, mk = 0;
   // pivoted-free Cholesky with column dropping (columns are ordered X, W, P)
   for (int j = 0; j < m; ++j) {
     // tentative column j against the kept ones
-    double rj[NS];
     for (int i = 0; i < mk; ++i) {
       double s = GB[keep[i] * m + j];
       for (int k = 0; k < i; ++k) s -= R[k * NS + i] * rj[k];
@@ -555,7 +781,6 @@ __device__ int rayleigh_ritz(const double *GA, const double *GB, int m, double *
     }
   jacobi_small(C, V, mk);
   // sort eigenvalues descending
-  int order[NS];
   for (int i = 0; i < mk; ++i) order[i] = i;
   for (int i = 0; i < mk; ++i)
     for (int j = i + 1; j < mk; ++j)
@@ -670,12 +895,14 @@ struct EigResult {
 
 // LOBPCG (block NB) for the largest mu of K_G x = mu K x with the factored
 // band as preconditioner; returns lambda = 1/mu
-template <typename B>
-__device__ EigResult lobpcg(const PlateGeom &g, const double *Ke, const double *KGe, const B *band, double *vec,
+template <typename B, int RING, int MAXB>
+__device__ __forceinline__ EigResult lobpcg(const PlateGeom &g, const double *Ke, const double *KGe, const B *band, double *vec,
                             double tol, int max_iter) {
   __shared__ double red[4];
   __shared__ double gram[2 * NS * NS];
   __shared__ double coef[NS * NB], mu[NB], resn[NB];
+  __shared__ double rr_wk[RR_WORK];
+  __shared__ int rr_iwk[2 * NS];
   const int n = g.nfree;
   auto V = [&](int k) { return vec + (size_t)k * n; };
   // ---- initial block: smooth mode shapes w = sin(p pi x/a) sin(pi y/b), theta = grad w,
@@ -733,7 +960,7 @@ __device__ EigResult lobpcg(const PlateGeom &g, const double *Ke, const double *
     res0 = resn[0];
     if (!(res0 > tol) || it >= max_iter || !isfinite(res0)) break;
     // W = T R with T = K^-1 (banded Cholesky)
-    band_solve<B>(g, band, V(V_R), V(V_W), n, (B *)V(V_T));
+    band_solve<B, RING, MAXB>(g, band, V(V_R), V(V_W), n, (B *)V(V_T));
     for (int v = 0; v < NB; ++v) {
       plate_apply<false>(g, Ke, V(V_W + v), V(V_KW + v));
       plate_apply<true>(g, KGe, V(V_W + v), V(V_GW + v));
@@ -759,7 +986,7 @@ __device__ EigResult lobpcg(const PlateGeom &g, const double *Ke, const double *
         }
       }
     __syncthreads();
-    if (threadIdx.x == 0) (void)rayleigh_ritz(gram, gram + NS * NS, ms, coef, mu);
+    if (threadIdx.x == 0) (void)rayleigh_ritz(gram, gram + NS * NS, ms, coef, mu, rr_wk, rr_iwk);
     __syncthreads();
     // new X = S c, new P = [W, P] c_{W,P}; images follow by linear combination
     for (int r = threadIdx.x; r < n; r += PT) {
@@ -819,7 +1046,7 @@ __global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   __shared__ double Ke[400], KGe[400], Dmb[36];
   // panel of the factorisation: FP64 room also in the FP32 form, for the FP64
   // lowest-mode check
-  __shared__ double panel_mem[(NBK + MAXBW) * NBK];
+  __shared__ double panel_mem[KP * LDP];
   B *panel = (B *)panel_mem;
   const int s = blockIdx.x;
   if (s >= J.n) return;
@@ -833,7 +1060,11 @@ __global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     if (threadIdx.x == 0) write_result(J, s, NAN, 0, 0.0, S_BREAKDOWN);
     return;
   }
-  EigResult r = lobpcg<B>(g, Ke, KGe, band, W.vec + (size_t)s * W.vec_stride, tol, max_iter);
+  // diagonal blocks of the factor to their inverses (staged in the panel's LDS)
+  constexpr int nstage = (int)(sizeof(panel_mem) / (PS * PS * sizeof(B)));
+  for (int b0 = 0; b0 * PS < g.nfree; b0 += nstage) invert_blocks<B>(band, g.bw + 1, g.nfree, b0, nstage, panel);
+  __syncthreads();
+  EigResult r = lobpcg<B, RING_ONE, ONE_MAXBW - 1>(g, Ke, KGe, band, W.vec + (size_t)s * W.vec_stride, tol, max_iter);
   // the FP64 band is free now (FP64: LOBPCG is done with the factor of K;
   // mixed: the factor lives in the FP32 band)
   if (r.status == S_OK && g.cert_shift > 0.0 &&
@@ -886,8 +1117,9 @@ __global__ __launch_bounds__(PT) void k_plate_assemble(PlateGeom g, PlateWork W,
 
 template <typename B>
 __global__ __launch_bounds__(PT) void k_band_step(PlateGeom g, PlateWork W, int n, int k0) {
-  __shared__ B Lp[MAXBW * NBK];               // previous panel's columns, rows k0 .. k0 + m - 1
-  __shared__ B P[(NBK + MAXBW) * NBK];        // this panel (work-group 0)
+  // column-major (columns contiguous: the tiles' reads are free of bank conflicts)
+  __shared__ B Lp[NBK * MAXBW];               // previous panel's columns, rows k0 .. k0 + m - 1
+  __shared__ B P[NBK * LDPW];                 // this panel (work-group 0)
   const int s = blockIdx.y, wg = blockIdx.x, nwg = gridDim.x;
   if (s >= n) return;
   if (__builtin_amdgcn_readfirstlane(W.flag[s])) return;
@@ -905,7 +1137,7 @@ __global__ __launch_bounds__(PT) void k_band_step(PlateGeom g, PlateWork W, int 
 #pragma unroll
     for (int j = 0; j < NBK; ++j) v[j] = row[min(r + NBK - j, g.bw)];
 #pragma unroll
-    for (int j = 0; j < NBK; ++j) Lp[r * NBK + j] = (r + NBK - j <= g.bw) ? v[j] : B(0);
+    for (int j = 0; j < NBK; ++j) Lp[j * MAXBW + r] = (r + NBK - j <= g.bw) ? v[j] : B(0);
   }
   __syncthreads();
   if (wg == 0) {
@@ -923,34 +1155,34 @@ __global__ __launch_bounds__(PT) void k_band_step(PlateGeom g, PlateWork W, int 
         // the previous panel's update of this entry (columns of this panel)
         if (j < nb && i >= j && i < m) {
           B acc = B(0);
-          for (int jj = 0; jj < NBK; ++jj) acc += Lp[i * NBK + jj] * Lp[j * NBK + jj];
+          for (int jj = 0; jj < NBK; ++jj) acc += Lp[jj * MAXBW + i] * Lp[jj * MAXBW + j];
           v -= acc;
         }
-        P[i * NBK + j] = v;
+        P[j * LDPW + i] = v;
       }
     }
     // panel factorisation (unblocked, in LDS), as in the one-work-group form
     for (int j = 0; j < nb; ++j) {
       __syncthreads();
-      const B piv2 = P[j * NBK + j];
+      const B piv2 = P[j * LDPW + j];
       if (!(piv2 > B(0))) {
         if (threadIdx.x == 0) W.flag[s] = 1;
         return;
       }
       const B piv = sqrt(piv2);
       __syncthreads();
-      for (int i = j + threadIdx.x; i < rows; i += PT) P[i * NBK + j] = (i == j) ? piv : P[i * NBK + j] / piv;
+      for (int i = j + threadIdx.x; i < rows; i += PT) P[j * LDPW + i] = (i == j) ? piv : P[j * LDPW + i] / piv;
       __syncthreads();
-      const int ncols = nb - 1 - j;
-      for (int idx = threadIdx.x; idx < (rows - j - 1) * ncols; idx += PT) {
-        const int i = j + 1 + idx / ncols, jj = j + 1 + idx % ncols;
-        if (i >= jj) P[i * NBK + jj] -= P[i * NBK + j] * P[jj * NBK + j];
+      const int nr = rows - j - 1;  // consecutive threads on consecutive rows
+      for (int idx = threadIdx.x; idx < nr * (nb - 1 - j); idx += PT) {
+        const int i = j + 1 + idx % nr, jj = j + 1 + idx / nr;
+        if (i >= jj) P[jj * LDPW + i] -= P[j * LDPW + i] * P[j * LDPW + jj];
       }
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < rows * NBK; idx += PT) {
       const int i = idx / NBK, j = idx % NBK;
-      if (j < nb && i >= j && i - j <= g.bw) band[(size_t)(k0 + i) * w + (i - j)] = P[idx];
+      if (j < nb && i >= j && i - j <= g.bw) band[(size_t)(k0 + i) * w + (i - j)] = P[j * LDPW + i];
     }
     return;
   }
@@ -971,14 +1203,27 @@ __global__ __launch_bounds__(PT) void k_band_step(PlateGeom g, PlateWork W, int 
     for (int j = 0; j < NBK; ++j) {
       B pr[4], pc[4];
       for (int a = 0; a < 4; ++a) {
-        pr[a] = (r0 + a < m) ? Lp[(r0 + a) * NBK + j] : B(0);
-        pc[a] = (c0 + a < m) ? Lp[(c0 + a) * NBK + j] : B(0);
+        pr[a] = (r0 + a < m) ? Lp[j * MAXBW + r0 + a] : B(0);
+        pc[a] = (c0 + a < m) ? Lp[j * MAXBW + c0 + a] : B(0);
       }
       for (int a = 0; a < 4; ++a)
         for (int c = 0; c < 4; ++c) acc[a][c] += pr[a] * pc[c];
     }
-    tile_store(band, w, k0, m, r0, c0, v, acc);
+    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 4; ++c) v[a][c] -= acc[a][c];
+    tile_store(band, w, k0, m, r0, c0, v);
   }
+}
+
+// diagonal blocks of each sample's factor to their inverses: 8 blocks per
+// work-group (one per half-wave), grid (blocks / 8, samples)
+template <typename B>
+__global__ __launch_bounds__(PT) void k_invert_blocks(PlateGeom g, PlateWork W, int n) {
+  __shared__ B Ls[8 * PS * PS];
+  const int s = blockIdx.y;
+  if (s >= n) return;
+  if (__builtin_amdgcn_readfirstlane(W.flag[s])) return;
+  invert_blocks<B>(sample_band<B>(W, s), g.bw + 1, g.nfree, blockIdx.x * 8, 8, Ls);
 }
 
 // LOBPCG of each sample on its factored band (element matrices from W.kel)
@@ -996,7 +1241,8 @@ __global__ __launch_bounds__(PT) void k_plate_lobpcg(PlateGeom g, PlateWork W, P
     if (threadIdx.x == 0) write_result(J, s, NAN, 0, 0.0, S_BREAKDOWN);
     return;
   }
-  const EigResult r = lobpcg<B>(g, Ke, KGe, sample_band<B>(W, s), W.vec + (size_t)s * W.vec_stride, tol, max_iter);
+  const EigResult r = lobpcg<B, RING_WIDE, MAXBW>(g, Ke, KGe, sample_band<B>(W, s), W.vec + (size_t)s * W.vec_stride, tol,
+                                            max_iter);
   if (threadIdx.x == 0) {
     write_result(J, s, r.lam, r.it, r.res, r.status);
     W.lam[s] = r.lam;
@@ -1074,7 +1320,7 @@ struct PlateCtx {
   double *d_xf = nullptr, *d_yf = nullptr;
   size_t xf_cap = 0;
   size_t budget = 0;               // bound on the batch workspaces of all levels
-  int wide_min_bw = 200;           // factorise over several work-groups from this band width on (0: never)
+  int wide_min_bw = 200;  // factorise over several work-groups from this band width on (0: from ONE_MAXBW on)
 };
 
 // the factorisation spread over work-groups: element matrices, band assembly
@@ -1093,6 +1339,8 @@ static void launch_wide(const PlateGeom &g, const PlateMat &m, const PlateWork &
   const int nwg = std::max(2, std::min(need, std::max(2, 2048 / std::max(n, 1))));
   for (int k0 = 0; k0 < g.nfree; k0 += NBK)
     hipLaunchKernelGGL(k_band_step<B>, dim3(nwg, n), dim3(PT), 0, st, g, W, n, k0);
+  const int nblk = (g.nfree + PS - 1) / PS;
+  hipLaunchKernelGGL(k_invert_blocks<B>, dim3((nblk + 7) / 8, n), dim3(PT), 0, st, g, W, n);
   hipLaunchKernelGGL(k_plate_lobpcg<B>, dim3(n), dim3(PT), 0, st, g, W, J, tol, max_iter);
   if (g.cert_shift > 0.0) {
     // lowest-mode check: FP64 factorisation of K - sigma K_G, spread as above
@@ -1371,7 +1619,7 @@ int plate_buckle_batch(PlateCtx *p, std::string &err, int n_req, const mlmc_requ
           return MLMC_EHIP;
         }
         PlateJob J{offsets, L.rows, L.outidx, coarse ? lam_coarse : lam_fine, info, coarse, n};
-        if (p->wide_min_bw > 0 && L.g.bw >= p->wide_min_bw) {
+        if (L.g.bw >= ONE_MAXBW || (p->wide_min_bw > 0 && L.g.bw >= p->wide_min_bw)) {
           if (mixed) launch_wide<float>(L.g, p->mat, Wk, J, n, tl, p->max_iter, st);
           else launch_wide<double>(L.g, p->mat, Wk, J, n, tl, p->max_iter, st);
         } else if (mixed) {
