@@ -279,7 +279,7 @@ __device__ __forceinline__ void tile_store(B *band, int w, int R, int m, int r0,
 // arrive while the panel is factored.
 constexpr int NBK = 8, KP = 2 * NBK;
 constexpr int LDP = KP + ONE_MAXBW, LDPW = NBK + MAXBW;  // LDS panels (column-major): one-work-group and wide form
-constexpr int TQ = 2;  // trailing tiles per thread in flight (the first TQ issued with the panel's loads)
+constexpr int TQ = 1;  // trailing tiles per thread in flight (the first TQ issued with the panel's loads)
 static_assert(KP + ONE_MAXBW <= 2 * PT, "panel rows: at most two per thread");
 
 // factors the nbs x nbs block of P at rows and columns c0 .. c0 + nbs - 1 (one
@@ -348,7 +348,7 @@ __device__ __forceinline__ bool band_cholesky(const PlateGeom &g, B *band, B *P 
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
   auto tile_of = [](int tix, int &r0, int &c0) {
-    int ti = (int)((sqrt(8.0 * tix + 1.0) - 1.0) * 0.5);
+    int ti = (int)((sqrtf(8.0f * tix + 1.0f) - 1.0f) * 0.5f);  // corrected below
     while ((ti + 1) * (ti + 2) / 2 <= tix) ++ti;
     while (ti * (ti + 1) / 2 > tix) --ti;
     r0 = 4 * ti;
@@ -448,7 +448,7 @@ __device__ __forceinline__ bool band_cholesky(const PlateGeom &g, B *band, B *P 
       }
       tile_store(band, w, R, m, r0, c0, v);
     };
-    // tiles q, q + 1 from tv[0], tv[1]; after each, the loads of the tile TQ on
+    // tiles in groups of TQ from tv; after each, the loads of the tile TQ further on
     for (int q = 0; threadIdx.x + q * PT < ntile; q += TQ) {
 #pragma unroll
       for (int u = 0; u < TQ; ++u) {
@@ -1024,19 +1024,19 @@ __device__ __forceinline__ EigResult lobpcg(const PlateGeom &g, const double *Ke
 // K - sigma K_G that meets no non-positive pivot shows lambda < lambda_1 /
 // (1 - cert_shift): no eigenvalue lies below the computed one by more than
 // the shift.  The band is assembled from the element matrix Ke - sigma KGe
-// (Ke is overwritten) into `band` and factored in FP64.
-__device__ bool lowest_mode_holds(const PlateGeom &g, double lam, double *Ke, const double *KGe, double *band,
-                                  double *panel) {
+// (Ke is overwritten) and factored in FP64.
+__device__ void shift_elements(const PlateGeom &g, double lam, double *Ke, const double *KGe) {
   const double sigma = lam * (1.0 - g.cert_shift);
   __syncthreads();
   for (int k = threadIdx.x; k < 400; k += PT) Ke[k] -= sigma * KGe[k];
   __syncthreads();
-  assemble_band<double>(g, Ke, band, 0, g.nfree, threadIdx.x, PT);
-  __syncthreads();
-  return band_cholesky<double>(g, band, panel);
 }
 
-// one work-group per sample from start to finish
+// one work-group per sample from start to finish: the band of K assembled and
+// factored, its diagonal blocks inverted, LOBPCG, then (FP64) the band of
+// K - sigma K_G assembled and factored for the lowest-mode check.  In the FP64
+// form both factorisations go through one call of the factorisation, so its
+// code (and register allocation) is the same for both.
 template <typename B>
 // two waves per SIMD (a few registers spill): batches of small panels need the
 // occupancy more than the solve's wide loads need registers
@@ -1051,25 +1051,51 @@ __global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const int s = blockIdx.x;
   if (s >= J.n) return;
   sample_elements(g, m, J, s, Dmb, Ke, KGe);
-  // ---- preconditioner: banded Cholesky factor of K
   B *band = sizeof(B) == 8 ? (B *)(W.band + (size_t)s * W.band_stride) : (B *)(W.bandf + (size_t)s * W.band_stride);
-  assemble_band<B>(g, Ke, band, 0, g.nfree, threadIdx.x, PT);
-  __syncthreads();
-  const bool ok = band_cholesky<B>(g, band, panel);
-  if (!ok) {
-    if (threadIdx.x == 0) write_result(J, s, NAN, 0, 0.0, S_BREAKDOWN);
-    return;
+  double *band64 = W.band + (size_t)s * W.band_stride;  // the check's band (free once LOBPCG is done)
+  auto solve = [&]() {
+    // diagonal blocks of the factor to their inverses (staged in the panel's LDS), then LOBPCG
+    constexpr int nstage = (int)(sizeof(panel_mem) / (PS * PS * sizeof(B)));
+    for (int b0 = 0; b0 * PS < g.nfree; b0 += nstage) invert_blocks<B>(band, g.bw + 1, g.nfree, b0, nstage, panel);
+    __syncthreads();
+    return lobpcg<B, RING_ONE, ONE_MAXBW - 1>(g, Ke, KGe, band, W.vec + (size_t)s * W.vec_stride, tol, max_iter);
+  };
+  EigResult r{};
+  if constexpr (sizeof(B) == 8) {
+    for (int pass = 0; pass < 2; ++pass) {
+      if (pass == 1) {
+        if (!(r.status == S_OK && g.cert_shift > 0.0)) break;
+        shift_elements(g, r.lam, Ke, KGe);
+      }
+      assemble_band<double>(g, Ke, band64, 0, g.nfree, threadIdx.x, PT);
+      __syncthreads();
+      const bool ok = band_cholesky<double>(g, band64, panel_mem);
+      if (pass == 0) {
+        if (!ok) {
+          if (threadIdx.x == 0) write_result(J, s, NAN, 0, 0.0, S_BREAKDOWN);
+          return;
+        }
+        r = solve();
+      } else if (!ok) {
+        r.status = S_NOTLOWEST;
+      }
+    }
+  } else {
+    assemble_band<B>(g, Ke, band, 0, g.nfree, threadIdx.x, PT);
+    __syncthreads();
+    if (!band_cholesky<B>(g, band, panel)) {
+      if (threadIdx.x == 0) write_result(J, s, NAN, 0, 0.0, S_BREAKDOWN);
+      return;
+    }
+    r = solve();
+    // the FP64 band is free (the FP32 factor lives in its own band)
+    if (r.status == S_OK && g.cert_shift > 0.0) {
+      shift_elements(g, r.lam, Ke, KGe);
+      assemble_band<double>(g, Ke, band64, 0, g.nfree, threadIdx.x, PT);
+      __syncthreads();
+      if (!band_cholesky<double>(g, band64, panel_mem)) r.status = S_NOTLOWEST;
+    }
   }
-  // diagonal blocks of the factor to their inverses (staged in the panel's LDS)
-  constexpr int nstage = (int)(sizeof(panel_mem) / (PS * PS * sizeof(B)));
-  for (int b0 = 0; b0 * PS < g.nfree; b0 += nstage) invert_blocks<B>(band, g.bw + 1, g.nfree, b0, nstage, panel);
-  __syncthreads();
-  EigResult r = lobpcg<B, RING_ONE, ONE_MAXBW - 1>(g, Ke, KGe, band, W.vec + (size_t)s * W.vec_stride, tol, max_iter);
-  // the FP64 band is free now (FP64: LOBPCG is done with the factor of K;
-  // mixed: the factor lives in the FP32 band)
-  if (r.status == S_OK && g.cert_shift > 0.0 &&
-      !lowest_mode_holds(g, r.lam, Ke, KGe, W.band + (size_t)s * W.band_stride, panel_mem))
-    r.status = S_NOTLOWEST;
   if (threadIdx.x == 0) write_result(J, s, r.lam, r.it, r.res, r.status);
 }
 
