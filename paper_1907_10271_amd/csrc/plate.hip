@@ -614,9 +614,7 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
     __syncthreads();  // tb holds t, Lb holds X
     if (threadIdx.x < 64) {
       B y = B(0);
-#pragma unroll
-      for (int j = 0; j < PS; ++j)
-        if (j < nb) y += Lb[i2 * PS + j] * tb[v2 * PS + j];
+      for (int j = 0; j < nb; ++j) y += Lb[i2 * PS + j] * tb[v2 * PS + j];
       if (i2 < nb) {
         win(v2, k0 + i2) = y;
         tmp[(size_t)v2 * n + k0 + i2] = y;
@@ -655,9 +653,7 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
     __syncthreads();  // rows k0 .. k0 + nb - 1 of the window are final, Lb holds X
     if (threadIdx.x < 64) {
       B y = B(0);
-#pragma unroll
-      for (int j = 0; j < PS; ++j)
-        if (j < nb) y += Lb[j * PS + i2] * win(v2, k0 + j);
+      for (int j = 0; j < nb; ++j) y += Lb[j * PS + i2] * win(v2, k0 + j);
       if (i2 < nb) {
         win(v2, k0 + i2) = y;  // every lane has read the window rows (one wave)
         z[(size_t)v2 * ld + k0 + i2] = (double)y;
