@@ -613,8 +613,14 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
       for (int v = 0; v < NB; ++v) tb[v * PS + fi] = (B)rc[v] - acc[v];
     __syncthreads();  // tb holds t, Lb holds X
     if (threadIdx.x < 64) {
-      B y = B(0);
-      for (int j = 0; j < nb; ++j) y += Lb[i2 * PS + j] * tb[v2 * PS + j];
+      // four partial sums: four independent chains of LDS reads and FMAs
+      B y4[4] = {B(0), B(0), B(0), B(0)};
+      int j = 0;
+      for (; j + 4 <= nb; j += 4)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) y4[q] += Lb[i2 * PS + j + q] * tb[v2 * PS + j + q];
+      for (; j < nb; ++j) y4[0] += Lb[i2 * PS + j] * tb[v2 * PS + j];
+      const B y = (y4[0] + y4[1]) + (y4[2] + y4[3]);
       if (i2 < nb) {
         win(v2, k0 + i2) = y;
         tmp[(size_t)v2 * n + k0 + i2] = y;
@@ -652,8 +658,13 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
     const int ent = k0 - 2 * PS - bw + threadIdx.x;  // row entering the window (threads < PS)
     __syncthreads();  // rows k0 .. k0 + nb - 1 of the window are final, Lb holds X
     if (threadIdx.x < 64) {
-      B y = B(0);
-      for (int j = 0; j < nb; ++j) y += Lb[j * PS + i2] * win(v2, k0 + j);
+      B y4[4] = {B(0), B(0), B(0), B(0)};
+      int j = 0;
+      for (; j + 4 <= nb; j += 4)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) y4[q] += Lb[(j + q) * PS + i2] * win(v2, k0 + j + q);
+      for (; j < nb; ++j) y4[0] += Lb[j * PS + i2] * win(v2, k0 + j);
+      const B y = (y4[0] + y4[1]) + (y4[2] + y4[3]);
       if (i2 < nb) {
         win(v2, k0 + i2) = y;  // every lane has read the window rows (one wave)
         z[(size_t)v2 * ld + k0 + i2] = (double)y;
