@@ -278,19 +278,19 @@ __device__ __forceinline__ void tile_store(B *band, int w, int R, int m, int r0,
 // work-group barrier), so a pass requests all of them first: the tile entries
 // arrive while the panel is factored.
 constexpr int NBK = 8, KP = 2 * NBK;
-constexpr int LDP = KP + ONE_MAXBW, LDPW = NBK + MAXBW;  // LDS panels (column-major): one-work-group and wide form
+constexpr int LDP = KP + ONE_MAXBW, LDPW = KP + MAXBW;  // LDS panels (column-major): one-work-group and wide form
 constexpr int TQ = 1;  // trailing tiles per thread in flight (the first TQ issued with the panel's loads)
 static_assert(KP + ONE_MAXBW <= 2 * PT, "panel rows: at most two per thread");
 
-// factors the nbs x nbs block of P at rows and columns c0 .. c0 + nbs - 1 (one
-// thread, unblocked order); false at a non-positive pivot
-template <typename B>
+// factors the nbs x nbs block of P (column-major, LD rows) at rows and columns
+// c0 .. c0 + nbs - 1 (one thread, unblocked order); false at a non-positive pivot
+template <int LD, typename B>
 __device__ bool factor_top(B *P, int c0, int nbs) {
   B a[NBK][NBK];
 #pragma unroll
   for (int i = 0; i < NBK; ++i)
 #pragma unroll
-    for (int j = 0; j <= i; ++j) a[i][j] = (i < nbs) ? P[(c0 + j) * LDP + c0 + i] : B(0);
+    for (int j = 0; j <= i; ++j) a[i][j] = (i < nbs) ? P[(c0 + j) * LD + c0 + i] : B(0);
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < NBK; ++j) {
@@ -315,30 +315,50 @@ __device__ bool factor_top(B *P, int c0, int nbs) {
   for (int i = 0; i < NBK; ++i)
 #pragma unroll
     for (int j = 0; j <= i; ++j)
-      if (i < nbs) P[(c0 + j) * LDP + c0 + i] = a[i][j];
+      if (i < nbs) P[(c0 + j) * LD + c0 + i] = a[i][j];
   return ok;
 }
 
 // rows i0 .. rows - 1 of sub-panel columns c0 .. c0 + nbs - 1: forward
 // substitution with the factored top block, one thread per row
-template <typename B>
+template <int LD, typename B>
 __device__ void factor_rows(B *P, int c0, int nbs, int i0, int rows) {
   for (int i = i0 + threadIdx.x; i < rows; i += PT) {
     B x[NBK];
 #pragma unroll
-    for (int j = 0; j < NBK; ++j) x[j] = P[(c0 + j) * LDP + i];
+    for (int j = 0; j < NBK; ++j) x[j] = P[(c0 + j) * LD + i];
 #pragma unroll
     for (int j = 0; j < NBK; ++j) {
       if (j < nbs) {
-        x[j] = x[j] / P[(c0 + j) * LDP + c0 + j];
+        x[j] = x[j] / P[(c0 + j) * LD + c0 + j];
 #pragma unroll
         for (int jj = j + 1; jj < NBK; ++jj)
-          if (jj < nbs) x[jj] -= x[j] * P[(c0 + j) * LDP + c0 + jj];
+          if (jj < nbs) x[jj] -= x[j] * P[(c0 + j) * LD + c0 + jj];
       }
     }
 #pragma unroll
     for (int j = 0; j < NBK; ++j)
-      if (j < nbs) P[(c0 + j) * LDP + i] = x[j];
+      if (j < nbs) P[(c0 + j) * LD + i] = x[j];
+  }
+}
+
+// sub-panel A's product subtracted from sub-panel B's columns (rows NBK on):
+// the NBK-term sum of the NBK-column form's trailing update, one thread per row
+template <int LD, typename B>
+__device__ void update_b(B *P, int nb, int rows) {
+  for (int i = NBK + threadIdx.x; i < rows; i += PT) {
+    B x[NBK];
+#pragma unroll
+    for (int j = 0; j < NBK; ++j) x[j] = P[j * LD + i];
+#pragma unroll
+    for (int jb = NBK; jb < KP; ++jb) {
+      if (jb < nb && jb <= i) {
+        B acc = B(0);
+#pragma unroll
+        for (int j = 0; j < NBK; ++j) acc += x[j] * P[j * LD + jb];
+        P[jb * LD + i] -= acc;
+      }
+    }
   }
 }
 
@@ -390,34 +410,19 @@ __device__ __forceinline__ bool band_cholesky(const PlateGeom &g, B *band, B *P 
     }
     __syncthreads();
     // ---- sub-panel A (columns 0 .. nbA - 1)
-    if (threadIdx.x == 0 && !factor_top(P, 0, nbA)) bad = 1;
+    if (threadIdx.x == 0 && !factor_top<LDP>(P, 0, nbA)) bad = 1;
     __syncthreads();
     if (bad) return false;
-    factor_rows(P, 0, nbA, nbA, rows);
+    factor_rows<LDP>(P, 0, nbA, nbA, rows);
     __syncthreads();
     if (nbB > 0) {
-      // sub-panel A's product subtracted from sub-panel B's columns (rows NBK
-      // on): the NBK-term sum of the NBK-column form's trailing update
-      for (int i = NBK + threadIdx.x; i < rows; i += PT) {
-        B x[NBK];
-#pragma unroll
-        for (int j = 0; j < NBK; ++j) x[j] = P[j * LDP + i];
-#pragma unroll
-        for (int jb = NBK; jb < KP; ++jb) {
-          if (jb < nb && jb <= i) {
-            B acc = B(0);
-#pragma unroll
-            for (int j = 0; j < NBK; ++j) acc += x[j] * P[j * LDP + jb];
-            P[jb * LDP + i] -= acc;
-          }
-        }
-      }
+      update_b<LDP>(P, nb, rows);
       __syncthreads();
       // ---- sub-panel B (columns NBK .. nb - 1)
-      if (threadIdx.x == 0 && !factor_top(P, NBK, nbB)) bad = 1;
+      if (threadIdx.x == 0 && !factor_top<LDP>(P, NBK, nbB)) bad = 1;
       __syncthreads();
       if (bad) return false;
-      factor_rows(P, NBK, nbB, nb, rows);
+      factor_rows<LDP>(P, NBK, nbB, nb, rows);
       __syncthreads();
     }
     for (int idx = threadIdx.x; idx < rows * KP; idx += PT) {
@@ -1154,100 +1159,130 @@ __global__ __launch_bounds__(PT) void k_plate_assemble(PlateGeom g, PlateWork W,
 
 template <typename B>
 __global__ __launch_bounds__(PT) void k_band_step(PlateGeom g, PlateWork W, int n, int k0) {
-  // column-major (columns contiguous: the tiles' reads are free of bank conflicts)
-  __shared__ B Lp[NBK * MAXBW];               // previous panel's columns, rows k0 .. k0 + m - 1
-  __shared__ B P[NBK * LDPW];                 // this panel (work-group 0)
+  // one LDS area, column-major (columns contiguous: the tiles' reads are free of
+  // bank conflicts): work-group 0 stages this panel in it (KP x LDPW), the others
+  // the previous panel's columns on the rows of its trailing window (KP x MAXBW)
+  __shared__ B S[KP * LDPW];
+  __shared__ B Lq[KP * KP];  // work-group 0: the previous panel's columns on this panel's rows
+  __shared__ int bad;
   const int s = blockIdx.y, wg = blockIdx.x, nwg = gridDim.x;
   if (s >= n) return;
   if (__builtin_amdgcn_readfirstlane(W.flag[s])) return;
   const int w = g.bw + 1, nf = g.nfree;
   B *band = sample_band<B>(W, s);
-  // trailing window of the previous panel (columns k0 - NBK .. k0 - 1): rows and
-  // columns k0 .. k0 + m - 1
-  // (one thread per band row: a row's NBK entries are contiguous, and all its
-  // loads are issued at once; entries outside the band read an in-range entry
-  // of the row and are replaced by zero)
+  // trailing window of the previous panel (columns k0 - KP .. k0 - 1): rows and
+  // columns k0 .. k0 + m - 1; its sub-panels A (first NBK columns) and B
   const int m = (k0 > 0) ? min(g.bw, nf - k0) : 0;
-  for (int r = threadIdx.x; r < m; r += PT) {
-    const B *row = band + (size_t)(k0 + r) * w;
-    B v[NBK];
-#pragma unroll
-    for (int j = 0; j < NBK; ++j) v[j] = row[min(r + NBK - j, g.bw)];
-#pragma unroll
-    for (int j = 0; j < NBK; ++j) Lp[j * MAXBW + r] = (r + NBK - j <= g.bw) ? v[j] : B(0);
-  }
-  __syncthreads();
+  const int pA = (k0 > 0) ? NBK : 0, pB = (k0 > 0) ? NBK : 0;  // previous panels are always whole
   if (wg == 0) {
     if (k0 >= nf) return;
-    const int nb = min(NBK, nf - k0);
-    const int rows = min(nb + g.bw, nf - k0);
+    B *P = S;
+    const int nbA = min(NBK, nf - k0), nbB = max(0, min(NBK, nf - k0 - NBK)), nb = nbA + nbB;
+    const int rows = min(nb + g.bw, nf - k0);  // panel rows k0 .. k0 + rows - 1
+    if (threadIdx.x == 0) bad = 0;
+    // the previous panel's columns on this panel's rows (the pc side of its update)
+    for (int idx = threadIdx.x; idx < KP * KP; idx += PT) {
+      const int j = idx / KP, c = idx % KP;  // row k0 + j, previous column k0 - KP + c
+      const bool in = k0 > 0 && j < nb && j + KP - c <= g.bw;
+      Lq[c * KP + j] = in ? band[(size_t)(k0 + j) * w + (j + KP - c)] : B(0);
+    }
+    __syncthreads();
+    // each row of the panel: its entries, less the previous panel's two
+    // NBK-term sums (sub-panel A first) where the row is inside that panel's window
     for (int i = threadIdx.x; i < rows; i += PT) {
       const B *row = band + (size_t)(k0 + i) * w;
-      B e[NBK];
+      B e[KP];
 #pragma unroll
-      for (int j = 0; j < NBK; ++j) e[j] = row[min(max(i - j, 0), g.bw)];
+      for (int j = 0; j < KP; ++j) e[j] = row[min(max(i - j, 0), g.bw)];
 #pragma unroll
-      for (int j = 0; j < NBK; ++j) {
-        B v = (j < nb && i >= j && i - j <= g.bw) ? e[j] : B(0);
-        // the previous panel's update of this entry (columns of this panel)
-        if (j < nb && i >= j && i < m) {
-          B acc = B(0);
-          for (int jj = 0; jj < NBK; ++jj) acc += Lp[jj * MAXBW + i] * Lp[jj * MAXBW + j];
-          v -= acc;
+      for (int j = 0; j < KP; ++j) P[j * LDPW + i] = (j < nb && i >= j && i - j <= g.bw) ? e[j] : B(0);
+      if (i < m) {
+        B x[KP];  // the row's entries in the previous panel's columns (zero outside the band)
+#pragma unroll
+        for (int c = 0; c < KP; ++c) x[c] = (i + KP - c <= g.bw) ? row[min(i + KP - c, g.bw)] : B(0);
+        for (int j = 0; j < min(nb, i + 1); ++j) {
+          B accA = B(0), accB = B(0);
+#pragma unroll
+          for (int c = 0; c < NBK; ++c) accA += x[c] * Lq[c * KP + j];
+#pragma unroll
+          for (int c = NBK; c < KP; ++c) accB += x[c] * Lq[c * KP + j];
+          B v = P[j * LDPW + i];
+          v -= accA;
+          v -= accB;
+          P[j * LDPW + i] = v;
         }
-        P[j * LDPW + i] = v;
-      }
-    }
-    // panel factorisation (unblocked, in LDS), as in the one-work-group form
-    for (int j = 0; j < nb; ++j) {
-      __syncthreads();
-      const B piv2 = P[j * LDPW + j];
-      if (!(piv2 > B(0))) {
-        if (threadIdx.x == 0) W.flag[s] = 1;
-        return;
-      }
-      const B piv = sqrt(piv2);
-      __syncthreads();
-      for (int i = j + threadIdx.x; i < rows; i += PT) P[j * LDPW + i] = (i == j) ? piv : P[j * LDPW + i] / piv;
-      __syncthreads();
-      const int nr = rows - j - 1;  // consecutive threads on consecutive rows
-      for (int idx = threadIdx.x; idx < nr * (nb - 1 - j); idx += PT) {
-        const int i = j + 1 + idx % nr, jj = j + 1 + idx / nr;
-        if (i >= jj) P[jj * LDPW + i] -= P[j * LDPW + i] * P[j * LDPW + jj];
       }
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < rows * NBK; idx += PT) {
-      const int i = idx / NBK, j = idx % NBK;
+    // the panel: sub-panel A, A's product on B's columns, sub-panel B
+    if (threadIdx.x == 0 && !factor_top<LDPW>(P, 0, nbA)) bad = 1;
+    __syncthreads();
+    if (bad) {
+      if (threadIdx.x == 0) W.flag[s] = 1;
+      return;
+    }
+    factor_rows<LDPW>(P, 0, nbA, nbA, rows);
+    __syncthreads();
+    if (nbB > 0) {
+      update_b<LDPW>(P, nb, rows);
+      __syncthreads();
+      if (threadIdx.x == 0 && !factor_top<LDPW>(P, NBK, nbB)) bad = 1;
+      __syncthreads();
+      if (bad) {
+        if (threadIdx.x == 0) W.flag[s] = 1;
+        return;
+      }
+      factor_rows<LDPW>(P, NBK, nbB, nb, rows);
+      __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < rows * KP; idx += PT) {
+      const int i = idx / KP, j = idx % KP;
       if (j < nb && i >= j && i - j <= g.bw) band[(size_t)(k0 + i) * w + (i - j)] = P[j * LDPW + i];
     }
     return;
   }
-  // the rest of the previous panel's trailing window: 4 x 4 tiles of column offset >= NBK
+  // ---- the other work-groups: the rest of the previous panel's trailing window
+  // (4 x 4 tiles of column offset >= KP), its sums A then B as in the
+  // one-work-group form
   if (m <= 0 || nwg < 2) return;
+  B *Lp = S;
+  for (int r = threadIdx.x; r < m; r += PT) {  // one thread per band row: its KP entries are contiguous
+    const B *row = band + (size_t)(k0 + r) * w;
+    B v[KP];
+#pragma unroll
+    for (int j = 0; j < KP; ++j) v[j] = row[min(r + KP - j, g.bw)];
+#pragma unroll
+    for (int j = 0; j < KP; ++j) Lp[j * MAXBW + r] = (r + KP - j <= g.bw) ? v[j] : B(0);
+  }
+  __syncthreads();
   const int mt = (m + 3) / 4, ntile = mt * (mt + 1) / 2;
   for (int tix = (wg - 1) * PT + threadIdx.x; tix < ntile; tix += (nwg - 1) * PT) {
-    int ti = (int)((sqrt(8.0 * tix + 1.0) - 1.0) * 0.5);
+    int ti = (int)((sqrtf(8.0f * tix + 1.0f) - 1.0f) * 0.5f);  // corrected below
     while ((ti + 1) * (ti + 2) / 2 <= tix) ++ti;
     while (ti * (ti + 1) / 2 > tix) --ti;
     const int tj = tix - ti * (ti + 1) / 2;
-    if (tj < NBK / 4) continue;                 // columns of panel k0: work-group 0
+    if (tj < KP / 4) continue;  // columns of panel k0: work-group 0
     const int r0 = 4 * ti, c0 = 4 * tj;
-    B v[4][4], acc[4][4];
+    B v[4][4];
     tile_load(band, w, k0, m, r0, c0, v);
-    for (int a = 0; a < 4; ++a)
-      for (int c = 0; c < 4; ++c) acc[a][c] = B(0);
-    for (int j = 0; j < NBK; ++j) {
-      B pr[4], pc[4];
-      for (int a = 0; a < 4; ++a) {
-        pr[a] = (r0 + a < m) ? Lp[j * MAXBW + r0 + a] : B(0);
-        pc[a] = (c0 + a < m) ? Lp[j * MAXBW + c0 + a] : B(0);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int j0 = half * NBK, j1 = half ? pA + pB : pA;
+      B acc[4][4];
+      for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 4; ++c) acc[a][c] = B(0);
+      for (int j = j0; j < j1; ++j) {
+        B pr[4], pc[4];
+        for (int a = 0; a < 4; ++a) {
+          pr[a] = (r0 + a < m) ? Lp[j * MAXBW + r0 + a] : B(0);
+          pc[a] = (c0 + a < m) ? Lp[j * MAXBW + c0 + a] : B(0);
+        }
+        for (int a = 0; a < 4; ++a)
+          for (int c = 0; c < 4; ++c) acc[a][c] += pr[a] * pc[c];
       }
       for (int a = 0; a < 4; ++a)
-        for (int c = 0; c < 4; ++c) acc[a][c] += pr[a] * pc[c];
+        for (int c = 0; c < 4; ++c) v[a][c] -= acc[a][c];
     }
-    for (int a = 0; a < 4; ++a)
-      for (int c = 0; c < 4; ++c) v[a][c] -= acc[a][c];
     tile_store(band, w, k0, m, r0, c0, v);
   }
 }
@@ -1374,7 +1409,7 @@ static void launch_wide(const PlateGeom &g, const PlateMat &m, const PlateWork &
   const int mt = (g.bw + 3) / 4, ntile = mt * (mt + 1) / 2;
   const int need = 1 + (ntile + PT - 1) / PT;
   const int nwg = std::max(2, std::min(need, std::max(2, 2048 / std::max(n, 1))));
-  for (int k0 = 0; k0 < g.nfree; k0 += NBK)
+  for (int k0 = 0; k0 < g.nfree; k0 += KP)
     hipLaunchKernelGGL(k_band_step<B>, dim3(nwg, n), dim3(PT), 0, st, g, W, n, k0);
   const int nblk = (g.nfree + PS - 1) / PS;
   hipLaunchKernelGGL(k_invert_blocks<B>, dim3((nblk + 7) / 8, n), dim3(PT), 0, st, g, W, n);
@@ -1383,7 +1418,7 @@ static void launch_wide(const PlateGeom &g, const PlateMat &m, const PlateWork &
     // lowest-mode check: FP64 factorisation of K - sigma K_G, spread as above
     hipLaunchKernelGGL(k_cert_assemble, dim3((g.nfree + rows_per_wg - 1) / rows_per_wg, n), dim3(PT), 0, st, g, W,
                        n, rows_per_wg);
-    for (int k0 = 0; k0 < g.nfree; k0 += NBK)
+    for (int k0 = 0; k0 < g.nfree; k0 += KP)
       hipLaunchKernelGGL(k_band_step<double>, dim3(nwg, n), dim3(PT), 0, st, g, W, n, k0);
     hipLaunchKernelGGL(k_cert_finish, dim3((n + 255) / 256), dim3(256), 0, st, W, J);
   }
