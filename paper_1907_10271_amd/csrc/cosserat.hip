@@ -513,6 +513,7 @@ __global__ __launch_bounds__(256) void k_cos_synth(CosGeom g, const double *X, c
                                                    const int64_t *rows, int n, double *theta, double *cs) {
   __shared__ double a[MAXKL];
   const int s = blockIdx.y;
+  if (s >= n) return;
   const int64_t row = rows ? rows[s] : s;
   for (int k = threadIdx.x; k < g.nkl; k += 256) a[k] = sqrt_mu[k] * xi[(size_t)row * ld_xi + k];
   __syncthreads();

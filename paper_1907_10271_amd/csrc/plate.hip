@@ -454,7 +454,7 @@ __device__ __forceinline__ bool band_cholesky(const PlateGeom &g, B *band, B *P 
       tile_store(band, w, R, m, r0, c0, v);
     };
     // tiles in groups of TQ from tv; after each, the loads of the tile TQ further on
-    for (int q = 0; threadIdx.x + q * PT < ntile; q += TQ) {
+    for (int q = 0; (int)threadIdx.x + q * PT < ntile; q += TQ) {
 #pragma unroll
       for (int u = 0; u < TQ; ++u) {
         const int tix = threadIdx.x + (q + u) * PT;
