@@ -334,16 +334,74 @@ __global__ __launch_bounds__(CTHREADS) void k_cos_setup(CosGeom g, CosMat m, Cos
 
 // operator pass of iteration `it`: stopping test on r_it, p_it = z_it +
 // beta p_{it-1} (halo included, owned nodes stored), A p_it, partials of p.Ap
+// K fixed-order work-group sums at once (256 threads): each value summed as by
+// block_sum (butterfly within each wave, then the four wave sums in order),
+// with one pair of barriers for all of them; red holds 4 K values
+template <int K>
+__device__ __forceinline__ void block_sums(double (&v)[K], double *red) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[4 * k + wid] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double t = red[4 * k];
+    for (int w = 1; w < 4; ++w) t += red[4 * k + w];
+    v[k] = t;
+  }
+}
+
+// the tiles' partial sums of a sample (entries t, t + 256, ... per thread, then
+// block_sums), K arrays at once
+template <int K>
+__device__ __forceinline__ void partial_sums(const double *const (&a)[K], int n, double (&v)[K], double *red) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (int t = threadIdx.x; t < n; t += 256)
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += a[k][t];
+  block_sums<K>(v, red);
+}
+
 __global__ __launch_bounds__(CTHREADS) void k_cos_pass1(CosGeom g, CosMat m, CosSlots S, int it) {
   __shared__ double xs[3][CH * CH];
   __shared__ double fe[12][CE * CE];
-  __shared__ double red[4];
+  __shared__ double red[12];
   const int s = blockIdx.y, tile = blockIdx.x;
   if (__builtin_amdgcn_readfirstlane(S.active[s]) == 0) return;
   const int nt = g.ntiles;
+  const double *pold = (it & 1) ? S.p0 : S.p1;
+  double *pnew = (it & 1) ? S.p1 : S.p0;
+  int i0, j0;
+  tile_origin(g, tile, &i0, &j0);
+  const size_t vb = (size_t)s * 3 * g.nnode;
+  // the tile's r, dinv and p_old (tile and halo), requested before the
+  // cross-tile sums so that both round trips overlap
+  constexpr int NPT = (CH * CH + CTHREADS - 1) / CTHREADS;
+  double dv[NPT][3], rv[NPT][3], pv[NPT][3];
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    const int k = threadIdx.x + q * CTHREADS;
+    const int i = i0 - 1 + k % CH, j = j0 - 1 + k / CH;
+    const bool in = k < CH * CH && i >= 0 && i < g.nnx && j >= 0 && j < g.nny;
+    const size_t o = in ? vb + 3 * ((size_t)j * g.nnx + i) : vb;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      dv[q][c] = in ? S.dinv[o + c] : 0.0;
+      rv[q][c] = in ? S.r[o + c] : 0.0;
+      pv[q][c] = (in && it > 0) ? pold[o + c] : 0.0;
+    }
+  }
   const size_t cur = ((size_t)((it + 1) & 1) * S.S + s) * nt;   // partials of r_it
-  const double rz = block_sum_strided(S.part_rz + cur, nt, red);
-  const double rr = block_sum_strided(S.part_rr + cur, nt, red);
+  const size_t prv = ((size_t)(it & 1) * S.S + s) * nt;         // partials of r_{it-1}
+  const double *const parts[3] = {S.part_rz + cur, S.part_rr + cur, S.part_rz + (it > 0 ? prv : cur)};
+  double sums[3];
+  partial_sums<3>(parts, nt, sums, red);
+  const double rz = sums[0], rr = sums[1];
   const double bb = it == 0 ? rr : S.bb[s];
   // stopping test (every work-group of the sample takes the same decision)
   const bool bad = !isfinite(rr) || !isfinite(rz);
@@ -358,21 +416,18 @@ __global__ __launch_bounds__(CTHREADS) void k_cos_pass1(CosGeom g, CosMat m, Cos
     return;
   }
   if (it == 0 && tile == 0 && threadIdx.x == 0) S.bb[s] = bb;
-  double beta = 0.0;
-  if (it > 0) beta = rz / block_sum_strided(S.part_rz + ((size_t)(it & 1) * S.S + s) * nt, nt, red);
-  const double *pold = (it & 1) ? S.p0 : S.p1;
-  double *pnew = (it & 1) ? S.p1 : S.p0;
-  int i0, j0;
-  tile_origin(g, tile, &i0, &j0);
-  const size_t vb = (size_t)s * 3 * g.nnode;
-  for (int k = threadIdx.x; k < CH * CH; k += CTHREADS) {
+  const double beta = it > 0 ? rz / sums[2] : 0.0;
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    const int k = threadIdx.x + q * CTHREADS;
+    if (k >= CH * CH) break;
     const int i = i0 - 1 + k % CH, j = j0 - 1 + k / CH;
     double v[3] = {0.0, 0.0, 0.0};
     if (i >= 0 && i < g.nnx && j >= 0 && j < g.nny) {
       const size_t o = vb + 3 * ((size_t)j * g.nnx + i);
       for (int c = 0; c < 3; ++c) {
-        v[c] = S.dinv[o + c] * S.r[o + c];
-        if (it > 0) v[c] += beta * pold[o + c];
+        v[c] = dv[q][c] * rv[q][c];
+        if (it > 0) v[c] += beta * pv[q][c];
       }
       if (i >= i0 && i < i0 + CT && j >= j0 && j < j0 + CT)
         for (int c = 0; c < 3; ++c) pnew[o + c] = v[c];
@@ -401,12 +456,30 @@ __global__ __launch_bounds__(CTHREADS) void k_cos_pass1(CosGeom g, CosMat m, Cos
 // vector pass of iteration `it`: alpha = r.z / p.Ap, x += alpha p, r -= alpha
 // A p, partials of r.z and r.r (parity it & 1)
 __global__ __launch_bounds__(CTHREADS) void k_cos_pass2(CosGeom g, CosSlots S, int it) {
-  __shared__ double red[4];
+  __shared__ double red[12];
   const int s = blockIdx.y, tile = blockIdx.x;
   if (__builtin_amdgcn_readfirstlane(S.active[s]) == 0) return;
   const int nt = g.ntiles;
-  const double rz = block_sum_strided(S.part_rz + ((size_t)((it + 1) & 1) * S.S + s) * nt, nt, red);
-  const double pap = block_sum_strided(S.part_pap + (size_t)s * nt, nt, red);
+  const double *p = (it & 1) ? S.p1 : S.p0;
+  int i0, j0;
+  tile_origin(g, tile, &i0, &j0);
+  const int li = threadIdx.x % CT, lj = threadIdx.x / CT, i = i0 + li, j = j0 + lj;
+  const bool in = i < g.nnx && j < g.nny;
+  const size_t o = (size_t)s * 3 * g.nnode + (in ? 3 * ((size_t)j * g.nnx + i) : 0);
+  // the node's vectors, requested before the cross-tile sums
+  double xv[3], pv[3], rv[3], av[3], dv[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    xv[c] = in ? S.x[o + c] : 0.0;
+    pv[c] = in ? p[o + c] : 0.0;
+    rv[c] = in ? S.r[o + c] : 0.0;
+    av[c] = in ? S.Ap[o + c] : 0.0;
+    dv[c] = in ? S.dinv[o + c] : 0.0;
+  }
+  const double *const parts[2] = {S.part_rz + ((size_t)((it + 1) & 1) * S.S + s) * nt, S.part_pap + (size_t)s * nt};
+  double sums[2];
+  partial_sums<2>(parts, nt, sums, red);
+  const double rz = sums[0], pap = sums[1];
   if (!(pap > 0.0)) {
     if (tile == 0 && threadIdx.x == 0) {
       S.active[s] = 0;
@@ -416,23 +489,20 @@ __global__ __launch_bounds__(CTHREADS) void k_cos_pass2(CosGeom g, CosSlots S, i
     return;
   }
   const double alpha = rz / pap;
-  const double *p = (it & 1) ? S.p1 : S.p0;
-  int i0, j0;
-  tile_origin(g, tile, &i0, &j0);
-  const int li = threadIdx.x % CT, lj = threadIdx.x / CT, i = i0 + li, j = j0 + lj;
   double prz = 0.0, prr = 0.0;
-  if (i < g.nnx && j < g.nny) {
-    const size_t o = (size_t)s * 3 * g.nnode + 3 * ((size_t)j * g.nnx + i);
+  if (in) {
     for (int c = 0; c < 3; ++c) {
-      S.x[o + c] += alpha * p[o + c];
-      const double r = S.r[o + c] - alpha * S.Ap[o + c];
+      S.x[o + c] = xv[c] + alpha * pv[c];
+      const double r = rv[c] - alpha * av[c];
       S.r[o + c] = r;
-      prz += r * S.dinv[o + c] * r;
+      prz += r * dv[c] * r;
       prr += r * r;
     }
   }
-  prz = block_sum(prz, red);
-  prr = block_sum(prr, red);
+  double pr2[2] = {prz, prr};
+  block_sums<2>(pr2, red);
+  prz = pr2[0];
+  prr = pr2[1];
   if (threadIdx.x == 0) {
     const size_t pp = ((size_t)(it & 1) * S.S + s) * nt + tile;
     S.part_rz[pp] = prz;
