@@ -208,9 +208,9 @@ __device__ void plate_apply(const PlateGeom &g, const double *Ke, const double *
 // (rows r0 .. r1 - 1, entries shared out over `nthreads` threads from thread t)
 template <typename B>
 __device__ void assemble_band(const PlateGeom &g, const double *Ke, B *band, int r0, int r1, int t, int nthreads) {
-  const int w = g.bw + 1;
-  for (long long idx = (long long)r0 * w + t; idx < (long long)r1 * w; idx += nthreads) {
-    const int r = (int)(idx / w), d = (int)(idx % w);
+  const int w = g.bw + 1;  // nfree w < 2^31 for every mesh the band form accepts
+  for (int idx = r0 * w + t; idx < r1 * w; idx += nthreads) {
+    const int r = idx / w, d = idx - r * w;
     double v = 0.0;
     const int cfree = r - d;
     if (cfree >= 0) {
