@@ -75,13 +75,19 @@ enum { V_X = 0, V_W = NB, V_P = 2 * NB, V_KX = 3 * NB, V_KW = 4 * NB, V_KP = 5 *
        V_GP = 8 * NB, V_R = 9 * NB, V_T = 10 * NB, NVEC = 11 * NB };
 
 // ---------------------------------------------------------------- small helpers
+// sum over the NT threads of a work-group (red: NT / 64 doubles of LDS); the
+// wave sums are added in wave order
+template <int NT = PT>
 __device__ double block_reduce(double v, double *red) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) red[wid] = v;
   __syncthreads();
-  return ((red[0] + red[1]) + red[2]) + red[3];
+  double sum = red[0];
+#pragma unroll
+  for (int k = 1; k < NT / 64; ++k) sum += red[k];
+  return sum;
 }
 
 // rotated ply stiffness (fibres at angle th from x), engineering shear
@@ -176,10 +182,11 @@ __device__ void element_matrices(const PlateGeom &g, const PlateMat &m, const do
   }
 }
 
-// y = P K P x on the free unknowns (element-by-element gather at every node)
-template <bool GEOM>
+// y = P K P x on the free unknowns (element-by-element gather at every node),
+// rows shared out over the NT threads of the work-group
+template <bool GEOM, int NT = PT>
 __device__ void plate_apply(const PlateGeom &g, const double *Ke, const double *x, double *y) {
-  for (int r = threadIdx.x; r < g.nfree; r += PT) {
+  for (int r = threadIdx.x; r < g.nfree; r += NT) {
     const int full = g.full_of_free[r];
     const int node = full / 5, c = full % 5;
     double acc = 0.0;
@@ -202,6 +209,14 @@ __device__ void plate_apply(const PlateGeom &g, const double *Ke, const double *
     }
     y[r] = acc;
   }
+}
+
+// plate_apply as a call of its own, for work-groups of more than PT threads,
+// whose register budget the inlined gathers would share with the
+// eigensolver's state
+template <bool GEOM, int NT>
+__device__ __noinline__ void plate_apply_call(const PlateGeom &g, const double *Ke, const double *x, double *y) {
+  plate_apply<GEOM, NT>(g, Ke, x, y);
 }
 
 // lower band of K on the free unknowns: band[r][d] = K[r][r - d], d = 0..bw
@@ -523,32 +538,38 @@ __device__ void invert_blocks(B *band, int w, int n, int blk0, int nstage, B *Ls
 }
 
 // z = (L L^T)^-1 r for NB right-hand sides, in steps of PS rows, with the
-// diagonal blocks of the band holding their inverses X.  The solved rows a
-// step needs (fewer than bw + 3 PS) live in an LDS window of RING rows.
+// diagonal blocks of the band holding their inverses X, by a work-group of NT
+// threads.  The solved rows a step needs (fewer than bw + 3 PS) live in an LDS
+// window of RING rows.
 // Forward step (rows k0 .. k0 + PS - 1): t_i = r_i - sum_c L_ic y_c over the
-// band columns c < k0, each row's entries read by 8 lanes in contiguous runs
-// (its band row is contiguous), the partial sums combined by lane shuffles;
+// band columns c < k0, each row's entries read by NT / PS lanes in contiguous
+// runs (its band row is contiguous), the partial sums combined by lane shuffles;
 // then y = X t, one wave (lane = right-hand side x row).  The band entries of
 // the next step are requested as soon as this step's are used, so they arrive
 // during its reductions and barriers.  Backward step: z = X^T t, then each
 // thread subtracts L_jc z_j from its rows c < k0 of the window (one column c
 // per thread: neighbouring threads read neighbouring band entries).
-template <typename B, int RING, int MAXB>
+template <typename B, int RING, int MAXB, int NT = PT>
 __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, double *z, int ld, B *tmp) {
   static_assert((RING & (RING - 1)) == 0 && RING >= MAXB + 3 * PS, "window rows: a power of two >= bw + 3 PS");
-  constexpr int CH = 32;  // band entries per lane and chunk: a chunk covers 8 CH columns of a row
-  constexpr int MAXCHUNK = (MAXB + 8 * CH - 1) / (8 * CH);  // chunks of the widest band (bw <= MAXB)
+  static_assert(NT % PS == 0 && (PS * PS) % NT == 0, "whole rows per step and whole X entries per thread");
+  constexpr int LPR = NT / PS;  // forward lanes per row of a step
+  // band entries per lane and chunk (a chunk covers LPR CH columns of a row):
+  // one chunk for the widest band when LPR 32 columns cover it, else 32
+  constexpr int CH = LPR * 32 >= MAXB ? (MAXB - 1) / LPR + 1 : 32;
+  constexpr int MAXCHUNK = (MAXB + LPR * CH - 1) / (LPR * CH);  // chunks of the widest band (bw <= MAXB)
+  constexpr int XE = PS * PS / NT;                              // entries of X per thread
   const int w = g.bw + 1, n = g.nfree, bw = g.bw;
   __shared__ B ring[NB * RING], Lb[PS * PS], tb[NB * PS];
   auto win = [&](int v, int row) -> B & { return ring[v * RING + (row & (RING - 1))]; };
   const int v2 = threadIdx.x / PS, i2 = threadIdx.x % PS;  // mat-vec lanes (wave 0)
-  const int fi = threadIdx.x / 8, fq = threadIdx.x % 8;     // forward: row fi of the step, part fq
-  B e[PS * PS / PT];
+  const int fi = threadIdx.x / LPR, fq = threadIdx.x % LPR; // forward: row fi of the step, part fq
+  B e[XE];
   auto x_load = [&](int k0) {  // X of the step at k0: Lb[i PS + j] = X_ij (j <= i < nb), identity past the end
     const int nb = min(PS, n - k0);
 #pragma unroll
-    for (int u = 0; u < PS * PS / PT; ++u) {
-      const int idx = threadIdx.x + u * PT, i = idx / PS, j = idx % PS;
+    for (int u = 0; u < XE; ++u) {
+      const int idx = threadIdx.x + u * NT, i = idx / PS, j = idx % PS;
       const int ii = min(i, nb - 1);
       const B v = band[(size_t)(k0 + ii) * w + max(ii - j, 0)];
       e[u] = (i < nb && j <= i) ? v : B(i == j ? 1 : 0);
@@ -556,29 +577,34 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
   };
   auto x_store = [&]() {
 #pragma unroll
-    for (int u = 0; u < PS * PS / PT; ++u) Lb[threadIdx.x + u * PT] = e[u];
+    for (int u = 0; u < XE; ++u) Lb[threadIdx.x + u * NT] = e[u];
   };
-  // chunk c of row fi's band entries left of the step: column k0 + fi - d, d = fi + 1 + fq + 8 u + 8 CH c
-  // (entries past the row's band are not loaded and not used)
+  // chunk c of row fi's band entries left of the step: column k0 + fi - d,
+  // d = fi + 1 + fq + LPR u + LPR CH c (entries past the row's band are not
+  // loaded and not used)
   auto row_load = [&](int k0, int c, B (&l)[CH]) {
-    const int nb = min(PS, n - k0), d0 = fi + 1 + fq + 8 * CH * c;
+    const int nb = min(PS, n - k0), d0 = fi + 1 + fq + LPR * CH * c;
     const B *p = band + (size_t)(k0 + min(fi, nb - 1)) * w + d0;
 #pragma unroll
     for (int u = 0; u < CH; ++u)
-      if (8 * u <= bw - d0) l[u] = p[8 * u];
+      if (LPR * u <= bw - d0) l[u] = p[LPR * u];
   };
   auto row_dot = [&](int k0, int c, const B (&l)[CH], B (&acc)[NB]) {
-    const int nb = min(PS, n - k0), d0 = fi + 1 + fq + 8 * CH * c;
+    const int nb = min(PS, n - k0), d0 = fi + 1 + fq + LPR * CH * c;
     const int col0 = k0 + fi - d0;                            // column of u = 0
-    const int lim = fi < nb ? min(bw - d0, col0) : -1;        // u is used while 8 u <= lim
+    const int lim = fi < nb ? min(bw - d0, col0) : -1;        // u is used while LPR u <= lim
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
-      const bool ok = 8 * u <= lim;
-      const int idx = (col0 - 8 * u) & (RING - 1);
+      const bool ok = LPR * u <= lim;
+      const int idx = (col0 - LPR * u) & (RING - 1);
       for (int v = 0; v < NB; ++v) acc[v] += ok ? l[u] * ring[v * RING + idx] : B(0);
+      // under the smaller register budget of a larger work-group, keep the
+      // window reads of a few entries in flight, not of the whole chunk
+      if constexpr (NT > PT)
+        if (u % 4 == 3) __builtin_amdgcn_sched_barrier(0);
     }
   };
-  const int nchunk = (bw + 8 * CH - 1) / (8 * CH);
+  const int nchunk = (bw + LPR * CH - 1) / (LPR * CH);
   // ---- forward: L y = r
   B l[CH];
   double rv[NB];
@@ -609,11 +635,9 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
         for (int v = 0; v < NB; ++v) rv[v] = r[(size_t)v * ld + k0 + PS + fi];
       row_load(k0 + PS, 0, l);
     }
-    for (int v = 0; v < NB; ++v) {
-      acc[v] += __shfl_xor(acc[v], 1, 8);
-      acc[v] += __shfl_xor(acc[v], 2, 8);
-      acc[v] += __shfl_xor(acc[v], 4, 8);
-    }
+    for (int v = 0; v < NB; ++v)
+#pragma unroll
+      for (int o = 1; o < LPR; o <<= 1) acc[v] += __shfl_xor(acc[v], o, LPR);
     if (fq == 0 && fi < nb)
       for (int v = 0; v < NB; ++v) tb[v * PS + fi] = (B)rc[v] - acc[v];
     __syncthreads();  // tb holds t, Lb holds X
@@ -639,7 +663,7 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
   // column entries and entering rows are requested at the end of the step
   // before, after the next X (whose wait covers the loads issued before it).
   const int last = ((n - 1) / PS) * PS;
-  for (int i = max(0, last - PS - bw) + threadIdx.x; i < n; i += PT)
+  for (int i = max(0, last - PS - bw) + threadIdx.x; i < n; i += NT)
     for (int v = 0; v < NB; ++v) win(v, i) = tmp[(size_t)v * n + i];
   x_load(last);
   x_store();
@@ -647,10 +671,20 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
   // (entries outside the band are not loaded and not used)
   auto col_load = [&](int k0, int c, B (&lv)[PS]) {
     const int nb = min(PS, n - k0);
-    const B *p = band + (size_t)k0 * w + (k0 - c);  // p[j (w + 1)] = L(k0 + j, c)
+    if constexpr (NT > PT) {
+      // 32-bit byte offsets from the sample's band (fewer than 2^32 bytes for
+      // bw <= MAXBW): one address register per entry in flight
+      const unsigned o = (unsigned)(k0 * w + (k0 - c)) * (unsigned)sizeof(B);  // L(k0 + j, c) at o + j (w + 1) B
+      const unsigned step = (unsigned)(w + 1) * (unsigned)sizeof(B);
 #pragma unroll
-    for (int j = 0; j < PS; ++j)
-      if (j < nb && k0 + j - c <= bw) lv[j] = p[(size_t)j * (w + 1)];
+      for (int j = 0; j < PS; ++j)
+        if (j < nb && k0 + j - c <= bw) lv[j] = *(const B *)((const char *)band + (o + j * step));
+    } else {
+      const B *p = band + (size_t)k0 * w + (k0 - c);  // p[j (w + 1)] = L(k0 + j, c)
+#pragma unroll
+      for (int j = 0; j < PS; ++j)
+        if (j < nb && k0 + j - c <= bw) lv[j] = p[(size_t)j * (w + 1)];
+    }
   };
   B l0[PS], yin[NB];
   if (last - 1 - (int)threadIdx.x >= max(0, last - bw)) col_load(last, last - 1 - threadIdx.x, l0);
@@ -686,12 +720,14 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
           const B lj = (k0 + j - c <= bw) ? lv[j] : B(0);
           for (int v = 0; v < NB; ++v) acc[v] += lj * win(v, k0 + j);
         }
+        if constexpr (NT > PT)
+          if (j % 4 == 3) __builtin_amdgcn_sched_barrier(0);
       }
       for (int v = 0; v < NB; ++v) win(v, c) -= acc[v];
     };
     if (c0 >= lo) col_update(c0, l0);
-    if constexpr (MAXB >= PT) {  // bands at least as wide as the work-group: further columns
-      for (int c = c0 - PT; c >= lo; c -= PT) {
+    if constexpr (MAXB >= NT) {  // bands at least as wide as the work-group: further columns
+      for (int c = c0 - NT; c >= lo; c -= NT) {
         B lv[PS];
         col_load(k0, c, lv);
         col_update(c, lv);
@@ -708,6 +744,17 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
     }
   }
   __syncthreads();
+}
+
+// The band solve as a call of its own: at more than PT threads a work-group's
+// register budget is too small for the eigensolver's state and the solve's
+// loads in flight together, and a call keeps the solve's registers its own
+// (the caller's live state is saved once per call, not spilled inside the
+// solve's steps).
+template <typename B, int RING, int MAXB, int NT>
+__device__ __noinline__ void band_solve_call(const PlateGeom &g, const B *band, const double *r, double *z, int ld,
+                                             B *tmp) {
+  band_solve<B, RING, MAXB, NT>(g, band, r, z, ld, tmp);
 }
 
 // symmetric eigen-decomposition of a small dense matrix (cyclic Jacobi), one thread
@@ -910,11 +957,11 @@ struct EigResult {
 };
 
 // LOBPCG (block NB) for the largest mu of K_G x = mu K x with the factored
-// band as preconditioner; returns lambda = 1/mu
-template <typename B, int RING, int MAXB>
+// band as preconditioner, by a work-group of NT threads; returns lambda = 1/mu
+template <typename B, int RING, int MAXB, int NT = PT>
 __device__ __forceinline__ EigResult lobpcg(const PlateGeom &g, const double *Ke, const double *KGe, const B *band, double *vec,
                             double tol, int max_iter) {
-  __shared__ double red[4];
+  __shared__ double red[NT / 64];
   __shared__ double gram[2 * NS * NS];
   __shared__ double coef[NS * NB], mu[NB], resn[NB];
   __shared__ double rr_wk[RR_WORK];
@@ -925,7 +972,7 @@ __device__ __forceinline__ EigResult lobpcg(const PlateGeom &g, const double *Ke
   // for p = p0, p0 + 1 half-waves along x, p0 the integer nearest to a/b (a long
   // panel buckles in about a/b half-waves; 1 for a square panel)
   const int p0 = g.start_p0 > 0 ? g.start_p0 : max(1, (int)lround(g.a / g.b));
-  for (int r = threadIdx.x; r < n; r += PT) {
+  for (int r = threadIdx.x; r < n; r += NT) {
     const int full = g.full_of_free[r], node = full / 5, c = full % 5;
     const double x = (node % g.nnx) * g.hx, y = (node / g.nnx) * g.hy;
     for (int v = 0; v < NB; ++v) {
@@ -939,8 +986,13 @@ __device__ __forceinline__ EigResult lobpcg(const PlateGeom &g, const double *Ke
   }
   __syncthreads();
   for (int v = 0; v < NB; ++v) {
-    plate_apply<false>(g, Ke, V(V_X + v), V(V_KX + v));
-    plate_apply<true>(g, KGe, V(V_X + v), V(V_GX + v));
+    if constexpr (NT > PT) {
+      plate_apply_call<false, NT>(g, Ke, V(V_X + v), V(V_KX + v));
+      plate_apply_call<true, NT>(g, KGe, V(V_X + v), V(V_GX + v));
+    } else {
+      plate_apply<false, NT>(g, Ke, V(V_X + v), V(V_KX + v));
+      plate_apply<true, NT>(g, KGe, V(V_X + v), V(V_GX + v));
+    }
   }
   __syncthreads();
   int it = 0, have_p = 0;
@@ -950,25 +1002,25 @@ __device__ __forceinline__ EigResult lobpcg(const PlateGeom &g, const double *Ke
     double acc[2 * NB];
     for (int v = 0; v < NB; ++v) {
       double a = 0.0, b = 0.0;
-      for (int r = threadIdx.x; r < n; r += PT) {
+      for (int r = threadIdx.x; r < n; r += NT) {
         a += V(V_X + v)[r] * V(V_GX + v)[r];
         b += V(V_X + v)[r] * V(V_KX + v)[r];
       }
-      acc[2 * v] = block_reduce(a, red);
-      acc[2 * v + 1] = block_reduce(b, red);
+      acc[2 * v] = block_reduce<NT>(a, red);
+      acc[2 * v + 1] = block_reduce<NT>(b, red);
     }
     double rq[NB];
     for (int v = 0; v < NB; ++v) rq[v] = acc[2 * v] / acc[2 * v + 1];
     for (int v = 0; v < NB; ++v) {
       double rn = 0.0, kn = 0.0;
-      for (int r = threadIdx.x; r < n; r += PT) {
+      for (int r = threadIdx.x; r < n; r += NT) {
         const double rv = V(V_GX + v)[r] - rq[v] * V(V_KX + v)[r];
         V(V_R + v)[r] = rv;
         rn += rv * rv;
         kn += V(V_KX + v)[r] * V(V_KX + v)[r];
       }
-      rn = block_reduce(rn, red);
-      kn = block_reduce(kn, red);
+      rn = block_reduce<NT>(rn, red);
+      kn = block_reduce<NT>(kn, red);
       if (threadIdx.x == 0) resn[v] = sqrt(rn) / (fabs(rq[v]) * sqrt(kn));
     }
     __syncthreads();
@@ -976,10 +1028,18 @@ __device__ __forceinline__ EigResult lobpcg(const PlateGeom &g, const double *Ke
     res0 = resn[0];
     if (!(res0 > tol) || it >= max_iter || !isfinite(res0)) break;
     // W = T R with T = K^-1 (banded Cholesky)
-    band_solve<B, RING, MAXB>(g, band, V(V_R), V(V_W), n, (B *)V(V_T));
+    if constexpr (NT > PT)
+      band_solve_call<B, RING, MAXB, NT>(g, band, V(V_R), V(V_W), n, (B *)V(V_T));
+    else
+      band_solve<B, RING, MAXB, NT>(g, band, V(V_R), V(V_W), n, (B *)V(V_T));
     for (int v = 0; v < NB; ++v) {
-      plate_apply<false>(g, Ke, V(V_W + v), V(V_KW + v));
-      plate_apply<true>(g, KGe, V(V_W + v), V(V_GW + v));
+      if constexpr (NT > PT) {
+        plate_apply_call<false, NT>(g, Ke, V(V_W + v), V(V_KW + v));
+        plate_apply_call<true, NT>(g, KGe, V(V_W + v), V(V_GW + v));
+      } else {
+        plate_apply<false, NT>(g, Ke, V(V_W + v), V(V_KW + v));
+        plate_apply<true, NT>(g, KGe, V(V_W + v), V(V_GW + v));
+      }
     }
     __syncthreads();
     // Gram matrices of S = [X, W, P]
@@ -990,12 +1050,12 @@ __device__ __forceinline__ EigResult lobpcg(const PlateGeom &g, const double *Ke
         const int vj = (j < NB) ? V_X + j : (j < 2 * NB) ? V_W + j - NB : V_P + j - 2 * NB;
         const int gj = vj + (V_GX - V_X), kj = vj + (V_KX - V_X);
         double a = 0.0, b = 0.0;
-        for (int r = threadIdx.x; r < n; r += PT) {
+        for (int r = threadIdx.x; r < n; r += NT) {
           a += V(vi)[r] * V(gj)[r];
           b += V(vi)[r] * V(kj)[r];
         }
-        a = block_reduce(a, red);
-        b = block_reduce(b, red);
+        a = block_reduce<NT>(a, red);
+        b = block_reduce<NT>(b, red);
         if (threadIdx.x == 0) {
           gram[i * ms + j] = gram[j * ms + i] = a;
           gram[NS * NS + i * ms + j] = gram[NS * NS + j * ms + i] = b;
@@ -1005,7 +1065,7 @@ __device__ __forceinline__ EigResult lobpcg(const PlateGeom &g, const double *Ke
     if (threadIdx.x == 0) (void)rayleigh_ritz(gram, gram + NS * NS, ms, coef, mu, rr_wk, rr_iwk);
     __syncthreads();
     // new X = S c, new P = [W, P] c_{W,P}; images follow by linear combination
-    for (int r = threadIdx.x; r < n; r += PT) {
+    for (int r = threadIdx.x; r < n; r += NT) {
       for (int grp = 0; grp < 3; ++grp) {
         const int base = grp == 0 ? 0 : grp == 1 ? V_KX : V_GX;
         double xs[NS];
@@ -1298,13 +1358,14 @@ __global__ __launch_bounds__(PT) void k_invert_blocks(PlateGeom g, PlateWork W, 
   invert_blocks<B>(sample_band<B>(W, s), g.bw + 1, g.nfree, blockIdx.x * 8, 8, Ls);
 }
 
-// LOBPCG of each sample on its factored band (element matrices from W.kel)
-template <typename B>
-__global__ __launch_bounds__(PT) void k_plate_lobpcg(PlateGeom g, PlateWork W, PlateJob J, double tol, int max_iter) {
+// LOBPCG of each sample on its factored band (element matrices from W.kel),
+// one work-group of NT threads per sample
+template <typename B, int NT>
+__global__ __launch_bounds__(NT) void k_plate_lobpcg(PlateGeom g, PlateWork W, PlateJob J, double tol, int max_iter) {
   __shared__ double Ke[400], KGe[400];
   const int s = blockIdx.x;
   if (s >= J.n) return;
-  for (int k = threadIdx.x; k < 400; k += PT) {
+  for (int k = threadIdx.x; k < 400; k += NT) {
     Ke[k] = W.kel[(size_t)s * KEL + k];
     KGe[k] = W.kel[(size_t)s * KEL + 400 + k];
   }
@@ -1313,7 +1374,7 @@ __global__ __launch_bounds__(PT) void k_plate_lobpcg(PlateGeom g, PlateWork W, P
     if (threadIdx.x == 0) write_result(J, s, NAN, 0, 0.0, S_BREAKDOWN);
     return;
   }
-  const EigResult r = lobpcg<B, RING_WIDE, MAXBW>(g, Ke, KGe, sample_band<B>(W, s), W.vec + (size_t)s * W.vec_stride, tol,
+  const EigResult r = lobpcg<B, RING_WIDE, MAXBW, NT>(g, Ke, KGe, sample_band<B>(W, s), W.vec + (size_t)s * W.vec_stride, tol,
                                             max_iter);
   if (threadIdx.x == 0) {
     write_result(J, s, r.lam, r.it, r.res, r.status);
@@ -1393,13 +1454,15 @@ struct PlateCtx {
   size_t xf_cap = 0;
   size_t budget = 0;               // bound on the batch workspaces of all levels
   int wide_min_bw = 200;  // factorise over several work-groups from this band width on (0: from ONE_MAXBW on)
+  int wide_eig_threads = 1024;  // threads of the wide-band eigensolver's work-group (256 or 1024)
 };
 
 // the factorisation spread over work-groups: element matrices, band assembly
-// (256 rows per work-group), one launch per panel, then LOBPCG per sample
+// (256 rows per work-group), one launch per panel, then LOBPCG per sample in
+// one work-group of eig_nt threads
 template <typename B>
 static void launch_wide(const PlateGeom &g, const PlateMat &m, const PlateWork &W, const PlateJob &J, int n,
-                        double tol, int max_iter, hipStream_t st) {
+                        double tol, int max_iter, int eig_nt, hipStream_t st) {
   hipLaunchKernelGGL(k_plate_prep, dim3(n), dim3(PT), 0, st, g, m, W, J);
   const int rows_per_wg = 256;
   hipLaunchKernelGGL(k_plate_assemble<B>, dim3((g.nfree + rows_per_wg - 1) / rows_per_wg, n), dim3(PT), 0, st, g, W,
@@ -1413,7 +1476,10 @@ static void launch_wide(const PlateGeom &g, const PlateMat &m, const PlateWork &
     hipLaunchKernelGGL(k_band_step<B>, dim3(nwg, n), dim3(PT), 0, st, g, W, n, k0);
   const int nblk = (g.nfree + PS - 1) / PS;
   hipLaunchKernelGGL(k_invert_blocks<B>, dim3((nblk + 7) / 8, n), dim3(PT), 0, st, g, W, n);
-  hipLaunchKernelGGL(k_plate_lobpcg<B>, dim3(n), dim3(PT), 0, st, g, W, J, tol, max_iter);
+  if (eig_nt == 1024)
+    hipLaunchKernelGGL((k_plate_lobpcg<B, 1024>), dim3(n), dim3(1024), 0, st, g, W, J, tol, max_iter);
+  else
+    hipLaunchKernelGGL((k_plate_lobpcg<B, PT>), dim3(n), dim3(PT), 0, st, g, W, J, tol, max_iter);
   if (g.cert_shift > 0.0) {
     // lowest-mode check: FP64 factorisation of K - sigma K_G, spread as above
     hipLaunchKernelGGL(k_cert_assemble, dim3((g.nfree + rows_per_wg - 1) / rows_per_wg, n), dim3(PT), 0, st, g, W,
@@ -1484,6 +1550,11 @@ PlateCtx *plate_create(const Json &cfg, std::string &err) {
     p->max_iter = (int)cfg.number_or("eig_max_iter", 500);
     // band width from which one sample's factorisation is spread over work-groups
     p->wide_min_bw = (int)cfg.number_or("wide_factor_min_bw", 200);
+    // threads of the wide-band eigensolver's work-group: 1024 keeps a step's
+    // band entries in flight at once; 256 is the one-work-group kernel's form
+    p->wide_eig_threads = (int)cfg.number_or("wide_eig_threads", 1024);
+    if (p->wide_eig_threads != 256 && p->wide_eig_threads != 1024)
+      throw std::runtime_error("wide_eig_threads must be 256 or 1024");
     // half-waves along x of the first LOBPCG start vector (0: nearest to a / b)
     const int start_p0 = (int)cfg.number_or("eig_start_p0", 0);
     if (start_p0 < 0 || start_p0 > 64) throw std::runtime_error("eig_start_p0 must be in 0..64");
@@ -1692,8 +1763,8 @@ int plate_buckle_batch(PlateCtx *p, std::string &err, int n_req, const mlmc_requ
         }
         PlateJob J{offsets, L.rows, L.outidx, coarse ? lam_coarse : lam_fine, info, coarse, n};
         if (L.g.bw >= ONE_MAXBW || (p->wide_min_bw > 0 && L.g.bw >= p->wide_min_bw)) {
-          if (mixed) launch_wide<float>(L.g, p->mat, Wk, J, n, tl, p->max_iter, st);
-          else launch_wide<double>(L.g, p->mat, Wk, J, n, tl, p->max_iter, st);
+          if (mixed) launch_wide<float>(L.g, p->mat, Wk, J, n, tl, p->max_iter, p->wide_eig_threads, st);
+          else launch_wide<double>(L.g, p->mat, Wk, J, n, tl, p->max_iter, p->wide_eig_threads, st);
         } else if (mixed) {
           hipLaunchKernelGGL(k_buckle<float>, dim3(n), dim3(PT), 0, st, L.g, p->mat, Wk, J, tl, p->max_iter);
         } else {
