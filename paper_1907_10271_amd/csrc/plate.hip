@@ -335,10 +335,10 @@ __device__ bool factor_top(B *P, int c0, int nbs) {
 }
 
 // rows i0 .. rows - 1 of sub-panel columns c0 .. c0 + nbs - 1: forward
-// substitution with the factored top block, one thread per row
-template <int LD, typename B>
+// substitution with the factored top block, one thread per row (NT threads)
+template <int LD, typename B, int NT = PT>
 __device__ void factor_rows(B *P, int c0, int nbs, int i0, int rows) {
-  for (int i = i0 + threadIdx.x; i < rows; i += PT) {
+  for (int i = i0 + threadIdx.x; i < rows; i += NT) {
     B x[NBK];
 #pragma unroll
     for (int j = 0; j < NBK; ++j) x[j] = P[(c0 + j) * LD + i];
@@ -359,9 +359,9 @@ __device__ void factor_rows(B *P, int c0, int nbs, int i0, int rows) {
 
 // sub-panel A's product subtracted from sub-panel B's columns (rows NBK on):
 // the NBK-term sum of the NBK-column form's trailing update, one thread per row
-template <int LD, typename B>
+template <int LD, typename B, int NT = PT>
 __device__ void update_b(B *P, int nb, int rows) {
-  for (int i = NBK + threadIdx.x; i < rows; i += PT) {
+  for (int i = NBK + threadIdx.x; i < rows; i += NT) {
     B x[NBK];
 #pragma unroll
     for (int j = 0; j < NBK; ++j) x[j] = P[j * LD + i];
@@ -1217,8 +1217,11 @@ __global__ __launch_bounds__(PT) void k_plate_assemble(PlateGeom g, PlateWork W,
   if (r0 < r1) assemble_band<B>(g, Ke, sample_band<B>(W, s), r0, r1, threadIdx.x, PT);
 }
 
-template <typename B>
-__global__ __launch_bounds__(PT) void k_band_step(PlateGeom g, PlateWork W, int n, int k0) {
+// one panel of the wide factorisation (launch k0 / KP of a sample's band), in
+// work-groups of NTB threads; a row's and a tile's arithmetic is one thread's
+// whatever NTB, so the factor does not depend on it
+template <typename B, int NTB>
+__global__ __launch_bounds__(NTB) void k_band_step(PlateGeom g, PlateWork W, int n, int k0) {
   // one LDS area, column-major (columns contiguous: the tiles' reads are free of
   // bank conflicts): work-group 0 stages this panel in it (KP x LDPW), the others
   // the previous panel's columns on the rows of its trailing window (KP x MAXBW)
@@ -1241,7 +1244,7 @@ __global__ __launch_bounds__(PT) void k_band_step(PlateGeom g, PlateWork W, int 
     const int rows = min(nb + g.bw, nf - k0);  // panel rows k0 .. k0 + rows - 1
     if (threadIdx.x == 0) bad = 0;
     // the previous panel's columns on this panel's rows (the pc side of its update)
-    for (int idx = threadIdx.x; idx < KP * KP; idx += PT) {
+    for (int idx = threadIdx.x; idx < KP * KP; idx += NTB) {
       const int j = idx / KP, c = idx % KP;  // row k0 + j, previous column k0 - KP + c
       const bool in = k0 > 0 && j < nb && j + KP - c <= g.bw;
       Lq[c * KP + j] = in ? band[(size_t)(k0 + j) * w + (j + KP - c)] : B(0);
@@ -1249,7 +1252,7 @@ __global__ __launch_bounds__(PT) void k_band_step(PlateGeom g, PlateWork W, int 
     __syncthreads();
     // each row of the panel: its entries, less the previous panel's two
     // NBK-term sums (sub-panel A first) where the row is inside that panel's window
-    for (int i = threadIdx.x; i < rows; i += PT) {
+    for (int i = threadIdx.x; i < rows; i += NTB) {
       const B *row = band + (size_t)(k0 + i) * w;
       B e[KP];
 #pragma unroll
@@ -1281,10 +1284,10 @@ __global__ __launch_bounds__(PT) void k_band_step(PlateGeom g, PlateWork W, int 
       if (threadIdx.x == 0) W.flag[s] = 1;
       return;
     }
-    factor_rows<LDPW>(P, 0, nbA, nbA, rows);
+    factor_rows<LDPW, B, NTB>(P, 0, nbA, nbA, rows);
     __syncthreads();
     if (nbB > 0) {
-      update_b<LDPW>(P, nb, rows);
+      update_b<LDPW, B, NTB>(P, nb, rows);
       __syncthreads();
       if (threadIdx.x == 0 && !factor_top<LDPW>(P, NBK, nbB)) bad = 1;
       __syncthreads();
@@ -1292,10 +1295,10 @@ __global__ __launch_bounds__(PT) void k_band_step(PlateGeom g, PlateWork W, int 
         if (threadIdx.x == 0) W.flag[s] = 1;
         return;
       }
-      factor_rows<LDPW>(P, NBK, nbB, nb, rows);
+      factor_rows<LDPW, B, NTB>(P, NBK, nbB, nb, rows);
       __syncthreads();
     }
-    for (int idx = threadIdx.x; idx < rows * KP; idx += PT) {
+    for (int idx = threadIdx.x; idx < rows * KP; idx += NTB) {
       const int i = idx / KP, j = idx % KP;
       if (j < nb && i >= j && i - j <= g.bw) band[(size_t)(k0 + i) * w + (i - j)] = P[j * LDPW + i];
     }
@@ -1306,7 +1309,7 @@ __global__ __launch_bounds__(PT) void k_band_step(PlateGeom g, PlateWork W, int 
   // one-work-group form
   if (m <= 0 || nwg < 2) return;
   B *Lp = S;
-  for (int r = threadIdx.x; r < m; r += PT) {  // one thread per band row: its KP entries are contiguous
+  for (int r = threadIdx.x; r < m; r += NTB) {  // one thread per band row: its KP entries are contiguous
     const B *row = band + (size_t)(k0 + r) * w;
     B v[KP];
 #pragma unroll
@@ -1316,7 +1319,7 @@ __global__ __launch_bounds__(PT) void k_band_step(PlateGeom g, PlateWork W, int 
   }
   __syncthreads();
   const int mt = (m + 3) / 4, ntile = mt * (mt + 1) / 2;
-  for (int tix = (wg - 1) * PT + threadIdx.x; tix < ntile; tix += (nwg - 1) * PT) {
+  for (int tix = (wg - 1) * NTB + threadIdx.x; tix < ntile; tix += (nwg - 1) * NTB) {
     int ti = (int)((sqrtf(8.0f * tix + 1.0f) - 1.0f) * 0.5f);  // corrected below
     while ((ti + 1) * (ti + 2) / 2 <= tix) ++ti;
     while (ti * (ti + 1) / 2 > tix) --ti;
@@ -1455,25 +1458,39 @@ struct PlateCtx {
   size_t budget = 0;               // bound on the batch workspaces of all levels
   int wide_min_bw = 200;  // factorise over several work-groups from this band width on (0: from ONE_MAXBW on)
   int wide_eig_threads = 1024;  // threads of the wide-band eigensolver's work-group (256 or 1024)
+  int wide_factor_threads = 1024;  // threads of a panel launch's work-groups (256 or 1024)
 };
 
 // the factorisation spread over work-groups: element matrices, band assembly
 // (256 rows per work-group), one launch per panel, then LOBPCG per sample in
 // one work-group of eig_nt threads
+template <typename B, int NTB>
+static void launch_band_steps(const PlateGeom &g, const PlateWork &W, int n, hipStream_t st) {
+  // work-groups per sample: work-group 0 plus enough for the window's 4 x 4
+  // tiles (one per thread), fewer when many samples share the launch
+  const int mt = (g.bw + 3) / 4, ntile = mt * (mt + 1) / 2;
+  const int need = 1 + (ntile + NTB - 1) / NTB;
+  const int nwg = std::max(2, std::min(need, std::max(2, (2048 * PT / NTB) / std::max(n, 1))));
+  for (int k0 = 0; k0 < g.nfree; k0 += KP)
+    hipLaunchKernelGGL((k_band_step<B, NTB>), dim3(nwg, n), dim3(NTB), 0, st, g, W, n, k0);
+}
+
+template <typename B>
+static void band_steps(const PlateGeom &g, const PlateWork &W, int n, int ntb, hipStream_t st) {
+  if (ntb == 1024)
+    launch_band_steps<B, 1024>(g, W, n, st);
+  else
+    launch_band_steps<B, PT>(g, W, n, st);
+}
+
 template <typename B>
 static void launch_wide(const PlateGeom &g, const PlateMat &m, const PlateWork &W, const PlateJob &J, int n,
-                        double tol, int max_iter, int eig_nt, hipStream_t st) {
+                        double tol, int max_iter, int eig_nt, int ntb, hipStream_t st) {
   hipLaunchKernelGGL(k_plate_prep, dim3(n), dim3(PT), 0, st, g, m, W, J);
   const int rows_per_wg = 256;
   hipLaunchKernelGGL(k_plate_assemble<B>, dim3((g.nfree + rows_per_wg - 1) / rows_per_wg, n), dim3(PT), 0, st, g, W,
                      n, rows_per_wg);
-  // work-groups per sample: work-group 0 plus enough for the window's 4 x 4
-  // tiles (one per thread), fewer when many samples share the launch
-  const int mt = (g.bw + 3) / 4, ntile = mt * (mt + 1) / 2;
-  const int need = 1 + (ntile + PT - 1) / PT;
-  const int nwg = std::max(2, std::min(need, std::max(2, 2048 / std::max(n, 1))));
-  for (int k0 = 0; k0 < g.nfree; k0 += KP)
-    hipLaunchKernelGGL(k_band_step<B>, dim3(nwg, n), dim3(PT), 0, st, g, W, n, k0);
+  band_steps<B>(g, W, n, ntb, st);
   const int nblk = (g.nfree + PS - 1) / PS;
   hipLaunchKernelGGL(k_invert_blocks<B>, dim3((nblk + 7) / 8, n), dim3(PT), 0, st, g, W, n);
   if (eig_nt == 1024)
@@ -1484,8 +1501,7 @@ static void launch_wide(const PlateGeom &g, const PlateMat &m, const PlateWork &
     // lowest-mode check: FP64 factorisation of K - sigma K_G, spread as above
     hipLaunchKernelGGL(k_cert_assemble, dim3((g.nfree + rows_per_wg - 1) / rows_per_wg, n), dim3(PT), 0, st, g, W,
                        n, rows_per_wg);
-    for (int k0 = 0; k0 < g.nfree; k0 += KP)
-      hipLaunchKernelGGL(k_band_step<double>, dim3(nwg, n), dim3(PT), 0, st, g, W, n, k0);
+    band_steps<double>(g, W, n, ntb, st);
     hipLaunchKernelGGL(k_cert_finish, dim3((n + 255) / 256), dim3(256), 0, st, W, J);
   }
 }
@@ -1555,6 +1571,10 @@ PlateCtx *plate_create(const Json &cfg, std::string &err) {
     p->wide_eig_threads = (int)cfg.number_or("wide_eig_threads", 1024);
     if (p->wide_eig_threads != 256 && p->wide_eig_threads != 1024)
       throw std::runtime_error("wide_eig_threads must be 256 or 1024");
+    // threads of a panel launch's work-groups (the factor is the same either way)
+    p->wide_factor_threads = (int)cfg.number_or("wide_factor_threads", 1024);
+    if (p->wide_factor_threads != 256 && p->wide_factor_threads != 1024)
+      throw std::runtime_error("wide_factor_threads must be 256 or 1024");
     // half-waves along x of the first LOBPCG start vector (0: nearest to a / b)
     const int start_p0 = (int)cfg.number_or("eig_start_p0", 0);
     if (start_p0 < 0 || start_p0 > 64) throw std::runtime_error("eig_start_p0 must be in 0..64");
@@ -1763,8 +1783,11 @@ int plate_buckle_batch(PlateCtx *p, std::string &err, int n_req, const mlmc_requ
         }
         PlateJob J{offsets, L.rows, L.outidx, coarse ? lam_coarse : lam_fine, info, coarse, n};
         if (L.g.bw >= ONE_MAXBW || (p->wide_min_bw > 0 && L.g.bw >= p->wide_min_bw)) {
-          if (mixed) launch_wide<float>(L.g, p->mat, Wk, J, n, tl, p->max_iter, p->wide_eig_threads, st);
-          else launch_wide<double>(L.g, p->mat, Wk, J, n, tl, p->max_iter, p->wide_eig_threads, st);
+          if (mixed)
+            launch_wide<float>(L.g, p->mat, Wk, J, n, tl, p->max_iter, p->wide_eig_threads, p->wide_factor_threads, st);
+          else
+            launch_wide<double>(L.g, p->mat, Wk, J, n, tl, p->max_iter, p->wide_eig_threads, p->wide_factor_threads,
+                                st);
         } else if (mixed) {
           hipLaunchKernelGGL(k_buckle<float>, dim3(n), dim3(PT), 0, st, L.g, p->mat, Wk, J, tl, p->max_iter);
         } else {
