@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 namespace mlmc {
@@ -28,6 +29,9 @@ constexpr int NB = 2;        // LOBPCG block size
 constexpr int NS = 3 * NB;   // Rayleigh-Ritz basis size [X, W, P]
 constexpr int MAXPLY = 32;
 constexpr int MAXBW = 664;  // largest band half-width (128 x 128 mesh: 654)
+// entries allocated past the last band of a workspace: the wide band solve
+// reads up to MAXBW + 64 entries past a row's band without using them
+constexpr size_t BAND_PAD = MAXBW + 128;
 // bands narrower than this are factored and solved by one work-group per
 // sample (k_buckle); wider ones always take the wide form
 constexpr int ONE_MAXBW = 256;
@@ -183,11 +187,13 @@ __device__ void element_matrices(const PlateGeom &g, const PlateMat &m, const do
 }
 
 // y = P K P x on the free unknowns (element-by-element gather at every node),
-// rows shared out over the NT threads of the work-group
-template <bool GEOM, int NT = PT>
-__device__ void plate_apply(const PlateGeom &g, const double *Ke, const double *x, double *y) {
+// rows shared out over the NT threads of the work-group (pointer types as the
+// caller names them: the call form below names their memory)
+template <bool GEOM, int NT, typename KPtr, typename XPtr, typename YPtr, typename IPtr>
+__device__ __forceinline__ void plate_apply_body(const PlateGeom &g, KPtr Ke, XPtr x, YPtr y, IPtr full_of_free,
+                                                 IPtr free_of_full) {
   for (int r = threadIdx.x; r < g.nfree; r += NT) {
-    const int full = g.full_of_free[r];
+    const int full = full_of_free[r];
     const int node = full / 5, c = full % 5;
     double acc = 0.0;
     if (!GEOM || c == 2) {
@@ -199,10 +205,10 @@ __device__ void plate_apply(const PlateGeom &g, const double *Ke, const double *
         const int n0 = ey * g.nnx + ex;
         const int nodes[4] = {n0, n0 + 1, n0 + g.nnx + 1, n0 + g.nnx};
         const int a = (e == 0) ? 2 : (e == 1) ? 3 : (e == 2) ? 1 : 0;  // local index of the node
-        const double *row = Ke + 20 * (5 * a + c);
+        const auto row = Ke + 20 * (5 * a + c);
         for (int b2 = 0; b2 < 4; ++b2)
           for (int d = (GEOM ? 2 : 0); d < (GEOM ? 3 : 5); ++d) {
-            const int f = g.free_of_full[5 * nodes[b2] + d];
+            const int f = free_of_full[5 * nodes[b2] + d];
             if (f >= 0) acc += row[5 * b2 + d] * x[f];
           }
       }
@@ -211,12 +217,22 @@ __device__ void plate_apply(const PlateGeom &g, const double *Ke, const double *
   }
 }
 
+template <bool GEOM, int NT = PT>
+__device__ void plate_apply(const PlateGeom &g, const double *Ke, const double *x, double *y) {
+  plate_apply_body<GEOM, NT>(g, Ke, x, y, g.full_of_free, g.free_of_full);
+}
+
 // plate_apply as a call of its own, for work-groups of more than PT threads,
 // whose register budget the inlined gathers would share with the
 // eigensolver's state
 template <bool GEOM, int NT>
 __device__ __noinline__ void plate_apply_call(const PlateGeom &g, const double *Ke, const double *x, double *y) {
-  plate_apply<GEOM, NT>(g, Ke, x, y);
+  // Ke is the work-group's LDS copy, x, y and the index maps global memory
+  using KL = const __attribute__((address_space(3))) double *;
+  using XG = const __attribute__((address_space(1))) double *;
+  using YG = __attribute__((address_space(1))) double *;
+  using IG = const __attribute__((address_space(1))) int *;
+  plate_apply_body<GEOM, NT>(g, (KL)Ke, (XG)x, (YG)y, (IG)g.full_of_free, (IG)g.free_of_full);
 }
 
 // lower band of K on the free unknowns: band[r][d] = K[r][r - d], d = 0..bw
@@ -560,34 +576,68 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
   constexpr int MAXCHUNK = (MAXB + LPR * CH - 1) / (LPR * CH);  // chunks of the widest band (bw <= MAXB)
   constexpr int XE = PS * PS / NT;                              // entries of X per thread
   const int w = g.bw + 1, n = g.nfree, bw = g.bw;
+  // At more than PT threads the solve is a call of its own, whose pointer
+  // arguments the compiler cannot place: named as global memory, its loads
+  // count only against the vector-memory counter, so the waits for LDS
+  // accesses do not also wait for the band entries in flight.  Loads are
+  // then issued unconditionally (addresses clamped into the band, values
+  // masked where used), so each wait covers just the loads it needs.
+  constexpr bool LONG = NT > PT;
+  using BP = std::conditional_t<LONG, const __attribute__((address_space(1))) B *, const B *>;
+  using RP = std::conditional_t<LONG, const __attribute__((address_space(1))) double *, const double *>;
+  using ZP = std::conditional_t<LONG, __attribute__((address_space(1))) double *, double *>;
+  using TP = std::conditional_t<LONG, __attribute__((address_space(1))) B *, B *>;
+  const BP bandp = (BP)band;
+  const RP rp = (RP)r;
+  const ZP zp = (ZP)z;
+  const TP tp = (TP)tmp;
   __shared__ B ring[NB * RING], Lb[PS * PS], tb[NB * PS];
   auto win = [&](int v, int row) -> B & { return ring[v * RING + (row & (RING - 1))]; };
   const int v2 = threadIdx.x / PS, i2 = threadIdx.x % PS;  // mat-vec lanes (wave 0)
   const int fi = threadIdx.x / LPR, fq = threadIdx.x % LPR; // forward: row fi of the step, part fq
   B e[XE];
+  int xnb = 0;  // rows of the step whose X is in e
   auto x_load = [&](int k0) {  // X of the step at k0: Lb[i PS + j] = X_ij (j <= i < nb), identity past the end
     const int nb = min(PS, n - k0);
+    xnb = nb;
 #pragma unroll
     for (int u = 0; u < XE; ++u) {
       const int idx = threadIdx.x + u * NT, i = idx / PS, j = idx % PS;
       const int ii = min(i, nb - 1);
-      const B v = band[(size_t)(k0 + ii) * w + max(ii - j, 0)];
-      e[u] = (i < nb && j <= i) ? v : B(i == j ? 1 : 0);
+      const B v = bandp[(size_t)(k0 + ii) * w + max(ii - j, 0)];
+      if constexpr (LONG)
+        e[u] = v;  // masked in x_store
+      else
+        e[u] = (i < nb && j <= i) ? v : B(i == j ? 1 : 0);
     }
   };
   auto x_store = [&]() {
 #pragma unroll
-    for (int u = 0; u < XE; ++u) Lb[threadIdx.x + u * NT] = e[u];
+    for (int u = 0; u < XE; ++u) {
+      const int idx = threadIdx.x + u * NT, i = idx / PS, j = idx % PS;
+      if constexpr (LONG)
+        Lb[idx] = (i < xnb && j <= i) ? e[u] : B(i == j ? 1 : 0);
+      else
+        Lb[idx] = e[u];
+    }
   };
   // chunk c of row fi's band entries left of the step: column k0 + fi - d,
   // d = fi + 1 + fq + LPR u + LPR CH c (entries past the row's band are not
-  // loaded and not used)
+  // used)
   auto row_load = [&](int k0, int c, B (&l)[CH]) {
     const int nb = min(PS, n - k0), d0 = fi + 1 + fq + LPR * CH * c;
-    const B *p = band + (size_t)(k0 + min(fi, nb - 1)) * w + d0;
+    if constexpr (LONG) {
+      // past the row's band the reads land in the next row or in the band
+      // allocation's padding (BAND_PAD entries)
+      const BP p = bandp + (size_t)(k0 + min(fi, nb - 1)) * w + d0;
 #pragma unroll
-    for (int u = 0; u < CH; ++u)
-      if (LPR * u <= bw - d0) l[u] = p[LPR * u];
+      for (int u = 0; u < CH; ++u) l[u] = p[LPR * u];
+    } else {
+      const B *p = bandp + (size_t)(k0 + min(fi, nb - 1)) * w + d0;
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (LPR * u <= bw - d0) l[u] = p[LPR * u];
+    }
   };
   auto row_dot = [&](int k0, int c, const B (&l)[CH], B (&acc)[NB]) {
     const int nb = min(PS, n - k0), d0 = fi + 1 + fq + LPR * CH * c;
@@ -609,8 +659,8 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
   B l[CH];
   double rv[NB];
   row_load(0, 0, l);
-  if (fq == 0 && fi < min(PS, n))
-    for (int v = 0; v < NB; ++v) rv[v] = r[(size_t)v * ld + fi];
+  if (LONG || (fq == 0 && fi < min(PS, n)))
+    for (int v = 0; v < NB; ++v) rv[v] = rp[(size_t)v * ld + (LONG ? min(fi, n - 1) : fi)];
   x_load(0);
   x_store();
   for (int k0 = 0; k0 < n; k0 += PS) {
@@ -631,8 +681,8 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
       // barriers; X first, since its wait at the end of this step covers all
       // loads issued before it
       x_load(k0 + PS);
-      if (fq == 0 && fi < min(PS, n - k0 - PS))
-        for (int v = 0; v < NB; ++v) rv[v] = r[(size_t)v * ld + k0 + PS + fi];
+      if (LONG || (fq == 0 && fi < min(PS, n - k0 - PS)))
+        for (int v = 0; v < NB; ++v) rv[v] = rp[(size_t)v * ld + (LONG ? min(k0 + PS + fi, n - 1) : k0 + PS + fi)];
       row_load(k0 + PS, 0, l);
     }
     for (int v = 0; v < NB; ++v)
@@ -652,7 +702,7 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
       const B y = (y4[0] + y4[1]) + (y4[2] + y4[3]);
       if (i2 < nb) {
         win(v2, k0 + i2) = y;
-        tmp[(size_t)v2 * n + k0 + i2] = y;
+        tp[(size_t)v2 * n + k0 + i2] = y;
       }
     }
     __syncthreads();  // y of the step in the window; Lb free
@@ -664,32 +714,41 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
   // before, after the next X (whose wait covers the loads issued before it).
   const int last = ((n - 1) / PS) * PS;
   for (int i = max(0, last - PS - bw) + threadIdx.x; i < n; i += NT)
-    for (int v = 0; v < NB; ++v) win(v, i) = tmp[(size_t)v * n + i];
+    for (int v = 0; v < NB; ++v) win(v, i) = tp[(size_t)v * n + i];
   x_load(last);
   x_store();
   // column c of step k0: L(k0 + j, c) = band[(k0 + j) w + k0 + j - c], for k0 + j - c <= bw
   // (entries outside the band are not loaded and not used)
   auto col_load = [&](int k0, int c, B (&lv)[PS]) {
     const int nb = min(PS, n - k0);
-    if constexpr (NT > PT) {
+    if constexpr (LONG) {
       // 32-bit byte offsets from the sample's band (fewer than 2^32 bytes for
-      // bw <= MAXBW): one address register per entry in flight
+      // bw <= MAXBW): one address register per entry in flight; rows past the
+      // last and entries past the band read a clamped position (masked where
+      // used)
+      // (past the band the reads land in the next row or in the padding)
+      using CP = const __attribute__((address_space(1))) char *;
       const unsigned o = (unsigned)(k0 * w + (k0 - c)) * (unsigned)sizeof(B);  // L(k0 + j, c) at o + j (w + 1) B
       const unsigned step = (unsigned)(w + 1) * (unsigned)sizeof(B);
 #pragma unroll
-      for (int j = 0; j < PS; ++j)
-        if (j < nb && k0 + j - c <= bw) lv[j] = *(const B *)((const char *)band + (o + j * step));
+      for (int j = 0; j < PS; ++j) lv[j] = *(BP)((CP)bandp + (o + min(j, nb - 1) * step));
     } else {
-      const B *p = band + (size_t)k0 * w + (k0 - c);  // p[j (w + 1)] = L(k0 + j, c)
+      const B *p = bandp + (size_t)k0 * w + (k0 - c);  // p[j (w + 1)] = L(k0 + j, c)
 #pragma unroll
       for (int j = 0; j < PS; ++j)
         if (j < nb && k0 + j - c <= bw) lv[j] = p[(size_t)j * (w + 1)];
     }
   };
   B l0[PS], yin[NB];
-  if (last - 1 - (int)threadIdx.x >= max(0, last - bw)) col_load(last, last - 1 - threadIdx.x, l0);
-  if (threadIdx.x < PS && last - 2 * PS - bw + (int)threadIdx.x >= 0)
-    for (int v = 0; v < NB; ++v) yin[v] = tmp[(size_t)v * n + last - 2 * PS - bw + threadIdx.x];
+  if constexpr (LONG) {  // every thread loads (clamped column and row), used where in range
+    col_load(last, max(last - 1 - (int)threadIdx.x, max(0, last - bw)), l0);
+    for (int v = 0; v < NB; ++v)
+      yin[v] = tp[(size_t)v * n + min(max(last - 2 * PS - bw + (int)threadIdx.x, 0), n - 1)];
+  } else {
+    if (last - 1 - (int)threadIdx.x >= max(0, last - bw)) col_load(last, last - 1 - threadIdx.x, l0);
+    if (threadIdx.x < PS && last - 2 * PS - bw + (int)threadIdx.x >= 0)
+      for (int v = 0; v < NB; ++v) yin[v] = tp[(size_t)v * n + last - 2 * PS - bw + threadIdx.x];
+  }
   for (int k0 = last; k0 >= 0; k0 -= PS) {
     const int nb = min(PS, n - k0);
     const bool next = k0 > 0;
@@ -706,7 +765,7 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
       const B y = (y4[0] + y4[1]) + (y4[2] + y4[3]);
       if (i2 < nb) {
         win(v2, k0 + i2) = y;  // every lane has read the window rows (one wave)
-        z[(size_t)v2 * ld + k0 + i2] = (double)y;
+        zp[(size_t)v2 * ld + k0 + i2] = (double)y;
       }
     }
     __syncthreads();
@@ -737,9 +796,14 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
       for (int v = 0; v < NB; ++v) win(v, ent) = yin[v];
     if (next) {
       const int kn = k0 - PS, cn = kn - 1 - threadIdx.x, en = kn - 2 * PS - bw + threadIdx.x;
-      if (cn >= max(0, kn - bw)) col_load(kn, cn, l0);
-      if (threadIdx.x < PS && en >= 0)
-        for (int v = 0; v < NB; ++v) yin[v] = tmp[(size_t)v * n + en];
+      if constexpr (LONG) {
+        col_load(kn, max(cn, max(0, kn - bw)), l0);
+        for (int v = 0; v < NB; ++v) yin[v] = tp[(size_t)v * n + min(max(en, 0), n - 1)];
+      } else {
+        if (cn >= max(0, kn - bw)) col_load(kn, cn, l0);
+        if (threadIdx.x < PS && en >= 0)
+          for (int v = 0; v < NB; ++v) yin[v] = tp[(size_t)v * n + en];
+      }
       x_store();
     }
   }
@@ -1669,8 +1733,8 @@ static int ensure_work(PlateCtx *p, std::string &err, int l, int n) {
   }
   free_work(L);
   const size_t bs = (size_t)L.g.nfree * (L.g.bw + 1);
-  if (hipMalloc(&L.band, bs * sizeof(double) * n) != hipSuccess ||
-      hipMalloc(&L.bandf, bs * sizeof(float) * n) != hipSuccess ||
+  if (hipMalloc(&L.band, (bs * n + BAND_PAD) * sizeof(double)) != hipSuccess ||
+      hipMalloc(&L.bandf, (bs * n + BAND_PAD) * sizeof(float)) != hipSuccess ||
       hipMalloc(&L.vec, (size_t)NVEC * L.g.nfree * sizeof(double) * n) != hipSuccess ||
       hipMalloc(&L.rows, sizeof(int64_t) * n) != hipSuccess || hipMalloc(&L.outidx, sizeof(int) * n) != hipSuccess ||
       hipMalloc(&L.kel, sizeof(double) * KEL * n) != hipSuccess || hipMalloc(&L.flag, sizeof(int) * n) != hipSuccess ||
