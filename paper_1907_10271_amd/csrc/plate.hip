@@ -583,6 +583,7 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
   // then issued unconditionally (addresses clamped into the band, values
   // masked where used), so each wait covers just the loads it needs.
   constexpr bool LONG = NT > PT;
+  constexpr bool EXACT = true;  // unconditional loads (every form)
   using BP = std::conditional_t<LONG, const __attribute__((address_space(1))) B *, const B *>;
   using RP = std::conditional_t<LONG, const __attribute__((address_space(1))) double *, const double *>;
   using ZP = std::conditional_t<LONG, __attribute__((address_space(1))) double *, double *>;
@@ -605,7 +606,7 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
       const int idx = threadIdx.x + u * NT, i = idx / PS, j = idx % PS;
       const int ii = min(i, nb - 1);
       const B v = bandp[(size_t)(k0 + ii) * w + max(ii - j, 0)];
-      if constexpr (LONG)
+      if constexpr (EXACT)
         e[u] = v;  // masked in x_store
       else
         e[u] = (i < nb && j <= i) ? v : B(i == j ? 1 : 0);
@@ -615,7 +616,7 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
 #pragma unroll
     for (int u = 0; u < XE; ++u) {
       const int idx = threadIdx.x + u * NT, i = idx / PS, j = idx % PS;
-      if constexpr (LONG)
+      if constexpr (EXACT)
         Lb[idx] = (i < xnb && j <= i) ? e[u] : B(i == j ? 1 : 0);
       else
         Lb[idx] = e[u];
@@ -626,7 +627,7 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
   // used)
   auto row_load = [&](int k0, int c, B (&l)[CH]) {
     const int nb = min(PS, n - k0), d0 = fi + 1 + fq + LPR * CH * c;
-    if constexpr (LONG) {
+    if constexpr (EXACT) {
       // past the row's band the reads land in the next row or in the band
       // allocation's padding (BAND_PAD entries)
       const BP p = bandp + (size_t)(k0 + min(fi, nb - 1)) * w + d0;
@@ -659,8 +660,8 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
   B l[CH];
   double rv[NB];
   row_load(0, 0, l);
-  if (LONG || (fq == 0 && fi < min(PS, n)))
-    for (int v = 0; v < NB; ++v) rv[v] = rp[(size_t)v * ld + (LONG ? min(fi, n - 1) : fi)];
+  if (EXACT || (fq == 0 && fi < min(PS, n)))
+    for (int v = 0; v < NB; ++v) rv[v] = rp[(size_t)v * ld + (EXACT ? min(fi, n - 1) : fi)];
   x_load(0);
   x_store();
   for (int k0 = 0; k0 < n; k0 += PS) {
@@ -681,8 +682,8 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
       // barriers; X first, since its wait at the end of this step covers all
       // loads issued before it
       x_load(k0 + PS);
-      if (LONG || (fq == 0 && fi < min(PS, n - k0 - PS)))
-        for (int v = 0; v < NB; ++v) rv[v] = rp[(size_t)v * ld + (LONG ? min(k0 + PS + fi, n - 1) : k0 + PS + fi)];
+      if (EXACT || (fq == 0 && fi < min(PS, n - k0 - PS)))
+        for (int v = 0; v < NB; ++v) rv[v] = rp[(size_t)v * ld + (EXACT ? min(k0 + PS + fi, n - 1) : k0 + PS + fi)];
       row_load(k0 + PS, 0, l);
     }
     for (int v = 0; v < NB; ++v)
@@ -721,7 +722,7 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
   // (entries outside the band are not loaded and not used)
   auto col_load = [&](int k0, int c, B (&lv)[PS]) {
     const int nb = min(PS, n - k0);
-    if constexpr (LONG) {
+    if constexpr (EXACT) {
       // 32-bit byte offsets from the sample's band (fewer than 2^32 bytes for
       // bw <= MAXBW): one address register per entry in flight; rows past the
       // last and entries past the band read a clamped position (masked where
@@ -740,7 +741,7 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
     }
   };
   B l0[PS], yin[NB];
-  if constexpr (LONG) {  // every thread loads (clamped column and row), used where in range
+  if constexpr (EXACT) {  // every thread loads (clamped column and row), used where in range
     col_load(last, max(last - 1 - (int)threadIdx.x, max(0, last - bw)), l0);
     for (int v = 0; v < NB; ++v)
       yin[v] = tp[(size_t)v * n + min(max(last - 2 * PS - bw + (int)threadIdx.x, 0), n - 1)];
@@ -796,7 +797,7 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
       for (int v = 0; v < NB; ++v) win(v, ent) = yin[v];
     if (next) {
       const int kn = k0 - PS, cn = kn - 1 - threadIdx.x, en = kn - 2 * PS - bw + threadIdx.x;
-      if constexpr (LONG) {
+      if constexpr (EXACT) {
         col_load(kn, max(cn, max(0, kn - bw)), l0);
         for (int v = 0; v < NB; ++v) yin[v] = tp[(size_t)v * n + min(max(en, 0), n - 1)];
       } else {
