@@ -217,9 +217,17 @@ __device__ __forceinline__ void plate_apply_body(const PlateGeom &g, KPtr Ke, XP
   }
 }
 
+// pointers as the gathers use them: every caller passes the element matrix as
+// its work-group's LDS copy, the vectors and index maps live in global memory
+// (named so, their loads are not generic: LDS waits do not wait for them)
+using KLds = const __attribute__((address_space(3))) double *;
+using XGlb = const __attribute__((address_space(1))) double *;
+using YGlb = __attribute__((address_space(1))) double *;
+using IGlb = const __attribute__((address_space(1))) int *;
+
 template <bool GEOM, int NT = PT>
 __device__ void plate_apply(const PlateGeom &g, const double *Ke, const double *x, double *y) {
-  plate_apply_body<GEOM, NT>(g, Ke, x, y, g.full_of_free, g.free_of_full);
+  plate_apply_body<GEOM, NT>(g, (KLds)Ke, (XGlb)x, (YGlb)y, (IGlb)g.full_of_free, (IGlb)g.free_of_full);
 }
 
 // plate_apply as a call of its own, for work-groups of more than PT threads,
@@ -227,25 +235,22 @@ __device__ void plate_apply(const PlateGeom &g, const double *Ke, const double *
 // eigensolver's state
 template <bool GEOM, int NT>
 __device__ __noinline__ void plate_apply_call(const PlateGeom &g, const double *Ke, const double *x, double *y) {
-  // Ke is the work-group's LDS copy, x, y and the index maps global memory
-  using KL = const __attribute__((address_space(3))) double *;
-  using XG = const __attribute__((address_space(1))) double *;
-  using YG = __attribute__((address_space(1))) double *;
-  using IG = const __attribute__((address_space(1))) int *;
-  plate_apply_body<GEOM, NT>(g, (KL)Ke, (XG)x, (YG)y, (IG)g.full_of_free, (IG)g.free_of_full);
+  plate_apply<GEOM, NT>(g, Ke, x, y);
 }
 
 // lower band of K on the free unknowns: band[r][d] = K[r][r - d], d = 0..bw
 // (rows r0 .. r1 - 1, entries shared out over `nthreads` threads from thread t)
 template <typename B>
-__device__ void assemble_band(const PlateGeom &g, const double *Ke, B *band, int r0, int r1, int t, int nthreads) {
+__device__ void assemble_band(const PlateGeom &g, const double *Ke_, B *band, int r0, int r1, int t, int nthreads) {
   const int w = g.bw + 1;  // nfree w < 2^31 for every mesh the band form accepts
+  const KLds Ke = (KLds)Ke_;  // every caller's element matrix is its work-group's LDS copy
+  const IGlb full_of_free = (IGlb)g.full_of_free;
   for (int idx = r0 * w + t; idx < r1 * w; idx += nthreads) {
     const int r = idx / w, d = idx - r * w;
     double v = 0.0;
     const int cfree = r - d;
     if (cfree >= 0) {
-      const int fr = g.full_of_free[r], fc = g.full_of_free[cfree];
+      const int fr = full_of_free[r], fc = full_of_free[cfree];
       const int nr = fr / 5, cr = fr % 5, nc = fc / 5, cc = fc % 5;
       const int ir = nr % g.nnx, jr = nr / g.nnx, ic = nc % g.nnx, jc = nc / g.nnx;
       if (abs(ir - ic) <= 1 && abs(jr - jc) <= 1) {
@@ -260,7 +265,7 @@ __device__ void assemble_band(const PlateGeom &g, const double *Ke, B *band, int
         }
       }
     }
-    band[idx] = (B)v;
+    ((__attribute__((address_space(1))) B *)band)[idx] = (B)v;
   }
 }
 
@@ -316,7 +321,7 @@ static_assert(KP + ONE_MAXBW <= 2 * PT, "panel rows: at most two per thread");
 // factors the nbs x nbs block of P (column-major, LD rows) at rows and columns
 // c0 .. c0 + nbs - 1 (one thread, unblocked order); false at a non-positive pivot
 template <int LD, typename B>
-__device__ bool factor_top(B *P, int c0, int nbs) {
+__device__ __forceinline__ bool factor_top(B *P, int c0, int nbs) {
   B a[NBK][NBK];
 #pragma unroll
   for (int i = 0; i < NBK; ++i)
@@ -353,7 +358,7 @@ __device__ bool factor_top(B *P, int c0, int nbs) {
 // rows i0 .. rows - 1 of sub-panel columns c0 .. c0 + nbs - 1: forward
 // substitution with the factored top block, one thread per row (NT threads)
 template <int LD, typename B, int NT = PT>
-__device__ void factor_rows(B *P, int c0, int nbs, int i0, int rows) {
+__device__ __forceinline__ void factor_rows(B *P, int c0, int nbs, int i0, int rows) {
   for (int i = i0 + threadIdx.x; i < rows; i += NT) {
     B x[NBK];
 #pragma unroll
@@ -376,7 +381,7 @@ __device__ void factor_rows(B *P, int c0, int nbs, int i0, int rows) {
 // sub-panel A's product subtracted from sub-panel B's columns (rows NBK on):
 // the NBK-term sum of the NBK-column form's trailing update, one thread per row
 template <int LD, typename B, int NT = PT>
-__device__ void update_b(B *P, int nb, int rows) {
+__device__ __forceinline__ void update_b(B *P, int nb, int rows) {
   for (int i = NBK + threadIdx.x; i < rows; i += NT) {
     B x[NBK];
 #pragma unroll
