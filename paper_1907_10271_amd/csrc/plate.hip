@@ -69,6 +69,7 @@ struct PlateWork {
   double *kel;     // [S][KEL] element matrices K_e, K_G,e (factorisation spread over work-groups)
   int *flag;       // [S] non-positive pivot met
   double *lam;     // [S] lambda of the last solve (lowest-mode check of the wide path)
+  double *side;    // [S][2][KP][LDPW] the last two factored panels of the wide factorisation (as B)
   int nvec;
   size_t band_stride, vec_stride;
 };
@@ -1275,6 +1276,15 @@ __device__ __forceinline__ B *sample_band(const PlateWork &W, int s) {
   return sizeof(B) == 8 ? (B *)(W.band + (size_t)s * W.band_stride) : (B *)(W.bandf + (size_t)s * W.band_stride);
 }
 
+// copy of the factored panel at k0 (column-major, KP x LDPW, row i at k0 + i),
+// one of two per sample by the parity of k0 / KP: the next panel launch reads
+// the previous panel's columns from it in rows (neighbouring threads,
+// neighbouring entries) instead of in the band's row-major layout
+template <typename B>
+__device__ __forceinline__ B *panel_copy(const PlateWork &W, int s, int k0) {
+  return (B *)(W.side + ((size_t)s * 2 + (k0 / KP) % 2) * (KP * LDPW));
+}
+
 // band rows [blockIdx.x * rows_per_wg, ...) of sample blockIdx.y
 template <typename B>
 __global__ __launch_bounds__(PT) void k_plate_assemble(PlateGeom g, PlateWork W, int n, int rows_per_wg) {
@@ -1313,26 +1323,28 @@ __global__ __launch_bounds__(NTB) void k_band_step(PlateGeom g, PlateWork W, int
     const int nbA = min(NBK, nf - k0), nbB = max(0, min(NBK, nf - k0 - NBK)), nb = nbA + nbB;
     const int rows = min(nb + g.bw, nf - k0);  // panel rows k0 .. k0 + rows - 1
     if (threadIdx.x == 0) bad = 0;
+    const B *prev = panel_copy<B>(W, s, k0 + KP);  // the previous panel's copy (parity of k0 - KP)
     // the previous panel's columns on this panel's rows (the pc side of its update)
     for (int idx = threadIdx.x; idx < KP * KP; idx += NTB) {
       const int j = idx / KP, c = idx % KP;  // row k0 + j, previous column k0 - KP + c
       const bool in = k0 > 0 && j < nb && j + KP - c <= g.bw;
-      Lq[c * KP + j] = in ? band[(size_t)(k0 + j) * w + (j + KP - c)] : B(0);
+      Lq[c * KP + j] = in ? prev[c * LDPW + KP + j] : B(0);
+    }
+    // the panel's entries, KP lanes per row (a row's entries in the panel's
+    // columns are contiguous in the band)
+    for (int idx = threadIdx.x; idx < rows * KP; idx += NTB) {
+      const int i = idx / KP, j = idx % KP;
+      const B v = band[(size_t)(k0 + i) * w + min(max(i - j, 0), g.bw)];
+      P[j * LDPW + i] = (j < nb && i >= j && i - j <= g.bw) ? v : B(0);
     }
     __syncthreads();
-    // each row of the panel: its entries, less the previous panel's two
-    // NBK-term sums (sub-panel A first) where the row is inside that panel's window
+    // each row of the panel less the previous panel's two NBK-term sums
+    // (sub-panel A first) where the row is inside that panel's window
     for (int i = threadIdx.x; i < rows; i += NTB) {
-      const B *row = band + (size_t)(k0 + i) * w;
-      B e[KP];
-#pragma unroll
-      for (int j = 0; j < KP; ++j) e[j] = row[min(max(i - j, 0), g.bw)];
-#pragma unroll
-      for (int j = 0; j < KP; ++j) P[j * LDPW + i] = (j < nb && i >= j && i - j <= g.bw) ? e[j] : B(0);
       if (i < m) {
         B x[KP];  // the row's entries in the previous panel's columns (zero outside the band)
 #pragma unroll
-        for (int c = 0; c < KP; ++c) x[c] = (i + KP - c <= g.bw) ? row[min(i + KP - c, g.bw)] : B(0);
+        for (int c = 0; c < KP; ++c) x[c] = (i + KP - c <= g.bw) ? prev[c * LDPW + KP + i] : B(0);
         for (int j = 0; j < min(nb, i + 1); ++j) {
           B accA = B(0), accB = B(0);
 #pragma unroll
@@ -1372,6 +1384,12 @@ __global__ __launch_bounds__(NTB) void k_band_step(PlateGeom g, PlateWork W, int
       const int i = idx / KP, j = idx % KP;
       if (j < nb && i >= j && i - j <= g.bw) band[(size_t)(k0 + i) * w + (i - j)] = P[j * LDPW + i];
     }
+    // the factored panel's copy for the next launch (rows of a column contiguous)
+    B *cur = panel_copy<B>(W, s, k0);
+    for (int idx = threadIdx.x; idx < KP * rows; idx += NTB) {
+      const int j = idx / rows, i = idx % rows;
+      cur[j * LDPW + i] = P[j * LDPW + i];
+    }
     return;
   }
   // ---- the other work-groups: the rest of the previous panel's trailing window
@@ -1379,13 +1397,12 @@ __global__ __launch_bounds__(NTB) void k_band_step(PlateGeom g, PlateWork W, int
   // one-work-group form
   if (m <= 0 || nwg < 2) return;
   B *Lp = S;
-  for (int r = threadIdx.x; r < m; r += NTB) {  // one thread per band row: its KP entries are contiguous
-    const B *row = band + (size_t)(k0 + r) * w;
-    B v[KP];
-#pragma unroll
-    for (int j = 0; j < KP; ++j) v[j] = row[min(r + KP - j, g.bw)];
-#pragma unroll
-    for (int j = 0; j < KP; ++j) Lp[j * MAXBW + r] = (r + KP - j <= g.bw) ? v[j] : B(0);
+  {
+    const B *prev = panel_copy<B>(W, s, k0 + KP);  // the previous panel's copy
+    for (int idx = threadIdx.x; idx < KP * m; idx += NTB) {
+      const int j = idx / m, r = idx % m;
+      Lp[j * MAXBW + r] = (r + KP - j <= g.bw) ? prev[j * LDPW + KP + r] : B(0);
+    }
   }
   __syncthreads();
   const int mt = (m + 3) / 4, ntile = mt * (mt + 1) / 2;
@@ -1510,7 +1527,7 @@ struct PlateLevelH {
   // batch workspace
   int cap = 0;
   size_t bytes = 0;
-  double *band = nullptr, *vec = nullptr, *kel = nullptr;
+  double *band = nullptr, *vec = nullptr, *kel = nullptr, *side = nullptr;
   float *bandf = nullptr;
   int64_t *rows = nullptr;
   int *outidx = nullptr, *flag = nullptr;
@@ -1705,6 +1722,8 @@ static void free_work(PlateLevelH &L) {
   if (L.kel) (void)hipFree(L.kel);
   if (L.flag) (void)hipFree(L.flag);
   if (L.lam) (void)hipFree(L.lam);
+  if (L.side) (void)hipFree(L.side);
+  L.side = nullptr;
   L.lam = nullptr;
   L.kel = nullptr;
   L.flag = nullptr;
@@ -1722,7 +1741,7 @@ static void free_work(PlateLevelH &L) {
 static size_t work_bytes(const PlateLevelH &L) {
   const size_t bs = (size_t)L.g.nfree * (L.g.bw + 1);
   return bs * (sizeof(double) + sizeof(float)) + (size_t)NVEC * L.g.nfree * sizeof(double) + sizeof(int64_t) +
-         2 * sizeof(int) + (KEL + 1) * sizeof(double);
+         2 * sizeof(int) + (KEL + 1) * sizeof(double) + 2 * (size_t)KP * LDPW * sizeof(double);
 }
 
 // grow the workspace of level l to at least n samples within the budget
@@ -1744,7 +1763,8 @@ static int ensure_work(PlateCtx *p, std::string &err, int l, int n) {
       hipMalloc(&L.vec, (size_t)NVEC * L.g.nfree * sizeof(double) * n) != hipSuccess ||
       hipMalloc(&L.rows, sizeof(int64_t) * n) != hipSuccess || hipMalloc(&L.outidx, sizeof(int) * n) != hipSuccess ||
       hipMalloc(&L.kel, sizeof(double) * KEL * n) != hipSuccess || hipMalloc(&L.flag, sizeof(int) * n) != hipSuccess ||
-      hipMalloc(&L.lam, sizeof(double) * n) != hipSuccess) {
+      hipMalloc(&L.lam, sizeof(double) * n) != hipSuccess ||
+      hipMalloc(&L.side, sizeof(double) * 2 * KP * LDPW * n) != hipSuccess) {
     free_work(L);
     err = "plate workspace allocation failed";
     return MLMC_ENOMEM;
@@ -1842,6 +1862,7 @@ int plate_buckle_batch(PlateCtx *p, std::string &err, int n_req, const mlmc_requ
       Wk.kel = L.kel;
       Wk.flag = L.flag;
       Wk.lam = L.lam;
+      Wk.side = L.side;
       Wk.band_stride = (size_t)L.g.nfree * (L.g.bw + 1);
       Wk.vec_stride = (size_t)NVEC * L.g.nfree;
       for (int off = 0; off < total; off += cap) {
