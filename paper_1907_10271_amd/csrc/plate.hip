@@ -585,11 +585,11 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
   // At more than PT threads the solve is a call of its own, whose pointer
   // arguments the compiler cannot place: named as global memory, its loads
   // count only against the vector-memory counter, so the waits for LDS
-  // accesses do not also wait for the band entries in flight.  Loads are
-  // then issued unconditionally (addresses clamped into the band, values
-  // masked where used), so each wait covers just the loads it needs.
+  // accesses do not also wait for the band entries in flight.  In every form
+  // the loads are issued unconditionally (addresses clamped into the band or
+  // its padding, values masked where used), so each wait covers just the
+  // loads before it.
   constexpr bool LONG = NT > PT;
-  constexpr bool EXACT = true;  // unconditional loads (every form)
   using BP = std::conditional_t<LONG, const __attribute__((address_space(1))) B *, const B *>;
   using RP = std::conditional_t<LONG, const __attribute__((address_space(1))) double *, const double *>;
   using ZP = std::conditional_t<LONG, __attribute__((address_space(1))) double *, double *>;
@@ -611,21 +611,14 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
     for (int u = 0; u < XE; ++u) {
       const int idx = threadIdx.x + u * NT, i = idx / PS, j = idx % PS;
       const int ii = min(i, nb - 1);
-      const B v = bandp[(size_t)(k0 + ii) * w + max(ii - j, 0)];
-      if constexpr (EXACT)
-        e[u] = v;  // masked in x_store
-      else
-        e[u] = (i < nb && j <= i) ? v : B(i == j ? 1 : 0);
+      e[u] = bandp[(size_t)(k0 + ii) * w + max(ii - j, 0)];  // masked in x_store
     }
   };
   auto x_store = [&]() {
 #pragma unroll
     for (int u = 0; u < XE; ++u) {
       const int idx = threadIdx.x + u * NT, i = idx / PS, j = idx % PS;
-      if constexpr (EXACT)
-        Lb[idx] = (i < xnb && j <= i) ? e[u] : B(i == j ? 1 : 0);
-      else
-        Lb[idx] = e[u];
+      Lb[idx] = (i < xnb && j <= i) ? e[u] : B(i == j ? 1 : 0);
     }
   };
   // chunk c of row fi's band entries left of the step: column k0 + fi - d,
@@ -633,18 +626,11 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
   // used)
   auto row_load = [&](int k0, int c, B (&l)[CH]) {
     const int nb = min(PS, n - k0), d0 = fi + 1 + fq + LPR * CH * c;
-    if constexpr (EXACT) {
-      // past the row's band the reads land in the next row or in the band
-      // allocation's padding (BAND_PAD entries)
-      const BP p = bandp + (size_t)(k0 + min(fi, nb - 1)) * w + d0;
+    // past the row's band the reads land in the next row or in the band
+    // allocation's padding (BAND_PAD entries)
+    const BP p = bandp + (size_t)(k0 + min(fi, nb - 1)) * w + d0;
 #pragma unroll
-      for (int u = 0; u < CH; ++u) l[u] = p[LPR * u];
-    } else {
-      const B *p = bandp + (size_t)(k0 + min(fi, nb - 1)) * w + d0;
-#pragma unroll
-      for (int u = 0; u < CH; ++u)
-        if (LPR * u <= bw - d0) l[u] = p[LPR * u];
-    }
+    for (int u = 0; u < CH; ++u) l[u] = p[LPR * u];
   };
   auto row_dot = [&](int k0, int c, const B (&l)[CH], B (&acc)[NB]) {
     const int nb = min(PS, n - k0), d0 = fi + 1 + fq + LPR * CH * c;
@@ -666,8 +652,7 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
   B l[CH];
   double rv[NB];
   row_load(0, 0, l);
-  if (EXACT || (fq == 0 && fi < min(PS, n)))
-    for (int v = 0; v < NB; ++v) rv[v] = rp[(size_t)v * ld + (EXACT ? min(fi, n - 1) : fi)];
+  for (int v = 0; v < NB; ++v) rv[v] = rp[(size_t)v * ld + min(fi, n - 1)];  // used where fq = 0, fi < nb
   x_load(0);
   x_store();
   for (int k0 = 0; k0 < n; k0 += PS) {
@@ -688,8 +673,7 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
       // barriers; X first, since its wait at the end of this step covers all
       // loads issued before it
       x_load(k0 + PS);
-      if (EXACT || (fq == 0 && fi < min(PS, n - k0 - PS)))
-        for (int v = 0; v < NB; ++v) rv[v] = rp[(size_t)v * ld + (EXACT ? min(k0 + PS + fi, n - 1) : k0 + PS + fi)];
+      for (int v = 0; v < NB; ++v) rv[v] = rp[(size_t)v * ld + min(k0 + PS + fi, n - 1)];
       row_load(k0 + PS, 0, l);
     }
     for (int v = 0; v < NB; ++v)
@@ -728,34 +712,21 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
   // (entries outside the band are not loaded and not used)
   auto col_load = [&](int k0, int c, B (&lv)[PS]) {
     const int nb = min(PS, n - k0);
-    if constexpr (EXACT) {
-      // 32-bit byte offsets from the sample's band (fewer than 2^32 bytes for
-      // bw <= MAXBW): one address register per entry in flight; rows past the
-      // last and entries past the band read a clamped position (masked where
-      // used)
-      // (past the band the reads land in the next row or in the padding)
-      using CP = const __attribute__((address_space(1))) char *;
-      const unsigned o = (unsigned)(k0 * w + (k0 - c)) * (unsigned)sizeof(B);  // L(k0 + j, c) at o + j (w + 1) B
-      const unsigned step = (unsigned)(w + 1) * (unsigned)sizeof(B);
+    // 32-bit byte offsets from the sample's band (fewer than 2^32 bytes for
+    // bw <= MAXBW): one address register per entry in flight.  Rows past the
+    // last read the last row; entries past the band land in the next row or in
+    // the padding; neither is used.
+    using CP = const __attribute__((address_space(1))) char *;
+    const unsigned o = (unsigned)(k0 * w + (k0 - c)) * (unsigned)sizeof(B);  // L(k0 + j, c) at o + j (w + 1) B
+    const unsigned step = (unsigned)(w + 1) * (unsigned)sizeof(B);
 #pragma unroll
-      for (int j = 0; j < PS; ++j) lv[j] = *(BP)((CP)bandp + (o + min(j, nb - 1) * step));
-    } else {
-      const B *p = bandp + (size_t)k0 * w + (k0 - c);  // p[j (w + 1)] = L(k0 + j, c)
-#pragma unroll
-      for (int j = 0; j < PS; ++j)
-        if (j < nb && k0 + j - c <= bw) lv[j] = p[(size_t)j * (w + 1)];
-    }
+    for (int j = 0; j < PS; ++j) lv[j] = *(BP)((CP)bandp + (o + min(j, nb - 1) * step));
   };
   B l0[PS], yin[NB];
-  if constexpr (EXACT) {  // every thread loads (clamped column and row), used where in range
-    col_load(last, max(last - 1 - (int)threadIdx.x, max(0, last - bw)), l0);
-    for (int v = 0; v < NB; ++v)
-      yin[v] = tp[(size_t)v * n + min(max(last - 2 * PS - bw + (int)threadIdx.x, 0), n - 1)];
-  } else {
-    if (last - 1 - (int)threadIdx.x >= max(0, last - bw)) col_load(last, last - 1 - threadIdx.x, l0);
-    if (threadIdx.x < PS && last - 2 * PS - bw + (int)threadIdx.x >= 0)
-      for (int v = 0; v < NB; ++v) yin[v] = tp[(size_t)v * n + last - 2 * PS - bw + threadIdx.x];
-  }
+  // every thread loads (clamped column and row), used where in range
+  col_load(last, max(last - 1 - (int)threadIdx.x, max(0, last - bw)), l0);
+  for (int v = 0; v < NB; ++v)
+    yin[v] = tp[(size_t)v * n + min(max(last - 2 * PS - bw + (int)threadIdx.x, 0), n - 1)];
   for (int k0 = last; k0 >= 0; k0 -= PS) {
     const int nb = min(PS, n - k0);
     const bool next = k0 > 0;
@@ -803,14 +774,8 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
       for (int v = 0; v < NB; ++v) win(v, ent) = yin[v];
     if (next) {
       const int kn = k0 - PS, cn = kn - 1 - threadIdx.x, en = kn - 2 * PS - bw + threadIdx.x;
-      if constexpr (EXACT) {
-        col_load(kn, max(cn, max(0, kn - bw)), l0);
-        for (int v = 0; v < NB; ++v) yin[v] = tp[(size_t)v * n + min(max(en, 0), n - 1)];
-      } else {
-        if (cn >= max(0, kn - bw)) col_load(kn, cn, l0);
-        if (threadIdx.x < PS && en >= 0)
-          for (int v = 0; v < NB; ++v) yin[v] = tp[(size_t)v * n + en];
-      }
+      col_load(kn, max(cn, max(0, kn - bw)), l0);  // clamped; used where cn is in range
+      for (int v = 0; v < NB; ++v) yin[v] = tp[(size_t)v * n + min(max(en, 0), n - 1)];
       x_store();
     }
   }
