@@ -29,8 +29,9 @@ constexpr int NB = 2;        // LOBPCG block size
 constexpr int NS = 3 * NB;   // Rayleigh-Ritz basis size [X, W, P]
 constexpr int MAXPLY = 32;
 constexpr int MAXBW = 664;  // largest band half-width (128 x 128 mesh: 654)
-// entries allocated past the last band of a workspace: the wide band solve
-// reads up to MAXBW + 64 entries past a row's band without using them
+// entries allocated past the last band of a workspace: a band solve's row
+// loads reach up to 799 entries past a row's start, and a row holds at least
+// 16 (bw = 5 (nx + 2) >= 15); what lies past the row's band is never used
 constexpr size_t BAND_PAD = MAXBW + 128;
 // bands narrower than this are factored and solved by one work-group per
 // sample (k_buckle); wider ones always take the wide form
@@ -581,6 +582,8 @@ __device__ void band_solve(const PlateGeom &g, const B *band, const double *r, d
   constexpr int CH = LPR * 32 >= MAXB ? (MAXB - 1) / LPR + 1 : 32;
   constexpr int MAXCHUNK = (MAXB + LPR * CH - 1) / (LPR * CH);  // chunks of the widest band (bw <= MAXB)
   constexpr int XE = PS * PS / NT;                              // entries of X per thread
+  // furthest reach of a row load past its row's start (fi + 1 + fq + LPR u + LPR CH c)
+  static_assert(PS + LPR * CH * MAXCHUNK - 1 - 16 <= (int)BAND_PAD, "row loads stay inside the padding");
   const int w = g.bw + 1, n = g.nfree, bw = g.bw;
   // At more than PT threads the solve is a call of its own, whose pointer
   // arguments the compiler cannot place: named as global memory, its loads
