@@ -1514,6 +1514,7 @@ struct PlateCtx {
   int wide_min_bw = 200;  // factorise over several work-groups from this band width on (0: from ONE_MAXBW on)
   int wide_eig_threads = 1024;  // threads of the wide-band eigensolver's work-group (256 or 1024)
   int wide_factor_threads = 1024;  // threads of a panel launch's work-groups (256 or 1024)
+  double wide_batch_per_bw = 1.5;  // narrower bands: batches of at most this times bw take the wide form
 };
 
 // the factorisation spread over work-groups: element matrices, band assembly
@@ -1630,6 +1631,12 @@ PlateCtx *plate_create(const Json &cfg, std::string &err) {
     p->wide_factor_threads = (int)cfg.number_or("wide_factor_threads", 1024);
     if (p->wide_factor_threads != 256 && p->wide_factor_threads != 1024)
       throw std::runtime_error("wide_factor_threads must be 256 or 1024");
+    // batches of bands narrower than that of at most wide_batch_per_bw * bw
+    // samples leave the one-work-group kernel's slots mostly empty: they take
+    // the wide factorisation with the one-work-group eigensolver's order of
+    // sums (the same results to the bit); 0 keeps them in the one-work-group kernel
+    p->wide_batch_per_bw = cfg.number_or("wide_batch_per_bw", 1.5);
+    if (!(p->wide_batch_per_bw >= 0.0)) throw std::runtime_error("wide_batch_per_bw must be >= 0");
     // half-waves along x of the first LOBPCG start vector (0: nearest to a / b)
     const int start_p0 = (int)cfg.number_or("eig_start_p0", 0);
     if (start_p0 < 0 || start_p0 > 64) throw std::runtime_error("eig_start_p0 must be in 0..64");
@@ -1841,12 +1848,15 @@ int plate_buckle_batch(PlateCtx *p, std::string &err, int n_req, const mlmc_requ
           return MLMC_EHIP;
         }
         PlateJob J{offsets, L.rows, L.outidx, coarse ? lam_coarse : lam_fine, info, coarse, n};
-        if (L.g.bw >= ONE_MAXBW || (p->wide_min_bw > 0 && L.g.bw >= p->wide_min_bw)) {
+        const bool wide_band = L.g.bw >= ONE_MAXBW || (p->wide_min_bw > 0 && L.g.bw >= p->wide_min_bw);
+        const bool small_batch = !wide_band && n <= p->wide_batch_per_bw * L.g.bw;
+        if (wide_band || small_batch) {
+          // a small batch of a narrower band keeps the one-work-group order of sums
+          const int eig_nt = wide_band ? p->wide_eig_threads : PT;
           if (mixed)
-            launch_wide<float>(L.g, p->mat, Wk, J, n, tl, p->max_iter, p->wide_eig_threads, p->wide_factor_threads, st);
+            launch_wide<float>(L.g, p->mat, Wk, J, n, tl, p->max_iter, eig_nt, p->wide_factor_threads, st);
           else
-            launch_wide<double>(L.g, p->mat, Wk, J, n, tl, p->max_iter, p->wide_eig_threads, p->wide_factor_threads,
-                                st);
+            launch_wide<double>(L.g, p->mat, Wk, J, n, tl, p->max_iter, eig_nt, p->wide_factor_threads, st);
         } else if (mixed) {
           hipLaunchKernelGGL(k_buckle<float>, dim3(n), dim3(PT), 0, st, L.g, p->mat, Wk, J, tl, p->max_iter);
         } else {

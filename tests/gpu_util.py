@@ -9,11 +9,15 @@ import mlmc_inputs as mi
 @functools.lru_cache(maxsize=None)
 def context(name: str, engine: str = "auto"):
     """Context of a workload; engine "lockstep" turns the one-work-group-per-
-    sample solver of the coarse levels off, so every level runs the lock-step
-    engine."""
+    sample solver of the coarse strip levels off, so every level runs the
+    lock-step engine; engine "one_wg" keeps small plate batches of the narrower
+    bands in the one-work-group kernel (otherwise they take the wide form, with
+    the same results to the bit)."""
     import paper_1907_10271_amd as pk
     if engine == "auto":
         return pk.Context(mi.config_text(name))
+    if engine == "one_wg":
+        return pk.Context(dict(mi.load_config(name), wide_batch_per_bw=0))
     assert engine == "lockstep"
     return pk.Context(dict(mi.load_config(name), small_solver="off"))
 

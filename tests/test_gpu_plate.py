@@ -51,7 +51,7 @@ def test_plate_operators_parity(level):
 def test_buckling_load_parity_fp64(level):
     """Levels 0-1: one work-group per sample; level 2 (64^2): the factorisation
     spread over work-groups."""
-    ctx = context("plate_c4")
+    ctx = context("plate_c4", "one_wg")
     om = oracle_plate(level)
     n = 4 if level < 2 else 1
     off = mi.plate_offsets(C4, level, 0, n)
@@ -65,7 +65,7 @@ def test_buckling_load_parity_fp64(level):
 
 def test_buckling_mixed_and_coupled():
     import paper_1907_10271_amd as pk
-    ctx = context("plate_c4")
+    ctx = context("plate_c4", "one_wg")
     n = 3
     off = mi.plate_offsets(C4, 1, 0, n)
     lf, lc, info = ctx.buckle_batch([(k, 1, True) for k in range(n)], dev(off), precision=pk.MIXED)
@@ -133,7 +133,7 @@ def test_wide_factorisation_gives_identical_bits(precision):
     256-thread form, whose sums follow the one-work-group kernel's order."""
     import paper_1907_10271_amd as pk
     cfg = mi.load_config("plate_c4")
-    one = pk.Context(dict(cfg, wide_factor_min_bw=0))
+    one = pk.Context(dict(cfg, wide_factor_min_bw=0, wide_batch_per_bw=0))
     wide = pk.Context(dict(cfg, wide_factor_min_bw=1, wide_eig_threads=256))
     for level, n in ((1, 5), (0, 7)):
         off = dev(mi.plate_offsets(cfg, level, 0, n))
@@ -147,6 +147,23 @@ def test_wide_factorisation_gives_identical_bits(precision):
         assert np.all(a[2]["status_f"] == 0)
     one.close()
     wide.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_small_batches_take_the_wide_form_with_the_same_bits(precision):
+    """Batches of a narrower band of at most 1.5 bw samples take the wide
+    factorisation with the one-work-group order of sums: a batch of 5 on the
+    32^2 mesh (band 170) gives the bits a batch of 300 (one-work-group kernel)
+    gives its first 5 samples, coupled requests included."""
+    ctx = context("plate_c4")
+    off = dev(mi.plate_offsets(C4, 1, 0, 300))
+    big = ctx.buckle_batch([(k, 1, True) for k in range(300)], off, precision=precision)
+    small = ctx.buckle_batch([(k, 1, True) for k in range(5)], off, precision=precision)
+    for i in (0, 1):
+        assert np.array_equal(big[i].cpu().numpy()[:5], small[i].cpu().numpy()), i
+    for f in ("iters_f", "iters_c", "relres_f", "relres_c", "status_f", "status_c"):
+        assert np.array_equal(big[2][f][:5], small[2][f]), f
+    assert np.all(small[2]["status_f"] == 0)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -343,10 +360,10 @@ def test_lowest_mode_check_flags_higher_modes(precision):
     reqs = [(k, 0, False) for k in range(len(rows))]
     model = PlateModel(T2, 0)
     ref = np.array([model.buckling_load(mi.plate_offsets(T2, 0, r, 1)[0]) for r in rows])
-    old = pk.Context(dict(T2, eig_start_p0=1))
+    old = pk.Context(dict(T2, eig_start_p0=1, wide_batch_per_bw=0))  # the one-work-group kernel's check
     lam_old, _, info_old = old.buckle_batch(reqs, off, precision=precision)
     lam_old = lam_old.cpu().numpy()
-    new = pk.Context(mi.config_text("plate_t2"))
+    new = pk.Context(dict(T2, wide_batch_per_bw=0))
     lam_new, _, info_new = new.buckle_batch(reqs, off, precision=precision)
     lam_new = lam_new.cpu().numpy()
     tol = 1e-10 if precision == 0 else 1e-6
@@ -385,7 +402,7 @@ def test_lowest_mode_check_on_the_wide_path():
     reqs = [(k, 0, False) for k in range(len(rows))]
     outs = {}
     for wide in (0, 100):
-        ctx = pk.Context(dict(T2, eig_start_p0=1, wide_factor_min_bw=wide))
+        ctx = pk.Context(dict(T2, eig_start_p0=1, wide_factor_min_bw=wide, wide_batch_per_bw=0))
         lam, _, info = ctx.buckle_batch(reqs, off)
         outs[wide] = (lam.cpu().numpy(), info["status_f"].copy())
     np.testing.assert_allclose(outs[100][0], outs[0][0], rtol=1e-10, atol=0)
